@@ -1,0 +1,202 @@
+"""Benchmark of the expression evaluator on one MI355X.
+
+Workload (one step): the FP32-at-scale pair of expressions
+  job 1  M1*M2*M3*M4*M5 with dims 8192x1024, 1024x8192, 8192x512, 512x4096,
+         4096x64, entries N(0, 1/k)   (reordered by the DP planner: four GEMMs)
+  job 2  0.5*exp(-(A%A)) + B/C over 16384 x 16384, A,B ~ N(0,1), C ~ U[1,2]
+         (one fused element-wise pass)
+Inputs are generated once, resident in HBM before timing. The value is the
+whole step's algorithmic GFLOP/s. Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "expression GFLOP/s & % roofline, chosen form vs plain FP64 at stated error"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, datasheet
+FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix, datasheet
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n", type=int, default=16384, help="element-wise matrix size")
+    return ap.parse_args()
+
+
+def cpu_baseline(chain_np, ew_host, ew_flops_per_elem):
+    """The FP64 oracle, as it stands, on the host cores: the full chain job
+    plus a column sample of the element-wise job."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # noqa: BLE001
+        threads = os.cpu_count() or 1
+    names = [f"M{i}" for i in range(len(chain_np))]
+    env = dict(zip(names, chain_np))
+    t0 = time.perf_counter()
+    oracle.evaluate("*".join(names), env)
+    t_chain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.evaluate("0.5*exp(-(A%A)) + B/C", ew_host)
+    t_ew = time.perf_counter() - t0
+    dims = [m.shape[0] for m in chain_np] + [chain_np[-1].shape[1]]
+    from oracle import chain as ch
+    chain_flops = 2.0 * ch.brute_force_min(dims)[0]
+    ew_elems = ew_host["A"].size
+    flops = chain_flops + ew_flops_per_elem * ew_elems
+    return {
+        "value": flops / (t_chain + t_ew) / 1e9, "unit": "GFLOP/s", "cores": int(threads),
+        "kind": "oracle",
+        "sample": f"full 5-factor chain ({t_chain:.2f} s) + element-wise job on "
+                  f"{ew_host['A'].shape[0]}x{ew_host['A'].shape[1]} columns sample "
+                  f"({t_ew:.2f} s), float64 numpy",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import inputs
+    from paper_2502_03000_amd import hexla as hx
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    ctx = hx.Context(0)
+
+    # ---- inputs resident in HBM
+    chain_np = inputs.fp32_chain(seed=1001)
+    chain_t = [torch.from_numpy(np.ascontiguousarray(m.T)).to(dev).t() for m in chain_np]
+    ew = inputs.fp32_elementwise_device(seed=1001, n=args.n, device=dev)
+    torch.cuda.synchronize()
+
+    # ---- plans (host-side, once)
+    t0 = time.perf_counter()
+    e1 = None
+    for t in chain_t:
+        x = ctx.leaf(t)
+        e1 = x if e1 is None else e1 @ x
+    p1 = ctx.plan(e1)
+    A, B, Cm = (ctx.leaf(ew[k]) for k in ("A", "B", "C"))
+    p2 = ctx.plan(0.5 * hx.exp(-(A % A)) + B / Cm)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    out1, out2 = p1.output(dev), p2.output(dev)
+    ws1, ws2 = p1.workspace(dev), p2.workspace(dev)
+    d1, d2 = p1.describe(), p2.describe()
+
+    def step():
+        p1.execute(out1, ws1)
+        p2.execute(out2, ws2)
+
+    for _ in range(args.warmup):
+        step()
+    r = ctx.sync()
+    if r.status != hx.OK:
+        raise SystemExit(f"deferred error {r.status}")
+
+    # ---- timed region: K whole steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed / args.steps * 1e3
+    flops_step = p1.info.flops + p2.info.flops
+
+    # ---- per-job kernel times with HIP events on the launch stream
+    stream = torch.cuda.current_stream()
+
+    def time_job(fn, reps):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps):
+            fn()
+        ev1.record(stream)
+        ev1.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    reps = max(args.steps, 5)
+    ms_chain = time_job(lambda: p1.execute(out1, ws1), reps)
+    ms_ew = time_job(lambda: p2.execute(out2, ws2), reps)
+
+    # ---- sampled parity against the FP64 oracle (rows of the chain, elements of job 2)
+    import oracle
+    g = inputs.rng(99)
+    rows = g.integers(0, chain_np[0].shape[0], 8)
+    y1 = out1.cpu().numpy().astype(np.float64)
+    err_chain = 0.0
+    for i in rows:
+        v = chain_np[0][i:i + 1, :].astype(np.float64)
+        for m in chain_np[1:]:
+            v = v @ m.astype(np.float64)
+        err_chain = max(err_chain, np.linalg.norm(y1[i] - v[0]) / np.linalg.norm(v[0]))
+    cols = g.integers(0, args.n, 4)
+    err_ew = 0.0
+    for j in cols:
+        env = {k: ew[k][:, j:j + 1].cpu().numpy() for k in ("A", "B", "C")}
+        ref = oracle.evaluate("0.5*exp(-(A%A)) + B/C", env)
+        got = out2[:, j:j + 1].cpu().numpy().astype(np.float64)
+        err_ew = max(err_ew, np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+    ew_bytes = d2["bytes"]
+    ew_kernel = {"bound": "hbm", "achieved": ew_bytes / (ms_ew * 1e-3) / 1e9,
+                 "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    ew_kernel["frac"] = ew_kernel["achieved"] / HBM_PEAK_GBS
+    ew_kernel["traffic"] = None
+    chain_tflops = p1.info.flops / (ms_chain * 1e-3) / 1e12
+
+    res = {
+        "metric": METRIC,
+        "value": flops_step / (ms_per_step * 1e-3) / 1e9,
+        "unit": "GFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (seeded)",
+        "config": {"workload": "fp32 chain 8192x1024x8192x512x4096x64 (DP order) + fused "
+                               f"0.5*exp(-(A%A))+B/C over {args.n}x{args.n}",
+                   "chain_dims": list(inputs.FP32_CHAIN_DIMS), "elementwise_n": args.n,
+                   "planner": "dp", "form": "plain fp32"},
+        "roofline": ew_kernel,
+        "jobs": {
+            "chain": {"ms": ms_chain, "gflop": p1.info.flops / 1e9, "tflops": chain_tflops,
+                      "frac_fp32_mfma_peak": chain_tflops / FP32_MFMA_PEAK_TFLOPS,
+                      "kernels": [f"{s['kernel']} {s['m']}x{s['n']}x{s['k']} split{s.get('split', 1)}"
+                                  for s in d1["steps"]],
+                      "max_rel_err_sampled_rows": err_chain},
+            "elementwise": {"ms": ms_ew, "gbytes": ew_bytes / 1e9,
+                            "gbs": ew_kernel["achieved"], "max_rel_err_sampled_cols": err_ew},
+        },
+        "plan_ms": plan_ms,
+    }
+    if not args.no_cpu_baseline:
+        ncol = max(1, args.n // 8)
+        ew_host = {k: ew[k][:, :ncol].cpu().numpy() for k in ("A", "B", "C")}
+        res["cpu_baseline"] = cpu_baseline(chain_np, ew_host, d2["flops"] / float(args.n) ** 2)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

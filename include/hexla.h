@@ -1,0 +1,213 @@
+/*
+ * hexla.h - C ABI of an MI355X (gfx950) evaluator for compound linear-algebra
+ * expressions.
+ *
+ * The library implements the expression-optimisation method of Sanderson &
+ * Curtin, "Armadillo: An Efficient Framework for Numerical Linear Algebra"
+ * (arXiv 2502.03000), on one GPU:
+ *   - an expression is described first and evaluated only when asked for
+ *     (delayed evaluation, Sec. II): builder calls record markers that hold
+ *     references to matrices and copies of scalars, and nothing runs until
+ *     hexla_execute;
+ *   - element-wise sub-expressions of any length are fused into one pass with
+ *     no temporaries (Sec. II, the Z = 0.4*X + 0.6*Y example);
+ *   - sizes are checked when the expression is built (Sec. II);
+ *   - inv(A)*B is solved by LU with partial pivoting without forming the
+ *     inverse (Sec. I, Sec. II; expression (9) of Sec. III);
+ *   - a product of one matrix with its own transpose runs as a symmetric
+ *     rank-k update (Sec. II; expression (8) of Sec. III);
+ *   - matrix chains are reordered by cost (Sec. II; expression (6) of
+ *     Sec. III): by exact dynamic programming over multiply-add counts by
+ *     default, or by the paper's own smallest-result-first rule.
+ *
+ * Conventions
+ *   - Matrices are column-major with a leading dimension ld >= rows (ld >= 1
+ *     when rows == 0), the storage of the BLAS/LAPACK routines the paper maps
+ *     expressions onto. A vector is an n x 1 matrix.
+ *   - Every function returns hexla_status. Out-parameters come last.
+ *   - Device memory is always owned by the caller. The library never
+ *     allocates device memory while planning or executing; the only device
+ *     allocation it makes is a 256-byte status block per context, at
+ *     hexla_ctx_create.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef HEXLA_H
+#define HEXLA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hexla_status {
+  HEXLA_OK = 0,
+  HEXLA_E_INVALID_ARG = 1,     /* null pointer, bad ld, aliasing, short workspace */
+  HEXLA_E_DIM = 2,             /* non-conforming sizes (Sec. II size checks)      */
+  HEXLA_E_DTYPE = 3,           /* mixed storage types in one expression           */
+  HEXLA_E_NOT_SQUARE = 4,      /* inv()/solve() of a non-square matrix            */
+  HEXLA_E_SINGULAR = 5,        /* deferred: exact zero pivot met during LU        */
+  HEXLA_E_NO_CONVERGENCE = 6,  /* deferred: refinement hit its iteration cap      */
+  HEXLA_E_UNSUPPORTED = 7,     /* expression form this library does not evaluate */
+  HEXLA_E_DEVICE = 8           /* HIP error; text in hexla_last_error             */
+} hexla_status;
+
+typedef enum hexla_dtype { HEXLA_F64 = 0, HEXLA_F32 = 1 } hexla_dtype;
+
+typedef enum hexla_op {
+  /* unary */
+  HEXLA_OP_TRANS = 1,  /* transpose (Op<.., op_htrans>, Fig. 3)                */
+  HEXLA_OP_NEG = 2,    /* element-wise negation                                */
+  HEXLA_OP_EXP = 3,    /* element-wise exponential                             */
+  HEXLA_OP_INV = 4,    /* inverse marker (Op<.., op_inv>, Sec. II)             */
+  /* binary */
+  HEXLA_OP_TIMES = 16, /* matrix product, or scaling when one side is a scalar */
+  HEXLA_OP_PLUS = 17,  /* element-wise sum (Glue<.., glue_plus>, Sec. II)      */
+  HEXLA_OP_MINUS = 18, /* element-wise difference                              */
+  HEXLA_OP_SCHUR = 19, /* element-wise product ("%")                           */
+  HEXLA_OP_DIV = 20,   /* element-wise division                                */
+  HEXLA_OP_SOLVE = 21  /* solve(A, B): X with A X = B                          */
+} hexla_op;
+
+typedef uint32_t hexla_node;            /* index into the context's node arena */
+typedef struct hexla_ctx hexla_ctx;
+typedef struct hexla_plan hexla_plan;
+
+/* ------------------------------------------------------------------ context */
+
+/* device >= 0: a HIP device ordinal; kernels run on `stream` (a hipStream_t,
+ * NULL = the default stream). device == -1: a dry-run context that builds and
+ * plans without a GPU (hexla_execute then returns HEXLA_E_UNSUPPORTED).
+ * Errors: HEXLA_E_INVALID_ARG (out NULL, device < -1), HEXLA_E_DEVICE. */
+hexla_status hexla_ctx_create(int device, void* stream, hexla_ctx** out);
+/* Frees nodes, the status block and every plan still owned by the context. */
+hexla_status hexla_ctx_destroy(hexla_ctx* ctx);
+hexla_status hexla_ctx_set_stream(hexla_ctx* ctx, void* stream);
+/* Drops every node (plans already created stay valid). */
+hexla_status hexla_ctx_clear_nodes(hexla_ctx* ctx);
+/* Text of the last error on this context; valid until the next call on it. */
+const char* hexla_last_error(const hexla_ctx* ctx);
+
+/* ------------------------------------------------------------- IR builder
+ * Markers hold references to matrices and copies of scalars (Sec. II).      */
+
+/* A leaf BORROWS `ptr` (device memory, column-major, rows x cols, leading
+ * dimension ld). The memory must stay valid until the last hexla_execute that
+ * reads it has completed in stream order. Two leaves with the same
+ * (ptr, rows, cols, ld, dtype) are the same matrix (this identity is what the
+ * symmetric-product rewrite checks; equal values in distinct buffers are not
+ * detected). Errors: HEXLA_E_INVALID_ARG (rows/cols < 0, ld < max(rows,1),
+ * ptr NULL with rows*cols > 0, bad dtype). */
+hexla_status hexla_leaf(hexla_ctx* ctx, const void* ptr, int64_t rows, int64_t cols,
+                        int64_t ld, hexla_dtype dtype, hexla_node* out);
+/* A scalar, copied. It broadcasts in element-wise operations and scales in
+ * products. */
+hexla_status hexla_scalar(hexla_ctx* ctx, double value, hexla_node* out);
+/* Errors: HEXLA_E_INVALID_ARG (bad node or op), HEXLA_E_NOT_SQUARE (INV of a
+ * non-square matrix). */
+hexla_status hexla_unary(hexla_ctx* ctx, hexla_op op, hexla_node a, hexla_node* out);
+/* Sizes are checked here (Sec. II): HEXLA_E_DIM for non-conforming operands,
+ * HEXLA_E_NOT_SQUARE for solve() with a non-square left side, HEXLA_E_DTYPE
+ * when the operands' storage types differ. */
+hexla_status hexla_binary(hexla_ctx* ctx, hexla_op op, hexla_node a, hexla_node b,
+                          hexla_node* out);
+/* Shape of a node (a scalar is 1 x 1 with *is_scalar = 1). */
+hexla_status hexla_node_shape(const hexla_ctx* ctx, hexla_node n, int64_t* rows,
+                              int64_t* cols, int32_t* is_scalar);
+
+/* ---------------------------------------------------------------- planner */
+
+typedef enum hexla_planner {
+  HEXLA_PLANNER_DP = 0,      /* exact minimum multiply-adds over all bracketings */
+  HEXLA_PLANNER_GREEDY = 1,  /* Sec. II rule: smallest-result pair first, leftmost on ties */
+  HEXLA_PLANNER_NAIVE = 2,   /* Sec. III "naive": left to right, no rewrites     */
+  HEXLA_PLANNER_LEARNED = 3  /* predicted-time DP with the loaded cost model     */
+} hexla_planner;
+
+typedef enum hexla_product_precision {
+  HEXLA_PRODUCT_PLAIN = 0,   /* products in the storage type                     */
+  HEXLA_PRODUCT_BF16X3 = 1,  /* FP32 products as 3 BF16 MFMA products (hi/lo split) */
+  HEXLA_PRODUCT_BF16X6 = 2   /* FP32 products as 6 BF16 MFMA products (3-term split) */
+} hexla_product_precision;
+
+typedef enum hexla_solve_precision {
+  HEXLA_SOLVE_PLAIN = 0,     /* LU and substitution in the storage type          */
+  HEXLA_SOLVE_IR_FP32 = 1,   /* FP32 LU (FP64 pivot search) + FP64 refinement     */
+  HEXLA_SOLVE_IR_FP16 = 2    /* FP16-MFMA trailing updates + FP64 refinement     */
+} hexla_solve_precision;
+
+typedef struct hexla_plan_opts {
+  int32_t planner;            /* hexla_planner                                   */
+  int32_t product_precision;  /* hexla_product_precision                         */
+  int32_t solve_precision;    /* hexla_solve_precision                           */
+  int32_t fuse;               /* 1: fuse element-wise subtrees (default); 0: one
+                                 kernel and one temporary per operation          */
+  int32_t syrk;               /* 1: X^T X / X X^T on one leaf -> SYRK (default)  */
+  int32_t ir_max_iter;        /* refinement cap (default 30)                      */
+  double ir_tol_scale;        /* stop when ||R||inf <= scale*2^-53*||S||inf*||X||inf;
+                                 0 = sqrt(n)                                     */
+  int32_t reserved[8];
+} hexla_plan_opts;
+
+/* Fills the defaults: DP, plain precision, fusion on, SYRK on, cap 30. */
+hexla_status hexla_plan_opts_default(hexla_plan_opts* opts);
+
+/* Plans the evaluation of `root` (opts NULL = defaults). Host only: nothing
+ * is launched. The plan copies every leaf descriptor it needs, so nodes may
+ * be cleared afterwards. Errors: HEXLA_E_INVALID_ARG, HEXLA_E_UNSUPPORTED
+ * (e.g. a scalar-valued root), HEXLA_E_DTYPE. */
+hexla_status hexla_plan_create(hexla_ctx* ctx, hexla_node root, const hexla_plan_opts* opts,
+                               hexla_plan** out);
+
+typedef struct hexla_plan_info {
+  int64_t rows, cols;         /* shape of the result                             */
+  int32_t dtype;              /* hexla_dtype of the result                       */
+  int32_t n_steps;            /* kernels launched per execute (upper bound)       */
+  uint64_t workspace_bytes;   /* workspace hexla_execute needs (may be 0)        */
+  double flops;               /* algorithmic flops of the chosen plan            */
+  double bytes;               /* algorithmic HBM bytes (each operand once)       */
+  double chain_macs;          /* multiply-adds of the chosen chain orders        */
+} hexla_plan_info;
+
+hexla_status hexla_plan_get_info(const hexla_plan* plan, hexla_plan_info* out);
+/* JSON description of the plan (the analogue of the paper's call trace,
+ * Fig. 3): steps, kernels, shapes, flops, bytes. Writes at most cap bytes
+ * (NUL-terminated when cap > 0) and the full length (without NUL) to *needed. */
+hexla_status hexla_plan_describe(const hexla_plan* plan, char* buf, size_t cap, size_t* needed);
+hexla_status hexla_plan_destroy(hexla_plan* plan);
+
+/* -------------------------------------------------------------- evaluator */
+
+/* Evaluates the plan on the context's stream, asynchronously. `out` is
+ * caller-owned device memory for the rows x cols result with leading dimension
+ * ld_out >= max(rows,1); `workspace` is caller-owned device memory of at least
+ * workspace_bytes (256-byte aligned), or NULL when that is 0. The workspace
+ * and out must not overlap each other or any leaf read by a product, solve or
+ * transpose of the plan (element-wise-only plans may write in place).
+ * Errors (synchronous): HEXLA_E_INVALID_ARG, HEXLA_E_DEVICE,
+ * HEXLA_E_UNSUPPORTED (dry-run context). Numerical failures are deferred to
+ * hexla_sync. */
+hexla_status hexla_execute(hexla_plan* plan, void* out, int64_t ld_out, void* workspace,
+                           size_t workspace_bytes);
+
+typedef struct hexla_report {
+  int32_t status;             /* deferred hexla_status of the work since the last sync */
+  int32_t ir_iterations;      /* refinement iterations of the last refined solve */
+  int64_t singular_column;    /* first zero-pivot column (or -1)                 */
+} hexla_report;
+
+/* Waits for the context's stream, then reports (and clears) the deferred
+ * status: HEXLA_E_SINGULAR (exact zero pivot; the result is unspecified),
+ * HEXLA_E_NO_CONVERGENCE (refinement cap reached). `report` may be NULL. The
+ * return value is HEXLA_E_DEVICE on a HIP error, else HEXLA_OK. */
+hexla_status hexla_sync(hexla_ctx* ctx, hexla_report* report);
+
+/* Library version string (static storage). */
+const char* hexla_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HEXLA_H */

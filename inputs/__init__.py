@@ -172,3 +172,24 @@ def random_chain_dims(seed: int = 1005, count: int = 2000, lmin: int = 3,
         d = np.rint(np.exp(g.uniform(math.log(lo), math.log(hi), length + 1)))
         out.append(tuple(int(x) for x in d))
     return out
+
+
+# ------------------------------------------------- device-side generation
+# Large inputs are drawn directly on the GPU with torch's seeded Philox
+# generator (same seed -> same values on any MI355X); a caller that needs them
+# on the host copies them back.
+
+def fp32_elementwise_device(seed: int = 1001, n: int = 16384, cols: int | None = None,
+                            device: str = "cuda") -> dict:
+    import torch
+    c = n if cols is None else cols
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+
+    def colmajor_normal():
+        return torch.randn((c, n), generator=g, device=device, dtype=torch.float32).t()
+
+    a = colmajor_normal()
+    b = colmajor_normal()
+    cc = torch.rand((c, n), generator=g, device=device, dtype=torch.float32).t() + 1.0
+    return {"A": a, "B": b, "C": cc}

@@ -1,0 +1,187 @@
+// Evaluator: binds the caller's output and workspace to the plan and launches
+// its kernels on the context's stream (the evaluation at assignment of
+// Sec. II, done asynchronously on the device).
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+#include <string>
+
+#include "internal.h"
+
+namespace hexla {
+namespace {
+
+struct Bind {
+  char* out;
+  int64_t ld_out;
+  char* ws;
+};
+
+void* addr(const Ref& r, const Bind& b) {
+  switch (r.buf) {
+    case Buf::Leaf: return const_cast<void*>(r.ptr);
+    case Buf::Work: return b.ws + r.off;
+    case Buf::Out: return b.out + r.off;
+    default: return nullptr;
+  }
+}
+
+View resolve(View v, const Bind& b) {
+  if (v.ld < 0) v.ld = b.ld_out;
+  return v;
+}
+
+int64_t si(const View& v) { return v.trans ? v.ld : 1; }
+int64_t sj(const View& v) { return v.trans ? 1 : v.ld; }
+
+k::EwProgram make_prog(const EwHost& h, int64_t rows, int64_t cols, const Bind& b) {
+  k::EwProgram p{};
+  p.n_instr = h.n_instr;
+  for (int i = 0; i < h.n_instr; ++i) {
+    p.op[i] = h.op[i];
+    p.arg[i] = h.arg[i];
+  }
+  for (int i = 0; i < h.n_cst; ++i) p.cst[i] = h.cst[i];
+  p.n_leaf = int32_t(h.leaves.size());
+  p.rows = rows;
+  p.cols = cols;
+  p.uses_ident = h.ident ? 1 : 0;
+  bool contig = true;
+  for (size_t i = 0; i < h.leaves.size(); ++i) {
+    const View v = resolve(h.leaves[i], b);
+    p.leaf[i].ptr = addr(v.ref, b);
+    p.leaf[i].si = si(v);
+    p.leaf[i].sj = sj(v);
+    contig = contig && (rows == 1 || p.leaf[i].si == 1) && (cols == 1 || p.leaf[i].sj == rows);
+  }
+  p.contiguous = contig ? 1 : 0;
+  return p;
+}
+
+bool overlap(const void* a, uint64_t na, const void* b, uint64_t nb) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return na && nb && x < y + nb && y < x + na;
+}
+
+hexla_status device_err(hexla_ctx* ctx, hipError_t e, const char* what) {
+  return set_err(ctx, HEXLA_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+}  // namespace hexla
+
+using namespace hexla;
+
+extern "C" {
+
+hexla_status hexla_execute(hexla_plan* plan, void* out, int64_t ld_out, void* workspace,
+                           size_t workspace_bytes) {
+  if (!plan) return HEXLA_E_INVALID_ARG;
+  hexla_ctx* ctx = plan->ctx;
+  if (ctx->device < 0) return set_err(ctx, HEXLA_E_UNSUPPORTED, "dry-run context cannot execute");
+  const size_t esz = dtype_size(plan->dtype);
+  if (ld_out < (plan->rows > 1 ? plan->rows : 1))
+    return set_err(ctx, HEXLA_E_INVALID_ARG, "execute: ld_out < rows");
+  const uint64_t out_bytes =
+      plan->rows * plan->cols > 0 ? uint64_t(((plan->cols - 1) * ld_out + plan->rows) * int64_t(esz)) : 0;
+  if (out_bytes && !out) return set_err(ctx, HEXLA_E_INVALID_ARG, "execute: null output");
+  if (workspace_bytes < plan->ws_bytes || (plan->ws_bytes && !workspace))
+    return set_err(ctx, HEXLA_E_INVALID_ARG,
+                   "execute: workspace smaller than " + std::to_string(plan->ws_bytes) + " bytes");
+  if (workspace && (reinterpret_cast<uintptr_t>(workspace) & 255u))
+    return set_err(ctx, HEXLA_E_INVALID_ARG, "execute: workspace not 256-byte aligned");
+  for (const Range& r : plan->leaf_ranges) {
+    if (overlap(out, out_bytes, r.ptr, r.bytes))
+      return set_err(ctx, HEXLA_E_INVALID_ARG, "execute: output overlaps an operand of a product or solve");
+    if (overlap(workspace, plan->ws_bytes, r.ptr, r.bytes))
+      return set_err(ctx, HEXLA_E_INVALID_ARG, "execute: workspace overlaps an operand");
+  }
+  for (const Range& r : plan->ew_leaf_ranges) {
+    const bool in_place = r.ptr == out && r.ld == ld_out && !r.trans;
+    if (!in_place && overlap(out, out_bytes, r.ptr, r.bytes))
+      return set_err(ctx, HEXLA_E_INVALID_ARG, "execute: output overlaps an operand");
+    if (overlap(workspace, plan->ws_bytes, r.ptr, r.bytes))
+      return set_err(ctx, HEXLA_E_INVALID_ARG, "execute: workspace overlaps an operand");
+  }
+  if (overlap(workspace, plan->ws_bytes, out, out_bytes))
+    return set_err(ctx, HEXLA_E_INVALID_ARG, "execute: workspace overlaps the output");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return device_err(ctx, e, "hipSetDevice");
+  const Bind b{static_cast<char*>(out), ld_out, static_cast<char*>(workspace)};
+  hipStream_t st = ctx->stream;
+  for (const Step& s : plan->steps) {
+    switch (s.kind) {
+      case StepKind::Ew: {
+        const View o = resolve(s.out, b);
+        const k::EwProgram p = make_prog(s.ew, o.rows, o.cols, b);
+        e = k::ew_launch(s.dtype, p, addr(o.ref, b), si(o), sj(o), st);
+        break;
+      }
+      case StepKind::Gemv: {
+        const View A = resolve(s.A, b), B = resolve(s.B, b), C = resolve(s.C, b);
+        const int trans = A.trans ? 1 : 0;
+        const int64_t ms = trans ? A.cols : A.rows, ns = trans ? A.rows : A.cols;
+        const int64_t incx = B.cols == 1 ? si(B) : sj(B);
+        const int64_t incy = C.cols == 1 ? si(C) : sj(C);
+        k::EwProgram p{};
+        if (s.has_epi) p = make_prog(s.ew, C.rows, C.cols, b);
+        e = k::gemv_launch(s.dtype, trans, ms, ns, s.alpha, addr(A.ref, b), A.ld, addr(B.ref, b),
+                           incx, addr(C.ref, b), incy, s.has_epi ? &p : nullptr, st);
+        break;
+      }
+      case StepKind::Gemm: {
+        const View A = resolve(s.A, b), B = resolve(s.B, b), C = resolve(s.C, b);
+        e = k::gemm_launch(s.dtype, s.precision, s.mode, A.trans ? 1 : 0, B.trans ? 1 : 0, s.m, s.n,
+                           s.kk, s.alpha, addr(A.ref, b), A.ld, addr(B.ref, b), B.ld, s.beta,
+                           addr(C.ref, b), C.ld, addr(s.partial, b), s.cfg, st);
+        break;
+      }
+      case StepKind::LuFactor: {
+        const View A = resolve(s.A, b);
+        e = k::lu_factor_launch(s.dtype, s.n, addr(A.ref, b), A.ld,
+                                static_cast<int32_t*>(addr(s.rowid, b)), addr(s.luwork, b),
+                                ctx->d_status, st);
+        break;
+      }
+      case StepKind::LuSolve: {
+        const View A = resolve(s.A, b), B = resolve(s.B, b), C = resolve(s.C, b);
+        e = k::lu_solve_launch(s.dtype, s.n, s.nrhs, addr(A.ref, b), A.ld,
+                               static_cast<const int32_t*>(addr(s.rowid, b)), addr(B.ref, b), B.ld,
+                               addr(C.ref, b), C.ld, st);
+        break;
+      }
+      default:
+        break;
+    }
+    if (e != hipSuccess) return device_err(ctx, e, s.name.c_str());
+  }
+  return HEXLA_OK;
+}
+
+hexla_status hexla_sync(hexla_ctx* ctx, hexla_report* report) {
+  if (!ctx) return HEXLA_E_INVALID_ARG;
+  hexla_report r{};
+  r.singular_column = -1;
+  if (ctx->device < 0) {
+    if (report) *report = r;
+    return HEXLA_OK;
+  }
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  int32_t h[4] = {0, 0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpy(h, ctx->d_status, sizeof(h), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemset(ctx->d_status, 0, sizeof(h));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return device_err(ctx, e, "hexla_sync");
+  r.status = h[0];
+  r.ir_iterations = h[3];
+  if (h[0] == HEXLA_E_SINGULAR) r.singular_column = h[2];
+  if (h[1]) {
+    r.status = HEXLA_E_DEVICE;
+    set_err(ctx, HEXLA_E_DEVICE, "a device-wide barrier timed out");
+  }
+  if (report) *report = r;
+  return HEXLA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+// Host-side structures shared by the builder, the planner and the evaluator.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hexla.h"
+#include "kernels.h"
+
+namespace hexla {
+
+enum NodeKind : uint8_t { NK_LEAF = 0, NK_SCALAR = 1, NK_UNARY = 2, NK_BINARY = 3 };
+
+// One marker of the delayed expression (the Op/Glue objects of Sec. II): a
+// leaf borrows a matrix, a scalar is copied, operators refer to children.
+struct Node {
+  uint8_t kind = NK_LEAF;
+  int op = 0;
+  uint32_t a = 0, b = 0;
+  const void* ptr = nullptr;
+  int64_t ld = 1;
+  int dtype = -1;  // storage type of the value (-1 for scalars)
+  double value = 0.0;
+  int64_t rows = 0, cols = 0;
+  bool scalar = false;
+};
+
+enum class Buf : uint8_t { None, Leaf, Work, Out };
+
+// Address of a matrix: a borrowed leaf pointer, or a byte offset into the
+// caller's workspace or output buffer (bound at execute time).
+struct Ref {
+  Buf buf = Buf::None;
+  int64_t off = 0;
+  const void* ptr = nullptr;
+};
+
+// A rows x cols view; element (i, j) lives at storage (j, i) when trans.
+// ld == -1 means "the leading dimension hexla_execute receives" (output).
+struct View {
+  Ref ref;
+  int64_t rows = 0, cols = 0, ld = 1;
+  bool trans = false;
+  bool is_leaf = false;       // a borrowed leaf (not a temporary)
+  const void* leaf_ptr = nullptr;
+};
+
+// Storage range of a borrowed leaf, for the aliasing checks at execute time.
+struct Range {
+  const void* ptr = nullptr;
+  uint64_t bytes = 0;
+  int64_t ld = 0;
+  bool trans = false;
+};
+
+struct EwHost {
+  int32_t n_instr = 0;
+  uint8_t op[k::kEwMaxInstr] = {};
+  uint8_t arg[k::kEwMaxInstr] = {};
+  double cst[k::kEwMaxConst] = {};
+  int n_cst = 0;
+  std::vector<View> leaves;
+  int n_arith = 0;  // arithmetic operations per element (flop count)
+  bool ident = false;
+};
+
+enum class StepKind : uint8_t { Ew, Gemv, Gemm, LuFactor, LuSolve, Fill };
+
+struct Step {
+  StepKind kind = StepKind::Ew;
+  int dtype = 0;
+  std::string name;
+  // Ew: program over `ew` written to `out`; Gemv/Gemm: C = alpha op(A) op(B) + beta C
+  EwHost ew;
+  bool has_epi = false;
+  View out, A, B, C;
+  double alpha = 1.0, beta = 0.0;
+  int mode = 0;       // gemm: 0 full, 1 symmetric (SYRK)
+  int precision = 0;  // gemm: k::GemmPrecision
+  k::GemmConfig cfg{};
+  Ref partial;
+  int64_t m = 0, n = 0, kk = 0, nrhs = 0;
+  Ref rowid, luwork;
+  double flops = 0.0, bytes = 0.0;
+};
+
+}  // namespace hexla
+
+struct hexla_ctx {
+  int device = -1;
+  hipStream_t stream = nullptr;
+  std::vector<hexla::Node> nodes;
+  std::string err;
+  int32_t* d_status = nullptr;  // [0] status, [1] timeout, [2] singular column, [3] ir iterations
+};
+
+struct hexla_plan {
+  hexla_ctx* ctx = nullptr;
+  hexla_plan_opts opts{};
+  std::vector<hexla::Step> steps;
+  int64_t rows = 0, cols = 0;
+  int dtype = 0;
+  uint64_t ws_bytes = 0;
+  double flops = 0, bytes = 0, macs = 0;
+  std::vector<hexla::Range> leaf_ranges;     // read by products, solves, epilogues
+  std::vector<hexla::Range> ew_leaf_ranges;  // read by element-wise passes
+};
+
+namespace hexla {
+hexla_status set_err(const hexla_ctx* ctx, hexla_status st, const std::string& msg);
+size_t dtype_size(int dtype);
+}  // namespace hexla

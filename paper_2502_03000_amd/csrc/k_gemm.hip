@@ -1,0 +1,135 @@
+// Plain-precision GEMM / SYRK launchers (FP32 and FP64 MFMA) and the tile
+// heuristics the planner uses to size split-K workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "gemm_device.h"
+#include "kernels.h"
+
+namespace hexla {
+namespace k {
+
+namespace {
+
+struct Tile {
+  int bm, bn, bk;
+};
+// FP32: 0 = 128x128, 1 = 128x64 (skinny N), 2 = 64x64 (small)
+constexpr Tile kTilesF32[] = {{128, 128, 16}, {128, 64, 16}, {64, 64, 16}};
+// FP64: 0 = 64x64x16, 1 = 128x128x8
+constexpr Tile kTilesF64[] = {{64, 64, 16}, {128, 128, 8}};
+
+typedef void (*GemmFn)(GemmArgs);
+
+template <typename T, int BM, int BN, int BK>
+GemmFn pick(bool ta, bool tb, bool vec) {
+  if (vec) {
+    if (ta) return tb ? gemm_kernel<T, true, true, BM, BN, BK, true> : gemm_kernel<T, true, false, BM, BN, BK, true>;
+    return tb ? gemm_kernel<T, false, true, BM, BN, BK, true> : gemm_kernel<T, false, false, BM, BN, BK, true>;
+  }
+  if (ta) return tb ? gemm_kernel<T, true, true, BM, BN, BK, false> : gemm_kernel<T, true, false, BM, BN, BK, false>;
+  return tb ? gemm_kernel<T, false, true, BM, BN, BK, false> : gemm_kernel<T, false, false, BM, BN, BK, false>;
+}
+
+GemmFn kernel_for(int dtype, int tile, bool ta, bool tb, bool vec) {
+  if (dtype == 1) {
+    switch (tile) {
+      case 0: return pick<float, 128, 128, 16>(ta, tb, vec);
+      case 1: return pick<float, 128, 64, 16>(ta, tb, vec);
+      default: return pick<float, 64, 64, 16>(ta, tb, vec);
+    }
+  }
+  return tile == 1 ? pick<double, 128, 128, 8>(ta, tb, vec) : pick<double, 64, 64, 16>(ta, tb, vec);
+}
+
+Tile tile_of(int dtype, int tile) { return dtype == 1 ? kTilesF32[tile] : kTilesF64[tile]; }
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+GemmConfig gemm_choose(int dtype, int precision, int mode, int64_t m, int64_t n, int64_t k) {
+  GemmConfig c{0, 1};
+  if (precision != GEMM_PLAIN) return gemm_choose_split(dtype, precision, mode, m, n, k);
+  if (dtype == 1) {
+    if (mode == 1) c.tile = (n >= 1024) ? 0 : 2;
+    else if (m <= 64 || (n <= 64 && m < 1024)) c.tile = 2;
+    else if (n <= 64) c.tile = 1;
+    else c.tile = (m * n >= 1024 * 1024) ? 0 : 2;
+  } else {
+    c.tile = (m * n >= int64_t(2048) * 2048) ? 1 : 0;
+  }
+  const Tile t = tile_of(dtype, c.tile);
+  int64_t tiles;
+  if (mode == 1) {
+    const int64_t tt = cdiv(n, t.bn);
+    tiles = tt * (tt + 1) / 2;
+  } else {
+    tiles = cdiv(m, t.bm) * cdiv(n, t.bn);
+  }
+  const int64_t target = 512;
+  int64_t split = 1;
+  if (tiles < target) split = cdiv(target, tiles);
+  split = std::min<int64_t>(split, std::max<int64_t>(1, k / (8 * t.bk)));
+  split = std::min<int64_t>(split, 32);
+  if (split > 1) {
+    const int64_t chunk = cdiv(cdiv(k, split), t.bk) * t.bk;
+    split = cdiv(k, chunk);
+  }
+  c.split = int(std::max<int64_t>(split, 1));
+  return c;
+}
+
+size_t gemm_partial_bytes(int dtype, const GemmConfig& cfg, int64_t m, int64_t n) {
+  if (cfg.split <= 1) return 0;
+  const size_t esz = dtype == 0 ? 8 : 4;
+  return size_t(cfg.split) * size_t(m) * size_t(n) * esz;
+}
+
+hipError_t gemm_launch(int dtype, int precision, int mode, int ta, int tb, int64_t m, int64_t n,
+                       int64_t k, double alpha, const void* A, int64_t lda, const void* B,
+                       int64_t ldb, double beta, void* C, int64_t ldc, void* partial,
+                       const GemmConfig& cfg, hipStream_t s) {
+  if (m == 0 || n == 0) return hipSuccess;
+  if (precision != GEMM_PLAIN)
+    return gemm_split_launch(dtype, precision, mode, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta,
+                             C, ldc, partial, cfg, s);
+  const Tile t = tile_of(dtype, cfg.tile);
+  GemmArgs g{};
+  g.m = m; g.n = n; g.k = k;
+  g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+  g.alpha = alpha; g.beta = beta; g.partial = partial;
+  g.mode = mode;
+  g.split = cfg.split;
+  g.k_chunk = cdiv(cdiv(k, cfg.split), t.bk) * t.bk;
+  if (g.k_chunk == 0) g.k_chunk = t.bk;
+  g.tiles_m = int(cdiv(m, t.bm));
+  g.tiles_n = int(cdiv(n, t.bn));
+  const int esz = dtype == 0 ? 8 : 4;
+  const int vw = 16 / esz;
+  const bool vec = (lda % vw == 0) && (ldb % vw == 0) &&
+                   (reinterpret_cast<uintptr_t>(A) % 16 == 0) &&
+                   (reinterpret_cast<uintptr_t>(B) % 16 == 0);
+  int64_t blocks;
+  if (mode == 1) {
+    const int64_t tt = g.tiles_n;
+    blocks = tt * (tt + 1) / 2;
+  } else {
+    blocks = int64_t(g.tiles_m) * g.tiles_n;
+  }
+  GemmFn fn = kernel_for(dtype, cfg.tile, ta != 0, tb != 0, vec);
+  hipLaunchKernelGGL(fn, dim3(unsigned(blocks), unsigned(cfg.split)), dim3(256), 0, s, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || cfg.split <= 1) return e;
+  int64_t rb = cdiv(m * n, 256);
+  if (rb > 4096) rb = 4096;
+  if (dtype == 0)
+    hipLaunchKernelGGL(splitk_reduce_kernel<double>, dim3(unsigned(rb)), dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL(splitk_reduce_kernel<float>, dim3(unsigned(rb)), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+}  // namespace k
+}  // namespace hexla

@@ -1,0 +1,109 @@
+// Launch interface of the gfx950 kernels. Host code (planner, evaluator)
+// includes this header only; every argument is a plain pointer or integer.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+namespace hexla {
+namespace k {
+
+// ------------------------------------------------------------ element-wise
+// A post-order program for a 4-deep value stack, evaluated per element with
+// uniform (scalar) control flow: the fused loop of Sec. II, with no temporaries.
+enum EwOp : uint8_t {
+  EW_LEAF = 0,   // push leaf[arg] at this element
+  EW_EXTRA = 1,  // push the producing kernel's value (GEMV epilogue)
+  EW_CONST = 2,  // push cst[arg]
+  EW_IDENT = 3,  // push (i == j) ? 1 : 0 (general path only)
+  EW_ADD = 4,    // b = pop, a = pop, push a + b
+  EW_SUB = 5,    //                    push a - b
+  EW_MUL = 6,    //                    push a * b
+  EW_DIV = 7,    //                    push a / b
+  EW_RSUB = 8,   //                    push b - a
+  EW_RDIV = 9,   //                    push b / a
+  EW_NEG = 10,   // top = -top
+  EW_EXP = 11,   // top = exp(top)
+  EW_SCALE = 12, // top = top * cst[arg]
+  EW_ADDC = 13,  // top = top + cst[arg]
+  EW_LEAFMUL = 14,  // top = top * leaf[arg]
+  EW_LEAFADD = 15   // top = top + leaf[arg]
+};
+
+constexpr int kEwMaxInstr = 32;
+constexpr int kEwMaxLeaf = 8;
+constexpr int kEwMaxConst = 8;
+constexpr int kEwMaxDepth = 4;
+
+struct EwLeaf {
+  const void* ptr;
+  int64_t si, sj;  // element (i, j) of the view is ptr[i*si + j*sj]
+};
+
+struct EwProgram {
+  int32_t n_instr;
+  int32_t n_leaf;
+  int32_t contiguous;  // every leaf is dense in flat column-major order
+  int32_t uses_ident;
+  int64_t rows, cols;  // shape of the evaluated view
+  uint8_t op[kEwMaxInstr];
+  uint8_t arg[kEwMaxInstr];
+  double cst[kEwMaxConst];
+  EwLeaf leaf[kEwMaxLeaf];
+};
+
+// out element (i, j) is written to out[i*osi + j*osj].
+hipError_t ew_launch(int dtype, const EwProgram& p, void* out, int64_t osi, int64_t osj,
+                     hipStream_t s);
+
+// -------------------------------------------------------------------- GEMV
+// y = alpha * op(A) x (+ epilogue), A stored ms x ns column-major (lda).
+// trans = 0: y has ms entries; trans = 1: y has ns entries. With an epilogue,
+// y_i = program(extra = alpha * (op(A) x)_i) evaluated at flat index i.
+hipError_t gemv_launch(int dtype, int trans, int64_t ms, int64_t ns, double alpha,
+                       const void* A, int64_t lda, const void* x, int64_t incx,
+                       void* y, int64_t incy, const EwProgram* epi, hipStream_t s);
+
+// -------------------------------------------------------------------- GEMM
+// C = alpha * op(A) op(B) + beta * C, op(A) m x k, op(B) k x n, all
+// column-major. mode 0: full product; mode 1: symmetric result, only
+// lower-triangle tiles are computed and mirrored (SYRK). split > 1 runs
+// split-K into `partial` (split * m * n elements) followed by a fixed-order
+// reduction (deterministic).
+struct GemmConfig {
+  int tile;   // index into the tile table of the kernel family
+  int split;  // K splits
+};
+enum GemmPrecision { GEMM_PLAIN = 0, GEMM_BF16X3 = 1, GEMM_BF16X6 = 2 };
+
+GemmConfig gemm_choose(int dtype, int precision, int mode, int64_t m, int64_t n, int64_t k);
+size_t gemm_partial_bytes(int dtype, const GemmConfig& cfg, int64_t m, int64_t n);
+// split-BF16 family (FP32 storage only), used by gemm_choose / gemm_launch
+GemmConfig gemm_choose_split(int dtype, int precision, int mode, int64_t m, int64_t n, int64_t k);
+hipError_t gemm_split_launch(int dtype, int precision, int mode, int ta, int tb, int64_t m,
+                             int64_t n, int64_t k, double alpha, const void* A, int64_t lda,
+                             const void* B, int64_t ldb, double beta, void* C, int64_t ldc,
+                             void* partial, const GemmConfig& cfg, hipStream_t s);
+hipError_t gemm_launch(int dtype, int precision, int mode, int ta, int tb, int64_t m, int64_t n,
+                       int64_t k, double alpha, const void* A, int64_t lda, const void* B,
+                       int64_t ldb, double beta, void* C, int64_t ldc, void* partial,
+                       const GemmConfig& cfg, hipStream_t s);
+
+// ---------------------------------------------------------------------- LU
+// In-place LU with partial pivoting of the n x n column-major matrix A (lda),
+// A = P^T L U. rowid (n ints) receives the original row held at each final
+// position (row i of L U is row rowid[i] of A). status[0] gets HEXLA_E_SINGULAR
+// and status[2..3] the first zero-pivot column on an exact zero pivot.
+size_t lu_workspace_bytes(int dtype, int64_t n);
+hipError_t lu_factor_launch(int dtype, int64_t n, void* A, int64_t lda, int32_t* rowid,
+                            void* work, int32_t* status, hipStream_t s);
+// X (n x nrhs, ldx) <- U^{-1} L^{-1} B[rowid], B with ldb. X may not alias B.
+hipError_t lu_solve_launch(int dtype, int64_t n, int64_t nrhs, const void* LU, int64_t lda,
+                           const int32_t* rowid, const void* B, int64_t ldb, void* X,
+                           int64_t ldx, hipStream_t s);
+
+// ------------------------------------------------------------------- utils
+hipError_t fill_i32_launch(int32_t* p, int64_t count, int32_t value, hipStream_t s);
+
+}  // namespace k
+}  // namespace hexla

@@ -1,0 +1,1061 @@
+// Planner: turns the delayed expression into a list of kernel launches.
+//
+// The rewrites are the paper's (Sec. II):
+//   * element-wise subtrees of any length become one fused program (no
+//     temporaries), and when such a program consumes a matrix-vector product
+//     it runs as that product's epilogue;
+//   * inv(S) * Y becomes an LU solve with Y as right-hand side (xGESV);
+//   * a product of a matrix with its own transpose (same storage) becomes a
+//     symmetric rank-k update computing one triangle (xSYRK);
+//   * scalars fold into the product's alpha or the element-wise program, and
+//     transposes fold into kernel flags;
+//   * matrix chains are bracketed by exact dynamic programming over
+//     multiply-add counts (default), by the paper's rule "multiply the
+//     adjacent pair with the smallest result first" (leftmost on ties), or
+//     left to right (the "naive" evaluation of Sec. III, which also disables
+//     the other rewrites).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace hexla {
+
+namespace {
+
+typedef __int128 i128;
+
+bool is_ew_binary(int op) {
+  return op == HEXLA_OP_PLUS || op == HEXLA_OP_MINUS || op == HEXLA_OP_SCHUR || op == HEXLA_OP_DIV;
+}
+
+struct Factor {
+  int kind = 0;  // 0 view, 1 inverse marker (node = S), 2 expression to materialize
+  uint32_t node = 0;
+  bool trans = false;
+  View v;
+};
+
+// Element-wise tree node.
+struct ENode {
+  int kind = 0;  // 0 op, 1 view, 2 const, 3 pending (product/solve/inverse), 4 extra
+  int op = 0;    // k::EwOp of an op node (binary or NEG/EXP)
+  int a = -1, b = -1;
+  View v;
+  double c = 0.0;
+  uint32_t node = 0;
+  bool trans = false;
+  int64_t rows = 0, cols = 0;
+};
+
+struct TNode {  // chain bracketing tree
+  int leaf = -1, left = -1, right = -1;
+  int lo = 0, hi = 0;
+};
+
+const char* planner_name(int p) {
+  switch (p) {
+    case HEXLA_PLANNER_GREEDY: return "greedy";
+    case HEXLA_PLANNER_NAIVE: return "naive";
+    case HEXLA_PLANNER_LEARNED: return "learned";
+    default: return "dp";
+  }
+}
+
+bool same_storage(const View& a, const View& b) {
+  return a.is_leaf && b.is_leaf && a.leaf_ptr == b.leaf_ptr && a.ld == b.ld &&
+         (a.trans ? a.cols : a.rows) == (b.trans ? b.cols : b.rows) &&
+         (a.trans ? a.rows : a.cols) == (b.trans ? b.rows : b.cols);
+}
+
+View transposed(const View& v) {
+  View t = v;
+  std::swap(t.rows, t.cols);
+  t.trans = !v.trans;
+  return t;
+}
+
+class Planner {
+ public:
+  Planner(hexla_ctx* ctx, const hexla_plan_opts& o, hexla_plan* plan)
+      : ctx_(ctx), o_(o), plan_(plan) {}
+
+  hexla_status run(hexla_node root) {
+    const Node& r = N(root);
+    if (r.scalar) return fail(HEXLA_E_UNSUPPORTED, "the expression is a scalar");
+    dtype_ = r.dtype;
+    esz_ = dtype_size(dtype_);
+    plan_->rows = r.rows;
+    plan_->cols = r.cols;
+    plan_->dtype = dtype_;
+    View out;
+    out.ref.buf = Buf::Out;
+    out.rows = r.rows;
+    out.cols = r.cols;
+    out.ld = -1;
+    materialize(root, false, &out);
+    if (status_ != HEXLA_OK) return status_;
+    plan_->ws_bytes = uint64_t(top_);
+    double fl = 0, by = 0;
+    for (const Step& s : steps_) {
+      fl += s.flops;
+      by += s.bytes;
+    }
+    plan_->flops = fl;
+    plan_->bytes = by;
+    plan_->macs = macs_;
+    plan_->steps = std::move(steps_);
+    return HEXLA_OK;
+  }
+
+ private:
+  hexla_ctx* ctx_;
+  hexla_plan_opts o_;
+  hexla_plan* plan_;
+  int dtype_ = 0;
+  size_t esz_ = 8;
+  int64_t top_ = 0;
+  double macs_ = 0;
+  std::vector<Step> steps_;
+  std::vector<ENode> E_;
+  hexla_status status_ = HEXLA_OK;
+
+  const Node& N(uint32_t i) const { return ctx_->nodes[i]; }
+
+  hexla_status fail(hexla_status st, const std::string& msg) {
+    if (status_ == HEXLA_OK) {
+      status_ = st;
+      set_err(ctx_, st, msg);
+    }
+    return st;
+  }
+
+  Ref work(int64_t bytes) {
+    Ref r;
+    r.buf = Buf::Work;
+    top_ = (top_ + 255) & ~int64_t(255);
+    r.off = top_;
+    top_ += std::max<int64_t>(bytes, 1);
+    return r;
+  }
+
+  View temp(int64_t rows, int64_t cols) {
+    View v;
+    v.ref = work(rows * cols * int64_t(esz_));
+    v.rows = rows;
+    v.cols = cols;
+    v.ld = std::max<int64_t>(rows, 1);
+    return v;
+  }
+
+  View leaf_view(uint32_t n, bool t) const {
+    const Node& x = N(n);
+    View v;
+    v.ref.buf = Buf::Leaf;
+    v.ref.ptr = x.ptr;
+    v.rows = t ? x.cols : x.rows;
+    v.cols = t ? x.rows : x.cols;
+    v.ld = x.ld;
+    v.trans = t;
+    v.is_leaf = true;
+    v.leaf_ptr = x.ptr;
+    return v;
+  }
+
+  static bool same_view(const View& a, const View& b) {
+    return a.ref.buf == b.ref.buf && a.ref.off == b.ref.off && a.ref.ptr == b.ref.ptr &&
+           a.rows == b.rows && a.cols == b.cols && a.ld == b.ld && a.trans == b.trans;
+  }
+
+  // ------------------------------------------------------------- scalars
+  double scalar_value(uint32_t n) const {
+    const Node& x = N(n);
+    if (x.kind == NK_SCALAR) return x.value;
+    if (x.kind == NK_UNARY) {
+      const double a = scalar_value(x.a);
+      switch (x.op) {
+        case HEXLA_OP_NEG: return -a;
+        case HEXLA_OP_EXP: return std::exp(a);
+        case HEXLA_OP_INV: return 1.0 / a;
+        default: return a;
+      }
+    }
+    const double a = scalar_value(x.a), b = scalar_value(x.b);
+    switch (x.op) {
+      case HEXLA_OP_PLUS: return a + b;
+      case HEXLA_OP_MINUS: return a - b;
+      case HEXLA_OP_DIV: return a / b;
+      default: return a * b;  // TIMES, SCHUR
+    }
+  }
+
+  // ------------------------------------------------------------ products
+  void flatten(uint32_t n, bool t, std::vector<Factor>& out, double& alpha) const {
+    const Node& x = N(n);
+    if (x.scalar) {
+      alpha *= scalar_value(n);
+      return;
+    }
+    if (x.kind == NK_BINARY && x.op == HEXLA_OP_TIMES) {
+      if (t) {
+        flatten(x.b, t, out, alpha);
+        flatten(x.a, t, out, alpha);
+      } else {
+        flatten(x.a, t, out, alpha);
+        flatten(x.b, t, out, alpha);
+      }
+      return;
+    }
+    Factor f;
+    f.trans = t;
+    if (x.kind == NK_UNARY && x.op == HEXLA_OP_TRANS) {
+      flatten(x.a, !t, out, alpha);
+      return;
+    }
+    if (x.kind == NK_UNARY && x.op == HEXLA_OP_INV) {
+      f.kind = 1;
+      f.node = x.a;
+      out.push_back(f);
+      return;
+    }
+    if (x.kind == NK_LEAF) {
+      f.kind = 0;
+      f.node = n;
+      f.v = leaf_view(n, t);
+      out.push_back(f);
+      return;
+    }
+    f.kind = 2;
+    f.node = n;
+    out.push_back(f);
+  }
+
+  // A product node that is a real chain (two or more matrix factors, or an
+  // inverse marker), as opposed to a scaled matrix.
+  bool is_chain(uint32_t n) const {
+    std::vector<Factor> f;
+    double alpha = 1.0;
+    flatten(n, false, f, alpha);
+    if (f.size() >= 2) return true;
+    return f.size() == 1 && f[0].kind == 1;
+  }
+
+  // The final product of this chain is a matrix-vector product.
+  bool gemv_final(uint32_t n, bool t) const {
+    const Node& x = N(n);
+    if (x.kind != NK_BINARY || x.op != HEXLA_OP_TIMES) return false;
+    std::vector<Factor> f;
+    double alpha = 1.0;
+    flatten(n, t, f, alpha);
+    if (f.size() < 2) return false;
+    for (const Factor& q : f)
+      if (q.kind == 1) return false;
+    const int64_t rows = t ? x.cols : x.rows, cols = t ? x.rows : x.cols;
+    return rows == 1 || cols == 1;
+  }
+
+  // ------------------------------------------------------ materialization
+  // Evaluates node (transposed when t) into dest, or into a new temporary
+  // (or returns a borrowed view) when dest is null.
+  View materialize(uint32_t n, bool t, const View* dest) {
+    if (status_ != HEXLA_OK) return View{};
+    const Node& x = N(n);
+    if (x.scalar) {
+      fail(HEXLA_E_UNSUPPORTED, "scalar used where a matrix is required");
+      return View{};
+    }
+    switch (x.kind) {
+      case NK_LEAF: {
+        View v = leaf_view(n, t);
+        if (!dest) return v;
+        return emit_ew(add_view(v), dest, v.rows, v.cols);
+      }
+      case NK_UNARY:
+        if (x.op == HEXLA_OP_TRANS) return materialize(x.a, !t, dest);
+        if (x.op == HEXLA_OP_INV) {
+          View s = materialize(x.a, t, nullptr);
+          return explicit_inverse(s, dest);
+        }
+        return emit_ew(build_ew(n, t), dest, t ? x.cols : x.rows, t ? x.rows : x.cols);
+      default:
+        break;
+    }
+    if (x.op == HEXLA_OP_TIMES) {
+      if (is_chain(n)) return lower_chain(n, t, dest, nullptr);
+      return emit_ew(build_ew(n, t), dest, t ? x.cols : x.rows, t ? x.rows : x.cols);
+    }
+    if (is_ew_binary(x.op))
+      return emit_ew(build_ew(n, t), dest, t ? x.cols : x.rows, t ? x.rows : x.cols);
+    if (x.op == HEXLA_OP_SOLVE) {
+      View s = materialize(x.a, false, nullptr);
+      View b = materialize(x.b, false, nullptr);
+      if (!t) {
+        View xo = dest ? *dest : temp(s.cols, b.cols);
+        solve(s, b, xo);
+        return xo;
+      }
+      View xo = temp(s.cols, b.cols);
+      solve(s, b, xo);
+      View tv = transposed(xo);
+      if (!dest) return tv;
+      return emit_ew(add_view(tv), dest, tv.rows, tv.cols);
+    }
+    fail(HEXLA_E_UNSUPPORTED, "unknown operation");
+    return View{};
+  }
+
+  // ------------------------------------------------------------- element-wise
+  int add_node(const ENode& e) {
+    E_.push_back(e);
+    return int(E_.size()) - 1;
+  }
+  int add_view(const View& v) {
+    ENode e;
+    e.kind = 1;
+    e.v = v;
+    e.rows = v.rows;
+    e.cols = v.cols;
+    return add_node(e);
+  }
+  int add_const(double c) {
+    ENode e;
+    e.kind = 2;
+    e.c = c;
+    return add_node(e);
+  }
+  int add_op(int op, int a, int b, int64_t rows, int64_t cols) {
+    ENode e;
+    e.kind = 0;
+    e.op = op;
+    e.a = a;
+    e.b = b;
+    e.rows = rows;
+    e.cols = cols;
+    return add_node(e);
+  }
+
+  int build_ew(uint32_t n, bool t) {
+    const Node& x = N(n);
+    if (x.scalar) return add_const(scalar_value(n));
+    const int64_t rows = t ? x.cols : x.rows, cols = t ? x.rows : x.cols;
+    if (x.kind == NK_LEAF) return add_view(leaf_view(n, t));
+    auto pending = [&]() {
+      ENode e;
+      e.kind = 3;
+      e.node = n;
+      e.trans = t;
+      e.rows = rows;
+      e.cols = cols;
+      return add_node(e);
+    };
+    if (x.kind == NK_UNARY) {
+      switch (x.op) {
+        case HEXLA_OP_TRANS: return build_ew(x.a, !t);
+        case HEXLA_OP_NEG: return add_op(k::EW_NEG, build_ew(x.a, t), -1, rows, cols);
+        case HEXLA_OP_EXP: return add_op(k::EW_EXP, build_ew(x.a, t), -1, rows, cols);
+        default: return pending();
+      }
+    }
+    switch (x.op) {
+      case HEXLA_OP_PLUS: return add_op(k::EW_ADD, build_ew(x.a, t), build_ew(x.b, t), rows, cols);
+      case HEXLA_OP_MINUS: return add_op(k::EW_SUB, build_ew(x.a, t), build_ew(x.b, t), rows, cols);
+      case HEXLA_OP_SCHUR: return add_op(k::EW_MUL, build_ew(x.a, t), build_ew(x.b, t), rows, cols);
+      case HEXLA_OP_DIV: return add_op(k::EW_DIV, build_ew(x.a, t), build_ew(x.b, t), rows, cols);
+      case HEXLA_OP_TIMES: {
+        if (is_chain(n)) return pending();
+        std::vector<Factor> f;
+        double alpha = 1.0;
+        flatten(n, t, f, alpha);
+        const int inner = f[0].kind == 0 ? add_view(f[0].v) : build_ew(f[0].node, f[0].trans);
+        if (alpha == 1.0) return inner;
+        return add_op(k::EW_MUL, inner, add_const(alpha), rows, cols);
+      }
+      default:
+        return pending();
+    }
+  }
+
+  void collect(int e, int kind, std::vector<int>& out) const {
+    if (e < 0) return;
+    if (E_[e].kind == kind) out.push_back(e);
+    if (E_[e].kind == 0) {
+      collect(E_[e].a, kind, out);
+      collect(E_[e].b, kind, out);
+    }
+  }
+
+  View out_or_temp(const View* dest, int64_t rows, int64_t cols) {
+    return dest ? *dest : temp(rows, cols);
+  }
+
+  View emit_ew(int root, const View* dest, int64_t rows, int64_t cols) {
+    if (status_ != HEXLA_OK) return View{};
+    if (E_[root].kind == 1 && !dest) return E_[root].v;
+    if (E_[root].kind == 3) return materialize(E_[root].node, E_[root].trans, dest);
+    std::vector<int> pend;
+    collect(root, 3, pend);
+    int epi = -1;
+    if (o_.fuse && o_.planner != HEXLA_PLANNER_NAIVE && E_[root].kind == 0) {
+      for (int p : pend)
+        if (gemv_final(E_[p].node, E_[p].trans)) {
+          epi = p;
+          break;
+        }
+    }
+    for (int p : pend) {
+      if (p == epi) continue;
+      View v = materialize(E_[p].node, E_[p].trans, nullptr);
+      E_[p].kind = 1;
+      E_[p].v = v;
+    }
+    if (status_ != HEXLA_OK) return View{};
+    if (!o_.fuse || o_.planner == HEXLA_PLANNER_NAIVE) return emit_unfused(root, dest);
+    if (epi >= 0) {
+      E_[epi].kind = 4;
+      EwHost prog;
+      if (!compile(root, prog, true)) return View{};
+      return lower_chain(E_[epi].node, E_[epi].trans, dest, &prog);
+    }
+    EwHost prog;
+    if (!compile(root, prog, false)) return View{};
+    View o = out_or_temp(dest, rows, cols);
+    push_ew(prog, o);
+    return o;
+  }
+
+  // One kernel and one temporary per operation (the eager evaluation the
+  // paper contrasts with fusion, Sec. II).
+  View emit_unfused(int e, const View* dest) {
+    const ENode node = E_[e];
+    if (node.kind == 1) {
+      if (!dest) return node.v;
+      EwHost p;
+      compile(e, p, false);
+      push_ew(p, *dest);
+      return *dest;
+    }
+    if (node.kind != 0) {
+      fail(HEXLA_E_UNSUPPORTED, "internal: unexpected element-wise node");
+      return View{};
+    }
+    int a = node.a, b = node.b;
+    if (E_[a].kind == 0) a = add_view(emit_unfused(a, nullptr));
+    if (b >= 0 && E_[b].kind == 0) b = add_view(emit_unfused(b, nullptr));
+    const int single = add_op(node.op, a, b, node.rows, node.cols);
+    EwHost p;
+    compile(single, p, false);
+    View o = out_or_temp(dest, node.rows, node.cols);
+    push_ew(p, o);
+    return o;
+  }
+
+  int need(int e) const {
+    const ENode& n = E_[e];
+    if (n.kind != 0) return 1;
+    if (n.b < 0) return need(n.a);
+    const ENode& a = E_[n.a];
+    const ENode& b = E_[n.b];
+    const bool comm = n.op == k::EW_ADD || n.op == k::EW_MUL;
+    if (b.kind == 2 && (comm || n.op == k::EW_SUB)) return need(n.a);
+    if (a.kind == 2 && comm) return need(n.b);
+    if (comm && b.kind == 1) return need(n.a);
+    if (comm && a.kind == 1) return need(n.b);
+    const int na = need(n.a), nb = need(n.b);
+    return na == nb ? na + 1 : std::max(na, nb);
+  }
+
+  struct Gen {
+    EwHost* p;
+    bool ok = true;
+    std::string why;
+  };
+
+  int leaf_slot(Gen& g, const View& v) {
+    for (size_t i = 0; i < g.p->leaves.size(); ++i)
+      if (same_view(g.p->leaves[i], v)) return int(i);
+    if (int(g.p->leaves.size()) >= k::kEwMaxLeaf) {
+      g.ok = false;
+      g.why = "leaves";
+      return 0;
+    }
+    g.p->leaves.push_back(v);
+    return int(g.p->leaves.size()) - 1;
+  }
+  int const_slot(Gen& g, double c) {
+    for (int i = 0; i < g.p->n_cst; ++i)
+      if (g.p->cst[i] == c) return i;
+    if (g.p->n_cst >= k::kEwMaxConst) {
+      g.ok = false;
+      g.why = "constants";
+      return 0;
+    }
+    g.p->cst[g.p->n_cst] = c;
+    return g.p->n_cst++;
+  }
+  void emit(Gen& g, int op, int arg) {
+    if (g.p->n_instr >= k::kEwMaxInstr) {
+      g.ok = false;
+      g.why = "length";
+      return;
+    }
+    g.p->op[g.p->n_instr] = uint8_t(op);
+    g.p->arg[g.p->n_instr] = uint8_t(arg);
+    g.p->n_instr++;
+    if (op >= k::EW_ADD) g.p->n_arith++;
+  }
+
+  void gen(Gen& g, int e) {
+    if (!g.ok) return;
+    const ENode& n = E_[e];
+    if (n.kind == 1) return emit(g, k::EW_LEAF, leaf_slot(g, n.v));
+    if (n.kind == 2) return emit(g, k::EW_CONST, const_slot(g, n.c));
+    if (n.kind == 4) return emit(g, k::EW_EXTRA, 0);
+    if (n.b < 0) {
+      gen(g, n.a);
+      return emit(g, n.op, 0);
+    }
+    const ENode& a = E_[n.a];
+    const ENode& b = E_[n.b];
+    const bool comm = n.op == k::EW_ADD || n.op == k::EW_MUL;
+    if (b.kind == 2 && (comm || n.op == k::EW_SUB)) {
+      gen(g, n.a);
+      if (n.op == k::EW_MUL) return emit(g, k::EW_SCALE, const_slot(g, b.c));
+      return emit(g, k::EW_ADDC, const_slot(g, n.op == k::EW_SUB ? -b.c : b.c));
+    }
+    if (a.kind == 2 && comm) {
+      gen(g, n.b);
+      return emit(g, n.op == k::EW_MUL ? k::EW_SCALE : k::EW_ADDC, const_slot(g, a.c));
+    }
+    if (comm && b.kind == 1) {
+      gen(g, n.a);
+      return emit(g, n.op == k::EW_MUL ? k::EW_LEAFMUL : k::EW_LEAFADD, leaf_slot(g, b.v));
+    }
+    if (comm && a.kind == 1) {
+      gen(g, n.b);
+      return emit(g, n.op == k::EW_MUL ? k::EW_LEAFMUL : k::EW_LEAFADD, leaf_slot(g, a.v));
+    }
+    if (need(n.b) > need(n.a)) {
+      gen(g, n.b);
+      gen(g, n.a);
+      int op = n.op;
+      if (op == k::EW_SUB) op = k::EW_RSUB;
+      else if (op == k::EW_DIV) op = k::EW_RDIV;
+      return emit(g, op, 0);
+    }
+    gen(g, n.a);
+    gen(g, n.b);
+    emit(g, n.op, 0);
+  }
+
+  // The deepest operation child of e (to split off when a program is too big).
+  int deepest_op(int e) const {
+    const ENode& n = E_[e];
+    int best = -1, bn = 0;
+    for (int c : {n.a, n.b}) {
+      if (c < 0 || E_[c].kind != 0) continue;
+      const int v = need(c) * 64 + size(c);
+      if (v > bn) {
+        bn = v;
+        best = c;
+      }
+    }
+    return best;
+  }
+  int size(int e) const {
+    const ENode& n = E_[e];
+    if (n.kind != 0) return 1;
+    return 1 + size(n.a) + (n.b >= 0 ? size(n.b) : 0);
+  }
+
+  bool compile(int root, EwHost& out, bool allow_extra) {
+    for (int attempt = 0; attempt < 64; ++attempt) {
+      EwHost p;
+      Gen g;
+      g.p = &p;
+      if (need(root) <= k::kEwMaxDepth) gen(g, root);
+      else {
+        g.ok = false;
+        g.why = "depth";
+      }
+      if (g.ok) {
+        for (int i = 0; i < p.n_instr; ++i)
+          if (p.op[i] == k::EW_IDENT) p.ident = true;
+        out = p;
+        return true;
+      }
+      // split the deepest operation subtree into its own pass and retry
+      int victim = -1;
+      for (int e = root; e >= 0;) {
+        const int d = deepest_op(e);
+        if (d < 0) break;
+        victim = d;
+        if (need(d) <= k::kEwMaxDepth && size(d) <= k::kEwMaxInstr / 2) break;
+        e = d;
+      }
+      if (victim < 0) {
+        fail(HEXLA_E_UNSUPPORTED, "element-wise program cannot be split (" + g.why + ")");
+        return false;
+      }
+      (void)allow_extra;
+      View v = emit_ew(victim, nullptr, E_[victim].rows, E_[victim].cols);
+      E_[victim].kind = 1;
+      E_[victim].v = v;
+      E_[victim].a = E_[victim].b = -1;
+    }
+    fail(HEXLA_E_UNSUPPORTED, "element-wise program too large");
+    return false;
+  }
+
+  void push_ew(const EwHost& p, const View& o) {
+    Step s;
+    s.kind = StepKind::Ew;
+    s.dtype = dtype_;
+    s.name = "elementwise";
+    s.ew = p;
+    s.out = o;
+    const double elems = double(o.rows) * double(o.cols);
+    s.flops = elems * p.n_arith;
+    s.bytes = elems * double(esz_) * double(p.leaves.size() + 1);
+    steps_.push_back(s);
+  }
+
+  // ----------------------------------------------------------------- chains
+  View lower_chain(uint32_t n, bool t, const View* dest, const EwHost* epi) {
+    std::vector<Factor> f;
+    double alpha = 1.0;
+    flatten(n, t, f, alpha);
+    for (Factor& q : f)
+      if (q.kind == 2) {
+        q.v = materialize(q.node, q.trans, nullptr);
+        q.kind = 0;
+      }
+    if (status_ != HEXLA_OK) return View{};
+    return chain_views(f, alpha, dest, epi);
+  }
+
+  View chain_views(std::vector<Factor> f, double alpha, const View* dest, const EwHost* epi) {
+    const bool naive = o_.planner == HEXLA_PLANNER_NAIVE;
+    for (size_t p = 0; p < f.size(); ++p) {
+      if (f[p].kind != 1) continue;
+      View s = materialize(f[p].node, f[p].trans, nullptr);
+      if (status_ != HEXLA_OK) return View{};
+      if (naive || p + 1 == f.size()) {
+        f[p].v = explicit_inverse(s, nullptr);
+        f[p].kind = 0;
+        continue;
+      }
+      std::vector<Factor> rest(f.begin() + p + 1, f.end());
+      double ra = 1.0;
+      if (p == 0) std::swap(ra, alpha);
+      View rhs = chain_views(rest, ra, nullptr, nullptr);
+      if (status_ != HEXLA_OK) return View{};
+      const bool direct = p == 0 && dest && !epi;
+      View xo = direct ? *dest : temp(s.cols, rhs.cols);
+      solve(s, rhs, xo);
+      f.resize(p);
+      Factor q;
+      q.kind = 0;
+      q.v = xo;
+      f.push_back(q);
+      break;
+    }
+    if (status_ != HEXLA_OK) return View{};
+    if (f.size() == 1) {
+      const View v = f[0].v;
+      if (epi) {
+        fail(HEXLA_E_UNSUPPORTED, "internal: epilogue without a product");
+        return View{};
+      }
+      if (alpha == 1.0 && (!dest || same_view(v, *dest))) return v;
+      const int leaf = add_view(v);
+      const int root = alpha == 1.0 ? leaf : add_op(k::EW_MUL, leaf, add_const(alpha), v.rows, v.cols);
+      EwHost prog;
+      if (!compile(root, prog, false)) return View{};
+      View o = out_or_temp(dest, v.rows, v.cols);
+      push_ew(prog, o);
+      return o;
+    }
+    const int L = int(f.size());
+    std::vector<int64_t> dims(L + 1);
+    dims[0] = f[0].v.rows;
+    for (int i = 0; i < L; ++i) dims[i + 1] = f[i].v.cols;
+    std::vector<char> sym(L, 0);
+    if (o_.syrk && !naive)
+      for (int i = 0; i + 1 < L; ++i)
+        sym[i] = same_storage(f[i].v, f[i + 1].v) && f[i].v.trans != f[i + 1].v.trans;
+    std::vector<TNode> tree;
+    int root;
+    if (o_.planner == HEXLA_PLANNER_GREEDY) root = order_greedy(dims, tree);
+    else if (naive) root = order_left(L, tree);
+    else root = order_dp(dims, sym, tree);
+    macs_ += double(tree_cost(root, tree, dims, sym));
+    return emit_tree(root, tree, f, sym, true, dest, alpha, epi);
+  }
+
+  i128 pair_cost(const std::vector<int64_t>& d, int lo, int split, int hi,
+                 const std::vector<char>& sym) const {
+    if (hi == lo + 1 && sym[lo]) return i128(d[lo]) * (d[lo] + 1) / 2 * d[lo + 1];
+    return i128(d[lo]) * d[split + 1] * d[hi + 1];
+  }
+
+  i128 tree_cost(int t, const std::vector<TNode>& tree, const std::vector<int64_t>& d,
+                 const std::vector<char>& sym) const {
+    const TNode& n = tree[t];
+    if (n.leaf >= 0) return 0;
+    const int split = tree[n.left].hi;
+    return pair_cost(d, n.lo, split, n.hi, sym) + tree_cost(n.left, tree, d, sym) +
+           tree_cost(n.right, tree, d, sym);
+  }
+
+  int mk_leaf(std::vector<TNode>& tree, int i) {
+    TNode n;
+    n.leaf = i;
+    n.lo = n.hi = i;
+    tree.push_back(n);
+    return int(tree.size()) - 1;
+  }
+  int mk_pair(std::vector<TNode>& tree, int l, int r) {
+    TNode n;
+    n.left = l;
+    n.right = r;
+    n.lo = tree[l].lo;
+    n.hi = tree[r].hi;
+    tree.push_back(n);
+    return int(tree.size()) - 1;
+  }
+
+  int order_left(int L, std::vector<TNode>& tree) {
+    int t = mk_leaf(tree, 0);
+    for (int i = 1; i < L; ++i) t = mk_pair(tree, t, mk_leaf(tree, i));
+    return t;
+  }
+
+  // Exact minimum over all bracketings (O(L^3)); ties keep the first split.
+  int order_dp(const std::vector<int64_t>& d, const std::vector<char>& sym,
+               std::vector<TNode>& tree) {
+    const int L = int(d.size()) - 1;
+    std::vector<std::vector<i128>> cost(L, std::vector<i128>(L, 0));
+    std::vector<std::vector<int>> arg(L, std::vector<int>(L, -1));
+    for (int len = 2; len <= L; ++len)
+      for (int lo = 0; lo + len - 1 < L; ++lo) {
+        const int hi = lo + len - 1;
+        i128 best = -1;
+        for (int s = lo; s < hi; ++s) {
+          const i128 c = cost[lo][s] + cost[s + 1][hi] + pair_cost(d, lo, s, hi, sym);
+          if (best < 0 || c < best) {
+            best = c;
+            arg[lo][hi] = s;
+          }
+        }
+        cost[lo][hi] = best;
+      }
+    std::function<int(int, int)> build = [&](int lo, int hi) -> int {
+      if (lo == hi) return mk_leaf(tree, lo);
+      const int s = arg[lo][hi];
+      const int l = build(lo, s);
+      const int r = build(s + 1, hi);
+      return mk_pair(tree, l, r);
+    };
+    return build(0, L - 1);
+  }
+
+  // The paper's rule (Sec. II): multiply the adjacent pair whose product has
+  // the fewest elements, leftmost on ties, and repeat.
+  int order_greedy(const std::vector<int64_t>& d, std::vector<TNode>& tree) {
+    struct Item {
+      int t;
+      int64_t rows, cols;
+    };
+    std::vector<Item> items;
+    for (int i = 0; i + 1 < int(d.size()); ++i) items.push_back({mk_leaf(tree, i), d[i], d[i + 1]});
+    while (items.size() > 1) {
+      size_t best = 0;
+      i128 bs = -1;
+      for (size_t j = 0; j + 1 < items.size(); ++j) {
+        const i128 sz = i128(items[j].rows) * items[j + 1].cols;
+        if (bs < 0 || sz < bs) {
+          bs = sz;
+          best = j;
+        }
+      }
+      Item merged{mk_pair(tree, items[best].t, items[best + 1].t), items[best].rows,
+                  items[best + 1].cols};
+      items.erase(items.begin() + best, items.begin() + best + 2);
+      items.insert(items.begin() + best, merged);
+    }
+    return items[0].t;
+  }
+
+  View emit_tree(int t, const std::vector<TNode>& tree, const std::vector<Factor>& f,
+                 const std::vector<char>& sym, bool is_root, const View* dest, double alpha,
+                 const EwHost* epi) {
+    const TNode n = tree[t];
+    if (n.leaf >= 0) return f[n.leaf].v;
+    View a = emit_tree(n.left, tree, f, sym, false, nullptr, 1.0, nullptr);
+    View b = emit_tree(n.right, tree, f, sym, false, nullptr, 1.0, nullptr);
+    if (status_ != HEXLA_OK) return View{};
+    const bool syrk = tree[n.left].leaf >= 0 && tree[n.right].leaf >= 0 && sym[n.lo] != 0;
+    View c = (is_root && dest) ? *dest : temp(a.rows, b.cols);
+    product(a, b, c, is_root ? alpha : 1.0, syrk, is_root ? epi : nullptr);
+    return c;
+  }
+
+  void product(const View& a, const View& b, const View& c, double alpha, bool syrk,
+               const EwHost* epi) {
+    const int64_t m = a.rows, kk = a.cols, n = b.cols;
+    Step s;
+    s.dtype = dtype_;
+    s.alpha = alpha;
+    s.C = c;
+    s.m = m;
+    s.n = n;
+    s.kk = kk;
+    if (n == 1 || m == 1) {
+      s.kind = StepKind::Gemv;
+      if (n == 1) {
+        s.A = a;
+        s.B = b;
+      } else {  // C^T = B^T A^T
+        s.A = transposed(b);
+        s.B = transposed(a);
+        s.m = n;
+        s.n = 1;
+      }
+      s.name = s.A.trans ? "gemv_t" : "gemv_n";
+      s.flops = 2.0 * double(m) * double(n) * double(kk);
+      s.bytes = double(esz_) * (double(m) * kk + double(kk) * n + double(m) * n);
+      if (epi) {
+        s.has_epi = true;
+        s.ew = *epi;
+        s.flops += double(m) * n * epi->n_arith;
+        s.bytes += double(esz_) * double(m) * n * double(epi->leaves.size());
+      }
+    } else {
+      if (epi) {
+        fail(HEXLA_E_UNSUPPORTED, "internal: epilogue on a matrix product");
+        return;
+      }
+      s.kind = StepKind::Gemm;
+      s.A = a;
+      s.B = b;
+      s.mode = syrk ? 1 : 0;
+      s.precision = (dtype_ == HEXLA_F32) ? o_.product_precision : 0;
+      s.cfg = k::gemm_choose(dtype_, s.precision, s.mode, m, n, kk);
+      const size_t pb = k::gemm_partial_bytes(dtype_, s.cfg, m, n);
+      if (pb) s.partial = work(int64_t(pb));
+      s.name = syrk ? "syrk" : "gemm";
+      if (s.precision == 1) s.name += "_bf16x3";
+      if (s.precision == 2) s.name += "_bf16x6";
+      if (syrk) {
+        s.flops = double(n) * double(n + 1) * double(kk);
+        s.bytes = double(esz_) * (double(n) * kk + double(n) * n);
+      } else {
+        s.flops = 2.0 * double(m) * double(n) * double(kk);
+        s.bytes = double(esz_) * (double(m) * kk + double(kk) * n + double(m) * n);
+      }
+    }
+    steps_.push_back(s);
+  }
+
+  // ------------------------------------------------------------------ solves
+  void solve(const View& s, const View& b, const View& x) {
+    const int64_t n = s.rows, r = b.cols;
+    View lu = temp(n, n);
+    EwHost copy;
+    if (!compile(add_view(s), copy, false)) return;
+    push_ew(copy, lu);
+    Step f;
+    f.kind = StepKind::LuFactor;
+    f.dtype = dtype_;
+    f.name = "lu_factor";
+    f.A = lu;
+    f.n = n;
+    f.rowid = work(n * 4);
+    f.luwork = work(int64_t(k::lu_workspace_bytes(dtype_, n)));
+    f.flops = 2.0 / 3.0 * double(n) * n * n;
+    f.bytes = 2.0 * double(esz_) * double(n) * n;
+    steps_.push_back(f);
+    Step q;
+    q.kind = StepKind::LuSolve;
+    q.dtype = dtype_;
+    q.name = "lu_solve";
+    q.A = lu;
+    q.B = b;
+    q.C = x;
+    q.n = n;
+    q.nrhs = r;
+    q.rowid = f.rowid;
+    q.flops = 2.0 * double(n) * n * r;
+    q.bytes = double(esz_) * (double(n) * n + 2.0 * double(n) * r);
+    if (b.trans || x.trans) {
+      fail(HEXLA_E_UNSUPPORTED, "internal: transposed solve operand");
+      return;
+    }
+    steps_.push_back(q);
+  }
+
+  View explicit_inverse(const View& s, const View* dest) {
+    const int64_t n = s.rows;
+    View id = temp(n, n);
+    EwHost p;
+    p.op[0] = k::EW_IDENT;
+    p.n_instr = 1;
+    p.ident = true;
+    push_ew(p, id);
+    View x = dest ? *dest : temp(n, n);
+    solve(s, id, x);
+    return x;
+  }
+};
+
+void json_view(std::ostringstream& js, const char* name, const View& v) {
+  js << "\"" << name << "\":{\"rows\":" << v.rows << ",\"cols\":" << v.cols
+     << ",\"trans\":" << (v.trans ? "true" : "false") << ",\"buf\":\""
+     << (v.ref.buf == Buf::Leaf ? "leaf" : v.ref.buf == Buf::Work ? "work" : "out") << "\"}";
+}
+
+}  // namespace
+
+std::string describe(const hexla_plan* p) {
+  std::ostringstream js;
+  js.precision(17);
+  js << "{\"rows\":" << p->rows << ",\"cols\":" << p->cols << ",\"dtype\":\""
+     << (p->dtype == HEXLA_F64 ? "f64" : "f32") << "\",\"planner\":\""
+     << planner_name(p->opts.planner) << "\",\"workspace_bytes\":" << p->ws_bytes
+     << ",\"flops\":" << p->flops << ",\"bytes\":" << p->bytes << ",\"chain_macs\":" << p->macs
+     << ",\"steps\":[";
+  for (size_t i = 0; i < p->steps.size(); ++i) {
+    const Step& s = p->steps[i];
+    if (i) js << ",";
+    js << "{\"kernel\":\"" << s.name << "\",\"flops\":" << s.flops << ",\"bytes\":" << s.bytes;
+    switch (s.kind) {
+      case StepKind::Ew:
+        js << ",\"instructions\":" << s.ew.n_instr << ",\"leaves\":" << s.ew.leaves.size() << ",";
+        json_view(js, "out", s.out);
+        break;
+      case StepKind::Gemv:
+      case StepKind::Gemm:
+        js << ",\"m\":" << s.m << ",\"n\":" << s.n << ",\"k\":" << s.kk << ",\"alpha\":" << s.alpha
+           << ",\"epilogue\":" << (s.has_epi ? "true" : "false");
+        if (s.kind == StepKind::Gemm)
+          js << ",\"tile\":" << s.cfg.tile << ",\"split\":" << s.cfg.split;
+        js << ",";
+        json_view(js, "A", s.A);
+        js << ",";
+        json_view(js, "B", s.B);
+        js << ",";
+        json_view(js, "C", s.C);
+        break;
+      case StepKind::LuFactor:
+        js << ",\"n\":" << s.n;
+        break;
+      case StepKind::LuSolve:
+        js << ",\"n\":" << s.n << ",\"nrhs\":" << s.nrhs;
+        break;
+      default:
+        break;
+    }
+    js << "}";
+  }
+  js << "]}";
+  return js.str();
+}
+
+void leaf_range(const View& v, size_t esz, std::vector<Range>& out) {
+  if (v.ref.buf != Buf::Leaf || !v.ref.ptr) return;
+  const int64_t rs = v.trans ? v.cols : v.rows, cs = v.trans ? v.rows : v.cols;
+  if (rs == 0 || cs == 0) return;
+  Range r;
+  r.ptr = v.ref.ptr;
+  r.bytes = uint64_t(((cs - 1) * v.ld + rs) * int64_t(esz));
+  r.ld = v.ld;
+  r.trans = v.trans;
+  out.push_back(r);
+}
+
+}  // namespace hexla
+
+using hexla::set_err;
+
+extern "C" {
+
+hexla_status hexla_plan_create(hexla_ctx* ctx, hexla_node root, const hexla_plan_opts* opts,
+                               hexla_plan** out) {
+  if (!ctx || !out) return HEXLA_E_INVALID_ARG;
+  *out = nullptr;
+  if (root >= ctx->nodes.size()) return set_err(ctx, HEXLA_E_INVALID_ARG, "plan: bad root node");
+  hexla_plan_opts o;
+  hexla_plan_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.planner < 0 || o.planner > HEXLA_PLANNER_LEARNED || o.product_precision < 0 ||
+      o.product_precision > HEXLA_PRODUCT_BF16X6 || o.solve_precision < 0 ||
+      o.solve_precision > HEXLA_SOLVE_IR_FP16)
+    return set_err(ctx, HEXLA_E_INVALID_ARG, "plan: bad options");
+  if (o.ir_max_iter <= 0) o.ir_max_iter = 30;
+  hexla_plan* p = new hexla_plan();
+  p->ctx = ctx;
+  p->opts = o;
+  hexla::Planner pl(ctx, o, p);
+  const hexla_status st = pl.run(root);
+  if (st != HEXLA_OK) {
+    delete p;
+    return st;
+  }
+  const size_t esz = hexla::dtype_size(p->dtype);
+  for (const hexla::Step& s : p->steps) {
+    if (s.kind == hexla::StepKind::Ew) {
+      for (const hexla::View& v : s.ew.leaves) hexla::leaf_range(v, esz, p->ew_leaf_ranges);
+    } else {
+      hexla::leaf_range(s.A, esz, p->leaf_ranges);
+      hexla::leaf_range(s.B, esz, p->leaf_ranges);
+      if (s.has_epi)
+        for (const hexla::View& v : s.ew.leaves) hexla::leaf_range(v, esz, p->leaf_ranges);
+    }
+  }
+  *out = p;
+  return HEXLA_OK;
+}
+
+hexla_status hexla_plan_get_info(const hexla_plan* p, hexla_plan_info* out) {
+  if (!p || !out) return HEXLA_E_INVALID_ARG;
+  out->rows = p->rows;
+  out->cols = p->cols;
+  out->dtype = p->dtype;
+  int n = 0;
+  for (const hexla::Step& s : p->steps) {
+    n += 1;
+    if (s.kind == hexla::StepKind::Gemm && s.cfg.split > 1) n += 1;
+  }
+  out->n_steps = n;
+  out->workspace_bytes = p->ws_bytes;
+  out->flops = p->flops;
+  out->bytes = p->bytes;
+  out->chain_macs = p->macs;
+  return HEXLA_OK;
+}
+
+hexla_status hexla_plan_describe(const hexla_plan* p, char* buf, size_t cap, size_t* needed) {
+  if (!p) return HEXLA_E_INVALID_ARG;
+  const std::string js = hexla::describe(p);
+  if (needed) *needed = js.size();
+  if (buf && cap > 0) {
+    const size_t n = std::min(cap - 1, js.size());
+    std::memcpy(buf, js.data(), n);
+    buf[n] = '\0';
+  }
+  return HEXLA_OK;
+}
+
+hexla_status hexla_plan_destroy(hexla_plan* p) {
+  if (!p) return HEXLA_E_INVALID_ARG;
+  delete p;
+  return HEXLA_OK;
+}
+
+}  // extern "C"

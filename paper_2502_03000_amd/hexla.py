@@ -1,0 +1,342 @@
+"""Python binding of the hexla C ABI (argument marshalling only).
+
+Every step of an evaluation runs in libhexla.so's kernels; this module only
+builds expression nodes through the C calls, hands torch-owned device memory
+to the library and reads back status. There is no fallback path: if the
+library is missing the import fails.
+
+Matrices are column-major. A torch tensor with stride(0) == 1 binds as a leaf
+directly (ld = stride(1)); a row-major tensor binds, without a copy, as the
+transpose of its column-major view. ``colmajor(rows, cols)`` allocates a
+column-major tensor.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libhexla.so")
+
+# status codes (hexla_status)
+OK, E_INVALID_ARG, E_DIM, E_DTYPE, E_NOT_SQUARE, E_SINGULAR, E_NO_CONVERGENCE, \
+    E_UNSUPPORTED, E_DEVICE = range(9)
+STATUS_NAMES = ["OK", "E_INVALID_ARG", "E_DIM", "E_DTYPE", "E_NOT_SQUARE", "E_SINGULAR",
+                "E_NO_CONVERGENCE", "E_UNSUPPORTED", "E_DEVICE"]
+F64, F32 = 0, 1
+OP_TRANS, OP_NEG, OP_EXP, OP_INV = 1, 2, 3, 4
+OP_TIMES, OP_PLUS, OP_MINUS, OP_SCHUR, OP_DIV, OP_SOLVE = 16, 17, 18, 19, 20, 21
+PLANNERS = {"dp": 0, "greedy": 1, "naive": 2, "learned": 3}
+PRODUCT_PRECISION = {"plain": 0, "bf16x3": 1, "bf16x6": 2}
+SOLVE_PRECISION = {"plain": 0, "ir_fp32": 1, "ir_fp16": 2}
+
+
+class HexlaError(RuntimeError):
+    def __init__(self, status, message=""):
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"{name}: {message}" if message else name)
+        self.status = status
+
+
+class PlanOpts(C.Structure):
+    _fields_ = [("planner", C.c_int32), ("product_precision", C.c_int32),
+                ("solve_precision", C.c_int32), ("fuse", C.c_int32), ("syrk", C.c_int32),
+                ("ir_max_iter", C.c_int32), ("ir_tol_scale", C.c_double),
+                ("reserved", C.c_int32 * 8)]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("rows", C.c_int64), ("cols", C.c_int64), ("dtype", C.c_int32),
+                ("n_steps", C.c_int32), ("workspace_bytes", C.c_uint64), ("flops", C.c_double),
+                ("bytes", C.c_double), ("chain_macs", C.c_double)]
+
+
+class Report(C.Structure):
+    _fields_ = [("status", C.c_int32), ("ir_iterations", C.c_int32),
+                ("singular_column", C.c_int64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2502_03000_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, i64, i32, u32 = C.c_void_p, C.c_int64, C.c_int32, C.c_uint32
+    sig = {
+        "hexla_ctx_create": [C.c_int, vp, C.POINTER(vp)],
+        "hexla_ctx_destroy": [vp],
+        "hexla_ctx_set_stream": [vp, vp],
+        "hexla_ctx_clear_nodes": [vp],
+        "hexla_leaf": [vp, vp, i64, i64, i64, C.c_int, C.POINTER(u32)],
+        "hexla_scalar": [vp, C.c_double, C.POINTER(u32)],
+        "hexla_unary": [vp, C.c_int, u32, C.POINTER(u32)],
+        "hexla_binary": [vp, C.c_int, u32, u32, C.POINTER(u32)],
+        "hexla_node_shape": [vp, u32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)],
+        "hexla_plan_opts_default": [C.POINTER(PlanOpts)],
+        "hexla_plan_create": [vp, u32, C.POINTER(PlanOpts), C.POINTER(vp)],
+        "hexla_plan_get_info": [vp, C.POINTER(PlanInfo)],
+        "hexla_plan_describe": [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)],
+        "hexla_plan_destroy": [vp],
+        "hexla_execute": [vp, vp, i64, vp, C.c_size_t],
+        "hexla_sync": [vp, C.POINTER(Report)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    lib.hexla_last_error.argtypes = [vp]
+    lib.hexla_last_error.restype = C.c_char_p
+    lib.hexla_version.argtypes = []
+    lib.hexla_version.restype = C.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def version() -> str:
+    return lib.hexla_version().decode()
+
+
+def colmajor(rows, cols, dtype=None, device="cuda"):
+    """A rows x cols column-major torch tensor (stride (1, rows))."""
+    import torch
+    dtype = dtype or torch.float64
+    return torch.empty((cols, rows), dtype=dtype, device=device).t()
+
+
+def to_colmajor(t):
+    """Copy of a 2-D (or 1-D: n x 1) tensor in column-major layout."""
+    if t.dim() == 1:
+        t = t[:, None]
+    out = colmajor(t.shape[0], t.shape[1], t.dtype, t.device)
+    out.copy_(t)
+    return out
+
+
+class Expr:
+    """A node of a delayed expression. Operators build new nodes:
+    ``@``/``*`` matrix product (or scaling by a number), ``+``, ``-``,
+    ``%`` element-wise product, ``/`` element-wise division, unary ``-``,
+    ``.t()`` transpose."""
+
+    def __init__(self, ctx, node):
+        self.ctx, self.node = ctx, node
+
+    def _lift(self, x):
+        if isinstance(x, Expr):
+            return x
+        if isinstance(x, (int, float)):
+            return self.ctx.scalar(float(x))
+        return self.ctx.leaf(x)
+
+    def _bin(self, op, other, rev=False):
+        o = self._lift(other)
+        a, b = (o, self) if rev else (self, o)
+        return self.ctx.binary(op, a, b)
+
+    def __matmul__(self, o): return self._bin(OP_TIMES, o)
+    def __rmatmul__(self, o): return self._bin(OP_TIMES, o, True)
+    def __mul__(self, o): return self._bin(OP_TIMES, o)
+    def __rmul__(self, o): return self._bin(OP_TIMES, o, True)
+    def __add__(self, o): return self._bin(OP_PLUS, o)
+    def __radd__(self, o): return self._bin(OP_PLUS, o, True)
+    def __sub__(self, o): return self._bin(OP_MINUS, o)
+    def __rsub__(self, o): return self._bin(OP_MINUS, o, True)
+    def __mod__(self, o): return self._bin(OP_SCHUR, o)
+    def __rmod__(self, o): return self._bin(OP_SCHUR, o, True)
+    def __truediv__(self, o): return self._bin(OP_DIV, o)
+    def __rtruediv__(self, o): return self._bin(OP_DIV, o, True)
+    def __neg__(self): return self.ctx.unary(OP_NEG, self)
+
+    def t(self):
+        return self.ctx.unary(OP_TRANS, self)
+
+    @property
+    def shape(self):
+        return self.ctx.shape(self)
+
+
+def trans(x): return x.ctx.unary(OP_TRANS, x)
+def inv(x): return x.ctx.unary(OP_INV, x)
+def exp(x): return x.ctx.unary(OP_EXP, x)
+def solve(a, b): return a.ctx.binary(OP_SOLVE, a, a._lift(b))
+
+
+class Plan:
+    def __init__(self, ctx, handle):
+        self.ctx, self.handle = ctx, handle
+        info = PlanInfo()
+        ctx._check(lib.hexla_plan_get_info(handle, C.byref(info)))
+        self.info = info
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            lib.hexla_plan_destroy(h)
+            self.handle = None
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self.info.workspace_bytes)
+
+    @property
+    def shape(self):
+        return int(self.info.rows), int(self.info.cols)
+
+    def describe(self) -> dict:
+        need = C.c_size_t(0)
+        lib.hexla_plan_describe(self.handle, None, 0, C.byref(need))
+        buf = C.create_string_buffer(need.value + 1)
+        self.ctx._check(lib.hexla_plan_describe(self.handle, buf, need.value + 1, C.byref(need)))
+        return json.loads(buf.value.decode())
+
+    def execute(self, out, workspace=None, ld_out=None):
+        """Launches the plan on the context's stream (asynchronous).
+        out / workspace: torch tensors (device memory) or raw integer pointers."""
+        optr, ld = _ptr_ld(out, ld_out)
+        wptr, wbytes = (0, 0)
+        if workspace is not None:
+            wptr = _addr(workspace)
+            wbytes = workspace.numel() * workspace.element_size() if hasattr(workspace, "numel") else self.workspace_bytes
+        self.ctx._check(lib.hexla_execute(self.handle, optr, ld, wptr or None, wbytes))
+
+    def workspace(self, device="cuda"):
+        import torch
+        return torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=device)
+
+    def output(self, device="cuda"):
+        import torch
+        dt = torch.float64 if self.info.dtype == F64 else torch.float32
+        return colmajor(self.shape[0], self.shape[1], dt, device)
+
+
+def _addr(t):
+    return t if isinstance(t, int) else t.data_ptr()
+
+
+def _ptr_ld(t, ld=None):
+    if isinstance(t, int):
+        return t, ld
+    if t.dim() == 1:
+        return t.data_ptr(), max(t.shape[0], 1)
+    if t.stride(0) != 1 and t.shape[0] > 1:
+        raise ValueError("output must be column-major (stride(0) == 1)")
+    return t.data_ptr(), ld or max(t.stride(1), t.shape[0], 1)
+
+
+class Context:
+    """A hexla context. device=-1 gives a dry-run context (planning only)."""
+
+    def __init__(self, device=0, stream=None):
+        h = C.c_void_p()
+        if device >= 0 and stream is None:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        st = lib.hexla_ctx_create(device, stream, C.byref(h))
+        if st != OK:
+            raise HexlaError(st, "context creation failed")
+        self.handle = h.value
+        self.device = device
+        self._keep = []  # tensors borrowed by leaves
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            lib.hexla_ctx_destroy(h)
+            self.handle = None
+
+    def last_error(self) -> str:
+        return lib.hexla_last_error(self.handle).decode()
+
+    def _check(self, st):
+        if st != OK:
+            raise HexlaError(st, self.last_error())
+
+    def set_stream(self, stream):
+        self._check(lib.hexla_ctx_set_stream(self.handle, stream))
+
+    def clear(self):
+        self._check(lib.hexla_ctx_clear_nodes(self.handle))
+        self._keep.clear()
+
+    # -------------------------------------------------------- builder calls
+    def leaf_raw(self, ptr, rows, cols, ld, dtype) -> Expr:
+        n = C.c_uint32()
+        self._check(lib.hexla_leaf(self.handle, ptr or None, rows, cols, ld, dtype, C.byref(n)))
+        return Expr(self, n.value)
+
+    def leaf(self, t) -> Expr:
+        """Leaf borrowing torch tensor t (1-D: n x 1; 2-D column-major, or
+        row-major bound as the transpose of its column-major view)."""
+        import torch
+        dt = {torch.float64: F64, torch.float32: F32}.get(t.dtype)
+        if dt is None:
+            raise TypeError(f"unsupported dtype {t.dtype}")
+        self._keep.append(t)
+        if t.dim() == 1:
+            if t.stride(0) != 1 and t.shape[0] > 1:
+                raise ValueError("vector must be contiguous")
+            return self.leaf_raw(t.data_ptr(), t.shape[0], 1, max(t.shape[0], 1), dt)
+        rows, cols = t.shape
+        if t.stride(0) == 1 or rows <= 1:
+            ld = max(t.stride(1), rows, 1) if cols > 1 else max(rows, 1)
+            return self.leaf_raw(t.data_ptr(), rows, cols, ld, dt)
+        if t.stride(1) == 1:
+            base = self.leaf_raw(t.data_ptr(), cols, rows, max(t.stride(0), cols, 1), dt)
+            return self.unary(OP_TRANS, base)
+        raise ValueError("tensor must be column- or row-major")
+
+    def scalar(self, v) -> Expr:
+        n = C.c_uint32()
+        self._check(lib.hexla_scalar(self.handle, float(v), C.byref(n)))
+        return Expr(self, n.value)
+
+    def unary(self, op, a) -> Expr:
+        n = C.c_uint32()
+        self._check(lib.hexla_unary(self.handle, op, a.node, C.byref(n)))
+        return Expr(self, n.value)
+
+    def binary(self, op, a, b) -> Expr:
+        n = C.c_uint32()
+        self._check(lib.hexla_binary(self.handle, op, a.node, b.node, C.byref(n)))
+        return Expr(self, n.value)
+
+    def shape(self, e):
+        r, c, s = C.c_int64(), C.c_int64(), C.c_int32()
+        self._check(lib.hexla_node_shape(self.handle, e.node, C.byref(r), C.byref(c), C.byref(s)))
+        return int(r.value), int(c.value)
+
+    # ------------------------------------------------------------- planning
+    def plan(self, root, planner="dp", product_precision="plain", solve_precision="plain",
+             fuse=True, syrk=True, ir_max_iter=30, ir_tol_scale=0.0) -> Plan:
+        o = PlanOpts()
+        lib.hexla_plan_opts_default(C.byref(o))
+        o.planner = PLANNERS[planner]
+        o.product_precision = PRODUCT_PRECISION[product_precision]
+        o.solve_precision = SOLVE_PRECISION[solve_precision]
+        o.fuse = 1 if fuse else 0
+        o.syrk = 1 if syrk else 0
+        o.ir_max_iter = ir_max_iter
+        o.ir_tol_scale = ir_tol_scale
+        h = C.c_void_p()
+        self._check(lib.hexla_plan_create(self.handle, root.node, C.byref(o), C.byref(h)))
+        return Plan(self, h.value)
+
+    def sync(self) -> Report:
+        r = Report()
+        self._check(lib.hexla_sync(self.handle, C.byref(r)))
+        return r
+
+    def evaluate(self, root, out=None, check=True, **opts):
+        """Plan, allocate (output if None, workspace), execute, sync."""
+        p = self.plan(root, **opts)
+        if out is None:
+            out = p.output()
+        ws = p.workspace()
+        p.execute(out, ws)
+        r = self.sync()
+        if check and r.status != OK:
+            raise HexlaError(r.status, f"deferred (column {r.singular_column})")
+        return out
