@@ -47,6 +47,19 @@ def _run(cmd, verbose):
     return out
 
 
+def _torch_lib():
+    try:
+        import importlib.util
+        spec = importlib.util.find_spec("torch")
+        if spec and spec.origin:
+            d = os.path.join(os.path.dirname(spec.origin), "lib")
+            if os.path.exists(os.path.join(d, "libamdhip64.so")):
+                return d
+    except Exception:  # noqa: BLE001
+        pass
+    return None
+
+
 def sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
@@ -72,8 +85,11 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
                 print(out)
     objs = [os.path.join(BUILD, s.rsplit(".", 1)[0] + ".o") for s in sources()]
     tmp = LIB + ".tmp"
+    # Prefer the HIP runtime bundled with torch (the process's torch uses it
+    # for device memory and streams); fall back to the system ROCm.
+    rpaths = [p for p in (_torch_lib(), f"{ROCM}/lib") if p]
     _run([_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp,
-          f"-L{ROCM}/lib", "-lamdhip64", f"-Wl,-rpath,{ROCM}/lib"], verbose)
+          f"-L{ROCM}/lib", "-lamdhip64", *[f"-Wl,-rpath,{p}" for p in rpaths]], verbose)
     shutil.move(tmp, LIB)
     return LIB
 

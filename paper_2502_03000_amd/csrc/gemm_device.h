@@ -36,12 +36,16 @@ struct GemmArgs {
 
 template <typename T>
 struct Mfma;
+// Both instructions take A[i][k] from lane i + 16k and B[k][j] from lane
+// j + 16k. The 16x16 result is spread differently: FP32 lane l, register r
+// holds row 4*(l/16) + r; FP64 holds row l/16 + 4*r (column l%16 in both).
 template <>
 struct Mfma<float> {
   typedef float acc_t __attribute__((ext_vector_type(4)));
   static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 template <>
 struct Mfma<double> {
@@ -49,6 +53,7 @@ struct Mfma<double> {
   static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 
 template <typename T, int N>
@@ -265,7 +270,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     __syncthreads();
   }
 
-  // epilogue: lane owns rows 4*(lane/16) + r of column lane%16 in each 16x16 tile
+  // epilogue: lane owns rows Mfma<T>::row(lane, r) of column lane%16 in each 16x16 tile
   const int lane = threadIdx.x & 63;
   const T alpha = T(g.alpha), beta = T(g.beta);
   T* C = static_cast<T*>(g.C);
@@ -276,7 +281,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
     for (int fn = 0; fn < G::FN; ++fn)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t i = m0 + wm * G::WM + fm * 16 + 4 * (lane >> 4) + r;
+        const int64_t i = m0 + wm * G::WM + fm * 16 + Mfma<T>::row(lane, r);
         const int64_t j = n0 + wn * G::WN + fn * 16 + (lane & 15);
         if (i >= g.m || j >= g.n) continue;
         const T v = acc[fm][fn][r];

@@ -58,6 +58,10 @@ class Report(C.Structure):
 
 
 def _load():
+    # torch ships its own HIP runtime (same soname, libamdhip64.so.7). Load it
+    # first so that libhexla binds to the runtime that owns torch's device
+    # memory and streams, rather than a second copy of HIP/HSA.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_2502_03000_amd.build`")
@@ -275,6 +279,9 @@ class Context:
         if dt is None:
             raise TypeError(f"unsupported dtype {t.dtype}")
         self._keep.append(t)
+        if t.numel() == 0:
+            rows, cols = (t.shape[0], 1) if t.dim() == 1 else tuple(t.shape)
+            return self.leaf_raw(t.data_ptr(), rows, cols, max(rows, 1), dt)
         if t.dim() == 1:
             if t.stride(0) != 1 and t.shape[0] > 1:
                 raise ValueError("vector must be contiguous")
