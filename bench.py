@@ -36,12 +36,15 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=16384, help="element-wise matrix size")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
 
 
-def cpu_baseline(chain_np, ew_host, ew_flops_per_elem):
+def cpu_baseline(chain_np, ew_host, ew_flops_per_elem, min_seconds=10.0):
     """The FP64 oracle, as it stands, on the host cores: the full chain job
-    plus a column sample of the element-wise job."""
+    plus a column sample of the element-wise job, repeated until at least
+    min_seconds of CPU work."""
     import oracle
     try:
         from threadpoolctl import threadpool_info
@@ -50,23 +53,27 @@ def cpu_baseline(chain_np, ew_host, ew_flops_per_elem):
         threads = os.cpu_count() or 1
     names = [f"M{i}" for i in range(len(chain_np))]
     env = dict(zip(names, chain_np))
-    t0 = time.perf_counter()
-    oracle.evaluate("*".join(names), env)
-    t_chain = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.evaluate("0.5*exp(-(A%A)) + B/C", ew_host)
-    t_ew = time.perf_counter() - t0
+    t_chain = t_ew = 0.0
+    reps = 0
+    while t_chain + t_ew < min_seconds:
+        t0 = time.perf_counter()
+        oracle.evaluate("*".join(names), env)
+        t_chain += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.evaluate("0.5*exp(-(A%A)) + B/C", ew_host)
+        t_ew += time.perf_counter() - t0
+        reps += 1
     dims = [m.shape[0] for m in chain_np] + [chain_np[-1].shape[1]]
     from oracle import chain as ch
     chain_flops = 2.0 * ch.brute_force_min(dims)[0]
     ew_elems = ew_host["A"].size
-    flops = chain_flops + ew_flops_per_elem * ew_elems
+    flops = reps * (chain_flops + ew_flops_per_elem * ew_elems)
     return {
         "value": flops / (t_chain + t_ew) / 1e9, "unit": "GFLOP/s", "cores": int(threads),
         "kind": "oracle",
-        "sample": f"full 5-factor chain ({t_chain:.2f} s) + element-wise job on "
-                  f"{ew_host['A'].shape[0]}x{ew_host['A'].shape[1]} columns sample "
-                  f"({t_ew:.2f} s), float64 numpy",
+        "sample": f"{reps} x (full 5-factor chain + element-wise job on a "
+                  f"{ew_host['A'].shape[0]}x{ew_host['A'].shape[1]} column sample); "
+                  f"chain {t_chain:.2f} s, element-wise {t_ew:.2f} s, float64 numpy",
     }
 
 
@@ -108,6 +115,13 @@ def main():
     def step():
         p1.execute(out1, ws1)
         p2.execute(out2, ws2)
+
+    if args.copy_probe:  # a plain copy of 1 GiB: reference for HBM byte counters
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         step()
@@ -192,7 +206,7 @@ def main():
         "plan_ms": plan_ms,
     }
     if not args.no_cpu_baseline:
-        ncol = max(1, args.n // 8)
+        ncol = max(1, args.n // 2)
         ew_host = {k: ew[k][:, :ncol].cpu().numpy() for k in ("A", "B", "C")}
         res["cpu_baseline"] = cpu_baseline(chain_np, ew_host, d2["flops"] / float(args.n) ** 2)
     print(json.dumps(res), flush=True)

@@ -147,10 +147,14 @@ typedef struct hexla_plan_opts {
   int32_t ir_max_iter;        /* refinement cap (default 30)                      */
   double ir_tol_scale;        /* stop when ||R||inf <= scale*2^-53*||S||inf*||X||inf;
                                  0 = sqrt(n)                                     */
-  int32_t reserved[8];
+  int32_t codegen;            /* 1: element-wise passes run as kernels generated
+                                 for the expression (hipRTC, default); 0: the
+                                 program interpreter kernel                     */
+  int32_t reserved[7];
 } hexla_plan_opts;
 
-/* Fills the defaults: DP, plain precision, fusion on, SYRK on, cap 30. */
+/* Fills the defaults: DP, plain precision, fusion on, SYRK on, cap 30,
+ * generated element-wise kernels on. */
 hexla_status hexla_plan_opts_default(hexla_plan_opts* opts);
 
 /* Plans the evaluation of `root` (opts NULL = defaults). Host only: nothing

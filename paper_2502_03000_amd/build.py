@@ -89,7 +89,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     # for device memory and streams); fall back to the system ROCm.
     rpaths = [p for p in (_torch_lib(), f"{ROCM}/lib") if p]
     _run([_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp,
-          f"-L{ROCM}/lib", "-lamdhip64", *[f"-Wl,-rpath,{p}" for p in rpaths]], verbose)
+          f"-L{ROCM}/lib", "-lamdhip64", "-lhiprtc", *[f"-Wl,-rpath,{p}" for p in rpaths]], verbose)
     shutil.move(tmp, LIB)
     return LIB
 

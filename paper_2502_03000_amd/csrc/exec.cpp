@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 
@@ -57,6 +58,8 @@ k::EwProgram make_prog(const EwHost& h, int64_t rows, int64_t cols, const Bind& 
   p.contiguous = contig ? 1 : 0;
   return p;
 }
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 bool overlap(const void* a, uint64_t na, const void* b, uint64_t nb) {
   const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
@@ -114,7 +117,17 @@ hexla_status hexla_execute(hexla_plan* plan, void* out, int64_t ld_out, void* wo
       case StepKind::Ew: {
         const View o = resolve(s.out, b);
         const k::EwProgram p = make_prog(s.ew, o.rows, o.cols, b);
-        e = k::ew_launch(s.dtype, p, addr(o.ref, b), si(o), sj(o), st);
+        void* optr = addr(o.ref, b);
+        bool dense = s.cg_fn && p.contiguous && !p.uses_ident && aligned16(optr) && si(o) == 1 &&
+                     (o.cols == 1 || sj(o) == o.rows);
+        for (int l = 0; l < p.n_leaf && dense; ++l) dense = aligned16(p.leaf[l].ptr);
+        if (dense) {
+          std::vector<const void*> lv(p.n_leaf);
+          for (int l = 0; l < p.n_leaf; ++l) lv[l] = p.leaf[l].ptr;
+          e = codegen_launch(s.cg_fn, s.dtype, lv, optr, o.rows * o.cols, st);
+        } else {
+          e = k::ew_launch(s.dtype, p, optr, si(o), sj(o), st);
+        }
         break;
       }
       case StepKind::Gemv: {

@@ -85,6 +85,10 @@ struct Step {
   int64_t m = 0, n = 0, kk = 0, nrhs = 0;
   Ref rowid, luwork;
   double flops = 0.0, bytes = 0.0;
+  // Ew: kernel generated for this program (null: interpreter)
+  std::string cg_src;
+  hipFunction_t cg_fn = nullptr;
+  std::string cg_err;
 };
 
 }  // namespace hexla
@@ -112,4 +116,10 @@ struct hexla_plan {
 namespace hexla {
 hexla_status set_err(const hexla_ctx* ctx, hexla_status st, const std::string& msg);
 size_t dtype_size(int dtype);
+// generated element-wise kernels (codegen.cpp)
+bool codegen_enabled();
+std::string codegen_source(const EwHost& p, int dtype);
+hipFunction_t codegen_get(int device, const std::string& src, std::string* err);
+hipError_t codegen_launch(hipFunction_t fn, int dtype, const std::vector<const void*>& leaves,
+                          void* out, int64_t n_total, hipStream_t s);
 }  // namespace hexla

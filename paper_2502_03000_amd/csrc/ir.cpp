@@ -230,6 +230,7 @@ hexla_status hexla_plan_opts_default(hexla_plan_opts* o) {
   o->syrk = 1;
   o->ir_max_iter = 30;
   o->ir_tol_scale = 0.0;
+  o->codegen = 1;
   return HEXLA_OK;
 }
 

@@ -40,42 +40,29 @@ __device__ __forceinline__ void store_pack(void* base, int64_t q, const Pack<T, 
 }
 
 // Contiguous path: every leaf and the output are dense in flat column-major
-// order and 16-byte aligned. Each lane handles U packs of V elements per
-// iteration so that U * n_leaf 16-byte loads are in flight before any use.
-template <typename T, int V, int U>
+// order and 16-byte aligned. One-shot grid: each lane loads one 16-byte pack
+// of every operand, evaluates it and stores it (no grid-stride loop, which
+// measured slower on this part); the last lanes take the ragged tail.
+template <typename T, int V>
 __global__ __launch_bounds__(kThreads) void ew_contig_kernel(EwProgram p, T* __restrict__ out,
                                                              int64_t n_pack, int64_t n_total) {
   using P = Pack<T, V>;
-  const int64_t stride = int64_t(gridDim.x) * kThreads * U;
-  P zero;
+  const int64_t q = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (q < n_pack) {
+    typename LeafRegs<T, V>::type L;
 #pragma unroll
-  for (int e = 0; e < V; ++e) zero.v[e] = T(0);
-  for (int64_t base = int64_t(blockIdx.x) * kThreads * U + threadIdx.x; base < n_pack;
-       base += stride) {
-    typename LeafRegs<T, V>::type L[U];
+    for (int l = 0; l < kEwMaxLeaf; ++l) {
+      typename Native<T, V>::type x = {};
+      if (l < p.n_leaf) x = load_native<T, V>(p.leaf[l].ptr, q);
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t q = base + int64_t(u) * kThreads;
-#pragma unroll
-      for (int l = 0; l < kEwMaxLeaf; ++l) {
-        typename Native<T, V>::type x = {};
-        if (l < p.n_leaf && q < n_pack) x = load_native<T, V>(p.leaf[l].ptr, q);
-#pragma unroll
-        for (int e = 0; e < V; ++e) L[u][l * V + e] = x[e];
-      }
+      for (int e = 0; e < V; ++e) L[l * V + e] = x[e];
     }
+    P zero;
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t q = base + int64_t(u) * kThreads;
-      if (q < n_pack) {
-        const P r = ew_eval<T, V>(p, L[u], zero, zero);
-        store_pack<T, V>(out, q, r);
-      }
-    }
-  }
-  // ragged tail (n_total not a multiple of V): first lanes of block 0
-  if (blockIdx.x == 0) {
-    const int64_t t = n_pack * V + threadIdx.x;
+    for (int e = 0; e < V; ++e) zero.v[e] = T(0);
+    store_pack<T, V>(out, q, ew_eval<T, V>(p, L, zero, zero));
+  } else {
+    const int64_t t = n_pack * V + (q - n_pack);
     if (t < n_total) out[t] = ew_eval_at<T>(p, t, T(0));
   }
 }
@@ -103,15 +90,12 @@ hipError_t launch_typed(const EwProgram& p, void* out, int64_t osi, int64_t osj,
                 (p.cols == 1 || osj == p.rows);
   for (int l = 0; l < p.n_leaf && contig; ++l) contig = aligned16(p.leaf[l].ptr);
   constexpr int V = 16 / sizeof(T);
-  if (contig && n_total >= V) {
-    constexpr int U = 2;
+  if (contig) {
     const int64_t n_pack = n_total / V;
-    int64_t blocks = (n_pack + int64_t(kThreads) * U - 1) / (int64_t(kThreads) * U);
-    const int64_t cap = 256 * 16;  // 16 workgroups per CU on a 256-CU part
-    if (blocks > cap) blocks = cap;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((ew_contig_kernel<T, V, U>), dim3(unsigned(blocks)), dim3(kThreads), 0, s,
-                       p, static_cast<T*>(out), n_pack, n_total);
+    const int64_t threads = n_pack + (n_total - n_pack * V);
+    const int64_t blocks = (threads + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL((ew_contig_kernel<T, V>), dim3(unsigned(blocks)), dim3(kThreads), 0, s, p,
+                       static_cast<T*>(out), n_pack, n_total);
   } else {
     int64_t blocks = (n_total + kThreads - 1) / kThreads;
     if (blocks > 256 * 32) blocks = 256 * 32;

@@ -622,6 +622,7 @@ class Planner {
     const double elems = double(o.rows) * double(o.cols);
     s.flops = elems * p.n_arith;
     s.bytes = elems * double(esz_) * double(p.leaves.size() + 1);
+    if (o_.codegen && codegen_enabled()) s.cg_src = codegen_source(p, dtype_);
     steps_.push_back(s);
   }
 
@@ -936,7 +937,8 @@ std::string describe(const hexla_plan* p) {
     js << "{\"kernel\":\"" << s.name << "\",\"flops\":" << s.flops << ",\"bytes\":" << s.bytes;
     switch (s.kind) {
       case StepKind::Ew:
-        js << ",\"instructions\":" << s.ew.n_instr << ",\"leaves\":" << s.ew.leaves.size() << ",";
+        js << ",\"instructions\":" << s.ew.n_instr << ",\"leaves\":" << s.ew.leaves.size()
+           << ",\"generated\":" << (s.cg_fn ? "true" : "false") << ",";
         json_view(js, "out", s.out);
         break;
       case StepKind::Gemv:
@@ -1006,6 +1008,12 @@ hexla_status hexla_plan_create(hexla_ctx* ctx, hexla_node root, const hexla_plan
   if (st != HEXLA_OK) {
     delete p;
     return st;
+  }
+  if (ctx->device >= 0) {  // plan time is the generated kernels' compile time
+    (void)hipSetDevice(ctx->device);
+    for (hexla::Step& s : p->steps)
+      if (s.kind == hexla::StepKind::Ew && !s.cg_src.empty())
+        s.cg_fn = hexla::codegen_get(ctx->device, s.cg_src, &s.cg_err);
   }
   const size_t esz = hexla::dtype_size(p->dtype);
   for (const hexla::Step& s : p->steps) {

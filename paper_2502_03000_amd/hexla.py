@@ -43,7 +43,7 @@ class PlanOpts(C.Structure):
     _fields_ = [("planner", C.c_int32), ("product_precision", C.c_int32),
                 ("solve_precision", C.c_int32), ("fuse", C.c_int32), ("syrk", C.c_int32),
                 ("ir_max_iter", C.c_int32), ("ir_tol_scale", C.c_double),
-                ("reserved", C.c_int32 * 8)]
+                ("codegen", C.c_int32), ("reserved", C.c_int32 * 7)]
 
 
 class PlanInfo(C.Structure):
@@ -317,7 +317,7 @@ class Context:
 
     # ------------------------------------------------------------- planning
     def plan(self, root, planner="dp", product_precision="plain", solve_precision="plain",
-             fuse=True, syrk=True, ir_max_iter=30, ir_tol_scale=0.0) -> Plan:
+             fuse=True, syrk=True, ir_max_iter=30, ir_tol_scale=0.0, codegen=True) -> Plan:
         o = PlanOpts()
         lib.hexla_plan_opts_default(C.byref(o))
         o.planner = PLANNERS[planner]
@@ -327,6 +327,7 @@ class Context:
         o.syrk = 1 if syrk else 0
         o.ir_max_iter = ir_max_iter
         o.ir_tol_scale = ir_tol_scale
+        o.codegen = 1 if codegen else 0
         h = C.c_void_p()
         self._check(lib.hexla_plan_create(self.handle, root.node, C.byref(o), C.byref(h)))
         return Plan(self, h.value)

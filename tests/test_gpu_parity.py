@@ -69,16 +69,33 @@ def test_small_chain_expression_fp64(ctx, planner):
 
 # ------------------------------------------------------------- element-wise
 
+@pytest.mark.parametrize("codegen", [True, False])
 @pytest.mark.parametrize("dt", [np.float32, np.float64])
 @pytest.mark.parametrize("shape", [(1000, 37), (1, 1), (4097, 3), (5, 0), (333, 257)])
-def test_elementwise_expression(ctx, dt, shape):
+def test_elementwise_expression(ctx, dt, shape, codegen):
     env = inputs.fp32_elementwise(seed=7, n=shape[0], cols=shape[1], dtype=dt)
     ref = oracle.evaluate(inputs.ELEMENTWISE_EXPR, env)
     L = leaves(ctx, env)
-    got = run(ctx, 0.5 * hx.exp(-(L["A"] % L["A"])) + L["B"] / L["C"])
+    e = 0.5 * hx.exp(-(L["A"] % L["A"])) + L["B"] / L["C"]
+    steps = ctx.plan(e, codegen=codegen).describe()["steps"]
+    assert steps[0]["generated"] is codegen
+    got = run(ctx, e, codegen=codegen)
     assert got.shape == shape
     if got.size:
         assert rel(got, ref) <= TOL[dt]
+
+
+def test_generated_and_interpreted_kernels_agree(ctx):
+    g = inputs.rng(31)
+    env = {k: inputs.normal(g, 513, 129, np.float32) for k in "ABC"}
+    env["C"] = np.abs(env["C"]) + 1.0
+    L = leaves(ctx, env)
+    e = (L["A"] - 2.0 * L["B"]) % (L["C"] + L["A"]) / L["C"] - hx.exp(L["B"] / 4.0) + 1.5
+    ref = oracle.evaluate("(A - 2*B) % (C + A) / C - exp(B/4) + 1.5", env)
+    a = run(ctx, e, codegen=True)
+    b = run(ctx, e, codegen=False)
+    assert rel(a, ref) <= 1e-6 and rel(b, ref) <= 1e-6
+    assert np.max(np.abs(a - b)) <= 4 * np.finfo(np.float32).eps * np.max(np.abs(ref))
 
 
 @pytest.mark.parametrize("dt", [np.float32, np.float64])
