@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=16384, help="element-wise matrix size")
+    ap.add_argument("--no-tune", action="store_true", help="skip product autotuning")
+    ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of graph replay")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -110,11 +112,23 @@ def main():
     plan_ms = (time.perf_counter() - t0) * 1e3
     out1, out2 = p1.output(dev), p2.output(dev)
     ws1, ws2 = p1.workspace(dev), p2.workspace(dev)
+    if not args.no_tune:  # tile / split-K choice of the chain's products, measured
+        p1.autotune(out1, ws1)
     d1, d2 = p1.describe(), p2.describe()
+    if args.no_graph:
+        def run1():
+            p1.execute(out1, ws1)
+
+        def run2():
+            p2.execute(out2, ws2)
+    else:  # each plan's launches recorded once into a HIP graph, then replayed
+        p1.capture(out1, ws1)
+        p2.capture(out2, ws2)
+        run1, run2 = p1.replay, p2.replay
 
     def step():
-        p1.execute(out1, ws1)
-        p2.execute(out2, ws2)
+        run1()
+        run2()
 
     if args.copy_probe:  # a plain copy of 1 GiB: reference for HBM byte counters
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -152,8 +166,8 @@ def main():
         return ev0.elapsed_time(ev1) / reps
 
     reps = max(args.steps, 5)
-    ms_chain = time_job(lambda: p1.execute(out1, ws1), reps)
-    ms_ew = time_job(lambda: p2.execute(out2, ws2), reps)
+    ms_chain = time_job(run1, reps)
+    ms_ew = time_job(run2, reps)
 
     # ---- sampled parity against the FP64 oracle (rows of the chain, elements of job 2)
     import oracle
@@ -192,13 +206,15 @@ def main():
         "config": {"workload": "fp32 chain 8192x1024x8192x512x4096x64 (DP order) + fused "
                                f"0.5*exp(-(A%A))+B/C over {args.n}x{args.n}",
                    "chain_dims": list(inputs.FP32_CHAIN_DIMS), "elementwise_n": args.n,
-                   "planner": "dp", "form": "plain fp32"},
+                   "planner": "dp", "form": "plain fp32",
+                   "launch": "eager" if args.no_graph else "hip graph replay",
+                   "autotuned": not args.no_tune},
         "roofline": ew_kernel,
         "jobs": {
             "chain": {"ms": ms_chain, "gflop": p1.info.flops / 1e9, "tflops": chain_tflops,
                       "frac_fp32_mfma_peak": chain_tflops / FP32_MFMA_PEAK_TFLOPS,
-                      "kernels": [f"{s['kernel']} {s['m']}x{s['n']}x{s['k']} split{s.get('split', 1)}"
-                                  for s in d1["steps"]],
+                      "kernels": [f"{s['kernel']} {s['m']}x{s['n']}x{s['k']} tile{s.get('tile')} "
+                                  f"split{s.get('split', 1)}" for s in d1["steps"]],
                       "max_rel_err_sampled_rows": err_chain},
             "elementwise": {"ms": ms_ew, "gbytes": ew_bytes / 1e9,
                             "gbs": ew_kernel["achieved"], "max_rel_err_sampled_cols": err_ew},

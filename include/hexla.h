@@ -207,6 +207,30 @@ typedef struct hexla_report {
  * return value is HEXLA_E_DEVICE on a HIP error, else HEXLA_OK. */
 hexla_status hexla_sync(hexla_ctx* ctx, hexla_report* report);
 
+/* ------------------------------------------------------- tuning and graphs */
+
+/* Times every candidate tile / split-K configuration of each matrix product
+ * of the plan on these buffers (valid as for hexla_execute; their contents
+ * are overwritten), keeps the fastest in the plan and records it in the
+ * context's tuning table, which later hexla_plan_create calls consult.
+ * reps: timed launches per candidate (<= 0: 5). Synchronous. Errors: as
+ * hexla_execute. */
+hexla_status hexla_plan_autotune(hexla_plan* plan, void* out, int64_t ld_out, void* workspace,
+                                 size_t workspace_bytes, int32_t reps);
+/* Writes / reads the tuning table as text, one "gfx950 key tile split" line
+ * per entry. Loading rejects a table made for another target
+ * (HEXLA_E_INVALID_ARG). */
+hexla_status hexla_tune_save(const hexla_ctx* ctx, const char* path);
+hexla_status hexla_tune_load(hexla_ctx* ctx, const char* path);
+
+/* Records the plan's launches, bound to these buffers, into a HIP graph owned
+ * by the plan (replacing any earlier capture); hexla_plan_replay launches it
+ * on the context's stream. Useful when the same expression is evaluated on
+ * the same buffers many times. Errors: as hexla_execute. */
+hexla_status hexla_plan_capture(hexla_plan* plan, void* out, int64_t ld_out, void* workspace,
+                                size_t workspace_bytes);
+hexla_status hexla_plan_replay(hexla_plan* plan);
+
 /* Library version string (static storage). */
 const char* hexla_version(void);
 

@@ -75,9 +75,9 @@ hexla_status device_err(hexla_ctx* ctx, hipError_t e, const char* what) {
 
 using namespace hexla;
 
-extern "C" {
+namespace hexla {
 
-hexla_status hexla_execute(hexla_plan* plan, void* out, int64_t ld_out, void* workspace,
+hexla_status check_buffers(hexla_plan* plan, void* out, int64_t ld_out, void* workspace,
                            size_t workspace_bytes) {
   if (!plan) return HEXLA_E_INVALID_ARG;
   hexla_ctx* ctx = plan->ctx;
@@ -108,10 +108,37 @@ hexla_status hexla_execute(hexla_plan* plan, void* out, int64_t ld_out, void* wo
   }
   if (overlap(workspace, plan->ws_bytes, out, out_bytes))
     return set_err(ctx, HEXLA_E_INVALID_ARG, "execute: workspace overlaps the output");
+  return HEXLA_OK;
+}
+
+hipError_t launch_gemm_step(const Step& s, const GemmBind& gb, const k::GemmConfig& cfg,
+                            hipStream_t st) {
+  return k::gemm_launch(s.dtype, s.precision, s.mode, gb.ta, gb.tb, s.m, s.n, s.kk, s.alpha,
+                        gb.A, gb.lda, gb.B, gb.ldb, s.beta, gb.C, gb.ldc, gb.partial, cfg, st);
+}
+
+GemmBind bind_gemm(const Step& s, void* out, int64_t ld_out, void* workspace) {
+  const Bind b{static_cast<char*>(out), ld_out, static_cast<char*>(workspace)};
+  const View A = resolve(s.A, b), B = resolve(s.B, b), C = resolve(s.C, b);
+  GemmBind g;
+  g.ta = A.trans ? 1 : 0;
+  g.tb = B.trans ? 1 : 0;
+  g.A = addr(A.ref, b);
+  g.lda = A.ld;
+  g.B = addr(B.ref, b);
+  g.ldb = B.ld;
+  g.C = addr(C.ref, b);
+  g.ldc = C.ld;
+  g.partial = addr(s.partial, b);
+  return g;
+}
+
+hexla_status run_steps(hexla_plan* plan, void* out, int64_t ld_out, void* workspace,
+                       hipStream_t st) {
+  hexla_ctx* ctx = plan->ctx;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return device_err(ctx, e, "hipSetDevice");
   const Bind b{static_cast<char*>(out), ld_out, static_cast<char*>(workspace)};
-  hipStream_t st = ctx->stream;
   for (const Step& s : plan->steps) {
     switch (s.kind) {
       case StepKind::Ew: {
@@ -142,13 +169,9 @@ hexla_status hexla_execute(hexla_plan* plan, void* out, int64_t ld_out, void* wo
                            incx, addr(C.ref, b), incy, s.has_epi ? &p : nullptr, st);
         break;
       }
-      case StepKind::Gemm: {
-        const View A = resolve(s.A, b), B = resolve(s.B, b), C = resolve(s.C, b);
-        e = k::gemm_launch(s.dtype, s.precision, s.mode, A.trans ? 1 : 0, B.trans ? 1 : 0, s.m, s.n,
-                           s.kk, s.alpha, addr(A.ref, b), A.ld, addr(B.ref, b), B.ld, s.beta,
-                           addr(C.ref, b), C.ld, addr(s.partial, b), s.cfg, st);
+      case StepKind::Gemm:
+        e = launch_gemm_step(s, bind_gemm(s, out, ld_out, workspace), s.cfg, st);
         break;
-      }
       case StepKind::LuFactor: {
         const View A = resolve(s.A, b);
         e = k::lu_factor_launch(s.dtype, s.n, addr(A.ref, b), A.ld,
@@ -169,6 +192,17 @@ hexla_status hexla_execute(hexla_plan* plan, void* out, int64_t ld_out, void* wo
     if (e != hipSuccess) return device_err(ctx, e, s.name.c_str());
   }
   return HEXLA_OK;
+}
+
+}  // namespace hexla
+
+extern "C" {
+
+hexla_status hexla_execute(hexla_plan* plan, void* out, int64_t ld_out, void* workspace,
+                           size_t workspace_bytes) {
+  const hexla_status st = check_buffers(plan, out, ld_out, workspace, workspace_bytes);
+  if (st != HEXLA_OK) return st;
+  return run_steps(plan, out, ld_out, workspace, plan->ctx->stream);
 }
 
 hexla_status hexla_sync(hexla_ctx* ctx, hexla_report* report) {

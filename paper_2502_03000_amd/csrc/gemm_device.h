@@ -303,6 +303,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
 }
 
 // C = alpha * sum_z P[z] + beta * C, summed in z order (deterministic).
+// Full mode: each lane reduces four consecutive elements of a column with
+// 16-byte loads when the shape allows, so the pass streams at HBM rate.
 template <typename T>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g) {
   const int64_t total = g.m * g.n;
@@ -310,11 +312,51 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g) {
   const T* P = static_cast<const T*>(g.partial);
   T* C = static_cast<T*>(g.C);
   const T alpha = T(g.alpha), beta = T(g.beta);
+  const int S = g.split;
+  if (g.mode == 0 && (g.m % 4) == 0) {
+    const int64_t quads = total / 4;
+    for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < quads; q += stride) {
+      const int64_t e = q * 4;
+      const int64_t i = e % g.m, j = e / g.m;
+      T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+      int z = 0;
+      for (; z + 4 <= S; z += 4) {
+        T v[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v[u][r] = P[int64_t(z + u) * total + e + r];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          s0 += v[u][0];
+          s1 += v[u][1];
+          s2 += v[u][2];
+          s3 += v[u][3];
+        }
+      }
+      for (; z < S; ++z) {
+        const T* p = P + int64_t(z) * total + e;
+        s0 += p[0];
+        s1 += p[1];
+        s2 += p[2];
+        s3 += p[3];
+      }
+      T* c = C + i + j * g.ldc;
+      const T sv[4] = {s0, s1, s2, s3};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        T out = alpha * sv[r];
+        if (beta != T(0)) out += beta * c[r];
+        c[r] = out;
+      }
+    }
+    return;
+  }
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += stride) {
     const int64_t i = e % g.m, j = e / g.m;
     if (g.mode == 1 && i < j) continue;
     T s = 0;
-    for (int z = 0; z < g.split; ++z) s += P[int64_t(z) * total + e];
+    for (int z = 0; z < S; ++z) s += P[int64_t(z) * total + e];
     T out = alpha * s;
     if (beta != T(0)) out += beta * C[i + j * g.ldc];
     C[i + j * g.ldc] = out;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -82,6 +83,7 @@ struct Step {
   int precision = 0;  // gemm: k::GemmPrecision
   k::GemmConfig cfg{};
   Ref partial;
+  int64_t partial_cap = 0;  // bytes reserved for split-K partials
   int64_t m = 0, n = 0, kk = 0, nrhs = 0;
   Ref rowid, luwork;
   double flops = 0.0, bytes = 0.0;
@@ -99,6 +101,7 @@ struct hexla_ctx {
   std::vector<hexla::Node> nodes;
   std::string err;
   int32_t* d_status = nullptr;  // [0] status, [1] timeout, [2] singular column, [3] ir iterations
+  std::map<std::string, hexla::k::GemmConfig> tuned;  // autotuned product configurations
 };
 
 struct hexla_plan {
@@ -111,9 +114,31 @@ struct hexla_plan {
   double flops = 0, bytes = 0, macs = 0;
   std::vector<hexla::Range> leaf_ranges;     // read by products, solves, epilogues
   std::vector<hexla::Range> ew_leaf_ranges;  // read by element-wise passes
+  hipGraph_t graph = nullptr;                 // captured launches (hexla_plan_capture)
+  hipGraphExec_t graph_exec = nullptr;
+  ~hexla_plan();
 };
 
 namespace hexla {
+struct GemmBind {
+  int ta = 0, tb = 0;
+  const void* A = nullptr;
+  int64_t lda = 0;
+  const void* B = nullptr;
+  int64_t ldb = 0;
+  void* C = nullptr;
+  int64_t ldc = 0;
+  void* partial = nullptr;
+};
+hexla_status check_buffers(hexla_plan* plan, void* out, int64_t ld_out, void* workspace,
+                           size_t workspace_bytes);
+hexla_status run_steps(hexla_plan* plan, void* out, int64_t ld_out, void* workspace,
+                       hipStream_t st);
+GemmBind bind_gemm(const Step& s, void* out, int64_t ld_out, void* workspace);
+hipError_t launch_gemm_step(const Step& s, const GemmBind& gb, const k::GemmConfig& cfg,
+                            hipStream_t st);
+std::string tune_key(const Step& s, int ta, int tb);
+size_t gemm_max_partial(const Step& s);
 hexla_status set_err(const hexla_ctx* ctx, hexla_status st, const std::string& msg);
 size_t dtype_size(int dtype);
 // generated element-wise kernels (codegen.cpp)

@@ -15,8 +15,10 @@ namespace {
 struct Tile {
   int bm, bn, bk;
 };
-// FP32: 0 = 128x128, 1 = 128x64 (skinny N), 2 = 64x64 (small)
-constexpr Tile kTilesF32[] = {{128, 128, 16}, {128, 64, 16}, {64, 64, 16}};
+// FP32: 0 = 128x128, 1 = 128x64 (skinny N), 2 = 64x64 (small), then the
+// same shapes with BK = 32 (longer steps: more bytes in flight per step)
+constexpr Tile kTilesF32[] = {{128, 128, 16}, {128, 64, 16}, {64, 64, 16},
+                              {128, 128, 32}, {128, 64, 32}, {64, 64, 32}};
 // FP64: 0 = 64x64x16, 1 = 128x128x8
 constexpr Tile kTilesF64[] = {{64, 64, 16}, {128, 128, 8}};
 
@@ -37,7 +39,10 @@ GemmFn kernel_for(int dtype, int tile, bool ta, bool tb, bool vec) {
     switch (tile) {
       case 0: return pick<float, 128, 128, 16>(ta, tb, vec);
       case 1: return pick<float, 128, 64, 16>(ta, tb, vec);
-      default: return pick<float, 64, 64, 16>(ta, tb, vec);
+      case 2: return pick<float, 64, 64, 16>(ta, tb, vec);
+      case 3: return pick<float, 128, 128, 32>(ta, tb, vec);
+      case 4: return pick<float, 128, 64, 32>(ta, tb, vec);
+      default: return pick<float, 64, 64, 32>(ta, tb, vec);
     }
   }
   return tile == 1 ? pick<double, 128, 128, 8>(ta, tb, vec) : pick<double, 64, 64, 16>(ta, tb, vec);
@@ -49,35 +54,52 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace
 
-GemmConfig gemm_choose(int dtype, int precision, int mode, int64_t m, int64_t n, int64_t k) {
-  GemmConfig c{0, 1};
-  if (precision != GEMM_PLAIN) return gemm_choose_split(dtype, precision, mode, m, n, k);
-  if (dtype == 1) {
-    if (mode == 1) c.tile = (n >= 1024) ? 0 : 2;
-    else if (m <= 64 || (n <= 64 && m < 1024)) c.tile = 2;
-    else if (n <= 64) c.tile = 1;
-    else c.tile = (m * n >= 1024 * 1024) ? 0 : 2;
-  } else {
-    c.tile = (m * n >= int64_t(2048) * 2048) ? 1 : 0;
-  }
-  const Tile t = tile_of(dtype, c.tile);
-  int64_t tiles;
+int gemm_tile_count(int dtype) { return dtype == 1 ? 6 : 2; }
+
+int64_t gemm_tiles_for(int dtype, int tile, int mode, int64_t m, int64_t n) {
+  const Tile t = tile_of(dtype, tile);
   if (mode == 1) {
     const int64_t tt = cdiv(n, t.bn);
-    tiles = tt * (tt + 1) / 2;
-  } else {
-    tiles = cdiv(m, t.bm) * cdiv(n, t.bn);
+    return tt * (tt + 1) / 2;
   }
-  const int64_t target = 512;
+  return cdiv(m, t.bm) * cdiv(n, t.bn);
+}
+
+bool gemm_tile_valid(int dtype, int tile, int mode) {
+  if (tile < 0 || tile >= gemm_tile_count(dtype)) return false;
+  const Tile t = tile_of(dtype, tile);
+  return mode != 1 || t.bm == t.bn;
+}
+
+// Split count giving about `target` workgroups with at least `min_steps` BK
+// steps each; the chunk is a multiple of BK.
+int gemm_split_for(int dtype, int tile, int mode, int64_t m, int64_t n, int64_t k,
+                   int64_t target, int64_t min_steps) {
+  const Tile t = tile_of(dtype, tile);
+  const int64_t tiles = gemm_tiles_for(dtype, tile, mode, m, n);
   int64_t split = 1;
   if (tiles < target) split = cdiv(target, tiles);
-  split = std::min<int64_t>(split, std::max<int64_t>(1, k / (8 * t.bk)));
-  split = std::min<int64_t>(split, 32);
+  split = std::min<int64_t>(split, std::max<int64_t>(1, k / (min_steps * t.bk)));
+  split = std::min<int64_t>(split, 64);
   if (split > 1) {
     const int64_t chunk = cdiv(cdiv(k, split), t.bk) * t.bk;
     split = cdiv(k, chunk);
   }
-  c.split = int(std::max<int64_t>(split, 1));
+  return int(std::max<int64_t>(split, 1));
+}
+
+GemmConfig gemm_choose(int dtype, int precision, int mode, int64_t m, int64_t n, int64_t k) {
+  GemmConfig c{0, 1};
+  if (precision != GEMM_PLAIN) return gemm_choose_split(dtype, precision, mode, m, n, k);
+  if (dtype == 1) {
+    if (mode == 1) c.tile = (n >= 1024) ? 3 : 5;
+    else if (m <= 64 || (n <= 64 && m < 1024)) c.tile = 5;
+    else if (n <= 64) c.tile = 4;
+    else c.tile = (m * n >= 1024 * 1024) ? 3 : 5;
+  } else {
+    c.tile = (m * n >= int64_t(2048) * 2048) ? 1 : 0;
+  }
+  c.split = gemm_split_for(dtype, c.tile, mode, m, n, k, 256, 8);
   return c;
 }
 

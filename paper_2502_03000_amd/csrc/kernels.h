@@ -77,6 +77,11 @@ struct GemmConfig {
 enum GemmPrecision { GEMM_PLAIN = 0, GEMM_BF16X3 = 1, GEMM_BF16X6 = 2 };
 
 GemmConfig gemm_choose(int dtype, int precision, int mode, int64_t m, int64_t n, int64_t k);
+// tile table access for the autotuner
+int gemm_tile_count(int dtype);
+bool gemm_tile_valid(int dtype, int tile, int mode);
+int gemm_split_for(int dtype, int tile, int mode, int64_t m, int64_t n, int64_t k, int64_t target,
+                   int64_t min_steps);
 size_t gemm_partial_bytes(int dtype, const GemmConfig& cfg, int64_t m, int64_t n);
 // split-BF16 family (FP32 storage only), used by gemm_choose / gemm_launch
 GemmConfig gemm_choose_split(int dtype, int precision, int mode, int64_t m, int64_t n, int64_t k);

@@ -848,8 +848,15 @@ class Planner {
       s.mode = syrk ? 1 : 0;
       s.precision = (dtype_ == HEXLA_F32) ? o_.product_precision : 0;
       s.cfg = k::gemm_choose(dtype_, s.precision, s.mode, m, n, kk);
-      const size_t pb = k::gemm_partial_bytes(dtype_, s.cfg, m, n);
-      if (pb) s.partial = work(int64_t(pb));
+      const auto tuned = ctx_->tuned.find(tune_key(s, a.trans ? 1 : 0, b.trans ? 1 : 0));
+      if (tuned != ctx_->tuned.end() && k::gemm_tile_valid(dtype_, tuned->second.tile, s.mode))
+        s.cfg = tuned->second;
+      // room for every candidate the autotuner may pick
+      const size_t pb = std::max(gemm_max_partial(s), k::gemm_partial_bytes(dtype_, s.cfg, m, n));
+      if (pb) {
+        s.partial = work(int64_t(pb));
+        s.partial_cap = int64_t(pb);
+      }
       s.name = syrk ? "syrk" : "gemm";
       if (s.precision == 1) s.name += "_bf16x3";
       if (s.precision == 2) s.name += "_bf16x6";

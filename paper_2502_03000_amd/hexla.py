@@ -84,6 +84,11 @@ def _load():
         "hexla_plan_destroy": [vp],
         "hexla_execute": [vp, vp, i64, vp, C.c_size_t],
         "hexla_sync": [vp, C.POINTER(Report)],
+        "hexla_plan_autotune": [vp, vp, i64, vp, C.c_size_t, i32],
+        "hexla_tune_save": [vp, C.c_char_p],
+        "hexla_tune_load": [vp, C.c_char_p],
+        "hexla_plan_capture": [vp, vp, i64, vp, C.c_size_t],
+        "hexla_plan_replay": [vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -205,6 +210,26 @@ class Plan:
             wptr = _addr(workspace)
             wbytes = workspace.numel() * workspace.element_size() if hasattr(workspace, "numel") else self.workspace_bytes
         self.ctx._check(lib.hexla_execute(self.handle, optr, ld, wptr or None, wbytes))
+
+    def _bufs(self, out, workspace, ld_out):
+        optr, ld = _ptr_ld(out, ld_out)
+        wptr, wbytes = (0, 0)
+        if workspace is not None:
+            wptr = _addr(workspace)
+            wbytes = workspace.numel() * workspace.element_size() if hasattr(workspace, "numel") else self.workspace_bytes
+        return optr, ld, wptr or None, wbytes
+
+    def autotune(self, out, workspace=None, ld_out=None, reps=5):
+        """Times the candidate configurations of every matrix product on these
+        buffers and keeps the fastest (synchronous)."""
+        self.ctx._check(lib.hexla_plan_autotune(self.handle, *self._bufs(out, workspace, ld_out), reps))
+
+    def capture(self, out, workspace=None, ld_out=None):
+        """Records the plan's launches on these buffers into a HIP graph."""
+        self.ctx._check(lib.hexla_plan_capture(self.handle, *self._bufs(out, workspace, ld_out)))
+
+    def replay(self):
+        self.ctx._check(lib.hexla_plan_replay(self.handle))
 
     def workspace(self, device="cuda"):
         import torch
@@ -331,6 +356,12 @@ class Context:
         h = C.c_void_p()
         self._check(lib.hexla_plan_create(self.handle, root.node, C.byref(o), C.byref(h)))
         return Plan(self, h.value)
+
+    def tune_save(self, path):
+        self._check(lib.hexla_tune_save(self.handle, os.fsencode(path)))
+
+    def tune_load(self, path):
+        self._check(lib.hexla_tune_load(self.handle, os.fsencode(path)))
 
     def sync(self) -> Report:
         r = Report()

@@ -278,3 +278,48 @@ def test_workspace_and_alias_checks(ctx):
     with pytest.raises(hx.HexlaError) as ei:
         p2.execute(a, p2.workspace())
     assert ei.value.status == hx.E_INVALID_ARG
+
+
+# ------------------------------------------------- tuning and graph replay
+
+def test_autotune_keeps_results_and_fills_table(ctx, tmp_path):
+    dims = inputs.fp32_chain_dims(scale=16)
+    mats = inputs.fp32_chain(seed=1002, dims=dims)
+    names = [f"M{i}" for i in range(len(mats))]
+    ref = oracle.evaluate("*".join(names), dict(zip(names, mats)))
+    e = None
+    for m in mats:
+        x = ctx.leaf(dev(m))
+        e = x if e is None else e @ x
+    p = ctx.plan(e)
+    out, ws = p.output(), p.workspace()
+    p.autotune(out, ws, reps=2)
+    p.execute(out, ws)
+    assert ctx.sync().status == hx.OK
+    assert rel(host(out), ref) <= 1e-5
+    path = tmp_path / "tune.txt"
+    ctx.tune_save(str(path))
+    lines = path.read_text().splitlines()
+    assert len(lines) == len(mats) - 1 and all(l.startswith("gfx950 ") for l in lines)
+    # a later plan of the same shapes takes the tuned configurations
+    p2 = ctx.plan(e)
+    assert [s["tile"] for s in p2.describe()["steps"]] == [s["tile"] for s in p.describe()["steps"]]
+
+
+def test_graph_replay_matches_eager(ctx):
+    g = inputs.rng(32)
+    a, b = inputs.normal(g, 300, 200, np.float32), inputs.normal(g, 200, 100, np.float32)
+    c = inputs.normal(g, 300, 100, np.float32)
+    ea, eb, ec = ctx.leaf(dev(a)), ctx.leaf(dev(b)), ctx.leaf(dev(c))
+    p = ctx.plan(hx.exp(ea @ eb % ec) - 2.0 * ec)
+    out, ws = p.output(), p.workspace()
+    p.execute(out, ws)
+    ctx.sync()
+    eager = host(out)
+    p.capture(out, ws)
+    for _ in range(3):
+        out.zero_()                      # eager work between replays
+        torch.cuda.synchronize()
+        p.replay()
+        assert ctx.sync().status == hx.OK
+        assert np.array_equal(host(out), eager)
