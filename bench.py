@@ -79,6 +79,23 @@ def cpu_baseline(chain_np, ew_host, ew_flops_per_elem, min_seconds=10.0):
     }
 
 
+def profiled_traffic(source_hash):
+    """HBM bytes per launch of the element-wise kernel from the committed
+    rocprofv3 counter summary, if that summary was taken on this very kernel
+    (same generated source); otherwise None."""
+    import re
+    path = os.path.join(ROOT, "profiles", "fused_elementwise_fp32_16384.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    h = re.search(r"source hash `([0-9a-f]+)`", text)
+    t = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    if h and t and h.group(1) == source_hash:
+        return int(t.group(1))
+    return None
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -192,7 +209,8 @@ def main():
     ew_kernel = {"bound": "hbm", "achieved": ew_bytes / (ms_ew * 1e-3) / 1e9,
                  "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     ew_kernel["frac"] = ew_kernel["achieved"] / HBM_PEAK_GBS
-    ew_kernel["traffic"] = None
+    ew_kernel["traffic"] = profiled_traffic(d2["steps"][0].get("source_hash", "")) \
+        if args.n == 16384 else None
     chain_tflops = p1.info.flops / (ms_chain * 1e-3) / 1e12
 
     res = {

@@ -922,6 +922,19 @@ class Planner {
   }
 };
 
+// FNV-1a of a generated kernel's source: identifies the kernel a profile
+// was taken on.
+std::string source_hash(const std::string& src) {
+  uint64_t h = 1469598103934665603ull;
+  for (unsigned char c : src) {
+    h ^= c;
+    h *= 1099511628211ull;
+  }
+  char buf[17];
+  std::snprintf(buf, sizeof buf, "%016llx", static_cast<unsigned long long>(h));
+  return buf;
+}
+
 void json_view(std::ostringstream& js, const char* name, const View& v) {
   js << "\"" << name << "\":{\"rows\":" << v.rows << ",\"cols\":" << v.cols
      << ",\"trans\":" << (v.trans ? "true" : "false") << ",\"buf\":\""
@@ -945,7 +958,8 @@ std::string describe(const hexla_plan* p) {
     switch (s.kind) {
       case StepKind::Ew:
         js << ",\"instructions\":" << s.ew.n_instr << ",\"leaves\":" << s.ew.leaves.size()
-           << ",\"generated\":" << (s.cg_fn ? "true" : "false") << ",";
+           << ",\"generated\":" << (s.cg_fn ? "true" : "false") << ",\"source_hash\":\""
+           << source_hash(s.cg_src) << "\",";
         json_view(js, "out", s.out);
         break;
       case StepKind::Gemv:

@@ -182,7 +182,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h:
+        if h and lib is not None:
             lib.hexla_plan_destroy(h)
             self.handle = None
 
@@ -272,7 +272,7 @@ class Context:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h:
+        if h and lib is not None:
             lib.hexla_ctx_destroy(h)
             self.handle = None
 
