@@ -207,6 +207,16 @@ typedef struct hexla_report {
  * return value is HEXLA_E_DEVICE on a HIP error, else HEXLA_OK. */
 hexla_status hexla_sync(hexla_ctx* ctx, hexla_report* report);
 
+/* The bfloat16 terms the split-BF16 products use (BF16 as a type for
+ * higher-precision results: Sec. IV). For FP32 x[i] (device memory):
+ * t0 = rne(x), t1 = rne(x - t0) and, when terms == 3, t2 = rne(x - t0 - t1),
+ * rne = round to nearest, ties to even; outputs are raw bfloat16 bit
+ * patterns (device memory, n entries each). Asynchronous on the context's
+ * stream. Errors: HEXLA_E_INVALID_ARG (terms not 2 or 3, null pointers),
+ * HEXLA_E_UNSUPPORTED (dry-run context), HEXLA_E_DEVICE. */
+hexla_status hexla_split_bf16(hexla_ctx* ctx, const float* x, int64_t n, uint16_t* t0,
+                              uint16_t* t1, uint16_t* t2, int32_t terms);
+
 /* ------------------------------------------------------- tuning and graphs */
 
 /* Times every candidate tile / split-K configuration of each matrix product

@@ -205,6 +205,18 @@ hexla_status hexla_execute(hexla_plan* plan, void* out, int64_t ld_out, void* wo
   return run_steps(plan, out, ld_out, workspace, plan->ctx->stream);
 }
 
+hexla_status hexla_split_bf16(hexla_ctx* ctx, const float* x, int64_t n, uint16_t* t0,
+                              uint16_t* t1, uint16_t* t2, int32_t terms) {
+  if (!ctx) return HEXLA_E_INVALID_ARG;
+  if (ctx->device < 0) return set_err(ctx, HEXLA_E_UNSUPPORTED, "dry-run context cannot execute");
+  if (n < 0 || (terms != 2 && terms != 3) || (n > 0 && (!x || !t0 || !t1 || (terms == 3 && !t2))))
+    return set_err(ctx, HEXLA_E_INVALID_ARG, "split_bf16: bad arguments");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = k::split_bf16_launch(x, n, t0, t1, t2, terms, ctx->stream);
+  if (e != hipSuccess) return device_err(ctx, e, "split_bf16");
+  return HEXLA_OK;
+}
+
 hexla_status hexla_sync(hexla_ctx* ctx, hexla_report* report) {
   if (!ctx) return HEXLA_E_INVALID_ARG;
   hexla_report r{};

@@ -1,17 +1,339 @@
-// split-BF16 GEMM family (placeholder until the kernel lands)
+// Split-BF16 products: FP32 operands, BF16 matrix instructions, FP32
+// accumulation. The paper names BF16 as a future element type and cites its
+// use for higher-precision results (Sec. IV, the Henry et al. reference).
+//
+// Each FP32 value x is split as hi = rne(x), mid = rne(x - hi)
+// (x - hi is exact in FP32), and for three terms lo = rne(x - hi - mid).
+// The product keeps the term products of weight >= 2^-16 (three products:
+// hi*hi + hi*mid + mid*hi) or >= 2^-24 (six products: + mid*mid + hi*lo +
+// lo*hi), each a v_mfma_f32_16x16x32_bf16 accumulating in FP32.
+//
+// The split happens on the way from HBM to LDS: a 128x128 tile of C reads
+// 128x32 FP32 slices of both operands, splits them in registers and stores
+// the BF16 terms in LDS as [row][k] (k contiguous, 16-byte fragment reads).
+// Lower-triangle tiles + mirrored stores give the symmetric product (SYRK).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
+#include "gemm_device.h"
 #include "kernels.h"
 
 namespace hexla {
 namespace k {
 
-GemmConfig gemm_choose_split(int, int, int, int64_t, int64_t, int64_t) { return GemmConfig{0, 1}; }
+namespace {
 
-hipError_t gemm_split_launch(int, int, int, int, int, int64_t, int64_t, int64_t, double,
-                             const void*, int64_t, const void*, int64_t, double, void*, int64_t,
-                             void*, const GemmConfig&, hipStream_t) {
-  return hipErrorNotSupported;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float accv __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128, BN = 128, BK = 32;
+constexpr int LDK = BK + 8;  // bf16 row stride in LDS (80 bytes: conflict-free 16-byte reads)
+
+template <int TERMS>
+__device__ __forceinline__ void split_terms(float x, __bf16 (&t)[TERMS]) {
+  float rest = x;
+#pragma unroll
+  for (int q = 0; q < TERMS; ++q) {
+    const __bf16 h = static_cast<__bf16>(rest);  // round to nearest even
+    t[q] = h;
+    rest = rest - static_cast<float>(h);
+  }
+}
+
+template <bool TA, bool TB, int TERMS>
+struct SplitTile {
+  static constexpr int kThreads = 256;
+  static constexpr int A_ELEMS = BM * LDK;  // per term
+  static constexpr int B_ELEMS = BN * LDK;
+  static constexpr int STAGE = TERMS * (A_ELEMS + B_ELEMS);  // bf16 elements
+  static constexpr int LV = BM * BK / (kThreads * 4);         // float4 loads per operand per thread
+
+  // Global -> registers (FP32, 4 consecutive elements along the contiguous dim).
+  static __device__ __forceinline__ void load(const GemmArgs& g, int64_t m0, int64_t n0,
+                                              int64_t k0, int64_t k_end, bool vec, f4 (&ra)[LV],
+                                              f4 (&rb)[LV]) {
+    const float* A = static_cast<const float*>(g.A);
+    const float* B = static_cast<const float*>(g.B);
+#pragma unroll
+    for (int r = 0; r < LV; ++r) {
+      const int e = threadIdx.x + kThreads * r;
+      int64_t row, kk;
+      if (TA) {  // k contiguous: rows of 32 k
+        row = m0 + e / (BK / 4);
+        kk = k0 + (e % (BK / 4)) * 4;
+        const float* p = A + kk + row * g.lda;
+        if (vec && row < g.m && kk + 4 <= k_end) ra[r] = *reinterpret_cast<const f4*>(p);
+        else
+#pragma unroll
+          for (int q = 0; q < 4; ++q) ra[r][q] = (row < g.m && kk + q < k_end) ? p[q] : 0.f;
+      } else {  // m contiguous: columns of 128 rows
+        kk = k0 + e / (BM / 4);
+        row = m0 + (e % (BM / 4)) * 4;
+        const float* p = A + row + kk * g.lda;
+        if (vec && kk < k_end && row + 4 <= g.m) ra[r] = *reinterpret_cast<const f4*>(p);
+        else
+#pragma unroll
+          for (int q = 0; q < 4; ++q) ra[r][q] = (kk < k_end && row + q < g.m) ? p[q] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < LV; ++r) {
+      const int e = threadIdx.x + kThreads * r;
+      int64_t col, kk;
+      if (!TB) {  // op(B)(k, col) = B[k + col*ldb]: k contiguous
+        col = n0 + e / (BK / 4);
+        kk = k0 + (e % (BK / 4)) * 4;
+        const float* p = B + kk + col * g.ldb;
+        if (vec && col < g.n && kk + 4 <= k_end) rb[r] = *reinterpret_cast<const f4*>(p);
+        else
+#pragma unroll
+          for (int q = 0; q < 4; ++q) rb[r][q] = (col < g.n && kk + q < k_end) ? p[q] : 0.f;
+      } else {  // op(B)(k, col) = B[col + k*ldb]: n contiguous
+        kk = k0 + e / (BN / 4);
+        col = n0 + (e % (BN / 4)) * 4;
+        const float* p = B + col + kk * g.ldb;
+        if (vec && kk < k_end && col + 4 <= g.n) rb[r] = *reinterpret_cast<const f4*>(p);
+        else
+#pragma unroll
+          for (int q = 0; q < 4; ++q) rb[r][q] = (kk < k_end && col + q < g.n) ? p[q] : 0.f;
+      }
+    }
+  }
+
+  // Split in registers and store the BF16 terms as [row][k].
+  static __device__ __forceinline__ void store(__bf16* sa, __bf16* sb, const f4 (&ra)[LV],
+                                               const f4 (&rb)[LV]) {
+#pragma unroll
+    for (int r = 0; r < LV; ++r) {
+      const int e = threadIdx.x + kThreads * r;
+      __bf16 t[4][TERMS];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) split_terms<TERMS>(ra[r][q], t[q]);
+      if (TA) {
+        const int row = e / (BK / 4), kk = (e % (BK / 4)) * 4;
+#pragma unroll
+        for (int s = 0; s < TERMS; ++s) {
+          bf16x4 v;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[q] = t[q][s];
+          *reinterpret_cast<bf16x4*>(sa + s * A_ELEMS + row * LDK + kk) = v;
+        }
+      } else {
+        const int kk = e / (BM / 4), row = (e % (BM / 4)) * 4;
+#pragma unroll
+        for (int s = 0; s < TERMS; ++s)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) sa[s * A_ELEMS + (row + q) * LDK + kk] = t[q][s];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < LV; ++r) {
+      const int e = threadIdx.x + kThreads * r;
+      __bf16 t[4][TERMS];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) split_terms<TERMS>(rb[r][q], t[q]);
+      if (!TB) {
+        const int col = e / (BK / 4), kk = (e % (BK / 4)) * 4;
+#pragma unroll
+        for (int s = 0; s < TERMS; ++s) {
+          bf16x4 v;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[q] = t[q][s];
+          *reinterpret_cast<bf16x4*>(sb + s * B_ELEMS + col * LDK + kk) = v;
+        }
+      } else {
+        const int kk = e / (BN / 4), col = (e % (BN / 4)) * 4;
+#pragma unroll
+        for (int s = 0; s < TERMS; ++s)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) sb[s * B_ELEMS + (col + q) * LDK + kk] = t[q][s];
+      }
+    }
+  }
+};
+
+template <bool TA, bool TB, int TERMS>
+__global__ __launch_bounds__(256) void gemm_split_kernel(GemmArgs g, int vec) {
+  using G = SplitTile<TA, TB, TERMS>;
+  __shared__ __attribute__((aligned(16))) __bf16 smem[2 * G::STAGE];
+  int tm, tn;
+  if (g.mode == 1) {
+    tri_tile(int(blockIdx.x), tm, tn);
+  } else {
+    tm = int(blockIdx.x) % g.tiles_m;
+    tn = int(blockIdx.x) / g.tiles_m;
+  }
+  const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
+  const int z = blockIdx.y;
+  const int64_t kb = int64_t(z) * g.k_chunk;
+  int64_t ke = kb + g.k_chunk;
+  if (ke > g.k) ke = g.k;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int l16 = lane & 15, grp = lane >> 4;
+
+  accv acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = accv{0.f, 0.f, 0.f, 0.f};
+
+  f4 ra[G::LV], rb[G::LV];
+  const int64_t nk = (ke > kb) ? (ke - kb + BK - 1) / BK : 0;
+  if (nk > 0) {
+    G::load(g, m0, n0, kb, ke, vec != 0, ra, rb);
+    G::store(smem, smem + TERMS * G::A_ELEMS, ra, rb);
+  }
+  __syncthreads();
+  for (int64_t t = 0; t < nk; ++t) {
+    __bf16* cur = smem + (t & 1) * G::STAGE;
+    __bf16* nxt = smem + ((t + 1) & 1) * G::STAGE;
+    const bool more = t + 1 < nk;
+    if (more) G::load(g, m0, n0, kb + (t + 1) * BK, ke, vec != 0, ra, rb);
+    const __bf16* sa = cur;
+    const __bf16* sb = cur + TERMS * G::A_ELEMS;
+    bf16x8 a[TERMS][4], b[TERMS][4];
+#pragma unroll
+    for (int s = 0; s < TERMS; ++s)
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        a[s][f] = *reinterpret_cast<const bf16x8*>(sa + s * G::A_ELEMS +
+                                                   (wm * 64 + f * 16 + l16) * LDK + grp * 8);
+        b[s][f] = *reinterpret_cast<const bf16x8*>(sb + s * G::B_ELEMS +
+                                                   (wn * 64 + f * 16 + l16) * LDK + grp * 8);
+      }
+#pragma unroll
+    for (int fm = 0; fm < 4; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < 4; ++fn) {
+        // small terms first
+        if (TERMS == 3) {
+          acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][fm], b[0][fn], acc[fm][fn], 0, 0, 0);
+          acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][fm], b[2][fn], acc[fm][fn], 0, 0, 0);
+          acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][fm], b[1][fn], acc[fm][fn], 0, 0, 0);
+        }
+        acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][fm], b[0][fn], acc[fm][fn], 0, 0, 0);
+        acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][fm], b[1][fn], acc[fm][fn], 0, 0, 0);
+        acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][fm], b[0][fn], acc[fm][fn], 0, 0, 0);
+      }
+    if (more) G::store(nxt, nxt + TERMS * G::A_ELEMS, ra, rb);
+    __syncthreads();
+  }
+
+  // epilogue (result layout of the 16x16 FP32-accumulating instructions:
+  // lane l, register r holds row 4*(l/16) + r, column l%16)
+  const float alpha = float(g.alpha), beta = float(g.beta);
+  float* C = static_cast<float*>(g.C);
+  float* P = static_cast<float*>(g.partial);
+#pragma unroll
+  for (int fm = 0; fm < 4; ++fm)
+#pragma unroll
+    for (int fn = 0; fn < 4; ++fn)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = m0 + wm * 64 + fm * 16 + 4 * grp + r;
+        const int64_t j = n0 + wn * 64 + fn * 16 + l16;
+        if (i >= g.m || j >= g.n) continue;
+        const float v = acc[fm][fn][r];
+        if (g.split > 1) {
+          P[int64_t(z) * g.m * g.n + i + j * g.m] = v;
+        } else if (g.mode == 1) {
+          if (i >= j) {
+            float out = alpha * v;
+            if (beta != 0.f) out += beta * C[i + j * g.ldc];
+            C[i + j * g.ldc] = out;
+            if (i > j) C[j + i * g.ldc] = out;
+          }
+        } else {
+          float out = alpha * v;
+          if (beta != 0.f) out += beta * C[i + j * g.ldc];
+          C[i + j * g.ldc] = out;
+        }
+      }
+}
+
+typedef void (*SplitFn)(GemmArgs, int);
+
+template <int TERMS>
+SplitFn pick(bool ta, bool tb) {
+  if (ta) return tb ? gemm_split_kernel<true, true, TERMS> : gemm_split_kernel<true, false, TERMS>;
+  return tb ? gemm_split_kernel<false, true, TERMS> : gemm_split_kernel<false, false, TERMS>;
+}
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+__global__ void split_bf16_kernel(const float* __restrict__ x, int64_t n, uint16_t* hi,
+                                  uint16_t* mid, uint16_t* lo, int terms) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+    __bf16 t[3];
+    split_terms<3>(x[i], t);
+    hi[i] = __builtin_bit_cast(uint16_t, t[0]);
+    mid[i] = __builtin_bit_cast(uint16_t, t[1]);
+    if (terms == 3) lo[i] = __builtin_bit_cast(uint16_t, t[2]);
+  }
+}
+
+}  // namespace
+
+GemmConfig gemm_choose_split(int, int, int mode, int64_t m, int64_t n, int64_t k) {
+  int64_t tiles;
+  if (mode == 1) {
+    const int64_t tt = cdiv(n, BN);
+    tiles = tt * (tt + 1) / 2;
+  } else {
+    tiles = cdiv(m, BM) * cdiv(n, BN);
+  }
+  // about 1024 workgroups; every workgroup runs at least 16 K steps
+  int64_t split = std::max<int64_t>(1, cdiv(1024, tiles));
+  split = std::min<int64_t>(split, std::max<int64_t>(1, k / (16 * BK)));
+  split = std::min<int64_t>(split, 64);
+  if (split > 1) {
+    const int64_t chunk = cdiv(cdiv(k, split), BK) * BK;
+    split = cdiv(k, chunk);
+  }
+  return GemmConfig{0, int(split)};
+}
+
+hipError_t gemm_split_launch(int dtype, int precision, int mode, int ta, int tb, int64_t m,
+                             int64_t n, int64_t k, double alpha, const void* A, int64_t lda,
+                             const void* B, int64_t ldb, double beta, void* C, int64_t ldc,
+                             void* partial, const GemmConfig& cfg, hipStream_t s) {
+  if (dtype != 1) return hipErrorNotSupported;  // FP32 storage only
+  GemmArgs g{};
+  g.m = m; g.n = n; g.k = k;
+  g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+  g.alpha = alpha; g.beta = beta; g.partial = partial;
+  g.mode = mode;
+  g.split = std::max(cfg.split, 1);
+  g.k_chunk = std::max<int64_t>(BK, cdiv(cdiv(k, g.split), BK) * BK);
+  g.tiles_m = int(cdiv(m, BM));
+  g.tiles_n = int(cdiv(n, BN));
+  const int vec = (lda % 4 == 0) && (ldb % 4 == 0) && (reinterpret_cast<uintptr_t>(A) % 16 == 0) &&
+                  (reinterpret_cast<uintptr_t>(B) % 16 == 0);
+  const int64_t blocks = mode == 1 ? int64_t(g.tiles_n) * (g.tiles_n + 1) / 2
+                                   : int64_t(g.tiles_m) * g.tiles_n;
+  SplitFn fn = precision == GEMM_BF16X6 ? pick<3>(ta != 0, tb != 0) : pick<2>(ta != 0, tb != 0);
+  hipLaunchKernelGGL(fn, dim3(unsigned(blocks), unsigned(g.split)), dim3(256), 0, s, g, vec);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || g.split <= 1) return e;
+  int64_t rb = cdiv(m * n, 256);
+  if (rb > 4096) rb = 4096;
+  hipLaunchKernelGGL(splitk_reduce_kernel<float>, dim3(unsigned(rb)), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t split_bf16_launch(const float* x, int64_t n, uint16_t* hi, uint16_t* mid, uint16_t* lo,
+                             int terms, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = cdiv(n, 256);
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(split_bf16_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, x, n, hi, mid, lo,
+                     terms);
+  return hipGetLastError();
 }
 
 }  // namespace k

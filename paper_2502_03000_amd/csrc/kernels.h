@@ -94,6 +94,11 @@ hipError_t gemm_launch(int dtype, int precision, int mode, int ta, int tb, int64
                        int64_t ldb, double beta, void* C, int64_t ldc, void* partial,
                        const GemmConfig& cfg, hipStream_t s);
 
+// The bfloat16 terms of FP32 values (raw bit patterns): t0 = rne(x),
+// t1 = rne(x - t0), t2 = rne(x - t0 - t1) (written when terms == 3).
+hipError_t split_bf16_launch(const float* x, int64_t n, uint16_t* t0, uint16_t* t1, uint16_t* t2,
+                             int terms, hipStream_t s);
+
 // ---------------------------------------------------------------------- LU
 // In-place LU with partial pivoting of the n x n column-major matrix A (lda),
 // A = P^T L U. rowid (n ints) receives the original row held at each final

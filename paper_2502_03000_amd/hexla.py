@@ -89,6 +89,7 @@ def _load():
         "hexla_tune_load": [vp, C.c_char_p],
         "hexla_plan_capture": [vp, vp, i64, vp, C.c_size_t],
         "hexla_plan_replay": [vp],
+        "hexla_split_bf16": [vp, vp, i64, vp, vp, vp, i32],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -356,6 +357,16 @@ class Context:
         h = C.c_void_p()
         self._check(lib.hexla_plan_create(self.handle, root.node, C.byref(o), C.byref(h)))
         return Plan(self, h.value)
+
+    def split_bf16(self, x, terms=2):
+        """bfloat16 terms of an FP32 tensor x (device), as int16 tensors holding
+        the raw bit patterns."""
+        import torch
+        n = x.numel()
+        outs = [torch.empty(n, dtype=torch.int16, device=x.device) for _ in range(3)]
+        self._check(lib.hexla_split_bf16(self.handle, x.data_ptr(), n, outs[0].data_ptr(),
+                                         outs[1].data_ptr(), outs[2].data_ptr(), terms))
+        return outs[:terms]
 
     def tune_save(self, path):
         self._check(lib.hexla_tune_save(self.handle, os.fsencode(path)))

@@ -1,0 +1,83 @@
+"""Precision form on the GPU: the bfloat16 split (bit-exact against the
+oracle's round-to-nearest-even emulation) and split-BF16 products (error
+against the FP64 oracle, within the stated bound)."""
+import numpy as np
+import pytest
+import torch
+
+import inputs
+import oracle
+from oracle import bf16
+from paper_2502_03000_amd import hexla as hx
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    a = np.asarray(a)
+    return torch.from_numpy(np.ascontiguousarray(a.T)).to("cuda").t()
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel(got, ref):
+    return np.linalg.norm(np.asarray(got) - ref) / np.linalg.norm(ref)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return hx.Context(0)
+
+
+@pytest.mark.parametrize("terms", [2, 3])
+def test_split_is_bit_exact(ctx, terms):
+    g = inputs.rng(40)
+    x = np.concatenate([
+        (g.standard_normal(100000) * 10.0 ** g.integers(-30, 30, 100000)).astype(np.float32),
+        np.array([0.0, -0.0, 1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 3.0e38, -1e-40, 6.1e-5], np.float32),
+    ])
+    parts = ctx.split_bf16(torch.from_numpy(x).cuda(), terms)
+    torch.cuda.synchronize()
+    ref = bf16.split(x, terms)
+    for got, want in zip(parts, ref):
+        got_bits = got.cpu().numpy().view(np.uint16)
+        want_bits = (want.view(np.uint32) >> 16).astype(np.uint16)
+        assert np.array_equal(got_bits, want_bits)
+
+
+@pytest.mark.parametrize("prec,bound", [("bf16x3", 1e-5), ("bf16x6", 2e-6)])
+@pytest.mark.parametrize("cond", [1e2, 1e4, 1e6])
+def test_split_syrk_error(ctx, prec, bound, cond):
+    x, u, s, v = inputs.svd_matrix(50 + int(np.log10(cond)), 4096, 256, cond, dtype=np.float32)
+    ref = oracle.evaluate("trans(X)*X", {"X": x})
+    ex = ctx.leaf(dev(x))
+    p = ctx.plan(hx.trans(ex) @ ex, product_precision=prec)
+    assert [st["kernel"] for st in p.describe()["steps"]] == [f"syrk_{prec}"]
+    out = ctx.evaluate(hx.trans(ex) @ ex, product_precision=prec)
+    got = host(out)
+    assert np.array_equal(got, got.T)
+    assert rel(got, ref) <= bound
+    # the split product is closer to FP64 than plain FP32 accumulation is
+    # allowed to be worse: both within the FP32-equivalent tolerance
+    plain = host(ctx.evaluate(hx.trans(ex) @ ex))
+    assert rel(plain, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("ta", [False, True])
+@pytest.mark.parametrize("tb", [False, True])
+@pytest.mark.parametrize("mnk", [(300, 200, 1000), (129, 257, 65), (64, 64, 4096)])
+def test_split_gemm_against_oracle(ctx, ta, tb, mnk):
+    m, n, k = mnk
+    g = inputs.rng(m + 3 * n + 7 * k + 2 * ta + tb)
+    a = inputs.normal(g, k, m, np.float32) if ta else inputs.normal(g, m, k, np.float32)
+    b = inputs.normal(g, n, k, np.float32) if tb else inputs.normal(g, k, n, np.float32)
+    expr = ("trans(A)" if ta else "A") + "*" + ("trans(B)" if tb else "B")
+    ref = oracle.evaluate(expr, {"A": a, "B": b})
+    ea, eb = ctx.leaf(dev(a)), ctx.leaf(dev(b))
+    e = (hx.trans(ea) if ta else ea) @ (hx.trans(eb) if tb else eb)
+    got3 = host(ctx.evaluate(e, product_precision="bf16x3"))
+    got6 = host(ctx.evaluate(e, product_precision="bf16x6"))
+    assert rel(got3, ref) <= 2e-5
+    assert rel(got6, ref) <= 2e-6
