@@ -193,3 +193,27 @@ def fp32_elementwise_device(seed: int = 1001, n: int = 16384, cols: int | None =
     b = colmajor_normal()
     cc = torch.rand((c, n), generator=g, device=device, dtype=torch.float32).t() + 1.0
     return {"A": a, "B": b, "C": cc}
+
+
+def svd_matrix_device(seed: int, rows: int, cols: int, cond: float, device: str = "cuda"):
+    """Device version of ``svd_matrix`` for large shapes: X = U diag(s) V^T in
+    float64 (torch's seeded generator and QR), returned as (X fp32 column-major,
+    s, V) with s and V as float64 host arrays."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    n = min(rows, cols)
+
+    def haar(r, c):
+        z = torch.randn((r, c), generator=g, device=device, dtype=torch.float64)
+        q, rr = torch.linalg.qr(z)
+        return q * torch.sign(torch.diagonal(rr))[None, :]
+
+    u = haar(rows, n)
+    v = haar(cols, n)
+    s = cond ** (-torch.arange(n, device=device, dtype=torch.float64) / max(n - 1, 1))
+    x = (u * s[None, :]) @ v.T
+    xc = torch.empty((cols, rows), device=device, dtype=torch.float32).t()
+    xc.copy_(x)
+    del u, x
+    return xc, s.cpu().numpy(), v.cpu().numpy()
