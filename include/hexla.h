@@ -131,10 +131,19 @@ typedef enum hexla_product_precision {
   HEXLA_PRODUCT_BF16X6 = 2   /* FP32 products as 6 BF16 MFMA products (3-term split) */
 } hexla_product_precision;
 
+/* Mixed-precision forms apply to FP64 systems: the LU is computed on an FP32
+ * copy (partial pivoting on the FP32 values), the residual R = B - S X and the
+ * update X += D in FP64, with D solved on the low-precision factors, until
+ * ||R||inf <= ir_tol_scale * 2^-53 * ||S||inf * ||X||inf (ir_tol_scale 0:
+ * sqrt(n)), the correction stagnates (||D|| > 0.5 ||D_prev||) or ir_max_iter
+ * is reached (deferred HEXLA_E_NO_CONVERGENCE). The refinement loop reads a
+ * small status block after every step, so hexla_execute of such a plan
+ * returns only when the solve is done and the plan cannot be captured. */
 typedef enum hexla_solve_precision {
   HEXLA_SOLVE_PLAIN = 0,     /* LU and substitution in the storage type          */
-  HEXLA_SOLVE_IR_FP32 = 1,   /* FP32 LU (FP64 pivot search) + FP64 refinement     */
-  HEXLA_SOLVE_IR_FP16 = 2    /* FP16-MFMA trailing updates + FP64 refinement     */
+  HEXLA_SOLVE_IR_FP32 = 1,   /* FP32 LU, FP32 trailing updates                   */
+  HEXLA_SOLVE_IR_FP16 = 2,   /* FP32 LU, FP16-MFMA trailing updates (FP32 accumulation) */
+  HEXLA_SOLVE_IR_BF16X3 = 3  /* FP32 LU, split-BF16 (x3) MFMA trailing updates   */
 } hexla_solve_precision;
 
 typedef struct hexla_plan_opts {

@@ -195,10 +195,11 @@ def fp32_elementwise_device(seed: int = 1001, n: int = 16384, cols: int | None =
     return {"A": a, "B": b, "C": cc}
 
 
-def svd_matrix_device(seed: int, rows: int, cols: int, cond: float, device: str = "cuda"):
+def svd_matrix_device(seed: int, rows: int, cols: int, cond: float, device: str = "cuda",
+                      dtype=None, return_u: bool = False):
     """Device version of ``svd_matrix`` for large shapes: X = U diag(s) V^T in
-    float64 (torch's seeded generator and QR), returned as (X fp32 column-major,
-    s, V) with s and V as float64 host arrays."""
+    float64 (torch's seeded generator and QR), returned as (X column-major in
+    ``dtype`` (default float32), s, V[, U]) with s, V, U as float64 host arrays."""
     import torch
     g = torch.Generator(device=device)
     g.manual_seed(seed)
@@ -213,7 +214,11 @@ def svd_matrix_device(seed: int, rows: int, cols: int, cond: float, device: str 
     v = haar(cols, n)
     s = cond ** (-torch.arange(n, device=device, dtype=torch.float64) / max(n - 1, 1))
     x = (u * s[None, :]) @ v.T
-    xc = torch.empty((cols, rows), device=device, dtype=torch.float32).t()
+    xc = torch.empty((cols, rows), device=device, dtype=dtype or torch.float32).t()
     xc.copy_(x)
-    del u, x
-    return xc, s.cpu().numpy(), v.cpu().numpy()
+    del x
+    out = (xc, s.cpu().numpy(), v.cpu().numpy())
+    if return_u:
+        out = out + (u.cpu().numpy(),)
+    del u
+    return out

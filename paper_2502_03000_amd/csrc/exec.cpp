@@ -3,8 +3,10 @@
 // Sec. II, done asynchronously on the device).
 #include <hip/hip_runtime_api.h>
 
+#include <cmath>
 #include <cstdint>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "internal.h"
@@ -133,6 +135,72 @@ GemmBind bind_gemm(const Step& s, void* out, int64_t ld_out, void* workspace) {
   return g;
 }
 
+// Mixed-precision solve of an FP64 system (see hexla_solve_precision): FP32
+// LU, first solve, then FP64 residual / low-precision correction steps. The
+// loop reads the norms after each step (one small device-to-host copy).
+hexla_status run_ir_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipStream_t st) {
+  const IrWork& w = s.ir;
+  const int64_t n = s.n, r = s.nrhs;
+  const View S = resolve(s.A, b), B = resolve(s.B, b), X = resolve(s.C, b);
+  void* s_low = addr(w.s_low, b);
+  int32_t* rowid = static_cast<int32_t*>(addr(w.rowid, b));
+  void* r64 = addr(w.r64, b);
+  void* r_low = addr(w.r_low, b);
+  void* d_low = addr(w.d_low, b);
+  double* scratch = static_cast<double*>(addr(w.scratch, b));
+  double* norms = static_cast<double*>(addr(w.norms, b));
+  const int64_t ldn = std::max<int64_t>(n, 1);
+  auto fail = [&](hipError_t e, const char* what) { return device_err(ctx, e, what); };
+  hipError_t e = k::cast_launch(0, 1, n, n, addr(S.ref, b), si(S), sj(S), s_low, ldn, st);
+  if (e != hipSuccess) return fail(e, "ir: cast S");
+  e = k::lu_factor_launch(1, n, s_low, ldn, rowid, addr(w.luwork, b), ctx->d_status, st,
+                          w.update_precision);
+  if (e != hipSuccess) return fail(e, "ir: lu");
+  e = k::norm_inf_launch(1, n, n, s_low, ldn, scratch, norms + 0, st);
+  if (e != hipSuccess) return fail(e, "ir: norm S");
+  // X0 = LU^-1 B in the low precision
+  e = k::cast_launch(0, 1, n, r, addr(B.ref, b), si(B), sj(B), r_low, ldn, st);
+  if (e == hipSuccess) e = k::lu_solve_launch(1, n, r, s_low, ldn, rowid, r_low, ldn, d_low, ldn, st);
+  if (e == hipSuccess) e = k::cast_launch(1, 0, n, r, d_low, 1, ldn, addr(X.ref, b), X.ld, st);
+  if (e != hipSuccess) return fail(e, "ir: first solve");
+  const double tol = (w.tol_scale > 0 ? w.tol_scale : std::sqrt(double(n))) * std::ldexp(1.0, -53);
+  double h[4] = {0, 0, 0, 0};
+  double d_prev = -1.0;
+  int it = 0;
+  bool converged = false;
+  for (;; ++it) {
+    // R = B - S X (FP64)
+    e = k::cast_launch(0, 0, n, r, addr(B.ref, b), si(B), sj(B), r64, ldn, st);
+    if (e == hipSuccess)
+      e = k::gemm_launch(0, 0, 0, S.trans ? 1 : 0, 0, n, r, n, -1.0, addr(S.ref, b), S.ld,
+                         addr(X.ref, b), X.ld, 1.0, r64, ldn, addr(w.partial, b), w.res_cfg, st);
+    if (e == hipSuccess) e = k::norm_inf_launch(0, n, r, r64, ldn, scratch, norms + 1, st);
+    if (e == hipSuccess) e = k::norm_inf_launch(0, n, r, addr(X.ref, b), X.ld, scratch, norms + 2, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, norms, 3 * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(e, "ir: residual");
+    if (h[1] <= tol * h[0] * h[2]) {
+      converged = true;
+      break;
+    }
+    if (it >= w.max_iter) break;
+    // D = LU^-1 R (low precision), stop when the correction stagnates
+    e = k::cast_launch(0, 1, n, r, r64, 1, ldn, r_low, ldn, st);
+    if (e == hipSuccess) e = k::lu_solve_launch(1, n, r, s_low, ldn, rowid, r_low, ldn, d_low, ldn, st);
+    if (e == hipSuccess) e = k::norm_inf_launch(1, n, r, d_low, ldn, scratch, norms + 3, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + 3, norms + 3, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(e, "ir: correction");
+    if (d_prev >= 0.0 && h[3] > 0.5 * d_prev) break;  // stagnated: keep X
+    e = k::add_mixed_launch(1, n, r, static_cast<double*>(addr(X.ref, b)), X.ld, d_low, ldn, st);
+    if (e != hipSuccess) return fail(e, "ir: update");
+    d_prev = h[3];
+  }
+  ctx->host_ir_iterations = it;
+  if (!converged && it >= w.max_iter && ctx->host_status == 0) ctx->host_status = HEXLA_E_NO_CONVERGENCE;
+  return HEXLA_OK;
+}
+
 hexla_status run_steps(hexla_plan* plan, void* out, int64_t ld_out, void* workspace,
                        hipStream_t st) {
   hexla_ctx* ctx = plan->ctx;
@@ -186,6 +254,11 @@ hexla_status run_steps(hexla_plan* plan, void* out, int64_t ld_out, void* worksp
                                addr(C.ref, b), C.ld, st);
         break;
       }
+      case StepKind::IrSolve: {
+        const hexla_status hs = run_ir_solve(ctx, s, b, st);
+        if (hs != HEXLA_OK) return hs;
+        break;
+      }
       default:
         break;
     }
@@ -232,8 +305,9 @@ hexla_status hexla_sync(hexla_ctx* ctx, hexla_report* report) {
   if (e == hipSuccess) e = hipMemset(ctx->d_status, 0, sizeof(h));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) return device_err(ctx, e, "hexla_sync");
-  r.status = h[0];
-  r.ir_iterations = h[3];
+  r.status = h[0] ? h[0] : ctx->host_status;
+  r.ir_iterations = ctx->host_ir_iterations;
+  ctx->host_status = 0;
   if (h[0] == HEXLA_E_SINGULAR) r.singular_column = h[2];
   if (h[1]) {
     r.status = HEXLA_E_DEVICE;

@@ -68,7 +68,24 @@ struct EwHost {
   bool ident = false;
 };
 
-enum class StepKind : uint8_t { Ew, Gemv, Gemm, LuFactor, LuSolve, Fill };
+enum class StepKind : uint8_t { Ew, Gemv, Gemm, LuFactor, LuSolve, IrSolve, Fill };
+
+// Workspace of a mixed-precision solve (low-precision LU + FP64 refinement).
+struct IrWork {
+  Ref s_low;     // n x n low-precision working copy (LU in place), ld n
+  Ref rowid;     // n ints
+  Ref luwork;    // panel scratch of the low-precision LU
+  Ref r64;       // n x nrhs FP64 residual
+  Ref r_low;     // n x nrhs residual in the low precision
+  Ref d_low;     // n x nrhs correction in the low precision
+  Ref scratch;   // norm partials
+  Ref norms;     // 4 doubles: ||S||, ||R||, ||X||, ||D||
+  Ref partial;   // split-K partials of the residual product
+  k::GemmConfig res_cfg{};
+  int update_precision = 0;  // k::GemmPrecision of the LU's trailing updates
+  int max_iter = 30;
+  double tol_scale = 0.0;    // 0: sqrt(n)
+};
 
 struct Step {
   StepKind kind = StepKind::Ew;
@@ -86,6 +103,7 @@ struct Step {
   int64_t partial_cap = 0;  // bytes reserved for split-K partials
   int64_t m = 0, n = 0, kk = 0, nrhs = 0;
   Ref rowid, luwork;
+  IrWork ir;
   double flops = 0.0, bytes = 0.0;
   // Ew: kernel generated for this program (null: interpreter)
   std::string cg_src;
@@ -102,6 +120,8 @@ struct hexla_ctx {
   std::string err;
   int32_t* d_status = nullptr;  // [0] status, [1] timeout, [2] singular column, [3] ir iterations
   std::map<std::string, hexla::k::GemmConfig> tuned;  // autotuned product configurations
+  int32_t host_status = 0;         // deferred status raised by host-driven loops
+  int32_t host_ir_iterations = 0;  // iterations of the last refined solve
 };
 
 struct hexla_plan {

@@ -24,27 +24,52 @@ namespace k {
 
 namespace {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef float accv __attribute__((ext_vector_type(4)));
+typedef accv accv_t;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+
+// Element type of the terms: bf16 (split products) or fp16 (one term: the
+// half-precision trailing updates of the low-precision LU).
+template <typename E>
+struct Mfma16;
+template <>
+struct Mfma16<__bf16> {
+  typedef bf16x8 v8;
+  typedef bf16x4 v4;
+  static __device__ __forceinline__ accv_t mma(v8 a, v8 b, accv_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma16<_Float16> {
+  typedef f16x8 v8;
+  typedef f16x4 v4;
+  static __device__ __forceinline__ accv_t mma(v8 a, v8 b, accv_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
 
 constexpr int BM = 128, BN = 128, BK = 32;
 constexpr int LDK = BK + 8;  // bf16 row stride in LDS (80 bytes: conflict-free 16-byte reads)
 
-template <int TERMS>
-__device__ __forceinline__ void split_terms(float x, __bf16 (&t)[TERMS]) {
+template <int TERMS, typename E = __bf16>
+__device__ __forceinline__ void split_terms(float x, E (&t)[TERMS]) {
   float rest = x;
 #pragma unroll
   for (int q = 0; q < TERMS; ++q) {
-    const __bf16 h = static_cast<__bf16>(rest);  // round to nearest even
+    const E h = static_cast<E>(rest);  // round to nearest even
     t[q] = h;
     rest = rest - static_cast<float>(h);
   }
 }
 
-template <bool TA, bool TB, int TERMS>
+template <bool TA, bool TB, int TERMS, typename E>
 struct SplitTile {
+  typedef typename Mfma16<E>::v4 v4;
   static constexpr int kThreads = 256;
   static constexpr int A_ELEMS = BM * LDK;  // per term
   static constexpr int B_ELEMS = BN * LDK;
@@ -104,22 +129,22 @@ struct SplitTile {
   }
 
   // Split in registers and store the BF16 terms as [row][k].
-  static __device__ __forceinline__ void store(__bf16* sa, __bf16* sb, const f4 (&ra)[LV],
+  static __device__ __forceinline__ void store(E* sa, E* sb, const f4 (&ra)[LV],
                                                const f4 (&rb)[LV]) {
 #pragma unroll
     for (int r = 0; r < LV; ++r) {
       const int e = threadIdx.x + kThreads * r;
-      __bf16 t[4][TERMS];
+      E t[4][TERMS];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) split_terms<TERMS>(ra[r][q], t[q]);
+      for (int q = 0; q < 4; ++q) split_terms<TERMS, E>(ra[r][q], t[q]);
       if (TA) {
         const int row = e / (BK / 4), kk = (e % (BK / 4)) * 4;
 #pragma unroll
         for (int s = 0; s < TERMS; ++s) {
-          bf16x4 v;
+          v4 v;
 #pragma unroll
           for (int q = 0; q < 4; ++q) v[q] = t[q][s];
-          *reinterpret_cast<bf16x4*>(sa + s * A_ELEMS + row * LDK + kk) = v;
+          *reinterpret_cast<v4*>(sa + s * A_ELEMS + row * LDK + kk) = v;
         }
       } else {
         const int kk = e / (BM / 4), row = (e % (BM / 4)) * 4;
@@ -132,17 +157,17 @@ struct SplitTile {
 #pragma unroll
     for (int r = 0; r < LV; ++r) {
       const int e = threadIdx.x + kThreads * r;
-      __bf16 t[4][TERMS];
+      E t[4][TERMS];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) split_terms<TERMS>(rb[r][q], t[q]);
+      for (int q = 0; q < 4; ++q) split_terms<TERMS, E>(rb[r][q], t[q]);
       if (!TB) {
         const int col = e / (BK / 4), kk = (e % (BK / 4)) * 4;
 #pragma unroll
         for (int s = 0; s < TERMS; ++s) {
-          bf16x4 v;
+          v4 v;
 #pragma unroll
           for (int q = 0; q < 4; ++q) v[q] = t[q][s];
-          *reinterpret_cast<bf16x4*>(sb + s * B_ELEMS + col * LDK + kk) = v;
+          *reinterpret_cast<v4*>(sb + s * B_ELEMS + col * LDK + kk) = v;
         }
       } else {
         const int kk = e / (BN / 4), col = (e % (BN / 4)) * 4;
@@ -155,10 +180,12 @@ struct SplitTile {
   }
 };
 
-template <bool TA, bool TB, int TERMS>
+template <bool TA, bool TB, int TERMS, typename E>
 __global__ __launch_bounds__(256) void gemm_split_kernel(GemmArgs g, int vec) {
-  using G = SplitTile<TA, TB, TERMS>;
-  __shared__ __attribute__((aligned(16))) __bf16 smem[2 * G::STAGE];
+  using G = SplitTile<TA, TB, TERMS, E>;
+  using M = Mfma16<E>;
+  typedef typename M::v8 v8;
+  __shared__ __attribute__((aligned(16))) E smem[2 * G::STAGE];
   int tm, tn;
   if (g.mode == 1) {
     tri_tile(int(blockIdx.x), tm, tn);
@@ -189,21 +216,21 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(GemmArgs g, int vec) {
   }
   __syncthreads();
   for (int64_t t = 0; t < nk; ++t) {
-    __bf16* cur = smem + (t & 1) * G::STAGE;
-    __bf16* nxt = smem + ((t + 1) & 1) * G::STAGE;
+    E* cur = smem + (t & 1) * G::STAGE;
+    E* nxt = smem + ((t + 1) & 1) * G::STAGE;
     const bool more = t + 1 < nk;
     if (more) G::load(g, m0, n0, kb + (t + 1) * BK, ke, vec != 0, ra, rb);
-    const __bf16* sa = cur;
-    const __bf16* sb = cur + TERMS * G::A_ELEMS;
-    bf16x8 a[TERMS][4], b[TERMS][4];
+    const E* sa = cur;
+    const E* sb = cur + TERMS * G::A_ELEMS;
+    v8 a[TERMS][4], b[TERMS][4];
 #pragma unroll
     for (int s = 0; s < TERMS; ++s)
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
-        a[s][f] = *reinterpret_cast<const bf16x8*>(sa + s * G::A_ELEMS +
-                                                   (wm * 64 + f * 16 + l16) * LDK + grp * 8);
-        b[s][f] = *reinterpret_cast<const bf16x8*>(sb + s * G::B_ELEMS +
-                                                   (wn * 64 + f * 16 + l16) * LDK + grp * 8);
+        a[s][f] = *reinterpret_cast<const v8*>(sa + s * G::A_ELEMS +
+                                               (wm * 64 + f * 16 + l16) * LDK + grp * 8);
+        b[s][f] = *reinterpret_cast<const v8*>(sb + s * G::B_ELEMS +
+                                               (wn * 64 + f * 16 + l16) * LDK + grp * 8);
       }
 #pragma unroll
     for (int fm = 0; fm < 4; ++fm)
@@ -211,13 +238,15 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(GemmArgs g, int vec) {
       for (int fn = 0; fn < 4; ++fn) {
         // small terms first
         if (TERMS == 3) {
-          acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][fm], b[0][fn], acc[fm][fn], 0, 0, 0);
-          acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][fm], b[2][fn], acc[fm][fn], 0, 0, 0);
-          acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][fm], b[1][fn], acc[fm][fn], 0, 0, 0);
+          acc[fm][fn] = M::mma(a[2 % TERMS][fm], b[0][fn], acc[fm][fn]);
+          acc[fm][fn] = M::mma(a[0][fm], b[2 % TERMS][fn], acc[fm][fn]);
+          acc[fm][fn] = M::mma(a[1 % TERMS][fm], b[1 % TERMS][fn], acc[fm][fn]);
         }
-        acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][fm], b[0][fn], acc[fm][fn], 0, 0, 0);
-        acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][fm], b[1][fn], acc[fm][fn], 0, 0, 0);
-        acc[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][fm], b[0][fn], acc[fm][fn], 0, 0, 0);
+        if (TERMS >= 2) {
+          acc[fm][fn] = M::mma(a[1 % TERMS][fm], b[0][fn], acc[fm][fn]);
+          acc[fm][fn] = M::mma(a[0][fm], b[1 % TERMS][fn], acc[fm][fn]);
+        }
+        acc[fm][fn] = M::mma(a[0][fm], b[0][fn], acc[fm][fn]);
       }
     if (more) G::store(nxt, nxt + TERMS * G::A_ELEMS, ra, rb);
     __syncthreads();
@@ -257,10 +286,10 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(GemmArgs g, int vec) {
 
 typedef void (*SplitFn)(GemmArgs, int);
 
-template <int TERMS>
+template <int TERMS, typename E>
 SplitFn pick(bool ta, bool tb) {
-  if (ta) return tb ? gemm_split_kernel<true, true, TERMS> : gemm_split_kernel<true, false, TERMS>;
-  return tb ? gemm_split_kernel<false, true, TERMS> : gemm_split_kernel<false, false, TERMS>;
+  if (ta) return tb ? gemm_split_kernel<true, true, TERMS, E> : gemm_split_kernel<true, false, TERMS, E>;
+  return tb ? gemm_split_kernel<false, true, TERMS, E> : gemm_split_kernel<false, false, TERMS, E>;
 }
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -270,7 +299,7 @@ __global__ void split_bf16_kernel(const float* __restrict__ x, int64_t n, uint16
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
     __bf16 t[3];
-    split_terms<3>(x[i], t);
+    split_terms<3, __bf16>(x[i], t);
     hi[i] = __builtin_bit_cast(uint16_t, t[0]);
     mid[i] = __builtin_bit_cast(uint16_t, t[1]);
     if (terms == 3) lo[i] = __builtin_bit_cast(uint16_t, t[2]);
@@ -316,7 +345,9 @@ hipError_t gemm_split_launch(int dtype, int precision, int mode, int ta, int tb,
                   (reinterpret_cast<uintptr_t>(B) % 16 == 0);
   const int64_t blocks = mode == 1 ? int64_t(g.tiles_n) * (g.tiles_n + 1) / 2
                                    : int64_t(g.tiles_m) * g.tiles_n;
-  SplitFn fn = precision == GEMM_BF16X6 ? pick<3>(ta != 0, tb != 0) : pick<2>(ta != 0, tb != 0);
+  SplitFn fn = precision == GEMM_BF16X6 ? pick<3, __bf16>(ta != 0, tb != 0)
+              : precision == GEMM_F16  ? pick<1, _Float16>(ta != 0, tb != 0)
+                                       : pick<2, __bf16>(ta != 0, tb != 0);
   hipLaunchKernelGGL(fn, dim3(unsigned(blocks), unsigned(g.split)), dim3(256), 0, s, g, vec);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || g.split <= 1) return e;

@@ -380,7 +380,7 @@ __global__ void iota_kernel(int32_t* p, int64_t n) {
 // C (m x ncol) -= A (m x kk) * B (kk x ncol), through GEMM or GEMV.
 template <typename T>
 hipError_t update(int dtype, int64_t m, int64_t ncol, int64_t kk, const T* A, int64_t lda,
-                  const T* B, int64_t ldb, T* C, int64_t ldc, hipStream_t s) {
+                  const T* B, int64_t ldb, T* C, int64_t ldc, hipStream_t s, int prec = 0) {
   if (m <= 0 || ncol <= 0 || kk <= 0) return hipSuccess;
   if (ncol == 1) {
     EwProgram epi{};
@@ -397,15 +397,15 @@ hipError_t update(int dtype, int64_t m, int64_t ncol, int64_t kk, const T* A, in
     epi.leaf[0].sj = ldc;
     return gemv_launch(dtype, 0, m, kk, -1.0, A, lda, B, 1, C, 1, &epi, s);
   }
-  GemmConfig cfg = gemm_choose(dtype, GEMM_PLAIN, 0, m, ncol, kk);
+  GemmConfig cfg = gemm_choose(dtype, prec, 0, m, ncol, kk);
   cfg.split = 1;
-  return gemm_launch(dtype, GEMM_PLAIN, 0, 0, 0, m, ncol, kk, -1.0, A, lda, B, ldb, 1.0, C, ldc,
+  return gemm_launch(dtype, prec, 0, 0, 0, m, ncol, kk, -1.0, A, lda, B, ldb, 1.0, C, ldc,
                      nullptr, cfg, s);
 }
 
 template <typename T>
 hipError_t factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* rowid, void* work,
-                        int32_t* status, hipStream_t s) {
+                        int32_t* status, hipStream_t s, int prec) {
   if (n == 0) return hipSuccess;
   const int64_t np = cdiv(n, kNB);
   LuWork w = carve(work, n);
@@ -434,7 +434,7 @@ hipError_t factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* rowid,
                          0, s, a11, lda, a12, lda, jb, right);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       e = update<T>(dtype, n - k - jb, right, jb, A + (k + jb) + k * lda, lda, a12, lda,
-                    A + (k + jb) + (k + jb) * lda, lda, s);
+                    A + (k + jb) + (k + jb) * lda, lda, s, prec);
       if (e != hipSuccess) return e;
     }
   }
@@ -487,9 +487,11 @@ size_t lu_workspace_bytes(int, int64_t n) {
 }
 
 hipError_t lu_factor_launch(int dtype, int64_t n, void* A, int64_t lda, int32_t* rowid,
-                            void* work, int32_t* status, hipStream_t s) {
-  return dtype == 0 ? factor_typed<double>(0, n, static_cast<double*>(A), lda, rowid, work, status, s)
-                    : factor_typed<float>(1, n, static_cast<float*>(A), lda, rowid, work, status, s);
+                            void* work, int32_t* status, hipStream_t s, int update_precision) {
+  return dtype == 0
+             ? factor_typed<double>(0, n, static_cast<double*>(A), lda, rowid, work, status, s, 0)
+             : factor_typed<float>(1, n, static_cast<float*>(A), lda, rowid, work, status, s,
+                                   update_precision);
 }
 
 hipError_t lu_solve_launch(int dtype, int64_t n, int64_t nrhs, const void* LU, int64_t lda,

@@ -74,7 +74,7 @@ struct GemmConfig {
   int tile;   // index into the tile table of the kernel family
   int split;  // K splits
 };
-enum GemmPrecision { GEMM_PLAIN = 0, GEMM_BF16X3 = 1, GEMM_BF16X6 = 2 };
+enum GemmPrecision { GEMM_PLAIN = 0, GEMM_BF16X3 = 1, GEMM_BF16X6 = 2, GEMM_F16 = 3 };
 
 GemmConfig gemm_choose(int dtype, int precision, int mode, int64_t m, int64_t n, int64_t k);
 // tile table access for the autotuner
@@ -104,13 +104,28 @@ hipError_t split_bf16_launch(const float* x, int64_t n, uint16_t* t0, uint16_t* 
 // A = P^T L U. rowid (n ints) receives the original row held at each final
 // position (row i of L U is row rowid[i] of A). status[0] gets HEXLA_E_SINGULAR
 // and status[2..3] the first zero-pivot column on an exact zero pivot.
+// update_precision: GemmPrecision of the trailing updates (FP32 storage only
+// for the non-plain values).
 size_t lu_workspace_bytes(int dtype, int64_t n);
 hipError_t lu_factor_launch(int dtype, int64_t n, void* A, int64_t lda, int32_t* rowid,
-                            void* work, int32_t* status, hipStream_t s);
+                            void* work, int32_t* status, hipStream_t s, int update_precision = 0);
 // X (n x nrhs, ldx) <- U^{-1} L^{-1} B[rowid], B with ldb. X may not alias B.
 hipError_t lu_solve_launch(int dtype, int64_t n, int64_t nrhs, const void* LU, int64_t lda,
                            const int32_t* rowid, const void* B, int64_t ldb, void* X,
                            int64_t ldx, hipStream_t s);
+
+// ------------------------------------------------------ mixed precision
+// b(i, j) = a(i, j) converted between types (0 FP64, 1 FP32); a(i, j) at
+// a[i*asi + j*asj].
+hipError_t cast_launch(int from, int to, int64_t rows, int64_t cols, const void* a, int64_t asi,
+                       int64_t asj, void* b, int64_t ldb, hipStream_t s);
+// *out = max_i sum_j |a_ij| (FP64), scratch holds norm_scratch_elems(rows) doubles.
+size_t norm_scratch_elems(int64_t rows);
+hipError_t norm_inf_launch(int dtype, int64_t rows, int64_t cols, const void* a, int64_t lda,
+                           double* scratch, double* out, hipStream_t s);
+// x(i, j) += d(i, j), x FP64, d of type dtype_d.
+hipError_t add_mixed_launch(int dtype_d, int64_t rows, int64_t cols, double* x, int64_t ldx,
+                            const void* d, int64_t ldd, hipStream_t s);
 
 // ------------------------------------------------------------------- utils
 hipError_t fill_i32_launch(int32_t* p, int64_t count, int32_t value, hipStream_t s);

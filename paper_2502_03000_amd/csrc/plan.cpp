@@ -872,7 +872,50 @@ class Planner {
   }
 
   // ------------------------------------------------------------------ solves
+  // Low-precision LU (FP32 storage; FP32, FP16-MFMA or split-BF16 trailing
+  // updates) and FP64 iterative refinement of an FP64 system.
+  void refined_solve(const View& s, const View& b, const View& x) {
+    const int64_t n = s.rows, r = b.cols;
+    if (b.trans || x.trans) {
+      fail(HEXLA_E_UNSUPPORTED, "internal: transposed solve operand");
+      return;
+    }
+    Step q;
+    q.kind = StepKind::IrSolve;
+    q.dtype = dtype_;
+    q.A = s;
+    q.B = b;
+    q.C = x;
+    q.n = n;
+    q.nrhs = r;
+    IrWork& w = q.ir;
+    w.s_low = work(n * n * 4);
+    w.rowid = work(n * 4);
+    w.luwork = work(int64_t(k::lu_workspace_bytes(HEXLA_F32, n)));
+    w.r64 = work(n * r * 8);
+    w.r_low = work(n * r * 4);
+    w.d_low = work(n * r * 4);
+    w.scratch = work(int64_t(k::norm_scratch_elems(n)) * 8);
+    w.norms = work(4 * 8);
+    w.res_cfg = k::gemm_choose(HEXLA_F64, 0, 0, n, r, n);
+    const size_t pb = k::gemm_partial_bytes(HEXLA_F64, w.res_cfg, n, r);
+    if (pb) w.partial = work(int64_t(pb));
+    w.update_precision = o_.solve_precision == HEXLA_SOLVE_IR_FP16   ? k::GEMM_F16
+                         : o_.solve_precision == HEXLA_SOLVE_IR_BF16X3 ? k::GEMM_BF16X3
+                                                                       : k::GEMM_PLAIN;
+    w.max_iter = o_.ir_max_iter;
+    w.tol_scale = o_.ir_tol_scale;
+    q.name = o_.solve_precision == HEXLA_SOLVE_IR_FP16     ? "lu_solve_ir_fp16"
+             : o_.solve_precision == HEXLA_SOLVE_IR_BF16X3 ? "lu_solve_ir_bf16x3"
+                                                           : "lu_solve_ir_fp32";
+    // LU + first solve; each refinement step adds a residual and a solve
+    q.flops = 2.0 / 3.0 * double(n) * n * n + 2.0 * double(n) * n * r;
+    q.bytes = double(n) * n * (8 + 2 * 4) + double(n) * r * 8 * 2;
+    steps_.push_back(q);
+  }
+
   void solve(const View& s, const View& b, const View& x) {
+    if (dtype_ == HEXLA_F64 && o_.solve_precision != HEXLA_SOLVE_PLAIN) return refined_solve(s, b, x);
     const int64_t n = s.rows, r = b.cols;
     View lu = temp(n, n);
     EwHost copy;
@@ -1018,7 +1061,7 @@ hexla_status hexla_plan_create(hexla_ctx* ctx, hexla_node root, const hexla_plan
   if (opts) o = *opts;
   if (o.planner < 0 || o.planner > HEXLA_PLANNER_LEARNED || o.product_precision < 0 ||
       o.product_precision > HEXLA_PRODUCT_BF16X6 || o.solve_precision < 0 ||
-      o.solve_precision > HEXLA_SOLVE_IR_FP16)
+      o.solve_precision > HEXLA_SOLVE_IR_BF16X3)
     return set_err(ctx, HEXLA_E_INVALID_ARG, "plan: bad options");
   if (o.ir_max_iter <= 0) o.ir_max_iter = 30;
   hexla_plan* p = new hexla_plan();

@@ -150,6 +150,9 @@ hexla_status hexla_plan_capture(hexla_plan* plan, void* out, int64_t ld_out, voi
   hexla_status st = check_buffers(plan, out, ld_out, workspace, workspace_bytes);
   if (st != HEXLA_OK) return st;
   hexla_ctx* ctx = plan->ctx;
+  for (const Step& s : plan->steps)
+    if (s.kind == StepKind::IrSolve)
+      return set_err(ctx, HEXLA_E_UNSUPPORTED, "capture: a refined solve reads status on the host");
   hipError_t e = hipSetDevice(ctx->device);
   hipStream_t cs = nullptr;  // capture needs a stream other than the null stream
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);

@@ -29,7 +29,7 @@ OP_TRANS, OP_NEG, OP_EXP, OP_INV = 1, 2, 3, 4
 OP_TIMES, OP_PLUS, OP_MINUS, OP_SCHUR, OP_DIV, OP_SOLVE = 16, 17, 18, 19, 20, 21
 PLANNERS = {"dp": 0, "greedy": 1, "naive": 2, "learned": 3}
 PRODUCT_PRECISION = {"plain": 0, "bf16x3": 1, "bf16x6": 2}
-SOLVE_PRECISION = {"plain": 0, "ir_fp32": 1, "ir_fp16": 2}
+SOLVE_PRECISION = {"plain": 0, "ir_fp32": 1, "ir_fp16": 2, "ir_bf16x3": 3}
 
 
 class HexlaError(RuntimeError):

@@ -81,3 +81,43 @@ def test_split_gemm_against_oracle(ctx, ta, tb, mnk):
     got6 = host(ctx.evaluate(e, product_precision="bf16x6"))
     assert rel(got3, ref) <= 2e-5
     assert rel(got6, ref) <= 2e-6
+
+
+# ------------------------------------------------ mixed-precision solves
+
+@pytest.mark.parametrize("form,cond", [("ir_fp32", 1e3), ("ir_bf16x3", 1e3), ("ir_fp16", 1e2)])
+@pytest.mark.parametrize("n", [200, 513])
+def test_refined_solve_reaches_fp64_accuracy(ctx, form, cond, n):
+    s, u, sv, v = inputs.svd_matrix(60 + n, n, n, cond)
+    b = inputs.normal(inputs.rng(61 + n), n, 3)
+    ref = oracle.evaluate("solve(S,B)", {"S": s, "B": b})
+    es, eb = ctx.leaf(dev(s)), ctx.leaf(dev(b))
+    p = ctx.plan(hx.solve(es, eb), solve_precision=form)
+    assert p.describe()["steps"][-1]["kernel"] == "lu_solve_" + form
+    out = p.output()
+    p.execute(out, p.workspace())
+    rep = ctx.sync()
+    assert rep.status == hx.OK
+    assert 1 <= rep.ir_iterations <= 30
+    assert rel(host(out), ref) <= 1e-12
+    # the inverse rewrite takes the same refined path
+    got = host(ctx.evaluate(hx.inv(es) @ eb, solve_precision=form))
+    assert rel(got, ref) <= 1e-12
+
+
+def test_refined_solve_reports_cap_and_singular(ctx):
+    s, _, _, _ = inputs.svd_matrix(70, 100, 100, 1e4)
+    b = inputs.normal(inputs.rng(71), 100, 1)
+    es, eb = ctx.leaf(dev(s)), ctx.leaf(dev(b))
+    with pytest.raises(hx.HexlaError) as ei:
+        ctx.evaluate(hx.solve(es, eb), solve_precision="ir_fp32", ir_max_iter=0)
+    assert ei.value.status == hx.E_NO_CONVERGENCE
+    z = np.eye(8)
+    z[:, 5] = 0.0
+    with pytest.raises(hx.HexlaError) as ei:
+        ctx.evaluate(hx.solve(ctx.leaf(dev(z)), ctx.leaf(dev(np.ones((8, 1))))), solve_precision="ir_fp32")
+    assert ei.value.status == hx.E_SINGULAR
+    p = ctx.plan(hx.solve(es, eb), solve_precision="ir_fp32")
+    with pytest.raises(hx.HexlaError) as ei:
+        p.capture(p.output(), p.workspace())
+    assert ei.value.status == hx.E_UNSUPPORTED
