@@ -135,10 +135,12 @@ typedef enum hexla_product_precision {
  * copy (partial pivoting on the FP32 values), the residual R = B - S X and the
  * update X += D in FP64, with D solved on the low-precision factors, until
  * ||R||inf <= ir_tol_scale * 2^-53 * ||S||inf * ||X||inf (ir_tol_scale 0:
- * sqrt(n)), the correction stagnates (||D|| > 0.5 ||D_prev||) or ir_max_iter
- * is reached (deferred HEXLA_E_NO_CONVERGENCE). The refinement loop reads a
+ * 1), the correction stagnates (||D|| > 0.5 ||D_prev||) or ir_max_iter is
+ * reached (deferred HEXLA_E_NO_CONVERGENCE). The refinement loop reads a
  * small status block after every step, so hexla_execute of such a plan
- * returns only when the solve is done and the plan cannot be captured. */
+ * returns only when the solve is done and the plan cannot be captured.
+ * A correction larger than the previous one is dropped (divergence); one
+ * larger than half the previous one is applied and ends the loop. */
 typedef enum hexla_solve_precision {
   HEXLA_SOLVE_PLAIN = 0,     /* LU and substitution in the storage type          */
   HEXLA_SOLVE_IR_FP32 = 1,   /* FP32 LU, FP32 trailing updates                   */
@@ -153,9 +155,9 @@ typedef struct hexla_plan_opts {
   int32_t fuse;               /* 1: fuse element-wise subtrees (default); 0: one
                                  kernel and one temporary per operation          */
   int32_t syrk;               /* 1: X^T X / X X^T on one leaf -> SYRK (default)  */
-  int32_t ir_max_iter;        /* refinement cap (default 30)                      */
+  int32_t ir_max_iter;        /* refinement cap (default 30; 0: none; < 0: 30)   */
   double ir_tol_scale;        /* stop when ||R||inf <= scale*2^-53*||S||inf*||X||inf;
-                                 0 = sqrt(n)                                     */
+                                 0 = 1                                           */
   int32_t codegen;            /* 1: element-wise passes run as kernels generated
                                  for the expression (hipRTC, default); 0: the
                                  program interpreter kernel                     */

@@ -8,10 +8,11 @@ choice here is a reading):
   X_0 = solve_low(B)
   repeat:
       R = B - S X                     (float64)
-      stop if ||R||_inf <= sqrt(n) * 2^-53 * ||S||_inf * ||X||_inf
+      stop if ||R||_inf <= 2^-53 * ||S||_inf * ||X||_inf
       D = solve_low(R)
-      stop (stagnated) if ||D||_inf > 0.5 * ||D_prev||_inf
+      stop (diverging) if ||D||_inf > ||D_prev||_inf, keeping X
       X = X + D                       (float64)
+      stop (stagnated) if ||D||_inf > 0.5 * ||D_prev||_inf
   until the iteration cap.
 
 ``solve_low`` solves with the low-precision factors; the oracle's default
@@ -47,7 +48,7 @@ def refine(s, b, solve_low=None, cap: int = 30) -> dict:
     if solve_low is None:
         solve_low = low_precision_solver(s)
     n = s.shape[0]
-    tol = np.sqrt(n) * 2.0 ** -53 * norm_inf(s)
+    tol = 2.0 ** -53 * norm_inf(s)
     x = solve_low(b)
     history = []
     d_prev = None
@@ -63,10 +64,13 @@ def refine(s, b, solve_low=None, cap: int = 30) -> dict:
             break
         d = solve_low(r)
         dn = norm_inf(d)
+        if d_prev is not None and dn > d_prev:
+            status = "diverging"
+            break
+        x = x + d
         if d_prev is not None and dn > 0.5 * d_prev:
             status = "stagnated"
             break
-        x = x + d
         d_prev = dn
     return {"x": x, "iterations": len(history) - 1, "residuals": history,
             "status": status}

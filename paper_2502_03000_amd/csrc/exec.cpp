@@ -163,7 +163,7 @@ hexla_status run_ir_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipStrea
   if (e == hipSuccess) e = k::lu_solve_launch(1, n, r, s_low, ldn, rowid, r_low, ldn, d_low, ldn, st);
   if (e == hipSuccess) e = k::cast_launch(1, 0, n, r, d_low, 1, ldn, addr(X.ref, b), X.ld, st);
   if (e != hipSuccess) return fail(e, "ir: first solve");
-  const double tol = (w.tol_scale > 0 ? w.tol_scale : std::sqrt(double(n))) * std::ldexp(1.0, -53);
+  const double tol = (w.tol_scale > 0 ? w.tol_scale : 1.0) * std::ldexp(1.0, -53);
   double h[4] = {0, 0, 0, 0};
   double d_prev = -1.0;
   int it = 0;
@@ -191,9 +191,14 @@ hexla_status run_ir_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipStrea
     if (e == hipSuccess) e = hipMemcpyAsync(h + 3, norms + 3, sizeof(double), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(e, "ir: correction");
-    if (d_prev >= 0.0 && h[3] > 0.5 * d_prev) break;  // stagnated: keep X
+    // a growing correction is dropped; a slowly shrinking one is the last
+    if (d_prev >= 0.0 && h[3] > d_prev) break;
     e = k::add_mixed_launch(1, n, r, static_cast<double*>(addr(X.ref, b)), X.ld, d_low, ldn, st);
     if (e != hipSuccess) return fail(e, "ir: update");
+    if (d_prev >= 0.0 && h[3] > 0.5 * d_prev) {
+      ++it;
+      break;
+    }
     d_prev = h[3];
   }
   ctx->host_ir_iterations = it;

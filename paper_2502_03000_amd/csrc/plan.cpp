@@ -1063,7 +1063,7 @@ hexla_status hexla_plan_create(hexla_ctx* ctx, hexla_node root, const hexla_plan
       o.product_precision > HEXLA_PRODUCT_BF16X6 || o.solve_precision < 0 ||
       o.solve_precision > HEXLA_SOLVE_IR_BF16X3)
     return set_err(ctx, HEXLA_E_INVALID_ARG, "plan: bad options");
-  if (o.ir_max_iter <= 0) o.ir_max_iter = 30;
+  if (o.ir_max_iter < 0) o.ir_max_iter = 30;  // 0: no refinement step
   hexla_plan* p = new hexla_plan();
   p->ctx = ctx;
   p->opts = o;
