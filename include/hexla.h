@@ -252,6 +252,86 @@ hexla_status hexla_plan_capture(hexla_plan* plan, void* out, int64_t ld_out, voi
                                 size_t workspace_bytes);
 hexla_status hexla_plan_replay(hexla_plan* plan);
 
+/* ---------------------------------------------------------------- batches
+ * Many small instances of one vector expression, evaluated by one persistent
+ * launch: each workgroup takes instances, largest first, from a queue and
+ * runs the whole expression on one instance with its intermediate vectors in
+ * on-chip memory. This is the same delayed evaluation (Sec. II) applied to a
+ * batch: one plan, made once from a template expression, evaluates every
+ * instance.
+ *
+ * The template is an expression over leaves of two shapes, t x t (matrices)
+ * and t x 1 (vectors) for one t >= 2 (the template leaves' pointers are not
+ * read), whose result is t x 1. Instance i binds every template leaf to an
+ * n_i x n_i or n_i x 1 matrix, 1 <= n_i <= 512 (n_i == 0: nothing is written).
+ * Supported forms:
+ *   - products whose last factor is vector-valued; the other factors are
+ *     matrix leaves, trans(leaf), inv(leaf) and scalars. They run right to
+ *     left as matrix-vector products (with square factors that is the
+ *     order the chain-cost minimisation of Sec. II picks: any other
+ *     bracketing multiplies two n x n matrices);
+ *   - solve(leaf, v) and inv(leaf) * v: LU with partial pivoting of the
+ *     instance's matrix (Sec. I, Sec. II), without forming the inverse;
+ *   - element-wise + - % / exp, unary minus and scalars over vectors, fused
+ *     into one pass (Sec. II).
+ * Other forms give HEXLA_E_UNSUPPORTED at creation. */
+typedef struct hexla_batch hexla_batch;
+
+typedef struct hexla_batch_info {
+  int64_t count;              /* instances                                       */
+  int64_t max_n;              /* largest instance size                          */
+  int32_t dtype;              /* hexla_dtype                                     */
+  int32_t n_ops;              /* operations of the per-instance program          */
+  int32_t panel;              /* LU panel width of the chosen configuration      */
+  int32_t threads;            /* threads per workgroup                           */
+  int32_t grid;               /* workgroups of the persistent launch             */
+  int32_t reserved;
+  uint64_t workspace_bytes;   /* workspace hexla_batch_execute needs             */
+  double flops;               /* algorithmic flops of all instances              */
+  double bytes;               /* algorithmic HBM bytes (each operand once)       */
+} hexla_batch_info;
+
+/* Creates a batch plan. `leaves` lists the template's leaf nodes (n_leaves <=
+ * 8); leaf_ptrs[i * n_leaves + l] is instance i's device pointer for leaf l,
+ * with leading dimension lds[i * n_leaves + l] (lds NULL: n_i for every
+ * leaf); outs[i] receives instance i's n_i x 1 result; sizes[i] = n_i. All
+ * arrays are host memory, read during this call only; the device pointers
+ * are borrowed and must stay valid while the plan is used. Outputs may not
+ * overlap each other or any input. Host only apart from the plan's pinned
+ * host copy of the instance table. opts: planner and precision fields are
+ * ignored. Errors: HEXLA_E_INVALID_ARG (null pointers, ld < n_i, overlapping
+ * outputs, a template leaf listed twice or missing), HEXLA_E_DIM (template
+ * shapes), HEXLA_E_UNSUPPORTED (form or n_i > 512), HEXLA_E_DTYPE. */
+hexla_status hexla_batch_create(hexla_ctx* ctx, hexla_node root, const hexla_node* leaves,
+                                int32_t n_leaves, int64_t count, const int64_t* sizes,
+                                const void* const* leaf_ptrs, const int64_t* lds,
+                                void* const* outs, const hexla_plan_opts* opts,
+                                hexla_batch** out);
+hexla_status hexla_batch_get_info(const hexla_batch* batch, hexla_batch_info* out);
+/* JSON description: the per-instance program and the launch configuration. */
+hexla_status hexla_batch_describe(const hexla_batch* batch, char* buf, size_t cap,
+                                  size_t* needed);
+/* Evaluates every instance on the context's stream, asynchronously: copies
+ * the instance table into the workspace (caller-owned device memory of at
+ * least workspace_bytes, 256-byte aligned), then one persistent launch. An
+ * exact zero pivot is deferred to hexla_sync as HEXLA_E_SINGULAR, with the
+ * index of a singular instance in singular_column. Errors: HEXLA_E_INVALID_ARG
+ * (short workspace), HEXLA_E_UNSUPPORTED (dry-run context), HEXLA_E_DEVICE. */
+hexla_status hexla_batch_execute(hexla_batch* batch, void* workspace, size_t workspace_bytes);
+/* Times every launch configuration (LU panel width, threads per workgroup,
+ * workgroups) on this workspace (reps timed launches each, <= 0: 3) and keeps
+ * the fastest. Synchronous. Errors: as hexla_batch_execute. */
+hexla_status hexla_batch_autotune(hexla_batch* batch, void* workspace, size_t workspace_bytes,
+                                  int32_t reps);
+/* Copies the instance table into the workspace, waits for it, then records
+ * the launches into a HIP graph owned by the batch (replacing any earlier
+ * capture); hexla_batch_replay launches the graph on the context's stream.
+ * Between capture and the last replay the workspace keeps the instance table
+ * and must not be written by the caller. Errors: as hexla_batch_execute. */
+hexla_status hexla_batch_capture(hexla_batch* batch, void* workspace, size_t workspace_bytes);
+hexla_status hexla_batch_replay(hexla_batch* batch);
+hexla_status hexla_batch_destroy(hexla_batch* batch);
+
 /* Library version string (static storage). */
 const char* hexla_version(void);
 

@@ -127,6 +127,63 @@ hipError_t norm_inf_launch(int dtype, int64_t rows, int64_t cols, const void* a,
 hipError_t add_mixed_launch(int dtype_d, int64_t rows, int64_t cols, double* x, int64_t ldx,
                             const void* d, int64_t ldd, hipStream_t s);
 
+// ---------------------------------------------------------------- batches
+// A per-instance program over vector slots held in LDS. Instances are
+// square (n x n matrices, n x 1 vectors), n <= kBMaxN.
+constexpr int kBMaxN = 512;
+constexpr int kBMaxSlots = 6;
+constexpr int kBMaxOps = 16;
+constexpr int kBMaxLeaf = 8;
+constexpr int kBMaxEw = 48;
+constexpr int kBMaxConst = 8;
+constexpr uint8_t kBSlotBit = 0x80;  // element-wise operand names a slot
+constexpr uint8_t kBOut = 0xff;      // destination: the instance's output
+
+enum BOpKind : uint8_t {
+  B_LOAD = 0,   // slot[dst] = vector leaf
+  B_GEMV = 1,   // slot[dst] = alpha * op(matrix leaf) slot[src]; dst != src
+  B_SOLVE = 2,  // slot[dst] = (matrix leaf)^-1 slot[src] (LU with partial pivoting)
+  B_EW = 3      // slot[dst] (or output) = element-wise program ew[begin, end)
+};
+
+struct BOp {
+  uint8_t kind, dst, src, leaf, trans, ew_begin, ew_end, pad;
+  double alpha;
+};
+
+struct BProgram {
+  int32_t n_ops;
+  int32_t out_slot;  // slot copied to the output at the end, or kBOut
+  BOp ops[kBMaxOps];
+  uint8_t ew_op[kBMaxEw];   // EwOp codes (EW_EXTRA and EW_IDENT excluded)
+  uint8_t ew_arg[kBMaxEw];  // leaf index, kBSlotBit | slot, or constant index
+  double cst[kBMaxConst];
+};
+
+struct BInst {
+  const void* leaf[kBMaxLeaf];
+  int64_t ld[kBMaxLeaf];
+  void* out;
+  int64_t n;
+};
+
+// Launch configurations: LU panel width x threads per workgroup.
+struct BatchConfig {
+  int variant;  // index into the variant table of the dtype
+  int grid;     // workgroups of the persistent launch
+};
+int batch_variant_count(int dtype);
+void batch_variant_shape(int dtype, int variant, int* panel, int* threads);
+BatchConfig batch_default(int dtype, int64_t count);
+// scratch elements per workgroup for instances up to max_n
+int64_t batch_scratch_stride(int64_t max_n);
+// Resets the queue counter, then runs every instance (order: instance indices,
+// largest first). status[0] <- HEXLA_E_SINGULAR and status[2] <- instance on
+// an exact zero pivot.
+hipError_t batch_launch(int dtype, const BatchConfig& cfg, const BProgram* p, const BInst* inst,
+                        const int32_t* order, int64_t count, unsigned* queue, void* scratch,
+                        int64_t scratch_stride, int32_t* status, hipStream_t s);
+
 // ------------------------------------------------------------------- utils
 hipError_t fill_i32_launch(int32_t* p, int64_t count, int32_t value, hipStream_t s);
 

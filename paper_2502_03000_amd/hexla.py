@@ -52,6 +52,13 @@ class PlanInfo(C.Structure):
                 ("bytes", C.c_double), ("chain_macs", C.c_double)]
 
 
+class BatchInfo(C.Structure):
+    _fields_ = [("count", C.c_int64), ("max_n", C.c_int64), ("dtype", C.c_int32),
+                ("n_ops", C.c_int32), ("panel", C.c_int32), ("threads", C.c_int32),
+                ("grid", C.c_int32), ("reserved", C.c_int32), ("workspace_bytes", C.c_uint64),
+                ("flops", C.c_double), ("bytes", C.c_double)]
+
+
 class Report(C.Structure):
     _fields_ = [("status", C.c_int32), ("ir_iterations", C.c_int32),
                 ("singular_column", C.c_int64)]
@@ -90,6 +97,16 @@ def _load():
         "hexla_plan_capture": [vp, vp, i64, vp, C.c_size_t],
         "hexla_plan_replay": [vp],
         "hexla_split_bf16": [vp, vp, i64, vp, vp, vp, i32],
+        "hexla_batch_create": [vp, u32, C.POINTER(u32), i32, i64, C.POINTER(i64),
+                               C.POINTER(vp), C.POINTER(i64), C.POINTER(vp),
+                               C.POINTER(PlanOpts), C.POINTER(vp)],
+        "hexla_batch_get_info": [vp, C.POINTER(BatchInfo)],
+        "hexla_batch_describe": [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)],
+        "hexla_batch_execute": [vp, vp, C.c_size_t],
+        "hexla_batch_autotune": [vp, vp, C.c_size_t, i32],
+        "hexla_batch_capture": [vp, vp, C.c_size_t],
+        "hexla_batch_replay": [vp],
+        "hexla_batch_destroy": [vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -242,6 +259,92 @@ class Plan:
         return colmajor(self.shape[0], self.shape[1], dt, device)
 
 
+class Batch:
+    """A batch plan: one template expression over many instances."""
+
+    def __init__(self, ctx, handle, keep):
+        self.ctx, self.handle, self._keep = ctx, handle, keep
+        info = BatchInfo()
+        ctx._check(lib.hexla_batch_get_info(handle, C.byref(info)))
+        self.info = info
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and lib is not None:
+            lib.hexla_batch_destroy(h)
+            self.handle = None
+
+    def refresh(self):
+        self.ctx._check(lib.hexla_batch_get_info(self.handle, C.byref(self.info)))
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self.info.workspace_bytes)
+
+    def describe(self) -> dict:
+        need = C.c_size_t(0)
+        lib.hexla_batch_describe(self.handle, None, 0, C.byref(need))
+        buf = C.create_string_buffer(need.value + 1)
+        self.ctx._check(lib.hexla_batch_describe(self.handle, buf, need.value + 1, C.byref(need)))
+        return json.loads(buf.value.decode())
+
+    def workspace(self, device="cuda"):
+        import torch
+        return torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=device)
+
+    def _ws(self, ws):
+        return _addr(ws), ws.numel() if hasattr(ws, "numel") else self.workspace_bytes
+
+    def execute(self, ws):
+        self.ctx._check(lib.hexla_batch_execute(self.handle, *self._ws(ws)))
+
+    def autotune(self, ws, reps=3):
+        self.ctx._check(lib.hexla_batch_autotune(self.handle, *self._ws(ws), reps))
+        self.refresh()
+
+    def capture(self, ws):
+        self.ctx._check(lib.hexla_batch_capture(self.handle, *self._ws(ws)))
+
+    def replay(self):
+        self.ctx._check(lib.hexla_batch_replay(self.handle))
+
+
+def pack_batch(instances, names, dtype, device="cuda", align=64):
+    """Packs per-instance host arrays (dicts name -> 2-D numpy array, n x n or
+    n x 1) into one column-major device arena, each array starting on an
+    `align`-element boundary. Returns (arena, ptrs) with ptrs an int64 array
+    [count, len(names)] of device addresses."""
+    import numpy as np
+    import torch
+    np_dt = np.float64 if dtype == torch.float64 else np.float32
+    count = len(instances)
+    offs = np.zeros((count, len(names)), dtype=np.int64)
+    total = 0
+    for i, inst in enumerate(instances):
+        for j, nm in enumerate(names):
+            offs[i, j] = total
+            total += -(-inst[nm].size // align) * align
+    host = np.zeros(max(total, 1), dtype=np_dt)
+    for i, inst in enumerate(instances):
+        for j, nm in enumerate(names):
+            a = inst[nm]
+            host[offs[i, j]:offs[i, j] + a.size] = a.ravel(order="F")
+    arena = torch.from_numpy(host).to(device)
+    ptrs = arena.data_ptr() + offs * arena.element_size()
+    return arena, ptrs
+
+
+def output_arena(sizes, dtype, device="cuda", align=64):
+    """One device arena for n_i x 1 outputs; returns (arena, ptrs, offsets)."""
+    import numpy as np
+    import torch
+    sizes = np.asarray(sizes, dtype=np.int64)
+    padded = -(-np.maximum(sizes, 1) // align) * align
+    offs = np.concatenate([[0], np.cumsum(padded)[:-1]]).astype(np.int64)
+    arena = torch.zeros(int(padded.sum()), dtype=dtype, device=device)
+    return arena, arena.data_ptr() + offs * arena.element_size(), offs
+
+
 def _addr(t):
     return t if isinstance(t, int) else t.data_ptr()
 
@@ -357,6 +460,42 @@ class Context:
         h = C.c_void_p()
         self._check(lib.hexla_plan_create(self.handle, root.node, C.byref(o), C.byref(h)))
         return Plan(self, h.value)
+
+    def template_leaf(self, t, kind, dtype) -> Expr:
+        """A leaf of a batch template: t x t ("matrix") or t x 1 ("vector").
+        Its storage (a small tensor the context keeps) is never read by a
+        batch plan."""
+        import torch
+        rows, cols = (t, t) if kind == "matrix" else (t, 1)
+        tdt = torch.float64 if dtype == F64 else torch.float32
+        dev = "cpu" if self.device < 0 else f"cuda:{self.device}"
+        buf = torch.zeros(rows * cols, dtype=tdt, device=dev)
+        self._keep.append(buf)
+        return self.leaf_raw(buf.data_ptr(), rows, cols, rows, dtype)
+
+    def batch(self, root, leaves, sizes, leaf_ptrs, outs, lds=None) -> Batch:
+        """Batch plan of template `root` over its template `leaves`:
+        sizes[i] = n_i, leaf_ptrs[i, l] = device address of instance i's leaf
+        l, outs[i] = address of its n_i x 1 output, lds[i, l] (optional)."""
+        import numpy as np
+        sizes = np.ascontiguousarray(sizes, dtype=np.int64)
+        count = sizes.shape[0]
+        ptrs = np.ascontiguousarray(leaf_ptrs, dtype=np.uint64).reshape(count, len(leaves))
+        outs = np.ascontiguousarray(outs, dtype=np.uint64).reshape(count)
+        nodes = (C.c_uint32 * len(leaves))(*[x.node for x in leaves])
+        lds_p = None
+        if lds is not None:
+            lds = np.ascontiguousarray(lds, dtype=np.int64).reshape(count, len(leaves))
+            lds_p = lds.ctypes.data_as(C.POINTER(C.c_int64))
+        o = PlanOpts()
+        lib.hexla_plan_opts_default(C.byref(o))
+        h = C.c_void_p()
+        self._check(lib.hexla_batch_create(
+            self.handle, root.node, nodes, len(leaves), count,
+            sizes.ctypes.data_as(C.POINTER(C.c_int64)),
+            ptrs.ctypes.data_as(C.POINTER(C.c_void_p)), lds_p,
+            outs.ctypes.data_as(C.POINTER(C.c_void_p)), C.byref(o), C.byref(h)))
+        return Batch(self, h.value, [sizes, ptrs, outs, lds])
 
     def split_bf16(self, x, terms=2):
         """bfloat16 terms of an FP32 tensor x (device), as int16 tensors holding
