@@ -25,10 +25,12 @@
  *     when rows == 0), the storage of the BLAS/LAPACK routines the paper maps
  *     expressions onto. A vector is an n x 1 matrix.
  *   - Every function returns hexla_status. Out-parameters come last.
- *   - Device memory is always owned by the caller. The library never
- *     allocates device memory while planning or executing; the only device
- *     allocation it makes is a 256-byte status block per context, at
- *     hexla_ctx_create.
+ *   - Operands, results and workspaces are always owned by the caller. The
+ *     library never allocates device memory while executing. Its own
+ *     allocations are a 256-byte status block per context
+ *     (hexla_ctx_create), the code of generated element-wise kernels, a
+ *     pinned host copy of each batch plan's instance table, and a learned
+ *     cost model's parameters and scratch (hexla_model_*).
  *   - A context is used by one host thread at a time.
  */
 #ifndef HEXLA_H
@@ -73,6 +75,7 @@ typedef enum hexla_op {
 typedef uint32_t hexla_node;            /* index into the context's node arena */
 typedef struct hexla_ctx hexla_ctx;
 typedef struct hexla_plan hexla_plan;
+typedef struct hexla_model hexla_model;
 
 /* ------------------------------------------------------------------ context */
 
@@ -122,7 +125,8 @@ typedef enum hexla_planner {
   HEXLA_PLANNER_DP = 0,      /* exact minimum multiply-adds over all bracketings */
   HEXLA_PLANNER_GREEDY = 1,  /* Sec. II rule: smallest-result pair first, leftmost on ties */
   HEXLA_PLANNER_NAIVE = 2,   /* Sec. III "naive": left to right, no rewrites     */
-  HEXLA_PLANNER_LEARNED = 3  /* predicted-time DP with the loaded cost model     */
+  HEXLA_PLANNER_LEARNED = 3  /* predicted-time DP with the context's cost model,
+                                judged by the DP (see hexla_ctx_set_model)      */
 } hexla_planner;
 
 typedef enum hexla_product_precision {
@@ -331,6 +335,84 @@ hexla_status hexla_batch_autotune(hexla_batch* batch, void* workspace, size_t wo
 hexla_status hexla_batch_capture(hexla_batch* batch, void* workspace, size_t workspace_bytes);
 hexla_status hexla_batch_replay(hexla_batch* batch);
 hexla_status hexla_batch_destroy(hexla_batch* batch);
+
+/* ------------------------------------------------------- learned planner
+ * A small FP32 network (32 features -> 64 -> 64 -> 64 -> 1, ReLU) predicts
+ * the log of a matrix product's run time in microseconds from its shape,
+ * type, transposes and launch configuration (tile, split-K). It is trained on
+ * the GPU by the library's own kernels (MSE loss, Adam) on timings the
+ * evaluator measures itself: hexla_timing_log makes hexla_plan_autotune
+ * append every configuration it times to a file. Nothing of this is in the
+ * paper, whose chain rule is the greedy heuristic of Sec. II; it is a
+ * planner variant beside the cost-count DP.
+ *
+ * With a model set on the context, HEXLA_PLANNER_LEARNED plans each chain by
+ * a DP over predicted times (each product at its predicted-fastest
+ * configuration; one inference launch per chain, on the context's stream,
+ * waited for by hexla_plan_create). The multiply-add DP is the judge: the
+ * learned order is kept only when its multiply-adds are at most twice the
+ * DP's and its predicted time is below the predicted time of the DP order;
+ * otherwise the DP order is used. Configurations in the context's tuning
+ * table (measured) take precedence over predicted ones. Without a model the
+ * learned planner is the DP planner. A model holds its parameters and Adam
+ * state in device memory allocated at creation (about 126 KB), and
+ * inference scratch grown on demand. */
+#define HEXLA_MODEL_FEATURES 32
+
+typedef struct hexla_train_opts {
+  int32_t epochs;             /* passes over the data (default 200)              */
+  int32_t batch;              /* samples per Adam step (default 256)             */
+  float lr;                   /* Adam step size (default 1e-3; betas 0.9, 0.999) */
+  int32_t reserved0;
+  uint64_t seed;              /* shuffling seed                                  */
+  int32_t reserved[8];
+} hexla_train_opts;
+
+/* The feature vector (HEXLA_MODEL_FEATURES floats, host memory) of a product
+ * C = op(A) op(B), op(A) m x k, op(B) k x n, in configuration (tile, split)
+ * of the kernel family of (dtype, precision); mode 1 = symmetric (SYRK).
+ * Errors: HEXLA_E_INVALID_ARG. */
+hexla_status hexla_product_features(int32_t dtype, int32_t precision, int32_t mode, int32_t ta,
+                                    int32_t tb, int64_t m, int64_t n, int64_t k, int32_t tile,
+                                    int32_t split, float* out);
+/* A network with He-normal weights drawn from `seed`, zero biases. */
+hexla_status hexla_model_create(hexla_ctx* ctx, uint64_t seed, hexla_model** out);
+hexla_status hexla_model_destroy(hexla_model* model);
+hexla_status hexla_model_param_count(int64_t* n);
+/* Parameters as one flat host array of param_count floats: W1 (64 x 32,
+ * row-major: out x in), b1, W2 (64 x 64), b2, W3, b3, W4 (1 x 64), b4, and
+ * the target standardisation (predictions are y_mean + y_std * network).
+ * set_params also clears the Adam state. */
+hexla_status hexla_model_get_params(hexla_model* model, float* host, int64_t n, float* y_mean,
+                                    float* y_std);
+hexla_status hexla_model_set_params(hexla_model* model, const float* host, int64_t n,
+                                    float y_mean, float y_std);
+/* Gradient (host, param_count floats) and value of the raw network's loss
+ * (1/count) sum_i (network(x_i) - t_i)^2 over x (device, row-major count x
+ * HEXLA_MODEL_FEATURES) and t (device, count). Synchronous. */
+hexla_status hexla_model_grad(hexla_model* model, const float* x, const float* t, int64_t count,
+                              float* grad, double* loss);
+/* One Adam step of the raw network on this batch. Synchronous. */
+hexla_status hexla_model_step(hexla_model* model, const float* x, const float* t, int64_t count,
+                              float lr, double* loss);
+/* Trains on (x, t) with t = log(microseconds) (device arrays): targets are
+ * standardised, then minibatch Adam over shuffled epochs; final_loss is the
+ * MSE over all samples in standardised units. Synchronous. */
+hexla_status hexla_model_train(hexla_model* model, const float* x, const float* t, int64_t count,
+                               const hexla_train_opts* opts, double* final_loss);
+/* y (device, count) = predicted log(microseconds) of x (device). Asynchronous
+ * on the context's stream. */
+hexla_status hexla_model_predict(hexla_model* model, const float* x, int64_t count, float* y);
+/* Text file: a "hexla-mlp 1 gfx950 32 P" header, y_mean y_std, then the
+ * parameters. Loading rejects other layouts and targets (HEXLA_E_INVALID_ARG). */
+hexla_status hexla_model_save(hexla_model* model, const char* path);
+hexla_status hexla_model_load(hexla_ctx* ctx, const char* path, hexla_model** out);
+/* The model HEXLA_PLANNER_LEARNED consults (borrowed; NULL clears). */
+hexla_status hexla_ctx_set_model(hexla_ctx* ctx, hexla_model* model);
+/* Appends every configuration hexla_plan_autotune times to `path`, one JSON
+ * object per line: dtype, precision, mode, ta, tb, m, n, k, tile, split, us
+ * (microseconds per launch). NULL stops logging. */
+hexla_status hexla_timing_log(hexla_ctx* ctx, const char* path);
 
 /* Library version string (static storage). */
 const char* hexla_version(void);

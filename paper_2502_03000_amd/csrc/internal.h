@@ -122,6 +122,8 @@ struct hexla_ctx {
   std::map<std::string, hexla::k::GemmConfig> tuned;  // autotuned product configurations
   int32_t host_status = 0;         // deferred status raised by host-driven loops
   int32_t host_ir_iterations = 0;  // iterations of the last refined solve
+  hexla_model* model = nullptr;    // cost model of the learned planner (borrowed)
+  std::string timing_log;          // autotune timings are appended here when set
 };
 
 struct hexla_plan {
@@ -134,6 +136,7 @@ struct hexla_plan {
   double flops = 0, bytes = 0, macs = 0;
   std::vector<hexla::Range> leaf_ranges;     // read by products, solves, epilogues
   std::vector<hexla::Range> ew_leaf_ranges;  // read by element-wise passes
+  std::vector<std::string> learned_notes;     // JSON of the learned planner's decisions
   hipGraph_t graph = nullptr;                 // captured launches (hexla_plan_capture)
   hipGraphExec_t graph_exec = nullptr;
   ~hexla_plan();
@@ -159,6 +162,12 @@ hipError_t launch_gemm_step(const Step& s, const GemmBind& gb, const k::GemmConf
                             hipStream_t st);
 std::string tune_key(const Step& s, int ta, int tb);
 size_t gemm_max_partial(const Step& s);
+std::vector<k::GemmConfig> gemm_candidates(const Step& s);
+// learned cost model (model.cpp)
+void product_features(int dtype, int precision, int mode, int ta, int tb, int64_t m, int64_t n,
+                      int64_t kk, int tile, int split, float* out);
+bool model_predict_us(hexla_model* md, const std::vector<float>& x, std::vector<float>& us,
+                      std::string* err);
 hexla_status set_err(const hexla_ctx* ctx, hexla_status st, const std::string& msg);
 size_t dtype_size(int dtype);
 // generated element-wise kernels (codegen.cpp)

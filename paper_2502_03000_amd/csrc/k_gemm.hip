@@ -56,6 +56,19 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 int gemm_tile_count(int dtype) { return dtype == 1 ? 6 : 2; }
 
+void gemm_tile_shape(int dtype, int precision, int tile, int* bm, int* bn, int* bk) {
+  if (precision != GEMM_PLAIN) {  // split-BF16 family: one 128 x 128 x 32 tile
+    *bm = 128;
+    *bn = 128;
+    *bk = 32;
+    return;
+  }
+  const Tile t = tile_of(dtype, tile);
+  *bm = t.bm;
+  *bn = t.bn;
+  *bk = t.bk;
+}
+
 int64_t gemm_tiles_for(int dtype, int tile, int mode, int64_t m, int64_t n) {
   const Tile t = tile_of(dtype, tile);
   if (mode == 1) {

@@ -79,6 +79,7 @@ enum GemmPrecision { GEMM_PLAIN = 0, GEMM_BF16X3 = 1, GEMM_BF16X6 = 2, GEMM_F16 
 GemmConfig gemm_choose(int dtype, int precision, int mode, int64_t m, int64_t n, int64_t k);
 // tile table access for the autotuner
 int gemm_tile_count(int dtype);
+void gemm_tile_shape(int dtype, int precision, int tile, int* bm, int* bn, int* bk);
 bool gemm_tile_valid(int dtype, int tile, int mode);
 int gemm_split_for(int dtype, int tile, int mode, int64_t m, int64_t n, int64_t k, int64_t target,
                    int64_t min_steps);
@@ -183,6 +184,29 @@ int64_t batch_scratch_stride(int64_t max_n);
 hipError_t batch_launch(int dtype, const BatchConfig& cfg, const BProgram* p, const BInst* inst,
                         const int32_t* order, int64_t count, unsigned* queue, void* scratch,
                         int64_t scratch_stride, int32_t* status, hipStream_t s);
+
+// ------------------------------------------------------- learned cost model
+// FP32 ReLU network kMlpFeatures -> 64 -> 64 -> 64 -> 1 over a flat
+// parameter vector of kMlpParams floats (W1 row-major, b1, W2, b2, W3, b3, W4,
+// b4). x is row-major [count][kMlpFeatures].
+constexpr int kMlpFeatures = 32;
+constexpr int kMlpHidden = 64;
+constexpr int kMlpParams = kMlpHidden * kMlpFeatures + kMlpHidden +
+                           2 * (kMlpHidden * kMlpHidden + kMlpHidden) + kMlpHidden + 1;
+int64_t mlp_blocks(int64_t count);
+// Per-block gradient partials of L = (1/count) sum (y - t)^2 (partial:
+// mlp_blocks(count) x kMlpParams floats; loss_partial: sum of squares per
+// block). idx (optional) maps sample positions to rows of x and t.
+hipError_t mlp_grad_launch(const float* params, const float* x, const float* t,
+                           const int32_t* idx, int64_t count, float* partial,
+                           float* loss_partial, hipStream_t s);
+// grad (optional) <- sum of the partials; with params: one Adam step (step >= 1).
+hipError_t mlp_reduce_launch(const float* partial, int64_t nblocks, float* grad, float* params,
+                             float* m, float* v, float lr, float beta1, float beta2, float eps,
+                             int64_t step, hipStream_t s);
+// y = shift + scale * network(x)
+hipError_t mlp_predict_launch(const float* params, const float* x, int64_t count, float scale,
+                              float shift, float* y, hipStream_t s);
 
 // ------------------------------------------------------------------- utils
 hipError_t fill_i32_launch(int32_t* p, int64_t count, int32_t value, hipStream_t s);

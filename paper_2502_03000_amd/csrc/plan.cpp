@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -110,6 +111,7 @@ class Planner {
     plan_->flops = fl;
     plan_->bytes = by;
     plan_->macs = macs_;
+    plan_->learned_notes = learned_notes_;
     plan_->steps = std::move(steps_);
     return HEXLA_OK;
   }
@@ -124,6 +126,8 @@ class Planner {
   double macs_ = 0;
   std::vector<Step> steps_;
   std::vector<ENode> E_;
+  std::map<std::string, k::GemmConfig> learned_cfg_;  // predicted-fastest configurations
+  std::vector<std::string> learned_notes_;           // the learned planner's decisions
   hexla_status status_ = HEXLA_OK;
 
   const Node& N(uint32_t i) const { return ctx_->nodes[i]; }
@@ -694,7 +698,9 @@ class Planner {
     int root;
     if (o_.planner == HEXLA_PLANNER_GREEDY) root = order_greedy(dims, tree);
     else if (naive) root = order_left(L, tree);
+    else if (o_.planner == HEXLA_PLANNER_LEARNED && ctx_->model) root = order_learned(dims, sym, f, tree);
     else root = order_dp(dims, sym, tree);
+    if (status_ != HEXLA_OK) return View{};
     macs_ += double(tree_cost(root, tree, dims, sym));
     return emit_tree(root, tree, f, sym, true, dest, alpha, epi);
   }
@@ -764,6 +770,113 @@ class Planner {
       return mk_pair(tree, l, r);
     };
     return build(0, L - 1);
+  }
+
+  // The learned planner: every product (lo, s, hi) a bracketing of the chain
+  // can contain is priced at its predicted-fastest configuration (one
+  // inference launch for all of them), a DP minimises the predicted time,
+  // and the multiply-add DP judges: its order is used unless the learned
+  // order costs at most twice its multiply-adds and is predicted faster.
+  // The chosen configurations are kept for product().
+  int order_learned(const std::vector<int64_t>& d, const std::vector<char>& sym,
+                    const std::vector<Factor>& f, std::vector<TNode>& tree) {
+    const int L = int(d.size()) - 1;
+    struct Prod {
+      Step st;
+      int ta = 0, tb = 0;
+      size_t first = 0, count = 0;
+      std::vector<k::GemmConfig> cands;
+      double us = 0.0;
+      k::GemmConfig best{};
+    };
+    auto at = [L](int lo, int s, int hi) { return (size_t(lo) * L + s) * L + hi; };
+    std::vector<int> index(size_t(L) * L * L, -1);
+    std::vector<Prod> prods;
+    std::vector<float> feats;
+    for (int lo = 0; lo < L; ++lo)
+      for (int hi = lo + 1; hi < L; ++hi)
+        for (int s = lo; s < hi; ++s) {
+          Prod p;
+          p.st.dtype = dtype_;
+          p.st.precision = dtype_ == HEXLA_F32 ? o_.product_precision : 0;
+          p.st.mode = (hi == lo + 1 && sym[lo] && o_.syrk) ? 1 : 0;
+          p.st.m = d[lo];
+          p.st.kk = d[s + 1];
+          p.st.n = d[hi + 1];
+          p.ta = s == lo && f[lo].v.trans ? 1 : 0;
+          p.tb = s + 1 == hi && f[hi].v.trans ? 1 : 0;
+          if (p.st.m == 1 || p.st.n == 1) {  // matrix-vector: memory-bound estimate
+            const double bytes = double(esz_) * (double(p.st.m) * p.st.kk +
+                                                 double(p.st.kk) * p.st.n + double(p.st.m) * p.st.n);
+            p.us = 4.0 + bytes / 4.0e6;
+          } else {
+            p.cands = gemm_candidates(p.st);
+            p.first = feats.size() / k::kMlpFeatures;
+            p.count = p.cands.size();
+            for (const k::GemmConfig& c : p.cands) {
+              feats.resize(feats.size() + k::kMlpFeatures);
+              product_features(dtype_, p.st.precision, p.st.mode, p.ta, p.tb, p.st.m, p.st.n,
+                               p.st.kk, c.tile, c.split, &feats[feats.size() - k::kMlpFeatures]);
+            }
+          }
+          index[at(lo, s, hi)] = int(prods.size());
+          prods.push_back(std::move(p));
+        }
+    std::vector<float> us;
+    std::string err;
+    if (!model_predict_us(ctx_->model, feats, us, &err)) {
+      fail(HEXLA_E_DEVICE, err);
+      return 0;
+    }
+    for (Prod& p : prods) {
+      if (p.count == 0) continue;
+      size_t bi = 0;
+      for (size_t c = 1; c < p.count; ++c)
+        if (us[p.first + c] < us[p.first + bi]) bi = c;
+      p.us = us[p.first + bi];
+      p.best = p.cands[bi];
+      learned_cfg_[tune_key(p.st, p.ta, p.tb)] = p.best;
+    }
+    // DP over predicted microseconds
+    std::vector<std::vector<double>> cost(L, std::vector<double>(L, 0.0));
+    std::vector<std::vector<int>> arg(L, std::vector<int>(L, -1));
+    for (int len = 2; len <= L; ++len)
+      for (int lo = 0; lo + len - 1 < L; ++lo) {
+        const int hi = lo + len - 1;
+        double best = -1.0;
+        for (int s = lo; s < hi; ++s) {
+          const double c = cost[lo][s] + cost[s + 1][hi] + prods[size_t(index[at(lo, s, hi)])].us;
+          if (best < 0 || c < best) {
+            best = c;
+            arg[lo][hi] = s;
+          }
+        }
+        cost[lo][hi] = best;
+      }
+    std::function<int(int, int)> build = [&](int lo, int hi) -> int {
+      if (lo == hi) return mk_leaf(tree, lo);
+      const int s = arg[lo][hi];
+      const int l = build(lo, s);
+      const int r = build(s + 1, hi);
+      return mk_pair(tree, l, r);
+    };
+    const int learned = build(0, L - 1);
+    const int dp = order_dp(d, sym, tree);
+    std::function<double(int)> pred = [&](int t) -> double {
+      const TNode& n = tree[t];
+      if (n.leaf >= 0) return 0.0;
+      const int s = tree[n.left].hi;
+      return prods[size_t(index[at(n.lo, s, n.hi)])].us + pred(n.left) + pred(n.right);
+    };
+    const double pl = pred(learned), pd = pred(dp);
+    const i128 ml = tree_cost(learned, tree, d, sym), md = tree_cost(dp, tree, d, sym);
+    const bool keep = ml <= 2 * md && pl < pd;
+    std::ostringstream js;
+    js << "{\"chain\":" << L << ",\"pred_us_learned\":" << pl << ",\"pred_us_dp\":" << pd
+       << ",\"macs_learned\":" << double(ml) << ",\"macs_dp\":" << double(md)
+       << ",\"chosen\":\"" << (keep ? "learned" : "dp") << "\"}";
+    learned_notes_.push_back(js.str());
+    return keep ? learned : dp;
   }
 
   // The paper's rule (Sec. II): multiply the adjacent pair whose product has
@@ -848,6 +961,8 @@ class Planner {
       s.mode = syrk ? 1 : 0;
       s.precision = (dtype_ == HEXLA_F32) ? o_.product_precision : 0;
       s.cfg = k::gemm_choose(dtype_, s.precision, s.mode, m, n, kk);
+      const auto learned = learned_cfg_.find(tune_key(s, a.trans ? 1 : 0, b.trans ? 1 : 0));
+      if (learned != learned_cfg_.end()) s.cfg = learned->second;
       const auto tuned = ctx_->tuned.find(tune_key(s, a.trans ? 1 : 0, b.trans ? 1 : 0));
       if (tuned != ctx_->tuned.end() && k::gemm_tile_valid(dtype_, tuned->second.tile, s.mode))
         s.cfg = tuned->second;
@@ -1029,7 +1144,13 @@ std::string describe(const hexla_plan* p) {
     }
     js << "}";
   }
-  js << "]}";
+  js << "]";
+  if (!p->learned_notes.empty()) {
+    js << ",\"learned\":[";
+    for (size_t i = 0; i < p->learned_notes.size(); ++i) js << (i ? "," : "") << p->learned_notes[i];
+    js << "]";
+  }
+  js << "}";
   return js.str();
 }
 

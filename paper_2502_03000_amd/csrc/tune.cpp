@@ -1,5 +1,6 @@
 // Autotuning of the matrix products' tile and split-K configuration, the
-// tuning table, and HIP-graph capture of a plan.
+// tuning table, the timing log the learned cost model trains on, and
+// HIP-graph capture of a plan.
 //
 // The autotuner times every candidate configuration of each product on the
 // caller's buffers (HIP events on the context's stream) and keeps the
@@ -11,6 +12,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <iomanip>
 #include <fstream>
 #include <set>
 #include <sstream>
@@ -83,6 +85,8 @@ hexla_status hexla_plan_autotune(hexla_plan* plan, void* out, int64_t ld_out, vo
   hipError_t e = hipSetDevice(ctx->device);
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
+  std::ofstream log;
+  if (!ctx->timing_log.empty()) log.open(ctx->timing_log, std::ios::app);
   for (Step& s : plan->steps) {
     if (e != hipSuccess) break;
     if (s.kind != StepKind::Gemm) continue;
@@ -99,6 +103,12 @@ hexla_status hexla_plan_autotune(hexla_plan* plan, void* out, int64_t ld_out, vo
       float ms = 0.f;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
       if (e != hipSuccess) break;
+      if (log.is_open())
+        log << "{\"dtype\":" << s.dtype << ",\"precision\":" << s.precision
+            << ",\"mode\":" << s.mode << ",\"ta\":" << gb.ta << ",\"tb\":" << gb.tb
+            << ",\"m\":" << s.m << ",\"n\":" << s.n << ",\"k\":" << s.kk
+            << ",\"tile\":" << c.tile << ",\"split\":" << c.split << ",\"us\":"
+            << std::setprecision(6) << double(ms) * 1e3 / reps << "}\n";
       if (ms < best_ms) {
         best_ms = ms;
         best = c;

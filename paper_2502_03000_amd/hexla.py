@@ -59,6 +59,11 @@ class BatchInfo(C.Structure):
                 ("flops", C.c_double), ("bytes", C.c_double)]
 
 
+class TrainOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float),
+                ("reserved0", C.c_int32), ("seed", C.c_uint64), ("reserved", C.c_int32 * 8)]
+
+
 class Report(C.Structure):
     _fields_ = [("status", C.c_int32), ("ir_iterations", C.c_int32),
                 ("singular_column", C.c_int64)]
@@ -107,6 +112,22 @@ def _load():
         "hexla_batch_capture": [vp, vp, C.c_size_t],
         "hexla_batch_replay": [vp],
         "hexla_batch_destroy": [vp],
+        "hexla_product_features": [i32, i32, i32, i32, i32, i64, i64, i64, i32, i32,
+                                   C.POINTER(C.c_float)],
+        "hexla_model_create": [vp, C.c_uint64, C.POINTER(vp)],
+        "hexla_model_destroy": [vp],
+        "hexla_model_param_count": [C.POINTER(i64)],
+        "hexla_model_get_params": [vp, C.POINTER(C.c_float), i64, C.POINTER(C.c_float),
+                                   C.POINTER(C.c_float)],
+        "hexla_model_set_params": [vp, C.POINTER(C.c_float), i64, C.c_float, C.c_float],
+        "hexla_model_grad": [vp, vp, vp, i64, C.POINTER(C.c_float), C.POINTER(C.c_double)],
+        "hexla_model_step": [vp, vp, vp, i64, C.c_float, C.POINTER(C.c_double)],
+        "hexla_model_train": [vp, vp, vp, i64, C.POINTER(TrainOpts), C.POINTER(C.c_double)],
+        "hexla_model_predict": [vp, vp, i64, vp],
+        "hexla_model_save": [vp, C.c_char_p],
+        "hexla_model_load": [vp, C.c_char_p, C.POINTER(vp)],
+        "hexla_ctx_set_model": [vp, vp],
+        "hexla_timing_log": [vp, C.c_char_p],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -309,6 +330,97 @@ class Batch:
         self.ctx._check(lib.hexla_batch_replay(self.handle))
 
 
+MODEL_FEATURES = 32
+
+
+def product_features(dtype, precision, mode, ta, tb, m, n, k, tile, split):
+    """The cost model's feature vector of one product configuration (numpy)."""
+    import numpy as np
+    out = (C.c_float * MODEL_FEATURES)()
+    st = lib.hexla_product_features(dtype, precision, mode, ta, tb, m, n, k, tile, split, out)
+    if st != OK:
+        raise HexlaError(st, "product_features")
+    return np.frombuffer(out, dtype=np.float32).copy()
+
+
+class Model:
+    """The learned cost model (parameters on the device). x: row-major float32
+    tensors [count, 32] on the device; targets are log(microseconds)."""
+
+    def __init__(self, ctx, handle):
+        self.ctx, self.handle = ctx, handle
+
+    @classmethod
+    def create(cls, ctx, seed=0):
+        h = C.c_void_p()
+        ctx._check(lib.hexla_model_create(ctx.handle, seed, C.byref(h)))
+        return cls(ctx, h.value)
+
+    @classmethod
+    def load(cls, ctx, path):
+        h = C.c_void_p()
+        ctx._check(lib.hexla_model_load(ctx.handle, os.fsencode(path), C.byref(h)))
+        return cls(ctx, h.value)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and lib is not None:
+            lib.hexla_model_destroy(h)
+            self.handle = None
+
+    @staticmethod
+    def param_count() -> int:
+        n = C.c_int64()
+        lib.hexla_model_param_count(C.byref(n))
+        return int(n.value)
+
+    def params(self):
+        import numpy as np
+        n = self.param_count()
+        buf = (C.c_float * n)()
+        mean, std = C.c_float(), C.c_float()
+        self.ctx._check(lib.hexla_model_get_params(self.handle, buf, n, C.byref(mean), C.byref(std)))
+        return np.frombuffer(buf, dtype=np.float32).copy(), float(mean.value), float(std.value)
+
+    def set_params(self, flat, y_mean=0.0, y_std=1.0):
+        import numpy as np
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        self.ctx._check(lib.hexla_model_set_params(
+            self.handle, flat.ctypes.data_as(C.POINTER(C.c_float)), flat.size, y_mean, y_std))
+
+    def grad(self, x, t):
+        import numpy as np
+        n = self.param_count()
+        buf = (C.c_float * n)()
+        loss = C.c_double()
+        self.ctx._check(lib.hexla_model_grad(self.handle, x.data_ptr(), t.data_ptr(), x.shape[0],
+                                             buf, C.byref(loss)))
+        return np.frombuffer(buf, dtype=np.float32).copy(), float(loss.value)
+
+    def step(self, x, t, lr=1e-3):
+        loss = C.c_double()
+        self.ctx._check(lib.hexla_model_step(self.handle, x.data_ptr(), t.data_ptr(), x.shape[0],
+                                             lr, C.byref(loss)))
+        return float(loss.value)
+
+    def train(self, x, t, epochs=200, batch=256, lr=1e-3, seed=1):
+        o = TrainOpts()
+        o.epochs, o.batch, o.lr, o.seed = epochs, batch, lr, seed
+        loss = C.c_double()
+        self.ctx._check(lib.hexla_model_train(self.handle, x.data_ptr(), t.data_ptr(), x.shape[0],
+                                              C.byref(o), C.byref(loss)))
+        return float(loss.value)
+
+    def predict(self, x):
+        import torch
+        y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        self.ctx._check(lib.hexla_model_predict(self.handle, x.data_ptr(), x.shape[0], y.data_ptr()))
+        return y
+
+    def save(self, path):
+        self.ctx._check(lib.hexla_model_save(self.handle, os.fsencode(path)))
+
+
 def pack_batch(instances, names, dtype, device="cuda", align=64):
     """Packs per-instance host arrays (dicts name -> 2-D numpy array, n x n or
     n x 1) into one column-major device arena, each array starting on an
@@ -496,6 +608,15 @@ class Context:
             ptrs.ctypes.data_as(C.POINTER(C.c_void_p)), lds_p,
             outs.ctypes.data_as(C.POINTER(C.c_void_p)), C.byref(o), C.byref(h)))
         return Batch(self, h.value, [sizes, ptrs, outs, lds])
+
+    def set_model(self, model):
+        """Cost model of the learned planner (None clears)."""
+        self._model = model
+        self._check(lib.hexla_ctx_set_model(self.handle, model.handle if model else None))
+
+    def timing_log(self, path):
+        """Append every configuration the autotuner times to `path` (None stops)."""
+        self._check(lib.hexla_timing_log(self.handle, os.fsencode(path) if path else None))
 
     def split_bf16(self, x, terms=2):
         """bfloat16 terms of an FP32 tensor x (device), as int16 tensors holding

@@ -117,3 +117,33 @@ def test_execute_on_dry_run_context_is_unsupported():
     with pytest.raises(hx.HexlaError) as ei:
         bt.execute(1 << 20)
     assert ei.value.status == hx.E_UNSUPPORTED
+
+
+def test_product_features():
+    f = hx.product_features(hx.F32, 0, 0, 0, 1, 1024, 64, 8192, 3, 4)
+    assert f.shape == (32,) and f.dtype == np.float32
+    assert f[7] == 1 and f[6] == 0 and f[10] == 1 and f[9] == 0  # FP32, tb
+    assert f[12 + 3] == 1 and f[12:20].sum() == 1               # tile one-hot
+    assert f[29] == 1                                            # split-K
+    assert abs(f[0] - 10 / 13) < 1e-6 and abs(f[2] - 1.0) < 1e-6  # log2 m, log2 k scaled
+    g = hx.product_features(hx.F64, 0, 1, 1, 0, 512, 512, 100, 0, 1)
+    assert g[6] == 1 and g[8] == 1 and g[29] == 0 and 0 < g[25] <= 1
+    with pytest.raises(hx.HexlaError):
+        hx.product_features(hx.F64, 0, 0, 0, 0, 16, 16, 16, 5, 1)  # FP64 has 2 tiles
+
+
+def test_learned_planner_without_model_is_dp():
+    ctx = hx.Context(-1)
+    import torch
+    dims = [300, 20, 500, 10, 400]
+    bufs = [torch.zeros(a * b, dtype=torch.float32) for a, b in zip(dims[:-1], dims[1:])]
+    def chain(planner):
+        ls = [ctx.leaf_raw(t.data_ptr(), a, b, a, hx.F32)
+              for t, a, b in zip(bufs, dims[:-1], dims[1:])]
+        e = ls[0]
+        for x in ls[1:]:
+            e = e @ x
+        return ctx.plan(e, planner=planner).describe()
+    d, l = chain("dp"), chain("learned")
+    assert l["chain_macs"] == d["chain_macs"] and "learned" not in l
+    assert [s["m"] for s in l["steps"]] == [s["m"] for s in d["steps"]]
