@@ -37,7 +37,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=16384, help="element-wise matrix size")
     ap.add_argument("--count", type=int, default=10000, help="instances (batched workload)")
-    ap.add_argument("--workload", default="expr", choices=["expr", "syrk", "solve", "batched"],
+    ap.add_argument("--chains", type=int, default=2000, help="random chains (learned workload)")
+    ap.add_argument("--sweep", type=int, default=600, help="training shapes (learned workload)")
+    ap.add_argument("--workload", default="expr",
+                    choices=["expr", "syrk", "solve", "batched", "learned"],
                     help="expr: the FP32 chain + fused element-wise step (default); "
                          "syrk: trans(X)*X, X 65536x2048, plain FP64/FP32 vs split-BF16")
     ap.add_argument("--forms", default="", help="comma-separated subset of forms (syrk, solve)")
@@ -228,6 +231,153 @@ def bench_solve(args, ctx, hx, torch, inputs):
     print(json.dumps(res), flush=True)
 
 
+def bench_learned(args, ctx, hx, torch, inputs):
+    """The learned planner: timings from the evaluator's own autotuner (the
+    products of the FP32 chain, trans(X)*X at 65536 x 2048 in FP32 and FP64,
+    and a log-uniform shape sweep whose seed is disjoint from the evaluation
+    chains), a model trained on the GPU, then `chains` random FP32 chains
+    (length 3-8, dims log-uniform in [16, 8192], N(0,1)) planned by the DP
+    (default tiles) and by the learned planner, each timed by graph replay."""
+    import tempfile
+    import oracle
+    from paper_2502_03000_amd import learn
+    log = os.path.join(tempfile.mkdtemp(), "timings.jsonl")
+    t0 = time.perf_counter()
+    # autotune records of the FP32 chain and the symmetric products
+    ctx.timing_log(log)
+    chain_np = inputs.fp32_chain(seed=1001)
+    chain_t = [torch.from_numpy(np.ascontiguousarray(m.T)).cuda().t() for m in chain_np]
+    e = None
+    for t in chain_t:
+        e = ctx.leaf(t) if e is None else e @ ctx.leaf(t)
+    p = ctx.plan(e)
+    p.autotune(p.output(), p.workspace(), reps=2)
+    x = torch.randn(2048, 65536, device="cuda").t()  # 65536 x 2048, column-major
+    for dt in (torch.float32, torch.float64):
+        xe = ctx.leaf(x.to(dt))
+        p = ctx.plan(hx.trans(xe) @ xe)
+        p.autotune(p.output(), p.workspace(), reps=1)
+    ctx.timing_log(None)
+    ctx.clear()
+    del p, x, chain_t
+    torch.cuda.empty_cache()
+    learn.timing_sweep(ctx, learn.log_uniform_shapes(2005, args.sweep, 16, 8192), log, reps=2)
+    sweep_s = time.perf_counter() - t0
+    recs = learn.read_log(log)
+    xs, ys = learn.dataset(recs)
+    t1 = time.perf_counter()
+    model, loss = learn.train(ctx, xs, ys, epochs=200)
+    train_s = time.perf_counter() - t1
+    ctx.set_model(model)
+
+    chains = inputs.random_chain_dims(seed=1005, count=args.chains)
+    need = max(sum(a * b for a, b in zip(d[:-1], d[1:])) for d in chains)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1005)
+    pool = torch.randn(need, generator=g, device="cuda")
+
+    def build(dims, planner):
+        off, ls = 0, []
+        for a, b in zip(dims[:-1], dims[1:]):
+            ls.append(ctx.leaf(pool[off:off + a * b].view(b, a).t()))
+            off += a * b
+        ex = ls[0]
+        for q in ls[1:]:
+            ex = ex @ q
+        return ctx.plan(ex, planner=planner)
+
+    def timed(pl, reps=3):
+        out, ws = pl.output(), pl.workspace()
+        pl.capture(out, ws)
+        pl.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            pl.replay()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps, out
+
+    rows = []
+    t_dp = t_ln = fl_dp = fl_ln = 0.0
+    n_learned = 0
+    sample = set(inputs.rng(12).choice(len(chains), 8, replace=False).tolist())
+    err = 0.0
+    t1 = time.perf_counter()
+    for i, dims in enumerate(chains):
+        pd = build(dims, "dp")
+        a, _ = timed(pd)
+        pl = build(dims, "learned")
+        b, out = timed(pl)
+        note = pl.describe()["learned"][0]
+        n_learned += note["chosen"] == "learned"
+        t_dp += a
+        t_ln += b
+        fl_dp += pd.info.flops
+        fl_ln += pl.info.flops
+        if i in sample:  # rows of the product against FP64 row-vector products
+            got = out.cpu().numpy().astype(np.float64)
+            mats, off = [], 0
+            for r, c in zip(dims[:-1], dims[1:]):
+                mats.append(pool[off:off + r * c].view(c, r).t().cpu().numpy().astype(np.float64))
+                off += r * c
+            for rr in inputs.rng(i).integers(0, dims[0], 2):
+                v = mats[0][rr:rr + 1]
+                for m in mats[1:]:
+                    v = v @ m
+                err = max(err, float(np.linalg.norm(got[rr] - v[0]) / np.linalg.norm(v[0])))
+        ctx.clear()
+        del pd, pl, out
+    eval_s = time.perf_counter() - t1
+    tflops = fl_ln / (t_ln * 1e-3) / 1e12
+    res = {
+        "metric": METRIC, "value": fl_ln / (t_ln * 1e-3) / 1e9, "unit": "GFLOP/s",
+        "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": t_ln,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded)",
+        "config": {"workload": f"{len(chains)} random FP32 chains, length 3-8, dims log-uniform "
+                               "in [16, 8192], N(0,1); learned planner vs FLOP DP",
+                   "training_records": len(recs), "training_loss_std_mse": loss,
+                   "sweep_s": sweep_s, "train_s": train_s, "eval_s": eval_s},
+        "roofline": {"bound": "mfma", "achieved": tflops, "peak": FP32_MFMA_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tflops / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
+                     "note": "all products of all chains, learned plans"},
+        "speedup_vs_dp": t_dp / t_ln,
+        "dp": {"total_ms": t_dp, "gflop": fl_dp / 1e9},
+        "learned": {"total_ms": t_ln, "gflop": fl_ln / 1e9, "chains_learned_order": n_learned},
+        "max_rel_err_sampled_rows": err,
+    }
+    if not args.no_cpu_baseline:  # the oracle on whole chains, in order, for about 10 s
+        t1 = time.perf_counter()
+        done, fl = 0, 0.0
+        from oracle import chain as ch
+        for dims in chains:
+            env, off = {}, 0
+            for j, (r, c) in enumerate(zip(dims[:-1], dims[1:])):
+                env[f"M{j}"] = pool[off:off + r * c].view(c, r).t().cpu().numpy()
+                off += r * c
+            oracle.evaluate("*".join(env), env)
+            fl += 2.0 * ch.brute_force_min(list(dims))[0]
+            done += 1
+            if time.perf_counter() - t1 >= 10.0:
+                break
+        el = time.perf_counter() - t1
+        res["cpu_baseline"] = {"value": fl / el / 1e9, "unit": "GFLOP/s", "cores": _threads(),
+                               "kind": "oracle",
+                               "sample": f"the first {done} of the {len(chains)} chains, in the "
+                                         f"oracle's cheapest order ({el:.1f} s, float64 numpy)"}
+    print(json.dumps(res), flush=True)
+
+
+def _threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([x.get("num_threads", 1) for x in threadpool_info()] or [1]))
+    except Exception:  # noqa: BLE001
+        return os.cpu_count() or 1
+
+
 BATCH_NAMES = ["A", "B", "v", "S", "b", "p", "q"]
 
 
@@ -406,6 +556,8 @@ def main():
         return bench_solve(args, ctx, hx, torch, inputs)
     if args.workload == "batched":
         return bench_batched(args, ctx, hx, torch, inputs)
+    if args.workload == "learned":
+        return bench_learned(args, ctx, hx, torch, inputs)
 
     # ---- inputs resident in HBM
     chain_np = inputs.fp32_chain(seed=1001)
