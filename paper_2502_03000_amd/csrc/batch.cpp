@@ -547,6 +547,10 @@ hexla_status hexla_batch_create(hexla_ctx* ctx, hexla_node root, const hexla_nod
         return set_err(ctx, HEXLA_E_INVALID_ARG, "batch: ld < n, instance " + std::to_string(i));
       const bool mat = bc.leaf_is_matrix[l];
       const uint64_t span = mat ? uint64_t((n - 1) * ld + n) * es : uint64_t(n) * es;
+      if (span >= (uint64_t(1) << 31))  // the kernel addresses an instance with 32-bit offsets
+        return set_err(ctx, HEXLA_E_UNSUPPORTED,
+                       "batch: an instance matrix spans 2^31 bytes or more, instance " +
+                           std::to_string(i));
       const uintptr_t lo = reinterpret_cast<uintptr_t>(ptr);
       iv.push_back({lo, lo + span, false});
       bytes += double(mat ? n * n : n) * double(es);

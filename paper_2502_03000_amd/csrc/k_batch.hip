@@ -11,6 +11,11 @@
 //                                 panels of PB columns factored in LDS, then
 //                                 back substitution
 //   EW     element-wise program over vectors (the fused loop of Sec. II)
+// One workgroup owns an instance, so the cost is latency: loops that touch
+// global memory issue their loads in batches before using them, the trailing
+// update loads its next tile while it computes the current one, and global
+// accesses go through global-typed pointers with wave-uniform bases (no flat
+// instructions, whose loads would also hold up the LDS wait counter).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,7 +27,14 @@ namespace k {
 
 namespace {
 
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+using gcptr = const __attribute__((address_space(1))) T*;
+
 constexpr int kStatusSingular = 5;
+constexpr int kR = kBMaxN / 64;  // rows per lane of a full column
+constexpr int kCW = 128;         // columns per chunk of the trailing update
 
 template <typename T>
 __device__ __forceinline__ T bexp(T x);
@@ -34,19 +46,56 @@ __device__ __forceinline__ double bexp<double>(double x) { return exp(x); }
 template <typename T, int PB, int NT>
 struct Smem {
   T slots[kBMaxSlots][kBMaxN];
-  T panel[kBMaxN * PB];  // LU panel; reused as the GEMV reduction buffer
-  T ustage[PB * 64];     // A12 chunk of the trailing update [column][k]; L11^-1
+  T panel[kBMaxN * PB];  // LU panel; GEMV reduction buffer; diagonal blocks of U
+  T ustage[PB * kCW];    // A12 chunk of the trailing update [k][column]; L11^-1
   int piv[kBMaxN];
-  double red_v[NT / 64];
-  int red_i[NT / 64];
   int q;
   int swapped;
 };
 
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// Orders a wave's LDS accesses (other lanes' writes become visible to the
+// wave's following reads); lanes of one wave need no barrier instruction.
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// dst(i, j) = src(i, j) for i < rows <= kBMaxN, j < cols (element offsets
+// i + j * ld). Lane l takes rows l + 64 a, wave w columns w, w + NW, ...; two
+// columns of up to kR rows per lane are loaded before any is stored.
+template <typename T, int NT, typename D, typename S>
+__device__ void copy_block(D dst, int ldd, S src, int lds, int rows, int cols) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  for (int j0 = wave; j0 < cols; j0 += 2 * NW) {
+    T v[2][kR];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int j = j0 + NW * b;
+#pragma unroll
+      for (int a = 0; a < kR; ++a) {
+        const int i = lane + 64 * a;
+        v[b][a] = (i < rows && j < cols) ? src[unsigned(i + j * lds)] : T(0);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int j = j0 + NW * b;
+#pragma unroll
+      for (int a = 0; a < kR; ++a) {
+        const int i = lane + 64 * a;
+        if (i < rows && j < cols) dst[unsigned(i + j * ldd)] = v[b][a];
+      }
+    }
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T operand(uint8_t a, const BInst* I, T (*slots)[kBMaxN], int i) {
   if (a & kBSlotBit) return slots[a & 0x7f][i];
-  return static_cast<const T*>(I->leaf[a])[i];
+  return gcptr<T>(I->leaf[a])[i];
 }
 
 // Element-wise program at element i: the opcodes of the single-expression
@@ -91,28 +140,33 @@ __device__ T ew_batch(const BProgram& p, const BOp& op, const BInst* I, T (*slot
   return s0;
 }
 
-// y = alpha * M x, M n x n (ld). Wave w takes columns w, w + NW, ...; lane l
-// rows l + 64 r; the per-wave partial sums are added through LDS.
+// y = alpha * M x, M n x n (ld). Wave w takes column pairs (w, w + NW),
+// (w + 2 NW, ...); lane l rows l + 64 r; per-wave partial sums are added
+// through LDS.
 template <typename T, int NT>
-__device__ void gemv_n(const T* __restrict__ M, int64_t ld, int n, T alpha, const T* x, T* y,
-                       T* red) {
+__device__ void gemv_n(gcptr<T> M, int ld, int n, T alpha, const T* x, T* y, T* red) {
   constexpr int NW = NT / 64;
-  constexpr int R = kBMaxN / 64;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  T acc[R];
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  T acc[kR];
 #pragma unroll
-  for (int r = 0; r < R; ++r) acc[r] = T(0);
-  for (int j = wave; j < n; j += NW) {
-    const T xj = x[j];
-    const T* col = M + int64_t(j) * ld;
+  for (int r = 0; r < kR; ++r) acc[r] = T(0);
+  for (int j = wave; j < n; j += 2 * NW) {
+    const int j2 = j + NW;
+    const T x1 = x[j], x2 = j2 < n ? x[j2] : T(0);
+    gcptr<T> c1 = M + unsigned(j * ld);
+    gcptr<T> c2 = M + unsigned((j2 < n ? j2 : j) * ld);
+    T v1[kR], v2[kR];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
+    for (int r = 0; r < kR; ++r) {
       const int i = lane + 64 * r;
-      if (i < n) acc[r] += col[i] * xj;
+      v1[r] = i < n ? c1[i] : T(0);
+      v2[r] = i < n ? c2[i] : T(0);
     }
+#pragma unroll
+    for (int r = 0; r < kR; ++r) acc[r] += v1[r] * x1 + v2[r] * x2;
   }
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
+  for (int r = 0; r < kR; ++r) {
     const int i = lane + 64 * r;
     if (i < n) red[wave * kBMaxN + i] = acc[r];
   }
@@ -125,18 +179,35 @@ __device__ void gemv_n(const T* __restrict__ M, int64_t ld, int n, T alpha, cons
   }
 }
 
-// y = alpha * M^T x: one wave per output entry, lanes over the column.
+// y = alpha * M^T x: one wave per output entry (two at a time), lanes over
+// the column.
 template <typename T, int NT>
-__device__ void gemv_t(const T* __restrict__ M, int64_t ld, int n, T alpha, const T* x, T* y) {
+__device__ void gemv_t(gcptr<T> M, int ld, int n, T alpha, const T* x, T* y) {
   constexpr int NW = NT / 64;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int j = wave; j < n; j += NW) {
-    const T* col = M + int64_t(j) * ld;
-    T acc = 0;
-    for (int i = lane; i < n; i += 64) acc += col[i] * x[i];
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  for (int j = wave; j < n; j += 2 * NW) {
+    const int j2 = j + NW;
+    gcptr<T> c1 = M + unsigned(j * ld);
+    gcptr<T> c2 = M + unsigned((j2 < n ? j2 : j) * ld);
+    T a1 = 0, a2 = 0;
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) y[j] = alpha * acc;
+    for (int r = 0; r < kR; ++r) {
+      const int i = lane + 64 * r;
+      if (i < n) {
+        const T xi = x[i];
+        a1 += c1[i] * xi;
+        a2 += c2[i] * xi;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      a1 += __shfl_xor(a1, off, 64);
+      a2 += __shfl_xor(a2, off, 64);
+    }
+    if (lane == 0) {
+      y[j] = alpha * a1;
+      if (j2 < n) y[j2] = alpha * a2;
+    }
   }
 }
 
@@ -149,90 +220,86 @@ __device__ void gemv_t(const T* __restrict__ M, int64_t ld, int n, T alpha, cons
 // panel rewritten as G = [I - L11^-1 ; L21 L11^-1] turns the rows k0.. of
 // those columns into U12 = L11^-1 A12 and A22 - L21 U12 (no separate
 // triangular solve). Then back substitution U y = c. y may be x.
+// The first panel and its update read S itself, so S is copied to W only
+// when that panel interchanges rows. Offsets are 32-bit: the planner keeps
+// every instance matrix within 2^31 bytes.
 template <typename T, int PB, int NT>
-__device__ void batch_solve(const T* __restrict__ S, int64_t lds, int n, const T* x, T* y,
-                            T* __restrict__ W, Smem<T, PB, NT>& sm, int32_t* status,
-                            int instance) {
+__device__ void batch_solve(gcptr<T> S, int lds, int n, const T* x, T* y, gptr<T> W,
+                            Smem<T, PB, NT>& sm, int32_t* status, int instance) {
   constexpr int NW = NT / 64;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t ldw = n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+  const int ldw = n;
   const int ncol = n + 1;
   T* panel = sm.panel;
-  for (int j = 0; j < n; ++j)
-    for (int i = tid; i < n; i += NT) W[i + j * ldw] = S[i + j * lds];
-  for (int i = tid; i < n; i += NT) W[i + int64_t(n) * ldw] = x[i];
-  __syncthreads();
+  gcptr<T> Wc = W;
+  for (int i = tid; i < n; i += NT) W[unsigned(i + n * ldw)] = x[i];
+  gcptr<T> src = S;  // columns < n of the matrix being factored: S for the first panel
+  int lsrc = lds;
   for (int k0 = 0; k0 < n; k0 += PB) {
     const int jb = min(PB, n - k0), m = n - k0;
-    for (int c = 0; c < jb; ++c)
-      for (int r = tid; r < m; r += NT) panel[r + c * m] = W[(k0 + r) + int64_t(k0 + c) * ldw];
+    copy_block<T, NT>(panel, m, src + unsigned(k0 + k0 * lsrc), lsrc, m, jb);
     if (tid == 0) sm.swapped = 0;
     __syncthreads();
-    for (int j = 0; j < jb; ++j) {
-      double bv = -1.0;
-      int bi = 1 << 30;
-      for (int r = j + tid; r < m; r += NT) {
-        const double a = fabs(double(panel[r + j * m]));
-        if (a > bv) {  // a thread visits its rows in increasing order
-          bv = a;
-          bi = r;
-        }
-      }
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        const double v2 = __shfl_xor(bv, off, 64);
-        const int i2 = __shfl_xor(bi, off, 64);
-        if (v2 > bv || (v2 == bv && i2 < bi)) {
-          bv = v2;
-          bi = i2;
-        }
-      }
-      if (lane == 0) {
-        sm.red_v[wave] = bv;
-        sm.red_i[wave] = bi;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        double v = sm.red_v[0];
-        int i = sm.red_i[0];
-        for (int w = 1; w < NW; ++w)
-          if (sm.red_v[w] > v || (sm.red_v[w] == v && sm.red_i[w] < i)) {
-            v = sm.red_v[w];
-            i = sm.red_i[w];
+    // The panel is factored by wave 0 alone: its LDS accesses are ordered
+    // within the wave, so a column step needs no workgroup barrier.
+    if (wave == 0)
+      for (int j = 0; j < jb; ++j) {
+        double bv = -1.0;
+        int bi = 1 << 30;
+        for (int r = j + lane; r < m; r += 64) {
+          const double a = fabs(double(panel[r + j * m]));
+          if (a > bv) {  // a lane visits its rows in increasing order
+            bv = a;
+            bi = r;
           }
-        if (i >= m) i = j;  // no candidate compared (NaN column): keep the row
-        sm.piv[k0 + j] = k0 + i;
-        if (i != j) sm.swapped = 1;
-        if (!(v > 0.0) && atomicCAS(status, 0, kStatusSingular) == 0) status[2] = instance;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {  // every lane ends with the result
+          const double v2 = __shfl_xor(bv, off, 64);
+          const int i2 = __shfl_xor(bi, off, 64);
+          if (v2 > bv || (v2 == bv && i2 < bi)) {
+            bv = v2;
+            bi = i2;
+          }
+        }
+        const int p = bi < m ? bi : j;  // no candidate compared (NaN column): keep the row
+        if (lane == 0) {
+          sm.piv[k0 + j] = k0 + p;
+          if (p != j) sm.swapped = 1;
+          if (!(bv > 0.0) && atomicCAS(status, 0, kStatusSingular) == 0) status[2] = instance;
+        }
+        if (p != j)
+          for (int c = lane; c < jb; c += 64) {
+            const T t = panel[j + c * m];
+            panel[j + c * m] = panel[p + c * m];
+            panel[p + c * m] = t;
+          }
+        wave_fence();
+        const T piv = panel[j + j * m];
+        if (piv != T(0))
+          for (int r = j + 1 + lane; r < m; r += 64) {
+            const T l = panel[r + j * m] / piv;
+            panel[r + j * m] = l;
+            for (int c = j + 1; c < jb; ++c) panel[r + c * m] -= l * panel[j + c * m];
+          }
+        wave_fence();
       }
-      __syncthreads();
-      const int p = sm.piv[k0 + j] - k0;
-      if (p != j)
-        for (int c = tid; c < jb; c += NT) {
-          const T t = panel[j + c * m];
-          panel[j + c * m] = panel[p + c * m];
-          panel[p + c * m] = t;
-        }
-      __syncthreads();
-      const T piv = panel[j + j * m];
-      if (piv != T(0))
-        for (int r = j + 1 + tid; r < m; r += NT) {
-          const T l = panel[r + j * m] / piv;
-          panel[r + j * m] = l;
-          for (int c = j + 1; c < jb; ++c) panel[r + c * m] -= l * panel[j + c * m];
-        }
-      __syncthreads();
-    }
+    __syncthreads();
     // U11 back to W (L11 below its diagonal is not needed there)
     for (int c = 0; c < jb; ++c)
-      for (int r = tid; r <= min(c, jb - 1); r += NT)
-        W[(k0 + r) + int64_t(k0 + c) * ldw] = panel[r + c * m];
+      for (int r = tid; r <= c; r += NT) W[unsigned((k0 + r) + (k0 + c) * ldw)] = panel[r + c * m];
     const int c0 = k0 + jb;
     if (c0 < ncol) {
-      // the panel's row interchanges on the columns to its right
-      if (sm.swapped)
+      if (sm.swapped) {
+        if (k0 == 0 && c0 < n) {  // interchanges may not touch S: work on a copy
+          copy_block<T, NT>(W + unsigned(c0 * ldw), ldw, S + unsigned(c0 * lds), lds, n, n - c0);
+          src = Wc;
+          lsrc = ldw;
+          __syncthreads();
+        }
+        // the panel's row interchanges on the columns to its right
         for (int c = c0 + tid; c < ncol; c += NT) {
-          T* col = W + int64_t(c) * ldw;
+          gptr<T> col = W + unsigned(c * ldw);
           for (int j = 0; j < jb; ++j) {
             const int pr = sm.piv[k0 + j];
             if (pr != k0 + j) {
@@ -242,104 +309,169 @@ __device__ void batch_solve(const T* __restrict__ S, int64_t lds, int n, const T
             }
           }
         }
-      // Linv = L11^-1 (unit lower), one thread per column, into ustage
+      }
+      // Linv = L11^-1 (unit lower): lane c of wave 0 solves L11 x = e_c with
+      // x in registers; the result goes to ustage
       T* linv = sm.ustage;  // [i + c * PB], reused below after a barrier
-      if (tid < jb) {
-        const int c = tid;
-        for (int i = 0; i < jb; ++i) {
-          T s = i == c ? T(1) : T(0);
-          if (i > c)
-            for (int l = c; l < i; ++l) s -= panel[i + l * m] * linv[l + c * PB];
-          linv[i + c * PB] = s;
+      if (wave == 0 && lane < jb) {
+        T xc[PB];
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+          T s = i == lane ? T(1) : T(0);
+          if (i < jb) {
+#pragma unroll
+            for (int l = 0; l < i; ++l) s -= panel[i + l * m] * xc[l];
+          }
+          xc[i] = s;
         }
+#pragma unroll
+        for (int i = 0; i < PB; ++i)
+          if (i < jb) linv[i + lane * PB] = xc[i];
       }
       __syncthreads();
       // G = [I - Linv ; L21 Linv] overwrites the panel, so that one update
       // A(k0.., right) -= G A12 gives U12 = Linv A12 in the top jb rows and
-      // A22 - L21 U12 below them. Row r of L21 Linv is built in place in
-      // increasing column order (column c reads L21(r, l) for l >= c only).
-      for (int r = jb + tid; r < m; r += NT)
-        for (int c = 0; c < jb; ++c) {
+      // A22 - L21 U12 below them. Row r of L21 is held in registers.
+      for (int r = jb + tid; r < m; r += NT) {
+        T lr[PB];
+#pragma unroll
+        for (int l = 0; l < PB; ++l) lr[l] = l < jb ? panel[r + l * m] : T(0);
+#pragma unroll
+        for (int c = 0; c < PB; ++c) {
+          if (c >= jb) break;
           T s = 0;
-          for (int l = c; l < jb; ++l) s += panel[r + l * m] * linv[l + c * PB];
+#pragma unroll
+          for (int l = c; l < PB; ++l)
+            if (l < jb) s += lr[l] * linv[l + c * PB];  // linv is unset beyond jb
           panel[r + c * m] = s;
         }
+      }
       for (int e = tid; e < jb * jb; e += NT) {
         const int i = e % jb, c = e / jb;
         panel[i + c * m] = (i == c ? T(1) : T(0)) - (i >= c ? linv[i + c * PB] : T(0));
       }
       __syncthreads();
-      // A(k0.., c0..) -= G A12 in chunks of 64 columns. A wave's tile: rows
-      // lane + 64 a (a < 4) of a 256-row block by 4 adjacent columns, so the
-      // G reads are consecutive across lanes and the A12 reads broadcast.
-      for (int cc = c0; cc < ncol; cc += 64) {
-        const int nc = min(64, ncol - cc);
-        for (int e = tid; e < PB * 64; e += NT) {
-          const int kk = e % PB, c = e / PB;
-          sm.ustage[kk + c * PB] =
-              (kk < jb && c < nc) ? W[(k0 + kk) + int64_t(cc + c) * ldw] : T(0);
+      // A(k0.., c0..) -= G A12 in chunks of kCW columns; the old values of a
+      // column come from src (S for the first panel) except the right-hand
+      // side, and the new ones go to W. A wave's tile: rows lane + 64 a
+      // (a < 4) of a 256-row block by 4 adjacent columns, so the G reads are
+      // consecutive across lanes and the A12 reads broadcast; a column's
+      // base address is wave-uniform. Two register tiles alternate: one is
+      // loaded while the other is updated. Row blocks that end inside the
+      // matrix load and store without masks; the last one clamps its load
+      // rows (always valid addresses) and masks its stores. G is read
+      // unconditionally (rows past m stay inside the panel array and only
+      // feed discarded values).
+      gcptr<T> colsrc = k0 == 0 ? src : Wc;
+      const int colld = k0 == 0 ? lsrc : ldw;
+      auto col_in = [&](int col) -> gcptr<T> {  // column `col` (<= n), row k0
+        return (col < n ? colsrc + unsigned(col * colld) : Wc + unsigned(n * ldw)) + k0;
+      };
+      for (int cc = c0; cc < ncol; cc += kCW) {
+        const int nc = min(kCW, ncol - cc);
+        static_assert((PB * kCW) % NT == 0, "staging loop");
+#pragma unroll
+        for (int u = 0; u < PB * kCW / NT; ++u) {
+          const int e = tid + NT * u;
+          const int kk = e / kCW, c = e % kCW;
+          const T v = col_in(cc + min(c, nc - 1))[min(kk, jb - 1)];
+          sm.ustage[c + kk * kCW] = (kk < jb && c < nc) ? v : T(0);
         }
         __syncthreads();
-        const int ncg = (nc + 3) >> 2, nrb = (m + 255) >> 8;
-        for (int t = wave; t < nrb * ncg; t += NW) {
+        const int ncg = (nc + 3) >> 2, nrb = (m + 255) >> 8, ntile = nrb * ncg;
+        auto load = [&](T (&v)[4][4], int t) {
           const int rb = t / ncg, cg = t - rb * ncg;
+          const int r0 = rb * 256 + lane;
+          const bool full = rb * 256 + 256 <= m;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            gcptr<T> cp = col_in(cc + min(cg * 4 + b, nc - 1));
+            if (full) {
+#pragma unroll
+              for (int a = 0; a < 4; ++a) v[a][b] = cp[unsigned(r0 + 64 * a)];
+            } else {
+#pragma unroll
+              for (int a = 0; a < 4; ++a) v[a][b] = cp[unsigned(min(r0 + 64 * a, m - 1))];
+            }
+          }
+        };
+        auto update = [&](T (&v)[4][4], int t) {
+          const int rb = t / ncg, cg = t - rb * ncg;
+          const int r0 = rb * 256 + lane;
+          const T* lp = panel + r0;
+          const T* up = sm.ustage + cg * 4;
+          // products into fresh registers: the loop never waits for the
+          // tile's loads, which are only needed after it
           T acc[4][4];
 #pragma unroll
           for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
-          const T* lp = panel + rb * 256 + lane;
-          const T* up = sm.ustage + cg * 4 * PB;
           for (int kk = 0; kk < jb; ++kk) {
             T av[4], bv[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
-              av[a] = (rb * 256 + lane + 64 * a < m) ? lp[64 * a + kk * m] : T(0);
+            for (int a = 0; a < 4; ++a) av[a] = lp[64 * a + kk * m];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) bv[b] = up[kk + b * PB];
+            for (int b = 0; b < 4; ++b) bv[b] = up[kk * kCW + b];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
               for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
           }
+          const bool full = rb * 256 + 256 <= m;
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
             if (cg * 4 + b >= nc) continue;
-            T* col = W + int64_t(cc + cg * 4 + b) * ldw + k0;
+            gptr<T> col = W + unsigned((cc + cg * 4 + b) * ldw + k0);
+            if (full) {
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-              const int r = rb * 256 + lane + 64 * a;
-              if (r < m) col[r] -= acc[a][b];
+              for (int a = 0; a < 4; ++a) col[unsigned(r0 + 64 * a)] = v[a][b] - acc[a][b];
+            } else {
+#pragma unroll
+              for (int a = 0; a < 4; ++a)
+                if (r0 + 64 * a < m) col[unsigned(r0 + 64 * a)] = v[a][b] - acc[a][b];
             }
           }
+        };
+        T ta[4][4], tb[4][4];
+        if (wave < ntile) load(ta, wave);
+        for (int t = wave; t < ntile; t += 2 * NW) {
+          if (t + NW < ntile) load(tb, t + NW);
+          update(ta, t);
+          if (t + NW >= ntile) break;
+          if (t + 2 * NW < ntile) load(ta, t + 2 * NW);
+          update(tb, t + NW);
         }
         __syncthreads();
       }
     }
+    src = Wc;
+    lsrc = ldw;
     __syncthreads();
   }
   // back substitution U y = c (column n), blocks of up to 64 rows from the
-  // bottom: wave 0 solves the diagonal block, then every thread updates the
-  // rows above it
-  const T* rhs = W + int64_t(n) * ldw;
-  for (int i = tid; i < n; i += NT) y[i] = rhs[i];
-  __syncthreads();
+  // bottom: the diagonal block is staged in LDS and solved by wave 0, then
+  // every thread updates the rows above it
+  for (int i = tid; i < n; i += NT) y[i] = Wc[unsigned(i + n * ldw)];
+  T* ub = sm.panel;  // [i + j * 64]
   for (int r1 = n; r1 > 0; r1 -= 64) {
-    const int r0 = max(0, r1 - 64);
+    const int r0 = max(0, r1 - 64), nb = r1 - r0;
+    copy_block<T, NT>(ub, 64, Wc + unsigned(r0 + r0 * ldw), ldw, nb, nb);
+    __syncthreads();
     if (wave == 0) {
-      T yi = (r0 + lane < r1) ? y[r0 + lane] : T(0);
-      for (int i = r1 - 1; i >= r0; --i) {
-        T xi = __shfl(yi, i - r0, 64);
-        xi = xi / W[i + int64_t(i) * ldw];
-        if (lane == i - r0) yi = xi;
-        if (lane < i - r0) yi -= W[(r0 + lane) + int64_t(i) * ldw] * xi;
+      T yi = lane < nb ? y[r0 + lane] : T(0);
+      for (int i = nb - 1; i >= 0; --i) {
+        const T xi = __shfl(yi, i, 64) / ub[i + i * 64];
+        if (lane == i) yi = xi;
+        if (lane < i) yi -= ub[lane + i * 64] * xi;
       }
-      if (r0 + lane < r1) y[r0 + lane] = yi;
+      if (lane < nb) y[r0 + lane] = yi;
     }
     __syncthreads();
     for (int r = tid; r < r0; r += NT) {
       T s = y[r];
-      for (int i = r0; i < r1; ++i) s -= W[r + int64_t(i) * ldw] * y[i];
+#pragma unroll 16
+      for (int i = r0; i < r1; ++i) s -= Wc[unsigned(r + i * ldw)] * y[i];
       y[r] = s;
     }
     __syncthreads();
@@ -355,42 +487,51 @@ __global__ __launch_bounds__(NT) void batch_kernel(const BProgram* __restrict__ 
   __shared__ Smem<T, PB, NT> sm;
   const BProgram& p = *prog;
   const int tid = threadIdx.x;
-  T* W = scratch + int64_t(blockIdx.x) * scratch_stride;
+  gptr<T> W = gptr<T>(scratch) + int64_t(blockIdx.x) * scratch_stride;
+  if (tid == 0) sm.q = int(atomicAdd(queue, 1u));
+  __syncthreads();
   for (;;) {
-    if (tid == 0) sm.q = int(atomicAdd(queue, 1u));
-    __syncthreads();
     const int q = __builtin_amdgcn_readfirstlane(sm.q);
     __syncthreads();
     if (q >= count) break;
+    // claim the next instance now: the atomic's latency overlaps this one
+    int next = 0;
+    if (tid == 0) next = int(atomicAdd(queue, 1u));
     const int idx = order[q];
     const BInst* I = inst + idx;
     const int n = int(I->n);
     for (int o = 0; o < p.n_ops; ++o) {
       const BOp& op = p.ops[o];
       if (op.kind == B_LOAD) {
-        const T* src = static_cast<const T*>(I->leaf[op.leaf]);
+        gcptr<T> src = gcptr<T>(I->leaf[op.leaf]);
         for (int i = tid; i < n; i += NT) sm.slots[op.dst][i] = src[i];
       } else if (op.kind == B_GEMV) {
-        const T* M = static_cast<const T*>(I->leaf[op.leaf]);
+        gcptr<T> M = gcptr<T>(I->leaf[op.leaf]);
+        const int ld = int(I->ld[op.leaf]);
         if (!op.trans)
-          gemv_n<T, NT>(M, I->ld[op.leaf], n, T(op.alpha), sm.slots[op.src], sm.slots[op.dst],
-                        sm.panel);
+          gemv_n<T, NT>(M, ld, n, T(op.alpha), sm.slots[op.src], sm.slots[op.dst], sm.panel);
         else
-          gemv_t<T, NT>(M, I->ld[op.leaf], n, T(op.alpha), sm.slots[op.src], sm.slots[op.dst]);
+          gemv_t<T, NT>(M, ld, n, T(op.alpha), sm.slots[op.src], sm.slots[op.dst]);
       } else if (op.kind == B_SOLVE) {
-        batch_solve<T, PB, NT>(static_cast<const T*>(I->leaf[op.leaf]), I->ld[op.leaf], n,
+        batch_solve<T, PB, NT>(gcptr<T>(I->leaf[op.leaf]), int(I->ld[op.leaf]), n,
                                sm.slots[op.src], sm.slots[op.dst], W, sm, status, idx);
-      } else {  // B_EW
-        T* out = op.dst == kBOut ? static_cast<T*>(I->out) : sm.slots[op.dst];
+      } else if (op.dst == kBOut) {  // B_EW into the output
+        gptr<T> out = gptr<T>(I->out);
+        for (int i = tid; i < n; i += NT) out[i] = ew_batch<T>(p, op, I, sm.slots, i);
+      } else {  // B_EW into a slot
         for (int i = tid; i < n; i += NT) {
           const T v = ew_batch<T>(p, op, I, sm.slots, i);
-          out[i] = v;
+          sm.slots[op.dst][i] = v;
         }
       }
       __syncthreads();
     }
-    if (p.out_slot != kBOut)
-      for (int i = tid; i < n; i += NT) static_cast<T*>(I->out)[i] = sm.slots[p.out_slot][i];
+    if (p.out_slot != kBOut) {
+      gptr<T> out = gptr<T>(I->out);
+      for (int i = tid; i < n; i += NT) out[i] = sm.slots[p.out_slot][i];
+    }
+    if (tid == 0) sm.q = next;
+    __syncthreads();
   }
 }
 
