@@ -1030,6 +1030,9 @@ class Planner {
   }
 
   void solve(const View& s, const View& b, const View& x) {
+    if (s.rows > k::kLuMaxN)
+      return (void)fail(HEXLA_E_UNSUPPORTED,
+                        "solve: n > " + std::to_string(k::kLuMaxN) + " is not supported");
     if (dtype_ == HEXLA_F64 && o_.solve_precision != HEXLA_SOLVE_PLAIN) return refined_solve(s, b, x);
     const int64_t n = s.rows, r = b.cols;
     View lu = temp(n, n);
@@ -1057,6 +1060,7 @@ class Planner {
     q.n = n;
     q.nrhs = r;
     q.rowid = f.rowid;
+    q.luwork = f.luwork;  // the inverses of the diagonal blocks
     q.flops = 2.0 * double(n) * n * r;
     q.bytes = double(esz_) * (double(n) * n + 2.0 * double(n) * r);
     if (b.trans || x.trans) {
