@@ -21,6 +21,7 @@
 #include <algorithm>
 
 #include "kernels.h"
+#include "wave_device.h"
 
 namespace hexla {
 namespace k {
@@ -43,11 +44,21 @@ __device__ __forceinline__ float bexp<float>(float x) { return expf(x); }
 template <>
 __device__ __forceinline__ double bexp<double>(double x) { return exp(x); }
 
+// A wave's pivot candidate for one column: |value|, position, and the
+// candidate's row (rotated, its multiplier part zeroed).
+template <typename T, int PB, int NW>
+struct alignas(16) Pub {
+  T row[NW][PB];
+  T val[NW];
+  int pos[NW];
+};
+
 template <typename T, int PB, int NT>
 struct Smem {
   T slots[kBMaxSlots][kBMaxN];
   T panel[kBMaxN * PB];  // LU panel; GEMV reduction buffer; diagonal blocks of U
   T ustage[PB * kCW];    // A12 chunk of the trailing update [k][column]; L11^-1
+  Pub<T, PB, NT / 64> pub[2];  // per column parity
   int piv[kBMaxN];
   int q;
   int swapped;
@@ -211,11 +222,134 @@ __device__ void gemv_t(gcptr<T> M, int ld, int n, T alpha, const T* x, T* y) {
   }
 }
 
+// GEPP of the m x jb panel P (column-major, ld lp; jb <= PB, m <= kBMaxN)
+// into sm.panel (ld m): multipliers below the diagonal, U on and above it,
+// rows at their final positions. piv[j] = k0 + the position chosen at step j
+// (positions j and piv[j] - k0 are interchanged, as in xGETRF). Each thread
+// holds rows tid + NT a in registers; rows never move between threads, each
+// tracks its current position instead. A row is kept rotated so that the
+// current column is v[0] (all register indices are static): after step j it
+// turns left by one and appends its multiplier (rows below the pivot) or
+// column j itself (finished rows). Per column every wave publishes its best
+// candidate (largest |a|, lowest position on ties, NaN below every number)
+// with the candidate's row, the workgroup meets at one barrier, and every
+// thread picks the same winner. The candidate buffers alternate with the
+// column's parity, so one barrier per column suffices.
+template <typename T, int PB, int NT>
+__device__ void panel_factor(gcptr<T> P, int lp, int m, int jb, Smem<T, PB, NT>& sm, int* piv,
+                             int k0, int32_t* status, int instance) {
+  constexpr int NW = NT / 64;
+  constexpr int RPT = kBMaxN / NT;
+  constexpr int kNone = 1 << 29;  // position of a thread's row slot past m
+  static_assert(RPT * NT == kBMaxN, "rows per thread");
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+  T v[RPT][PB];
+  int pos[RPT];
+#pragma unroll
+  for (int a = 0; a < RPT; ++a) {
+    const int r = tid + NT * a;
+    pos[a] = r < m ? r : kNone;
+    const int rr = min(r, m - 1);  // clamped: every load is issued unconditionally
+#pragma unroll
+    for (int c = 0; c < PB; ++c) v[a][c] = P[unsigned(rr + min(c, jb - 1) * lp)];
+  }
+#pragma unroll
+  for (int a = 0; a < RPT; ++a)
+#pragma unroll
+    for (int c = 0; c < PB; ++c)
+      if (pos[a] == kNone || c >= jb) v[a][c] = T(0);
+  int swapped = 0;
+#pragma unroll 1
+  for (int j = 0; j < jb; ++j) {
+    auto& pub = sm.pub[j & 1];
+    T best = T(-2);
+    int bp = -1;
+#pragma unroll
+    for (int a = 0; a < RPT; ++a) {
+      T x = fabs(v[a][0]);
+      x = x == x ? x : T(-0.5);
+      const bool take =
+          (pos[a] >= j) & (pos[a] < m) & ((x > best) | ((x == best) & (pos[a] < bp)));
+      best = take ? x : best;
+      bp = take ? pos[a] : bp;
+    }
+    wave_argmax(best, bp);
+    if (lane == 0) {
+      pub.val[wave] = best;
+      pub.pos[wave] = bp;
+    }
+    // the candidate's row as it is; then lanes < j zero its multiplier part
+    // (the last j positions) in the wave's own slot, after it in LDS order
+#pragma unroll
+    for (int a = 0; a < RPT; ++a)
+      if (pos[a] == bp) {
+#pragma unroll
+        for (int c = 0; c < PB; ++c) pub.row[wave][c] = v[a][c];
+      }
+    wave_fence();
+    if (lane < j) pub.row[wave][PB - j + lane] = T(0);
+    __syncthreads();
+    T cv[NW];
+    int cp[NW];
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      cv[q] = pub.val[q];
+      cp[q] = pub.pos[q];
+    }
+    T wv = cv[0];
+    int wp = cp[0], w = 0;
+#pragma unroll
+    for (int q = 1; q < NW; ++q) {
+      const bool take = (cv[q] > wv) | ((cv[q] == wv) & (cp[q] < wp));
+      wv = take ? cv[q] : wv;
+      wp = take ? cp[q] : wp;
+      w = take ? q : w;
+    }
+    T prow[PB];
+#pragma unroll
+    for (int c = 0; c < PB; ++c) prow[c] = pub.row[w][c];
+    const T pv = prow[0];
+    const T rp = T(1) / pv;  // multipliers as a * (1 / pivot)
+    if (tid == 0) {
+      piv[j] = k0 + wp;
+      if (!(wv > T(0)) && atomicCAS(status, 0, kStatusSingular) == 0) status[2] = instance;
+    }
+    swapped |= wp != j;
+#pragma unroll
+    for (int a = 0; a < RPT; ++a) {
+      pos[a] = pos[a] == wp ? j : (pos[a] == j ? wp : pos[a]);
+      const bool act = (pos[a] > j) & (pos[a] < m) & (pv != T(0));
+      const T v0 = v[a][0];
+      const T l = act ? v0 * rp : T(0);
+#pragma unroll
+      for (int c = 0; c < PB - 1; ++c) v[a][c] = v[a][c + 1] - l * prow[c + 1];
+      v[a][PB - 1] = act ? l : v0;
+    }
+  }
+  // a narrow last panel: turn the rows the rest of the way round
+#pragma unroll 1
+  for (int j = jb; j < PB; ++j)
+#pragma unroll
+    for (int a = 0; a < RPT; ++a) {
+      const T v0 = v[a][0];
+#pragma unroll
+      for (int c = 0; c < PB - 1; ++c) v[a][c] = v[a][c + 1];
+      v[a][PB - 1] = v0;
+    }
+#pragma unroll
+  for (int a = 0; a < RPT; ++a)
+    if (pos[a] < m)
+#pragma unroll
+      for (int c = 0; c < PB; ++c)
+        if (c < jb) sm.panel[pos[a] + c * m] = v[a][c];
+  if (tid == 0) sm.swapped = swapped;
+}
+
 // Solves S y = x for one instance by Gaussian elimination with partial
 // pivoting on the augmented matrix [S | x] (n x (n+1) in W, ld n): the right-
 // hand side rides along as column n, so the multipliers L are never stored
-// outside the panel. Panels of PB columns are factored in LDS (pivot = first
-// largest |value| of the column, as in GEPP); the panel's row interchanges
+// outside the panel. Panels of PB columns are factored in registers (pivot =
+// first largest |value| of the column, as in GEPP); the panel's row interchanges
 // are applied to the columns on its right, and one rank-PB update with the
 // panel rewritten as G = [I - L11^-1 ; L21 L11^-1] turns the rows k0.. of
 // those columns into U12 = L11^-1 A12 and A22 - L21 U12 (no separate
@@ -237,53 +371,8 @@ __device__ void batch_solve(gcptr<T> S, int lds, int n, const T* x, T* y, gptr<T
   int lsrc = lds;
   for (int k0 = 0; k0 < n; k0 += PB) {
     const int jb = min(PB, n - k0), m = n - k0;
-    copy_block<T, NT>(panel, m, src + unsigned(k0 + k0 * lsrc), lsrc, m, jb);
-    if (tid == 0) sm.swapped = 0;
-    __syncthreads();
-    // The panel is factored by wave 0 alone: its LDS accesses are ordered
-    // within the wave, so a column step needs no workgroup barrier.
-    if (wave == 0)
-      for (int j = 0; j < jb; ++j) {
-        double bv = -1.0;
-        int bi = 1 << 30;
-        for (int r = j + lane; r < m; r += 64) {
-          const double a = fabs(double(panel[r + j * m]));
-          if (a > bv) {  // a lane visits its rows in increasing order
-            bv = a;
-            bi = r;
-          }
-        }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {  // every lane ends with the result
-          const double v2 = __shfl_xor(bv, off, 64);
-          const int i2 = __shfl_xor(bi, off, 64);
-          if (v2 > bv || (v2 == bv && i2 < bi)) {
-            bv = v2;
-            bi = i2;
-          }
-        }
-        const int p = bi < m ? bi : j;  // no candidate compared (NaN column): keep the row
-        if (lane == 0) {
-          sm.piv[k0 + j] = k0 + p;
-          if (p != j) sm.swapped = 1;
-          if (!(bv > 0.0) && atomicCAS(status, 0, kStatusSingular) == 0) status[2] = instance;
-        }
-        if (p != j)
-          for (int c = lane; c < jb; c += 64) {
-            const T t = panel[j + c * m];
-            panel[j + c * m] = panel[p + c * m];
-            panel[p + c * m] = t;
-          }
-        wave_fence();
-        const T piv = panel[j + j * m];
-        if (piv != T(0))
-          for (int r = j + 1 + lane; r < m; r += 64) {
-            const T l = panel[r + j * m] / piv;
-            panel[r + j * m] = l;
-            for (int c = j + 1; c < jb; ++c) panel[r + c * m] -= l * panel[j + c * m];
-          }
-        wave_fence();
-      }
+    panel_factor<T, PB, NT>(src + unsigned(k0 + k0 * lsrc), lsrc, m, jb, sm, sm.piv + k0, k0,
+                            status, instance);
     __syncthreads();
     // U11 back to W (L11 below its diagonal is not needed there)
     for (int c = 0; c < jb; ++c)

@@ -24,6 +24,7 @@
 
 #include "ew_device.h"
 #include "kernels.h"
+#include "wave_device.h"
 
 namespace hexla {
 namespace k {
@@ -104,37 +105,6 @@ __device__ bool grid_barrier(unsigned* counter, unsigned target, int* abort_flag
   }
   __syncthreads();
   return *s_flag != 0;
-}
-
-// One step of a wave-wide argmax on DPP moves (largest a, lowest i on ties):
-// lanes whose DPP source is outside the row keep their own pair.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ void argmax_step(double& a, int& i) {
-  const int lo = __double2loint(a), hi = __double2hiint(a);
-  const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xF, false);
-  const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xF, false);
-  const int i2 = __builtin_amdgcn_update_dpp(i, i, CTRL, ROW_MASK, 0xF, false);
-  const double a2 = __hiloint2double(hi2, lo2);
-  if (a2 > a || (a2 == a && i2 < i)) {
-    a = a2;
-    i = i2;
-  }
-}
-
-// Argmax over the 64 lanes of a wave (every lane active), returned to every
-// lane: row shifts 1, 2, 4, 8 leave each row's result in its lane 15, the row
-// broadcasts 15 and 31 combine the rows into lane 63, which is read back.
-__device__ __forceinline__ void wave_argmax(double& a, int& i) {
-  argmax_step<0x111, 0xF>(a, i);  // row_shr:1
-  argmax_step<0x112, 0xF>(a, i);  // row_shr:2
-  argmax_step<0x114, 0xF>(a, i);  // row_shr:4
-  argmax_step<0x118, 0xF>(a, i);  // row_shr:8
-  argmax_step<0x142, 0xA>(a, i);  // row_bcast:15 into rows 1 and 3
-  argmax_step<0x143, 0xC>(a, i);  // row_bcast:31 into rows 2 and 3
-  const int lo = __builtin_amdgcn_readlane(__double2loint(a), 63);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(a), 63);
-  i = __builtin_amdgcn_readlane(i, 63);
-  a = __hiloint2double(hi, lo);
 }
 
 // Panel factorisation. Participants are the workgroups with blockIdx a
