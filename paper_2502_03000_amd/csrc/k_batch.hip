@@ -7,15 +7,15 @@
 //                                 in a vector reduces to (ordering, Sec. II)
 //   SOLVE  y = S^-1 x             the inv(S)*b rewrite (Sec. I, Sec. II): LU
 //                                 with partial pivoting of the augmented
-//                                 matrix [S | x] in per-workgroup scratch,
-//                                 panels of PB columns factored in LDS, then
-//                                 back substitution
+//                                 matrix [S | x], panels of PB columns held
+//                                 in registers, then back substitution
 //   EW     element-wise program over vectors (the fused loop of Sec. II)
-// One workgroup owns an instance, so the cost is latency: loops that touch
-// global memory issue their loads in batches before using them, the trailing
-// update loads its next tile while it computes the current one, and global
-// accesses go through global-typed pointers with wave-uniform bases (no flat
-// instructions, whose loads would also hold up the LDS wait counter).
+// One workgroup owns an instance, so the cost is latency and the trailing
+// matrix's trips through memory: loops that touch global memory issue their
+// loads in batches before using them, the trailing update loads its next
+// chunk while it computes the current one, and global accesses go through
+// global-typed pointers with wave-uniform bases (no flat instructions, whose
+// loads would also hold up the LDS wait counter).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,7 +35,6 @@ using gcptr = const __attribute__((address_space(1))) T*;
 
 constexpr int kStatusSingular = 5;
 constexpr int kR = kBMaxN / 64;  // rows per lane of a full column
-constexpr int kCW = 128;         // columns per chunk of the trailing update
 
 template <typename T>
 __device__ __forceinline__ T bexp(T x);
@@ -53,15 +52,28 @@ struct alignas(16) Pub {
   int pos[NW];
 };
 
+// Columns per chunk of the trailing update: two chunks of RPT rows per
+// thread stay in registers (64 VGPRs) beside the panel's G rows.
+template <typename T, int NT>
+constexpr int update_chunk() {
+  return 64 / (2 * (kBMaxN / NT) * int(sizeof(T) / 4));
+}
+
 template <typename T, int PB, int NT>
 struct Smem {
+  static constexpr int UC = update_chunk<T, NT>();
   T slots[kBMaxSlots][kBMaxN];
-  T panel[kBMaxN * PB];  // LU panel; GEMV reduction buffer; diagonal blocks of U
-  T ustage[PB * kCW];    // A12 chunk of the trailing update [k][column]; L11^-1
-  Pub<T, PB, NT / 64> pub[2];  // per column parity
-  int piv[kBMaxN];
+  union {
+    T red[NT / 64][kBMaxN];  // GEMV: per-wave partial sums
+    T ub[64 * 64];           // back substitution: diagonal block of U
+    struct {
+      alignas(16) T l11[PB][PB];     // pivot rows of the panel, by position
+      alignas(16) T linvt[PB][PB];   // linvt[c][l] = (L11^-1)(l, c)
+      alignas(16) T ust[2][PB][UC];  // A12 chunk [k][column], by chunk parity
+    } lu;
+  } u;
+  Pub<T, PB, NT / 64> pub[2];  // pivot candidates, by column parity
   int q;
-  int swapped;
 };
 
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
@@ -73,34 +85,12 @@ __device__ __forceinline__ void wave_fence() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// dst(i, j) = src(i, j) for i < rows <= kBMaxN, j < cols (element offsets
-// i + j * ld). Lane l takes rows l + 64 a, wave w columns w, w + NW, ...; two
-// columns of up to kR rows per lane are loaded before any is stored.
-template <typename T, int NT, typename D, typename S>
-__device__ void copy_block(D dst, int ldd, S src, int lds, int rows, int cols) {
-  constexpr int NW = NT / 64;
-  const int lane = threadIdx.x & 63, wave = wave_id();
-  for (int j0 = wave; j0 < cols; j0 += 2 * NW) {
-    T v[2][kR];
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int j = j0 + NW * b;
-#pragma unroll
-      for (int a = 0; a < kR; ++a) {
-        const int i = lane + 64 * a;
-        v[b][a] = (i < rows && j < cols) ? src[unsigned(i + j * lds)] : T(0);
-      }
-    }
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int j = j0 + NW * b;
-#pragma unroll
-      for (int a = 0; a < kR; ++a) {
-        const int i = lane + 64 * a;
-        if (i < rows && j < cols) dst[unsigned(i + j * ldd)] = v[b][a];
-      }
-    }
-  }
+// Workgroup barrier that orders LDS only: global loads and stores in flight
+// stay in flight (a full barrier waits for every one of them).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 template <typename T>
@@ -222,29 +212,30 @@ __device__ void gemv_t(gcptr<T> M, int ld, int n, T alpha, const T* x, T* y) {
   }
 }
 
-// GEPP of the m x jb panel P (column-major, ld lp; jb <= PB, m <= kBMaxN)
-// into sm.panel (ld m): multipliers below the diagonal, U on and above it,
-// rows at their final positions. piv[j] = k0 + the position chosen at step j
-// (positions j and piv[j] - k0 are interchanged, as in xGETRF). Each thread
-// holds rows tid + NT a in registers; rows never move between threads, each
-// tracks its current position instead. A row is kept rotated so that the
-// current column is v[0] (all register indices are static): after step j it
-// turns left by one and appends its multiplier (rows below the pivot) or
-// column j itself (finished rows). Per column every wave publishes its best
-// candidate (largest |a|, lowest position on ties, NaN below every number)
-// with the candidate's row, the workgroup meets at one barrier, and every
-// thread picks the same winner. The candidate buffers alternate with the
-// column's parity, so one barrier per column suffices.
+// GEPP of the m x jb panel P (column-major, ld lp; jb <= PB <= 64, m <=
+// kBMaxN). Thread t holds panel rows ("slots") t + NT a in v[a] and never
+// hands them to another thread: pos[a] tracks the slot's current position
+// (kNone past m), and the interchange of positions j and p at step j only
+// relabels two slots. A row is kept rotated so that the current column is
+// v[0] (all register indices are static): after step j it turns left by one
+// and appends its multiplier (rows below the pivot) or column j itself
+// (finished rows). Per column every wave publishes its best candidate
+// (largest |a|, lowest position on ties, NaN below every number) with the
+// candidate's row, the workgroup meets at one barrier, and every thread
+// picks the same winner; the candidate buffers alternate with the column's
+// parity, so one barrier per column suffices. On return v[a][c] is column c
+// of the factored row: multipliers left of the row's pivot column, U from it
+// on (pivot rows), multipliers throughout (the others); zero beyond jb.
 template <typename T, int PB, int NT>
-__device__ void panel_factor(gcptr<T> P, int lp, int m, int jb, Smem<T, PB, NT>& sm, int* piv,
-                             int k0, int32_t* status, int instance) {
+__device__ __forceinline__ void panel_factor(gcptr<T> P, int lp, int m, int jb,
+                                             Smem<T, PB, NT>& sm, T (&v)[kBMaxN / NT][PB],
+                                             int (&pos)[kBMaxN / NT], int32_t* status,
+                                             int instance) {
   constexpr int NW = NT / 64;
   constexpr int RPT = kBMaxN / NT;
-  constexpr int kNone = 1 << 29;  // position of a thread's row slot past m
-  static_assert(RPT * NT == kBMaxN, "rows per thread");
+  constexpr int kNone = 1 << 29;
+  static_assert(RPT * NT == kBMaxN && PB <= 64, "panel shape");
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
-  T v[RPT][PB];
-  int pos[RPT];
 #pragma unroll
   for (int a = 0; a < RPT; ++a) {
     const int r = tid + NT * a;
@@ -258,7 +249,6 @@ __device__ void panel_factor(gcptr<T> P, int lp, int m, int jb, Smem<T, PB, NT>&
 #pragma unroll
     for (int c = 0; c < PB; ++c)
       if (pos[a] == kNone || c >= jb) v[a][c] = T(0);
-  int swapped = 0;
 #pragma unroll 1
   for (int j = 0; j < jb; ++j) {
     auto& pub = sm.pub[j & 1];
@@ -310,11 +300,8 @@ __device__ void panel_factor(gcptr<T> P, int lp, int m, int jb, Smem<T, PB, NT>&
     for (int c = 0; c < PB; ++c) prow[c] = pub.row[w][c];
     const T pv = prow[0];
     const T rp = T(1) / pv;  // multipliers as a * (1 / pivot)
-    if (tid == 0) {
-      piv[j] = k0 + wp;
-      if (!(wv > T(0)) && atomicCAS(status, 0, kStatusSingular) == 0) status[2] = instance;
-    }
-    swapped |= wp != j;
+    if (tid == 0 && !(wv > T(0)) && atomicCAS(status, 0, kStatusSingular) == 0)
+      status[2] = instance;
 #pragma unroll
     for (int a = 0; a < RPT; ++a) {
       pos[a] = pos[a] == wp ? j : (pos[a] == j ? wp : pos[a]);
@@ -336,216 +323,174 @@ __device__ void panel_factor(gcptr<T> P, int lp, int m, int jb, Smem<T, PB, NT>&
       for (int c = 0; c < PB - 1; ++c) v[a][c] = v[a][c + 1];
       v[a][PB - 1] = v0;
     }
-#pragma unroll
-  for (int a = 0; a < RPT; ++a)
-    if (pos[a] < m)
-#pragma unroll
-      for (int c = 0; c < PB; ++c)
-        if (c < jb) sm.panel[pos[a] + c * m] = v[a][c];
-  if (tid == 0) sm.swapped = swapped;
 }
 
 // Solves S y = x for one instance by Gaussian elimination with partial
-// pivoting on the augmented matrix [S | x] (n x (n+1) in W, ld n): the right-
-// hand side rides along as column n, so the multipliers L are never stored
-// outside the panel. Panels of PB columns are factored in registers (pivot =
-// first largest |value| of the column, as in GEPP); the panel's row interchanges
-// are applied to the columns on its right, and one rank-PB update with the
-// panel rewritten as G = [I - L11^-1 ; L21 L11^-1] turns the rows k0.. of
-// those columns into U12 = L11^-1 A12 and A22 - L21 U12 (no separate
-// triangular solve). Then back substitution U y = c. y may be x.
-// The first panel and its update read S itself, so S is copied to W only
-// when that panel interchanges rows. Offsets are 32-bit: the planner keeps
-// every instance matrix within 2^31 bytes.
+// pivoting on the augmented matrix [S | x]: the right-hand side rides along
+// as column n, so L is never stored. Per panel of PB columns (k0, jb = its
+// width, m = n - k0 rows):
+//   1. panel_factor leaves the factored rows in registers, by slot.
+//   2. L11 (the pivot rows) goes to LDS, U11 to memory; lanes < PB form
+//      L11^-1 column by column.
+//   3. Each thread turns its rows into rows of G = [I - L11^-1 ; L21 L11^-1]
+//      in place, so that one product A(k0.., right) -= G A12 gives U12 =
+//      L11^-1 A12 in the pivot rows and A22 - L21 U12 in the others.
+//   4. The columns right of the panel (with the right-hand side) are
+//      updated in chunks of UC columns: a thread loads its slots' old
+//      values (coalesced), the pivot rows' owners stage them as A12 in LDS,
+//      and the thread writes its new values at the slots' final positions.
+//      The row interchanges of GEPP thus cost nothing extra. Each panel reads
+//      one scratch buffer and writes the other (S itself for the first
+//      panel), so no thread's store can reach a value another thread has yet
+//      to load, and the chunk barriers need to order LDS only. The next
+//      chunk is loaded while the current one is computed.
+// Then back substitution U y = c; row i of U and of c sits in the buffer its
+// panel wrote. The two buffers W and W + half hold (n+1) x (n+2) matrices
+// (ld n+1): row n and column n+1 take the stores of empty slots and of
+// columns past the end, so every load and store is issued unconditionally.
+// y may be x. Offsets are 32-bit: the planner keeps every instance matrix
+// within 2^31 bytes.
 template <typename T, int PB, int NT>
-__device__ void batch_solve(gcptr<T> S, int lds, int n, const T* x, T* y, gptr<T> W,
+__device__ void batch_solve(gcptr<T> S, int lds, int n, const T* x, T* y, gptr<T> W, int64_t half,
                             Smem<T, PB, NT>& sm, int32_t* status, int instance) {
-  constexpr int NW = NT / 64;
+  constexpr int RPT = kBMaxN / NT;
+  constexpr int UC = Smem<T, PB, NT>::UC;
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
-  const int ldw = n;
-  const int ncol = n + 1;
-  T* panel = sm.panel;
-  gcptr<T> Wc = W;
-  for (int i = tid; i < n; i += NT) W[unsigned(i + n * ldw)] = x[i];
-  gcptr<T> src = S;  // columns < n of the matrix being factored: S for the first panel
-  int lsrc = lds;
-  for (int k0 = 0; k0 < n; k0 += PB) {
+  const int ld = n + 1, ncol = n + 1;
+  gptr<T> B0 = W, B1 = W + half;
+  for (int i = tid; i < n; i += NT) B1[unsigned(i + n * ld)] = x[i];  // read by the first panel
+  __syncthreads();
+  int p = 0;
+  for (int k0 = 0; k0 < n; k0 += PB, ++p) {
     const int jb = min(PB, n - k0), m = n - k0;
-    panel_factor<T, PB, NT>(src + unsigned(k0 + k0 * lsrc), lsrc, m, jb, sm, sm.piv + k0, k0,
-                            status, instance);
+    gptr<T> D = (p & 1) ? B1 : B0;             // written by this panel
+    gcptr<T> R = (p & 1) ? B0 : B1;            // written by the previous panel
+    gcptr<T> P = p == 0 ? S : R;               // columns < n of the matrix being factored
+    const int lp = p == 0 ? lds : ld;
+    T v[RPT][PB];
+    int pos[RPT];
+    panel_factor<T, PB, NT>(P + unsigned(k0 + k0 * lp), lp, m, jb, sm, v, pos, status, instance);
+
+    // 2. the pivot rows: whole rows to LDS (the inverse reads below the
+    // diagonal), their U part to memory
+#pragma unroll
+    for (int a = 0; a < RPT; ++a)
+      if (pos[a] < jb) {
+#pragma unroll
+        for (int c = 0; c < PB; ++c) sm.u.lu.l11[pos[a]][c] = v[a][c];
+        gptr<T> dr = D + unsigned(k0 + pos[a]);
+#pragma unroll
+        for (int c = 0; c < PB; ++c)
+          if (c >= pos[a] && c < jb) dr[unsigned((k0 + c) * ld)] = v[a][c];
+      }
     __syncthreads();
-    // U11 back to W (L11 below its diagonal is not needed there)
-    for (int c = 0; c < jb; ++c)
-      for (int r = tid; r <= c; r += NT) W[unsigned((k0 + r) + (k0 + c) * ldw)] = panel[r + c * m];
-    const int c0 = k0 + jb;
-    if (c0 < ncol) {
-      if (sm.swapped) {
-        if (k0 == 0 && c0 < n) {  // interchanges may not touch S: work on a copy
-          copy_block<T, NT>(W + unsigned(c0 * ldw), ldw, S + unsigned(c0 * lds), lds, n, n - c0);
-          src = Wc;
-          lsrc = ldw;
-          __syncthreads();
-        }
-        // the panel's row interchanges on the columns to its right
-        for (int c = c0 + tid; c < ncol; c += NT) {
-          gptr<T> col = W + unsigned(c * ldw);
-          for (int j = 0; j < jb; ++j) {
-            const int pr = sm.piv[k0 + j];
-            if (pr != k0 + j) {
-              const T t = col[k0 + j];
-              col[k0 + j] = col[pr];
-              col[pr] = t;
-            }
-          }
-        }
+    if (tid < PB) {  // column c of L11^-1 (zero above the diagonal and past jb)
+      const int c = tid;
+      T xr[PB];
+#pragma unroll
+      for (int i = 0; i < PB; ++i) {
+        T s = i == c ? T(1) : T(0);
+#pragma unroll
+        for (int l = 0; l < i; ++l) s -= sm.u.lu.l11[i][l] * xr[l];
+        xr[i] = (i < jb) & (c < jb) ? s : T(0);
       }
-      // Linv = L11^-1 (unit lower): lane c of wave 0 solves L11 x = e_c with
-      // x in registers; the result goes to ustage
-      T* linv = sm.ustage;  // [i + c * PB], reused below after a barrier
-      if (wave == 0 && lane < jb) {
-        T xc[PB];
 #pragma unroll
-        for (int i = 0; i < PB; ++i) {
-          T s = i == lane ? T(1) : T(0);
-          if (i < jb) {
+      for (int i = 0; i < PB; ++i) sm.u.lu.linvt[c][i] = xr[i];
+    }
+    __syncthreads();
+
+    // 3. rows of G in place: L21 L11^-1 (ascending c: g_c needs v[l], l >= c)
+    // or, for the pivot row at position q, e_q - row q of L11^-1
 #pragma unroll
-            for (int l = 0; l < i; ++l) s -= panel[i + l * m] * xc[l];
-          }
-          xc[i] = s;
-        }
+    for (int a = 0; a < RPT; ++a) {
+      if (pos[a] < jb) {
+        const int q = pos[a];
 #pragma unroll
-        for (int i = 0; i < PB; ++i)
-          if (i < jb) linv[i + lane * PB] = xc[i];
-      }
-      __syncthreads();
-      // G = [I - Linv ; L21 Linv] overwrites the panel, so that one update
-      // A(k0.., right) -= G A12 gives U12 = Linv A12 in the top jb rows and
-      // A22 - L21 U12 below them. Row r of L21 is held in registers.
-      for (int r = jb + tid; r < m; r += NT) {
-        T lr[PB];
-#pragma unroll
-        for (int l = 0; l < PB; ++l) lr[l] = l < jb ? panel[r + l * m] : T(0);
+        for (int c = 0; c < PB; ++c) v[a][c] = (c == q ? T(1) : T(0)) - sm.u.lu.linvt[c][q];
+      } else {
 #pragma unroll
         for (int c = 0; c < PB; ++c) {
-          if (c >= jb) break;
           T s = 0;
 #pragma unroll
-          for (int l = c; l < PB; ++l)
-            if (l < jb) s += lr[l] * linv[l + c * PB];  // linv is unset beyond jb
-          panel[r + c * m] = s;
+          for (int l = c & ~3; l < PB; ++l) s += v[a][l] * sm.u.lu.linvt[c][l];
+          v[a][c] = s;
         }
-      }
-      for (int e = tid; e < jb * jb; e += NT) {
-        const int i = e % jb, c = e / jb;
-        panel[i + c * m] = (i == c ? T(1) : T(0)) - (i >= c ? linv[i + c * PB] : T(0));
-      }
-      __syncthreads();
-      // A(k0.., c0..) -= G A12 in chunks of kCW columns; the old values of a
-      // column come from src (S for the first panel) except the right-hand
-      // side, and the new ones go to W. A wave's tile: rows lane + 64 a
-      // (a < 4) of a 256-row block by 4 adjacent columns, so the G reads are
-      // consecutive across lanes and the A12 reads broadcast; a column's
-      // base address is wave-uniform. Two register tiles alternate: one is
-      // loaded while the other is updated. Row blocks that end inside the
-      // matrix load and store without masks; the last one clamps its load
-      // rows (always valid addresses) and masks its stores. G is read
-      // unconditionally (rows past m stay inside the panel array and only
-      // feed discarded values).
-      gcptr<T> colsrc = k0 == 0 ? src : Wc;
-      const int colld = k0 == 0 ? lsrc : ldw;
-      auto col_in = [&](int col) -> gcptr<T> {  // column `col` (<= n), row k0
-        return (col < n ? colsrc + unsigned(col * colld) : Wc + unsigned(n * ldw)) + k0;
-      };
-      for (int cc = c0; cc < ncol; cc += kCW) {
-        const int nc = min(kCW, ncol - cc);
-        static_assert((PB * kCW) % NT == 0, "staging loop");
-#pragma unroll
-        for (int u = 0; u < PB * kCW / NT; ++u) {
-          const int e = tid + NT * u;
-          const int kk = e / kCW, c = e % kCW;
-          const T v = col_in(cc + min(c, nc - 1))[min(kk, jb - 1)];
-          sm.ustage[c + kk * kCW] = (kk < jb && c < nc) ? v : T(0);
-        }
-        __syncthreads();
-        const int ncg = (nc + 3) >> 2, nrb = (m + 255) >> 8, ntile = nrb * ncg;
-        auto load = [&](T (&v)[4][4], int t) {
-          const int rb = t / ncg, cg = t - rb * ncg;
-          const int r0 = rb * 256 + lane;
-          const bool full = rb * 256 + 256 <= m;
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            gcptr<T> cp = col_in(cc + min(cg * 4 + b, nc - 1));
-            if (full) {
-#pragma unroll
-              for (int a = 0; a < 4; ++a) v[a][b] = cp[unsigned(r0 + 64 * a)];
-            } else {
-#pragma unroll
-              for (int a = 0; a < 4; ++a) v[a][b] = cp[unsigned(min(r0 + 64 * a, m - 1))];
-            }
-          }
-        };
-        auto update = [&](T (&v)[4][4], int t) {
-          const int rb = t / ncg, cg = t - rb * ncg;
-          const int r0 = rb * 256 + lane;
-          const T* lp = panel + r0;
-          const T* up = sm.ustage + cg * 4;
-          // products into fresh registers: the loop never waits for the
-          // tile's loads, which are only needed after it
-          T acc[4][4];
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
-          for (int kk = 0; kk < jb; ++kk) {
-            T av[4], bv[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) av[a] = lp[64 * a + kk * m];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) bv[b] = up[kk * kCW + b];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-              for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
-          }
-          const bool full = rb * 256 + 256 <= m;
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            if (cg * 4 + b >= nc) continue;
-            gptr<T> col = W + unsigned((cc + cg * 4 + b) * ldw + k0);
-            if (full) {
-#pragma unroll
-              for (int a = 0; a < 4; ++a) col[unsigned(r0 + 64 * a)] = v[a][b] - acc[a][b];
-            } else {
-#pragma unroll
-              for (int a = 0; a < 4; ++a)
-                if (r0 + 64 * a < m) col[unsigned(r0 + 64 * a)] = v[a][b] - acc[a][b];
-            }
-          }
-        };
-        T ta[4][4], tb[4][4];
-        if (wave < ntile) load(ta, wave);
-        for (int t = wave; t < ntile; t += 2 * NW) {
-          if (t + NW < ntile) load(tb, t + NW);
-          update(ta, t);
-          if (t + NW >= ntile) break;
-          if (t + 2 * NW < ntile) load(ta, t + 2 * NW);
-          update(tb, t + NW);
-        }
-        __syncthreads();
       }
     }
-    src = Wc;
-    lsrc = ldw;
-    __syncthreads();
+    // A12 rows past jb stay zero (G is zero there too, but LDS may hold NaN)
+    if (jb < PB)
+      for (int e = tid; e < 2 * PB * UC; e += NT) {
+        const int k = (e / UC) % PB;
+        if (k >= jb) sm.u.lu.ust[e / (PB * UC)][k][e % UC] = T(0);
+      }
+
+    // 4. trailing update
+    int rowc[RPT], rowd[RPT];
+#pragma unroll
+    for (int a = 0; a < RPT; ++a) {
+      rowc[a] = min(tid + NT * a, m - 1);        // slot to load (clamped)
+      rowd[a] = pos[a] < m ? k0 + pos[a] : n;    // row to store (row n: no slot)
+    }
+    auto colp = [&](int col) -> gcptr<T> {  // old column col (<= n) from row k0
+      return (p == 0 && col < n ? S + unsigned(col * lds) : R + unsigned(col * ld)) + k0;
+    };
+    auto load = [&](T (&o)[RPT][UC], int cc) {
+#pragma unroll
+      for (int u = 0; u < UC; ++u) {
+        gcptr<T> cp = colp(min(cc + u, n));
+#pragma unroll
+        for (int a = 0; a < RPT; ++a) o[a][u] = cp[unsigned(rowc[a])];
+      }
+    };
+    T cur[RPT][UC], nxt[RPT][UC];
+    load(cur, k0 + jb);
+    int par = 0;
+    for (int cc = k0 + jb; cc < ncol; cc += UC) {
+      load(nxt, cc + UC);  // past the end it reloads column n
+#pragma unroll
+      for (int a = 0; a < RPT; ++a)
+        if (pos[a] < jb) {
+#pragma unroll
+          for (int u = 0; u < UC; ++u) sm.u.lu.ust[par][pos[a]][u] = cur[a][u];
+        }
+      lds_barrier();
+#pragma unroll
+      for (int k = 0; k < PB; ++k) {
+        T w[UC];
+#pragma unroll
+        for (int u = 0; u < UC; ++u) w[u] = sm.u.lu.ust[par][k][u];
+#pragma unroll
+        for (int a = 0; a < RPT; ++a)
+#pragma unroll
+          for (int u = 0; u < UC; ++u) cur[a][u] -= v[a][k] * w[u];
+      }
+#pragma unroll
+      for (int u = 0; u < UC; ++u) {
+        gptr<T> dc = D + unsigned((cc + u <= n ? cc + u : n + 1) * ld);
+#pragma unroll
+        for (int a = 0; a < RPT; ++a) dc[unsigned(rowd[a])] = cur[a][u];
+      }
+#pragma unroll
+      for (int a = 0; a < RPT; ++a)
+#pragma unroll
+        for (int u = 0; u < UC; ++u) cur[a][u] = nxt[a][u];
+      par ^= 1;
+    }
+    __syncthreads();  // this panel's stores are read by the next one
   }
-  // back substitution U y = c (column n), blocks of up to 64 rows from the
-  // bottom: the diagonal block is staged in LDS and solved by wave 0, then
-  // every thread updates the rows above it
-  for (int i = tid; i < n; i += NT) y[i] = Wc[unsigned(i + n * ldw)];
-  T* ub = sm.panel;  // [i + j * 64]
+
+  // back substitution U y = c, blocks of up to 64 rows from the bottom: the
+  // diagonal block is staged in LDS and solved by wave 0, then every thread
+  // updates the rows above it
+  auto urow = [&](int i) -> gcptr<T> { return ((i / PB) & 1 ? B1 : B0) + unsigned(i); };
+  for (int i = tid; i < n; i += NT) y[i] = urow(i)[unsigned(n * ld)];
+  T* ub = sm.u.ub;  // [i + j * 64]
   for (int r1 = n; r1 > 0; r1 -= 64) {
     const int r0 = max(0, r1 - 64), nb = r1 - r0;
-    copy_block<T, NT>(ub, 64, Wc + unsigned(r0 + r0 * ldw), ldw, nb, nb);
+    for (int e = tid; e < nb * nb; e += NT) {
+      const int i = e % nb, j = e / nb;
+      if (j >= i) ub[i + j * 64] = urow(r0 + i)[unsigned((r0 + j) * ld)];
+    }
     __syncthreads();
     if (wave == 0) {
       T yi = lane < nb ? y[r0 + lane] : T(0);
@@ -558,9 +503,10 @@ __device__ void batch_solve(gcptr<T> S, int lds, int n, const T* x, T* y, gptr<T
     }
     __syncthreads();
     for (int r = tid; r < r0; r += NT) {
+      gcptr<T> ur = urow(r);
       T s = y[r];
 #pragma unroll 16
-      for (int i = r0; i < r1; ++i) s -= Wc[unsigned(r + i * ldw)] * y[i];
+      for (int i = r0; i < r1; ++i) s -= ur[unsigned(i * ld)] * y[i];
       y[r] = s;
     }
     __syncthreads();
@@ -598,12 +544,13 @@ __global__ __launch_bounds__(NT) void batch_kernel(const BProgram* __restrict__ 
         gcptr<T> M = gcptr<T>(I->leaf[op.leaf]);
         const int ld = int(I->ld[op.leaf]);
         if (!op.trans)
-          gemv_n<T, NT>(M, ld, n, T(op.alpha), sm.slots[op.src], sm.slots[op.dst], sm.panel);
+          gemv_n<T, NT>(M, ld, n, T(op.alpha), sm.slots[op.src], sm.slots[op.dst], &sm.u.red[0][0]);
         else
           gemv_t<T, NT>(M, ld, n, T(op.alpha), sm.slots[op.src], sm.slots[op.dst]);
       } else if (op.kind == B_SOLVE) {
         batch_solve<T, PB, NT>(gcptr<T>(I->leaf[op.leaf]), int(I->ld[op.leaf]), n,
-                               sm.slots[op.src], sm.slots[op.dst], W, sm, status, idx);
+                               sm.slots[op.src], sm.slots[op.dst], W, scratch_stride / 2, sm,
+                               status, idx);
       } else if (op.dst == kBOut) {  // B_EW into the output
         gptr<T> out = gptr<T>(I->out);
         for (int i = tid; i < n; i += NT) out[i] = ew_batch<T>(p, op, I, sm.slots, i);
@@ -629,8 +576,8 @@ __global__ void zero_u32_kernel(unsigned* p) { *p = 0u; }
 struct Variant {
   int panel, threads;
 };
-constexpr Variant kF32[] = {{16, 256}, {16, 512}, {32, 256}, {32, 512}};
-constexpr Variant kF64[] = {{8, 256}, {8, 512}, {16, 256}, {16, 512}};
+constexpr Variant kF32[] = {{64, 256}, {32, 256}, {64, 512}, {32, 512}};
+constexpr Variant kF64[] = {{32, 256}, {16, 256}, {32, 512}, {16, 512}};
 
 template <typename T, int PB, int NT>
 void launch_one(int grid, const BProgram* p, const BInst* inst, const int32_t* order, int count,
@@ -655,9 +602,11 @@ BatchConfig batch_default(int dtype, int64_t count) {
   return BatchConfig{0, 512};
 }
 
+// Two (max_n + 1) x (max_n + 2) buffers per workgroup, each 256-byte aligned
+// for FP32 and FP64.
 int64_t batch_scratch_stride(int64_t max_n) {
-  const int64_t e = max_n * (max_n + 1);
-  return (e + 63) & ~int64_t(63);  // 256-byte aligned slices for FP32 and FP64
+  const int64_t e = (max_n + 1) * (max_n + 2);
+  return 2 * ((e + 63) & ~int64_t(63));
 }
 
 hipError_t batch_launch(int dtype, const BatchConfig& cfg, const BProgram* p, const BInst* inst,
@@ -674,16 +623,16 @@ hipError_t batch_launch(int dtype, const BatchConfig& cfg, const BProgram* p, co
   launch_one<T, PB, NT>(cfg.grid, p, inst, order, c, queue, scratch, scratch_stride, status, s)
   if (dtype == 0) {
     switch (cfg.variant) {
-      case 0: HEXLA_BATCH_CASE(double, 8, 256); break;
-      case 1: HEXLA_BATCH_CASE(double, 8, 512); break;
-      case 2: HEXLA_BATCH_CASE(double, 16, 256); break;
+      case 0: HEXLA_BATCH_CASE(double, 32, 256); break;
+      case 1: HEXLA_BATCH_CASE(double, 16, 256); break;
+      case 2: HEXLA_BATCH_CASE(double, 32, 512); break;
       default: HEXLA_BATCH_CASE(double, 16, 512); break;
     }
   } else {
     switch (cfg.variant) {
-      case 0: HEXLA_BATCH_CASE(float, 16, 256); break;
-      case 1: HEXLA_BATCH_CASE(float, 16, 512); break;
-      case 2: HEXLA_BATCH_CASE(float, 32, 256); break;
+      case 0: HEXLA_BATCH_CASE(float, 64, 256); break;
+      case 1: HEXLA_BATCH_CASE(float, 32, 256); break;
+      case 2: HEXLA_BATCH_CASE(float, 64, 512); break;
       default: HEXLA_BATCH_CASE(float, 32, 512); break;
     }
   }
