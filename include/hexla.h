@@ -327,6 +327,13 @@ hexla_status hexla_batch_execute(hexla_batch* batch, void* workspace, size_t wor
  * the fastest. Synchronous. Errors: as hexla_batch_execute. */
 hexla_status hexla_batch_autotune(hexla_batch* batch, void* workspace, size_t workspace_bytes,
                                   int32_t reps);
+/* Selects the launch configuration by hand: LU panel width and threads per
+ * workgroup name one of the compiled variants (hexla_batch_describe lists the
+ * chosen one), grid is 1..the largest grid the workspace was sized for
+ * (768). A captured graph is dropped. Host only. Errors: HEXLA_E_INVALID_ARG
+ * (no such variant, grid out of range). */
+hexla_status hexla_batch_set_config(hexla_batch* batch, int32_t panel, int32_t threads,
+                                    int32_t grid);
 /* Copies the instance table into the workspace, waits for it, then records
  * the launches into a HIP graph owned by the batch (replacing any earlier
  * capture); hexla_batch_replay launches the graph on the context's stream.

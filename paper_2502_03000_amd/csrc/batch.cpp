@@ -447,6 +447,15 @@ hexla_status check_ws(hexla_batch* b, void* ws, size_t bytes) {
   return HEXLA_OK;
 }
 
+// A captured graph holds the configuration it was captured with.
+void drop_graph(hexla_batch* b) {
+  if (!b->graph_exec) return;
+  (void)hipGraphExecDestroy(b->graph_exec);
+  (void)hipGraphDestroy(b->graph);
+  b->graph_exec = nullptr;
+  b->graph = nullptr;
+}
+
 }  // namespace
 }  // namespace hexla
 
@@ -690,13 +699,24 @@ hexla_status hexla_batch_autotune(hexla_batch* b, void* ws, size_t bytes, int32_
   if (e != hipSuccess)
     return set_err(b->ctx, HEXLA_E_DEVICE, std::string("batch autotune: ") + hipGetErrorString(e));
   b->cfg = best;
-  if (b->graph_exec) {  // a captured graph holds the old configuration
-    (void)hipGraphExecDestroy(b->graph_exec);
-    (void)hipGraphDestroy(b->graph);
-    b->graph_exec = nullptr;
-    b->graph = nullptr;
-  }
+  drop_graph(b);
   return HEXLA_OK;
+}
+
+hexla_status hexla_batch_set_config(hexla_batch* b, int32_t panel, int32_t threads, int32_t grid) {
+  if (!b) return HEXLA_E_INVALID_ARG;
+  if (grid < 1 || grid > b->max_grid)
+    return set_err(b->ctx, HEXLA_E_INVALID_ARG, "batch config: grid out of range");
+  for (int v = 0; v < k::batch_variant_count(b->dtype); ++v) {
+    int p = 0, t = 0;
+    k::batch_variant_shape(b->dtype, v, &p, &t);
+    if (p == panel && t == threads) {
+      b->cfg = k::BatchConfig{v, grid};
+      drop_graph(b);
+      return HEXLA_OK;
+    }
+  }
+  return set_err(b->ctx, HEXLA_E_INVALID_ARG, "batch config: no variant with this panel and threads");
 }
 
 hexla_status hexla_batch_capture(hexla_batch* b, void* ws, size_t bytes) {

@@ -43,14 +43,30 @@ __device__ __forceinline__ float bexp<float>(float x) { return expf(x); }
 template <>
 __device__ __forceinline__ double bexp<double>(double x) { return exp(x); }
 
-// A wave's pivot candidate for one column: |value|, position, and the
-// candidate's row (rotated, its multiplier part zeroed).
+// A wave's pivot candidate for one column: |value| as an ordered key (high
+// and low words), position, and the candidate's row (rotated, its
+// multiplier part zeroed).
 template <typename T, int PB, int NW>
 struct alignas(16) Pub {
   T row[NW][PB];
-  T val[NW];
+  unsigned kh[NW], kl[NW];
   int pos[NW];
 };
+
+// |x| as an unsigned key pair that orders like |x|: the high word of the bit
+// pattern plus one, then the low word (FP64 only). NaN gets (0, 0), which
+// also stands for "no candidate", so it ranks below every number.
+__device__ __forceinline__ void abs_key(float x, unsigned& h, unsigned& l) {
+  const unsigned b = __float_as_uint(x) & 0x7fffffffu;
+  h = b > 0x7f800000u ? 0u : b + 1u;
+  l = 0u;
+}
+__device__ __forceinline__ void abs_key(double x, unsigned& h, unsigned& l) {
+  const unsigned hb = unsigned(__double2hiint(x)) & 0x7fffffffu, lb = unsigned(__double2loint(x));
+  const bool nan = hb > 0x7ff00000u || (hb == 0x7ff00000u && lb != 0u);
+  h = nan ? 0u : hb + 1u;
+  l = nan ? 0u : lb;
+}
 
 // Columns per chunk of the trailing update: two chunks of RPT rows per
 // thread stay in registers (64 VGPRs) beside the panel's G rows.
@@ -67,9 +83,10 @@ struct Smem {
     T red[NT / 64][kBMaxN];  // GEMV: per-wave partial sums
     T ub[64 * 64];           // back substitution: diagonal block of U
     struct {
-      alignas(16) T l11[PB][PB];     // pivot rows of the panel, by position
-      alignas(16) T linvt[PB][PB];   // linvt[c][l] = (L11^-1)(l, c)
-      alignas(16) T ust[2][PB][UC];  // A12 chunk [k][column], by chunk parity
+      alignas(16) T l11[PB][PB];       // pivot rows of the panel, by position
+      alignas(16) T linv[PB][PB + 4];   // L11^-1, rows padded (gathers by row)
+      alignas(16) T linvt[PB][PB + 4];  // linvt[c][l] = L11^-1(l, c)
+      alignas(16) T ust[2][PB][UC];    // A12 chunk [k][column], by chunk parity
     } lu;
   } u;
   Pub<T, PB, NT / 64> pub[2];  // pivot candidates, by column parity
@@ -252,20 +269,29 @@ __device__ __forceinline__ void panel_factor(gcptr<T> P, int lp, int m, int jb,
 #pragma unroll 1
   for (int j = 0; j < jb; ++j) {
     auto& pub = sm.pub[j & 1];
-    T best = T(-2);
-    int bp = -1;
+    // the thread's best candidate, then the wave's: largest key, lowest
+    // position among equal keys (positions of non-candidates: INT_MAX)
+    unsigned kh = 0u, kl = 0u;
+    int kp = 0x7fffffff;
 #pragma unroll
     for (int a = 0; a < RPT; ++a) {
-      T x = fabs(v[a][0]);
-      x = x == x ? x : T(-0.5);
-      const bool take =
-          (pos[a] >= j) & (pos[a] < m) & ((x > best) | ((x == best) & (pos[a] < bp)));
-      best = take ? x : best;
-      bp = take ? pos[a] : bp;
+      const bool cand = (pos[a] >= j) & (pos[a] < m);
+      unsigned h, l;
+      abs_key(v[a][0], h, l);
+      h = cand ? h : 0u;
+      l = cand ? l : 0u;
+      const int pp = cand ? pos[a] : 0x7fffffff;
+      const bool take = (h > kh) | ((h == kh) & ((l > kl) | ((l == kl) & (pp < kp))));
+      kh = take ? h : kh;
+      kl = take ? l : kl;
+      kp = take ? pp : kp;
     }
-    wave_argmax(best, bp);
+    const unsigned mh = wave_max_u32(kh);
+    const unsigned ml = sizeof(T) == 8 ? wave_max_u32(kh == mh ? kl : 0u) : 0u;
+    const int bp = wave_min_i32((kh == mh) & (kl == ml) ? kp : 0x7fffffff);
     if (lane == 0) {
-      pub.val[wave] = best;
+      pub.kh[wave] = mh;
+      pub.kl[wave] = ml;
       pub.pos[wave] = bp;
     }
     // the candidate's row as it is; then lanes < j zero its multiplier part
@@ -279,19 +305,22 @@ __device__ __forceinline__ void panel_factor(gcptr<T> P, int lp, int m, int jb,
     wave_fence();
     if (lane < j) pub.row[wave][PB - j + lane] = T(0);
     __syncthreads();
-    T cv[NW];
+    unsigned ch[NW], cl[NW];
     int cp[NW];
 #pragma unroll
     for (int q = 0; q < NW; ++q) {
-      cv[q] = pub.val[q];
+      ch[q] = pub.kh[q];
+      cl[q] = pub.kl[q];
       cp[q] = pub.pos[q];
     }
-    T wv = cv[0];
+    unsigned wh = ch[0], wl = cl[0];
     int wp = cp[0], w = 0;
 #pragma unroll
     for (int q = 1; q < NW; ++q) {
-      const bool take = (cv[q] > wv) | ((cv[q] == wv) & (cp[q] < wp));
-      wv = take ? cv[q] : wv;
+      const bool take =
+          (ch[q] > wh) | ((ch[q] == wh) & ((cl[q] > wl) | ((cl[q] == wl) & (cp[q] < wp))));
+      wh = take ? ch[q] : wh;
+      wl = take ? cl[q] : wl;
       wp = take ? cp[q] : wp;
       w = take ? q : w;
     }
@@ -300,7 +329,9 @@ __device__ __forceinline__ void panel_factor(gcptr<T> P, int lp, int m, int jb,
     for (int c = 0; c < PB; ++c) prow[c] = pub.row[w][c];
     const T pv = prow[0];
     const T rp = T(1) / pv;  // multipliers as a * (1 / pivot)
-    if (tid == 0 && !(wv > T(0)) && atomicCAS(status, 0, kStatusSingular) == 0)
+    // |pivot| > 0: key above (1, 0); a zero or NaN pivot flags the instance
+    if (tid == 0 && !((wh > 1u) | ((wh == 1u) & (wl > 0u))) &&
+        atomicCAS(status, 0, kStatusSingular) == 0)
       status[2] = instance;
 #pragma unroll
     for (int a = 0; a < RPT; ++a) {
@@ -384,29 +415,49 @@ __device__ void batch_solve(gcptr<T> S, int lds, int n, const T* x, T* y, gptr<T
           if (c >= pos[a] && c < jb) dr[unsigned((k0 + c) * ld)] = v[a][c];
       }
     __syncthreads();
-    if (tid < PB) {  // column c of L11^-1 (zero above the diagonal and past jb)
+    // L11^-1: thread c < PB solves L11 x = e_c for column c (zero above the
+    // diagonal and past jb) and writes it as column c of L11^-1 and as row c
+    // of the transposed copy. Up to 32 columns the solve runs in registers;
+    // a 64-column panel has no registers to spare and reads its own earlier
+    // entries back from LDS.
+    if (tid < PB) {
       const int c = tid;
-      T xr[PB];
+      if constexpr (PB <= 32) {
+        T xr[PB];
 #pragma unroll
-      for (int i = 0; i < PB; ++i) {
-        T s = i == c ? T(1) : T(0);
+        for (int i = 0; i < PB; ++i) {
+          T s = i == c ? T(1) : T(0);
 #pragma unroll
-        for (int l = 0; l < i; ++l) s -= sm.u.lu.l11[i][l] * xr[l];
-        xr[i] = (i < jb) & (c < jb) ? s : T(0);
+          for (int l = 0; l < i; ++l) s -= sm.u.lu.l11[i][l] * xr[l];
+          xr[i] = (i < jb) & (c < jb) ? s : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+          sm.u.lu.linv[i][c] = xr[i];
+          sm.u.lu.linvt[c][i] = xr[i];
+        }
+      } else {
+        for (int i = 0; i < PB; ++i) {
+          T s = i == c ? T(1) : T(0);
+#pragma unroll 4
+          for (int l = 0; l < i; ++l) s -= sm.u.lu.l11[i][l] * sm.u.lu.linv[l][c];
+          s = (i < jb) & (c < jb) ? s : T(0);
+          sm.u.lu.linv[i][c] = s;
+          sm.u.lu.linvt[c][i] = s;
+        }
       }
-#pragma unroll
-      for (int i = 0; i < PB; ++i) sm.u.lu.linvt[c][i] = xr[i];
     }
     __syncthreads();
 
-    // 3. rows of G in place: L21 L11^-1 (ascending c: g_c needs v[l], l >= c)
-    // or, for the pivot row at position q, e_q - row q of L11^-1
+    // 3. rows of G in place: the pivot row at position q takes e_q - row q
+    // of L11^-1; the others g_c = sum_{l >= c} v_l L11^-1(l, c), for
+    // ascending c (g_c needs v_l for l >= c only)
 #pragma unroll
     for (int a = 0; a < RPT; ++a) {
       if (pos[a] < jb) {
         const int q = pos[a];
 #pragma unroll
-        for (int c = 0; c < PB; ++c) v[a][c] = (c == q ? T(1) : T(0)) - sm.u.lu.linvt[c][q];
+        for (int c = 0; c < PB; ++c) v[a][c] = (c == q ? T(1) : T(0)) - sm.u.lu.linv[q][c];
       } else {
 #pragma unroll
         for (int c = 0; c < PB; ++c) {
@@ -576,8 +627,8 @@ __global__ void zero_u32_kernel(unsigned* p) { *p = 0u; }
 struct Variant {
   int panel, threads;
 };
-constexpr Variant kF32[] = {{64, 256}, {32, 256}, {64, 512}, {32, 512}};
-constexpr Variant kF64[] = {{32, 256}, {16, 256}, {32, 512}, {16, 512}};
+constexpr Variant kF32[] = {{32, 256}, {64, 256}, {16, 256}};
+constexpr Variant kF64[] = {{16, 256}, {8, 256}};
 
 template <typename T, int PB, int NT>
 void launch_one(int grid, const BProgram* p, const BInst* inst, const int32_t* order, int count,
@@ -588,7 +639,7 @@ void launch_one(int grid, const BProgram* p, const BInst* inst, const int32_t* o
 
 }  // namespace
 
-int batch_variant_count(int dtype) { return dtype == 0 ? 4 : 4; }
+int batch_variant_count(int dtype) { return dtype == 0 ? 2 : 3; }
 
 void batch_variant_shape(int dtype, int variant, int* panel, int* threads) {
   const Variant v = dtype == 0 ? kF64[variant] : kF32[variant];
@@ -623,17 +674,14 @@ hipError_t batch_launch(int dtype, const BatchConfig& cfg, const BProgram* p, co
   launch_one<T, PB, NT>(cfg.grid, p, inst, order, c, queue, scratch, scratch_stride, status, s)
   if (dtype == 0) {
     switch (cfg.variant) {
-      case 0: HEXLA_BATCH_CASE(double, 32, 256); break;
-      case 1: HEXLA_BATCH_CASE(double, 16, 256); break;
-      case 2: HEXLA_BATCH_CASE(double, 32, 512); break;
-      default: HEXLA_BATCH_CASE(double, 16, 512); break;
+      case 0: HEXLA_BATCH_CASE(double, 16, 256); break;
+      default: HEXLA_BATCH_CASE(double, 8, 256); break;
     }
   } else {
     switch (cfg.variant) {
-      case 0: HEXLA_BATCH_CASE(float, 64, 256); break;
-      case 1: HEXLA_BATCH_CASE(float, 32, 256); break;
-      case 2: HEXLA_BATCH_CASE(float, 64, 512); break;
-      default: HEXLA_BATCH_CASE(float, 32, 512); break;
+      case 0: HEXLA_BATCH_CASE(float, 32, 256); break;
+      case 1: HEXLA_BATCH_CASE(float, 64, 256); break;
+      default: HEXLA_BATCH_CASE(float, 16, 256); break;
     }
   }
 #undef HEXLA_BATCH_CASE

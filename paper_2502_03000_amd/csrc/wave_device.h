@@ -57,5 +57,36 @@ __device__ __forceinline__ void wave_argmax(T& a, int& i) {
   a = lane63(a);
 }
 
+// Wave-wide max of unsigned values and min of ints, returned to every lane.
+// The DPP source is the operation's identity where a lane has no source
+// (bound_ctrl zero for max, old = INT_MAX for min), so the compiler folds
+// each move into one v_max_u32_dpp / v_min_i32_dpp.
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ unsigned max_step(unsigned a) {
+  return max(a, unsigned(__builtin_amdgcn_update_dpp(0u, a, CTRL, ROW_MASK, 0xF, BOUND)));
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int min_step(int a) {
+  return min(a, __builtin_amdgcn_update_dpp(0x7fffffff, a, CTRL, ROW_MASK, 0xF, false));
+}
+__device__ __forceinline__ unsigned wave_max_u32(unsigned a) {
+  a = max_step<0x111, 0xF, true>(a);
+  a = max_step<0x112, 0xF, true>(a);
+  a = max_step<0x114, 0xF, true>(a);
+  a = max_step<0x118, 0xF, true>(a);
+  a = max_step<0x142, 0xA, false>(a);
+  a = max_step<0x143, 0xC, false>(a);
+  return __builtin_amdgcn_readlane(a, 63);
+}
+__device__ __forceinline__ int wave_min_i32(int a) {
+  a = min_step<0x111, 0xF>(a);
+  a = min_step<0x112, 0xF>(a);
+  a = min_step<0x114, 0xF>(a);
+  a = min_step<0x118, 0xF>(a);
+  a = min_step<0x142, 0xA>(a);
+  a = min_step<0x143, 0xC>(a);
+  return __builtin_amdgcn_readlane(a, 63);
+}
+
 }  // namespace k
 }  // namespace hexla

@@ -109,6 +109,7 @@ def _load():
         "hexla_batch_describe": [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)],
         "hexla_batch_execute": [vp, vp, C.c_size_t],
         "hexla_batch_autotune": [vp, vp, C.c_size_t, i32],
+        "hexla_batch_set_config": [vp, i32, i32, i32],
         "hexla_batch_capture": [vp, vp, C.c_size_t],
         "hexla_batch_replay": [vp],
         "hexla_batch_destroy": [vp],
@@ -321,6 +322,11 @@ class Batch:
 
     def autotune(self, ws, reps=3):
         self.ctx._check(lib.hexla_batch_autotune(self.handle, *self._ws(ws), reps))
+        self.refresh()
+
+    def set_config(self, panel, threads, grid):
+        """Selects a compiled launch variant (LU panel width, threads) and grid."""
+        self.ctx._check(lib.hexla_batch_set_config(self.handle, panel, threads, grid))
         self.refresh()
 
     def capture(self, ws):

@@ -46,7 +46,7 @@ def template(ctx, dt, t=4):
     return leaves
 
 
-def run_batch(ctx, expr_fn, insts, np_dt, autotune=False):
+def run_batch(ctx, expr_fn, insts, np_dt, autotune=False, config=None):
     tdt = torch.float64 if np_dt == np.float64 else torch.float32
     dt = hx.F64 if np_dt == np.float64 else hx.F32
     lv = template(ctx, dt)
@@ -58,6 +58,8 @@ def run_batch(ctx, expr_fn, insts, np_dt, autotune=False):
     ws = bt.workspace()
     if autotune:
         bt.autotune(ws, reps=1)
+    if config is not None:
+        bt.set_config(*config)
     bt.execute(ws)
     r = ctx.sync()
     host = out.cpu().numpy().astype(np.float64)
@@ -86,6 +88,34 @@ def test_batched_expression_edges(np_dt):
     bt, r, res, _ = run_batch(ctx, BATCHED, insts, np_dt)
     assert r.status == hx.OK
     print(f"worst {check(insts, res, inputs.BATCHED_EXPR, np_dt):.3e}")
+
+
+# every compiled launch variant (LU panel width, threads), on a small grid
+# (instances queue up) and on a full one
+VARIANTS = [(np.float32, 32, 256), (np.float32, 64, 256), (np.float32, 16, 256),
+            (np.float64, 16, 256), (np.float64, 8, 256)]
+
+
+@pytest.mark.parametrize("np_dt,panel,threads", VARIANTS)
+@pytest.mark.parametrize("grid", [5, 512])
+def test_batched_every_variant(np_dt, panel, threads, grid):
+    g = inputs.rng(4107)
+    insts = [instance(g, n, np_dt, permute=(n % 2 == 1)) for n in EDGE_SIZES]
+    ctx = hx.Context(0)
+    bt, r, res, _ = run_batch(ctx, BATCHED, insts, np_dt, config=(panel, threads, grid))
+    assert r.status == hx.OK
+    info = bt.describe()
+    assert (info["panel"], info["threads"], info["grid"]) == (panel, threads, grid)
+    check(insts, res, inputs.BATCHED_EXPR, np_dt)
+
+
+def test_batched_set_config_rejects():
+    insts = [instance(inputs.rng(4108), 8, np.float32)]
+    ctx = hx.Context(0)
+    bt, r, _, _ = run_batch(ctx, BATCHED, insts, np.float32)
+    for bad in [(12, 256, 512), (32, 100, 512), (32, 256, 0), (32, 256, 10 ** 6)]:
+        with pytest.raises(hx.HexlaError):
+            bt.set_config(*bad)
 
 
 @pytest.mark.parametrize("np_dt", [np.float32, np.float64])
