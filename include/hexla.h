@@ -32,6 +32,13 @@
  *     pinned host copy of each batch plan's instance table, and a learned
  *     cost model's parameters and scratch (hexla_model_*).
  *   - A context is used by one host thread at a time.
+ *   - Plans, batch plans and models belong to the context that made them.
+ *     Destroying the context first detaches them: afterwards they may only
+ *     be destroyed (any other call returns HEXLA_E_INVALID_ARG), so the
+ *     objects can be released in any order.
+ *   - Errors left behind by HIP calls made outside the library are cleared
+ *     when a call makes the context's device current; they are not
+ *     reported as the library's.
  */
 #ifndef HEXLA_H
 #define HEXLA_H

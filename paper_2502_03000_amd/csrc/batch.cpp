@@ -436,13 +436,13 @@ hipError_t launch(hexla_batch* b, const k::BatchConfig& cfg, void* ws, hipStream
 }
 
 hexla_status check_ws(hexla_batch* b, void* ws, size_t bytes) {
-  if (!b) return HEXLA_E_INVALID_ARG;
+  if (!b || !b->ctx) return HEXLA_E_INVALID_ARG;
   if (b->ctx->device < 0) return set_err(b->ctx, HEXLA_E_UNSUPPORTED, "batch: dry-run context");
   if (!ws || bytes < b->ws_bytes || (reinterpret_cast<uintptr_t>(ws) & 255))
     return set_err(b->ctx, HEXLA_E_INVALID_ARG,
                    "batch: workspace must be 256-byte aligned and hold " +
                        std::to_string(b->ws_bytes) + " bytes");
-  if (hipSetDevice(b->ctx->device) != hipSuccess)
+  if (enter_device(b->ctx->device) != hipSuccess)
     return set_err(b->ctx, HEXLA_E_DEVICE, "batch: hipSetDevice");
   return HEXLA_OK;
 }
@@ -457,6 +457,9 @@ void drop_graph(hexla_batch* b) {
 }
 
 }  // namespace
+
+void detach_batch(hexla_batch* b) { b->ctx = nullptr; }
+
 }  // namespace hexla
 
 using namespace hexla;
@@ -610,12 +613,13 @@ hexla_status hexla_batch_create(hexla_ctx* ctx, hexla_node root, const hexla_nod
     std::memcpy(tab + b->off_order, order.data(), order.size() * sizeof(int32_t));
     std::memcpy(tab + b->off_inst, inst.data(), inst.size() * sizeof(k::BInst));
   }
+  ctx->batches.insert(b.get());
   *out = b.release();
   return HEXLA_OK;
 }
 
 hexla_status hexla_batch_get_info(const hexla_batch* b, hexla_batch_info* out) {
-  if (!b || !out) return HEXLA_E_INVALID_ARG;
+  if (!b || !b->ctx || !out) return HEXLA_E_INVALID_ARG;
   std::memset(out, 0, sizeof(*out));
   out->count = b->count;
   out->max_n = b->max_n;
@@ -633,7 +637,7 @@ hexla_status hexla_batch_get_info(const hexla_batch* b, hexla_batch_info* out) {
 }
 
 hexla_status hexla_batch_describe(const hexla_batch* b, char* buf, size_t cap, size_t* needed) {
-  if (!b) return HEXLA_E_INVALID_ARG;
+  if (!b || !b->ctx) return HEXLA_E_INVALID_ARG;
   int panel = 0, threads = 0;
   k::batch_variant_shape(b->dtype, b->cfg.variant, &panel, &threads);
   std::ostringstream js;
@@ -704,7 +708,7 @@ hexla_status hexla_batch_autotune(hexla_batch* b, void* ws, size_t bytes, int32_
 }
 
 hexla_status hexla_batch_set_config(hexla_batch* b, int32_t panel, int32_t threads, int32_t grid) {
-  if (!b) return HEXLA_E_INVALID_ARG;
+  if (!b || !b->ctx) return HEXLA_E_INVALID_ARG;
   if (grid < 1 || grid > b->max_grid)
     return set_err(b->ctx, HEXLA_E_INVALID_ARG, "batch config: grid out of range");
   for (int v = 0; v < k::batch_variant_count(b->dtype); ++v) {
@@ -751,9 +755,9 @@ hexla_status hexla_batch_capture(hexla_batch* b, void* ws, size_t bytes) {
 }
 
 hexla_status hexla_batch_replay(hexla_batch* b) {
-  if (!b) return HEXLA_E_INVALID_ARG;
+  if (!b || !b->ctx) return HEXLA_E_INVALID_ARG;
   if (!b->graph_exec) return set_err(b->ctx, HEXLA_E_INVALID_ARG, "batch replay: nothing captured");
-  hipError_t e = hipSetDevice(b->ctx->device);
+  hipError_t e = enter_device(b->ctx->device);
   if (e == hipSuccess) e = hipGraphLaunch(b->graph_exec, b->ctx->stream);
   if (e != hipSuccess)
     return set_err(b->ctx, HEXLA_E_DEVICE, std::string("batch replay: ") + hipGetErrorString(e));
@@ -762,7 +766,10 @@ hexla_status hexla_batch_replay(hexla_batch* b) {
 
 hexla_status hexla_batch_destroy(hexla_batch* b) {
   if (!b) return HEXLA_E_INVALID_ARG;
-  if (b->ctx && b->ctx->device >= 0) (void)hipSetDevice(b->ctx->device);
+  if (b->ctx) {
+    b->ctx->batches.erase(b);
+    if (b->ctx->device >= 0) (void)hipSetDevice(b->ctx->device);
+  }
   delete b;
   return HEXLA_OK;
 }

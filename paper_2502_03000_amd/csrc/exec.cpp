@@ -81,7 +81,7 @@ namespace hexla {
 
 hexla_status check_buffers(hexla_plan* plan, void* out, int64_t ld_out, void* workspace,
                            size_t workspace_bytes) {
-  if (!plan) return HEXLA_E_INVALID_ARG;
+  if (!plan || !plan->ctx) return HEXLA_E_INVALID_ARG;
   hexla_ctx* ctx = plan->ctx;
   if (ctx->device < 0) return set_err(ctx, HEXLA_E_UNSUPPORTED, "dry-run context cannot execute");
   const size_t esz = dtype_size(plan->dtype);
@@ -209,7 +209,7 @@ hexla_status run_ir_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipStrea
 hexla_status run_steps(hexla_plan* plan, void* out, int64_t ld_out, void* workspace,
                        hipStream_t st) {
   hexla_ctx* ctx = plan->ctx;
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = enter_device(ctx->device);
   if (e != hipSuccess) return device_err(ctx, e, "hipSetDevice");
   const Bind b{static_cast<char*>(out), ld_out, static_cast<char*>(workspace)};
   for (const Step& s : plan->steps) {
@@ -289,7 +289,7 @@ hexla_status hexla_split_bf16(hexla_ctx* ctx, const float* x, int64_t n, uint16_
   if (ctx->device < 0) return set_err(ctx, HEXLA_E_UNSUPPORTED, "dry-run context cannot execute");
   if (n < 0 || (terms != 2 && terms != 3) || (n > 0 && (!x || !t0 || !t1 || (terms == 3 && !t2))))
     return set_err(ctx, HEXLA_E_INVALID_ARG, "split_bf16: bad arguments");
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = enter_device(ctx->device);
   if (e == hipSuccess) e = k::split_bf16_launch(x, n, t0, t1, t2, terms, ctx->stream);
   if (e != hipSuccess) return device_err(ctx, e, "split_bf16");
   return HEXLA_OK;
@@ -303,7 +303,7 @@ hexla_status hexla_sync(hexla_ctx* ctx, hexla_report* report) {
     if (report) *report = r;
     return HEXLA_OK;
   }
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = enter_device(ctx->device);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   int32_t h[4] = {0, 0, 0, 0};
   if (e == hipSuccess) e = hipMemcpy(h, ctx->d_status, sizeof(h), hipMemcpyDeviceToHost);

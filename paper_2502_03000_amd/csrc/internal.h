@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <map>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -124,6 +125,10 @@ struct hexla_ctx {
   int32_t host_ir_iterations = 0;  // iterations of the last refined solve
   hexla_model* model = nullptr;    // cost model of the learned planner (borrowed)
   std::string timing_log;          // autotune timings are appended here when set
+  // objects made from this context; destroying the context detaches them
+  std::set<hexla_plan*> plans;
+  std::set<hexla_batch*> batches;
+  std::set<hexla_model*> models;
 };
 
 struct hexla_plan {
@@ -141,6 +146,21 @@ struct hexla_plan {
   hipGraphExec_t graph_exec = nullptr;
   ~hexla_plan();
 };
+
+namespace hexla {
+// Makes the device current and drops an error left behind by HIP calls made
+// outside the library, so that hipGetLastError after a launch reports that
+// launch only.
+inline hipError_t enter_device(int device) {
+  const hipError_t e = hipSetDevice(device);
+  (void)hipGetLastError();
+  return e;
+}
+// A destroyed context leaves its batches and models without one: they can
+// then only be destroyed.
+void detach_batch(hexla_batch* b);
+void detach_model(hexla_model* md);
+}  // namespace hexla
 
 namespace hexla {
 struct GemmBind {

@@ -67,6 +67,9 @@ hexla_status hexla_ctx_create(int device, void* stream, hexla_ctx** out) {
 
 hexla_status hexla_ctx_destroy(hexla_ctx* ctx) {
   if (!ctx) return HEXLA_E_INVALID_ARG;
+  for (hexla_plan* p : ctx->plans) p->ctx = nullptr;
+  for (hexla_batch* b : ctx->batches) hexla::detach_batch(b);
+  for (hexla_model* md : ctx->models) hexla::detach_model(md);
   if (ctx->d_status) {
     (void)hipSetDevice(ctx->device);
     (void)hipFree(ctx->d_status);

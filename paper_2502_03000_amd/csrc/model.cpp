@@ -129,7 +129,7 @@ bool model_predict_us(hexla_model* md, const std::vector<float>& x, std::vector<
   us.assign(size_t(count), 0.f);
   if (count == 0) return true;
   hipStream_t s = md->ctx->stream;
-  hipError_t e = hipSetDevice(md->ctx->device);
+  hipError_t e = enter_device(md->ctx->device);
   if (e == hipSuccess && count > md->cap) {
     if (md->x_buf) (void)hipFree(md->x_buf);
     if (md->y_buf) (void)hipFree(md->y_buf);
@@ -154,6 +154,8 @@ bool model_predict_us(hexla_model* md, const std::vector<float>& x, std::vector<
   for (float& y : us) y = std::exp(y);  // the network predicts log(microseconds)
   return true;
 }
+
+void detach_model(hexla_model* md) { md->ctx = nullptr; }
 
 }  // namespace hexla
 
@@ -189,21 +191,25 @@ hexla_status hexla_model_create(hexla_ctx* ctx, uint64_t seed, hexla_model** out
     for (int e = 0; e < in * outw; ++e) h[off + e] = float(nd(g) * sd);
     off += size_t(in) * outw + outw;
   }
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = enter_device(ctx->device);
   for (float** p : {&md->params, &md->m, &md->v})
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(p), P * sizeof(float));
   if (e == hipSuccess) e = hipMemcpy(md->params, h.data(), P * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(md->m, 0, P * sizeof(float));
   if (e == hipSuccess) e = hipMemset(md->v, 0, P * sizeof(float));
   if (e != hipSuccess) return dev_err(ctx, e, "model_create");
+  ctx->models.insert(md.get());
   *out = md.release();
   return HEXLA_OK;
 }
 
 hexla_status hexla_model_destroy(hexla_model* md) {
   if (!md) return HEXLA_E_INVALID_ARG;
-  if (md->ctx && md->ctx->model == md) md->ctx->model = nullptr;
-  (void)hipSetDevice(md->ctx->device);
+  if (md->ctx) {
+    if (md->ctx->model == md) md->ctx->model = nullptr;
+    md->ctx->models.erase(md);
+    (void)hipSetDevice(md->ctx->device);
+  }
   delete md;
   return HEXLA_OK;
 }
@@ -216,8 +222,8 @@ hexla_status hexla_model_param_count(int64_t* n) {
 
 hexla_status hexla_model_get_params(hexla_model* md, float* host, int64_t n, float* y_mean,
                                     float* y_std) {
-  if (!md || !host || n != P) return HEXLA_E_INVALID_ARG;
-  hipError_t e = hipSetDevice(md->ctx->device);
+  if (!md || !md->ctx || !host || n != P) return HEXLA_E_INVALID_ARG;
+  hipError_t e = enter_device(md->ctx->device);
   if (e == hipSuccess) e = hipStreamSynchronize(md->ctx->stream);
   if (e == hipSuccess) e = hipMemcpy(host, md->params, P * sizeof(float), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return dev_err(md->ctx, e, "model_get_params");
@@ -228,8 +234,8 @@ hexla_status hexla_model_get_params(hexla_model* md, float* host, int64_t n, flo
 
 hexla_status hexla_model_set_params(hexla_model* md, const float* host, int64_t n, float y_mean,
                                     float y_std) {
-  if (!md || !host || n != P || !(y_std > 0.f)) return HEXLA_E_INVALID_ARG;
-  hipError_t e = hipSetDevice(md->ctx->device);
+  if (!md || !md->ctx || !host || n != P || !(y_std > 0.f)) return HEXLA_E_INVALID_ARG;
+  hipError_t e = enter_device(md->ctx->device);
   if (e == hipSuccess) e = hipStreamSynchronize(md->ctx->stream);
   if (e == hipSuccess) e = hipMemcpy(md->params, host, P * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(md->m, 0, P * sizeof(float));
@@ -243,10 +249,10 @@ hexla_status hexla_model_set_params(hexla_model* md, const float* host, int64_t 
 
 hexla_status hexla_model_grad(hexla_model* md, const float* x, const float* t, int64_t count,
                               float* grad_host, double* loss) {
-  if (!md || !x || !t || count < 1 || !grad_host) return HEXLA_E_INVALID_ARG;
+  if (!md || !md->ctx || !x || !t || count < 1 || !grad_host) return HEXLA_E_INVALID_ARG;
   hipStream_t s = md->ctx->stream;
   GradBufs b;
-  hipError_t e = hipSetDevice(md->ctx->device);
+  hipError_t e = enter_device(md->ctx->device);
   if (e == hipSuccess) e = b.alloc(count);
   if (e == hipSuccess) e = k::mlp_grad_launch(md->params, x, t, nullptr, count, b.partial, b.loss, s);
   if (e == hipSuccess)
@@ -263,10 +269,10 @@ hexla_status hexla_model_grad(hexla_model* md, const float* x, const float* t, i
 
 hexla_status hexla_model_step(hexla_model* md, const float* x, const float* t, int64_t count,
                               float lr, double* loss) {
-  if (!md || !x || !t || count < 1 || !(lr > 0.f)) return HEXLA_E_INVALID_ARG;
+  if (!md || !md->ctx || !x || !t || count < 1 || !(lr > 0.f)) return HEXLA_E_INVALID_ARG;
   hipStream_t s = md->ctx->stream;
   GradBufs b;
-  hipError_t e = hipSetDevice(md->ctx->device);
+  hipError_t e = enter_device(md->ctx->device);
   if (e == hipSuccess) e = b.alloc(count);
   if (e == hipSuccess) e = k::mlp_grad_launch(md->params, x, t, nullptr, count, b.partial, b.loss, s);
   if (e == hipSuccess)
@@ -282,7 +288,7 @@ hexla_status hexla_model_step(hexla_model* md, const float* x, const float* t, i
 
 hexla_status hexla_model_train(hexla_model* md, const float* x, const float* t, int64_t count,
                                const hexla_train_opts* opts, double* final_loss) {
-  if (!md || !x || !t || count < 1) return HEXLA_E_INVALID_ARG;
+  if (!md || !md->ctx || !x || !t || count < 1) return HEXLA_E_INVALID_ARG;
   hexla_train_opts o{};
   o.epochs = 200;
   o.batch = 256;
@@ -292,7 +298,7 @@ hexla_status hexla_model_train(hexla_model* md, const float* x, const float* t, 
   if (o.epochs < 1 || o.batch < 1 || !(o.lr > 0.f))
     return set_err(md->ctx, HEXLA_E_INVALID_ARG, "model_train: bad options");
   hipStream_t s = md->ctx->stream;
-  hipError_t e = hipSetDevice(md->ctx->device);
+  hipError_t e = enter_device(md->ctx->device);
   // standardised targets
   std::vector<float> th(static_cast<size_t>(count));
   if (e == hipSuccess) e = hipMemcpy(th.data(), t, size_t(count) * sizeof(float), hipMemcpyDeviceToHost);
@@ -345,8 +351,8 @@ hexla_status hexla_model_train(hexla_model* md, const float* x, const float* t, 
 }
 
 hexla_status hexla_model_predict(hexla_model* md, const float* x, int64_t count, float* y) {
-  if (!md || (count > 0 && (!x || !y)) || count < 0) return HEXLA_E_INVALID_ARG;
-  hipError_t e = hipSetDevice(md->ctx->device);
+  if (!md || !md->ctx || (count > 0 && (!x || !y)) || count < 0) return HEXLA_E_INVALID_ARG;
+  hipError_t e = enter_device(md->ctx->device);
   if (e == hipSuccess)
     e = k::mlp_predict_launch(md->params, x, count, md->y_std, md->y_mean, y, md->ctx->stream);
   if (e != hipSuccess) return dev_err(md->ctx, e, "model_predict");
@@ -354,7 +360,7 @@ hexla_status hexla_model_predict(hexla_model* md, const float* x, int64_t count,
 }
 
 hexla_status hexla_model_save(hexla_model* md, const char* path) {
-  if (!md || !path) return HEXLA_E_INVALID_ARG;
+  if (!md || !md->ctx || !path) return HEXLA_E_INVALID_ARG;
   std::vector<float> h(P);
   hexla_status st = hexla_model_get_params(md, h.data(), P, nullptr, nullptr);
   if (st != HEXLA_OK) return st;
@@ -392,7 +398,7 @@ hexla_status hexla_model_load(hexla_ctx* ctx, const char* path, hexla_model** ou
   if (st != HEXLA_OK) return st;
   st = hexla_model_set_params(md, h.data(), P, mean, sd);
   if (st != HEXLA_OK) {
-    delete md;
+    (void)hexla_model_destroy(md);
     return st;
   }
   *out = md;

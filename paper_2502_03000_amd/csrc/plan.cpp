@@ -1215,12 +1215,13 @@ hexla_status hexla_plan_create(hexla_ctx* ctx, hexla_node root, const hexla_plan
         for (const hexla::View& v : s.ew.leaves) hexla::leaf_range(v, esz, p->leaf_ranges);
     }
   }
+  ctx->plans.insert(p);
   *out = p;
   return HEXLA_OK;
 }
 
 hexla_status hexla_plan_get_info(const hexla_plan* p, hexla_plan_info* out) {
-  if (!p || !out) return HEXLA_E_INVALID_ARG;
+  if (!p || !p->ctx || !out) return HEXLA_E_INVALID_ARG;
   out->rows = p->rows;
   out->cols = p->cols;
   out->dtype = p->dtype;
@@ -1238,7 +1239,7 @@ hexla_status hexla_plan_get_info(const hexla_plan* p, hexla_plan_info* out) {
 }
 
 hexla_status hexla_plan_describe(const hexla_plan* p, char* buf, size_t cap, size_t* needed) {
-  if (!p) return HEXLA_E_INVALID_ARG;
+  if (!p || !p->ctx) return HEXLA_E_INVALID_ARG;
   const std::string js = hexla::describe(p);
   if (needed) *needed = js.size();
   if (buf && cap > 0) {
@@ -1251,6 +1252,7 @@ hexla_status hexla_plan_describe(const hexla_plan* p, char* buf, size_t cap, siz
 
 hexla_status hexla_plan_destroy(hexla_plan* p) {
   if (!p) return HEXLA_E_INVALID_ARG;
+  if (p->ctx) p->ctx->plans.erase(p);
   delete p;
   return HEXLA_OK;
 }

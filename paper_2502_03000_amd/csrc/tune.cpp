@@ -82,7 +82,7 @@ hexla_status hexla_plan_autotune(hexla_plan* plan, void* out, int64_t ld_out, vo
   hexla_ctx* ctx = plan->ctx;
   if (reps <= 0) reps = 5;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = enter_device(ctx->device);
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   std::ofstream log;
@@ -163,7 +163,7 @@ hexla_status hexla_plan_capture(hexla_plan* plan, void* out, int64_t ld_out, voi
   for (const Step& s : plan->steps)
     if (s.kind == StepKind::IrSolve)
       return set_err(ctx, HEXLA_E_UNSUPPORTED, "capture: a refined solve reads status on the host");
-  hipError_t e = hipSetDevice(ctx->device);
+  hipError_t e = enter_device(ctx->device);
   hipStream_t cs = nullptr;  // capture needs a stream other than the null stream
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -193,9 +193,9 @@ hexla_status hexla_plan_capture(hexla_plan* plan, void* out, int64_t ld_out, voi
 }
 
 hexla_status hexla_plan_replay(hexla_plan* plan) {
-  if (!plan) return HEXLA_E_INVALID_ARG;
+  if (!plan || !plan->ctx) return HEXLA_E_INVALID_ARG;
   if (!plan->graph_exec) return set_err(plan->ctx, HEXLA_E_INVALID_ARG, "replay: nothing captured");
-  hipError_t e = hipSetDevice(plan->ctx->device);
+  hipError_t e = enter_device(plan->ctx->device);
   if (e == hipSuccess) e = hipGraphLaunch(plan->graph_exec, plan->ctx->stream);
   if (e != hipSuccess) return set_err(plan->ctx, HEXLA_E_DEVICE, std::string("replay: ") + hipGetErrorString(e));
   return HEXLA_OK;

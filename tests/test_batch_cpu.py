@@ -147,3 +147,23 @@ def test_learned_planner_without_model_is_dp():
     d, l = chain("dp"), chain("learned")
     assert l["chain_macs"] == d["chain_macs"] and "learned" not in l
     assert [s["m"] for s in l["steps"]] == [s["m"] for s in d["steps"]]
+
+
+def test_objects_outliving_their_context():
+    """Destroying a context first detaches its plans and batch plans: they
+    reject every call but destruction, in either order of release."""
+    import ctypes as C
+    ctx, L = setup()
+    sizes, ptrs, outs = fake([8, 16])
+    bt = ctx.batch(batched(L), [L[n] for n in NAMES], sizes, ptrs, outs)
+    plan = ctx.plan(L["p"] % L["q"])
+    info, binfo = hx.PlanInfo(), hx.BatchInfo()
+    assert hx.lib.hexla_plan_get_info(plan.handle, C.byref(info)) == hx.OK
+    assert hx.lib.hexla_ctx_destroy(ctx.handle) == hx.OK
+    ctx.handle = None
+    assert hx.lib.hexla_plan_get_info(plan.handle, C.byref(info)) == hx.E_INVALID_ARG
+    assert hx.lib.hexla_batch_get_info(bt.handle, C.byref(binfo)) == hx.E_INVALID_ARG
+    assert hx.lib.hexla_batch_set_config(bt.handle, 32, 256, 512) == hx.E_INVALID_ARG
+    assert hx.lib.hexla_plan_destroy(plan.handle) == hx.OK
+    assert hx.lib.hexla_batch_destroy(bt.handle) == hx.OK
+    plan.handle = bt.handle = None
