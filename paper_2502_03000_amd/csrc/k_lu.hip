@@ -389,6 +389,26 @@ hipError_t update(int dtype, int64_t m, int64_t ncol, int64_t kk, const T* A, in
                      nullptr, cfg, s);
 }
 
+// A second stream for the lookahead: the trailing update beyond the next
+// panel's columns runs there while the next panel is factored. Default
+// priority, like the caller's stream; released when the factorization has
+// been issued (its work completes first).
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t ready = nullptr, done = nullptr;
+  hipError_t open() {
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+    return e;
+  }
+  ~SideStream() {
+    if (done) (void)hipEventDestroy(done);
+    if (ready) (void)hipEventDestroy(ready);
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
+
 template <typename T>
 hipError_t factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* rowid, void* work,
                         int32_t* status, hipStream_t s, int prec) {
@@ -396,6 +416,15 @@ hipError_t factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* rowid,
   if (n > kLuMaxN) return hipErrorInvalidValue;
   const int64_t np = cdiv(n, kNB);
   LuWork w = carve(work, n);
+  // Lookahead from three panels on, outside graph capture (a captured
+  // sequence stays on one stream).
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  hipError_t ce = hipStreamIsCapturing(s, &cap);
+  if (ce != hipSuccess) return ce;
+  SideStream side;
+  const bool lookahead = np >= 3 && cap == hipStreamCaptureStatusNone;
+  if (lookahead && (ce = side.open()) != hipSuccess) return ce;
+  bool pending = false;  // the side stream holds an update the next interchanges must wait for
   hipError_t e = fill_i32_launch(reinterpret_cast<int32_t*>(w.barrier), 2 * np, 0, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(iota_kernel, dim3(unsigned(std::min<int64_t>(cdiv(n, 256), 1024))), dim3(256),
@@ -411,6 +440,10 @@ hipError_t factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* rowid,
     hipLaunchKernelGGL((panel_kernel<T>), dim3(G * stride), dim3(kPT), 0, s, A, lda, n, k, jb, G,
                        stride, w.slots, w.diag, w.barrier + p, w.swap_cnt + p, list, status);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (pending) {  // the interchanges touch the columns the side stream updates
+      if ((e = hipStreamWaitEvent(s, side.done, 0)) != hipSuccess) return e;
+      pending = false;
+    }
     const int64_t cols = n - jb + 1;
     hipLaunchKernelGGL((laswp_kernel<T>), dim3(unsigned(cdiv(cols, 4))), dim3(256), 0, s, A, lda,
                        n, k, jb, w.swap_cnt + p, list, rowid);
@@ -430,11 +463,27 @@ hipError_t factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* rowid,
       e = gemm_launch(dtype, 0, 0, 0, 0, jb, right, jb, 1.0, linv, kNB, a12, lda, 0.0, a12, lda,
                       nullptr, tc, s);
       if (e != hipSuccess) return e;
-      e = update<T>(dtype, n - k - jb, right, jb, A + (k + jb) + k * lda, lda, a12, lda,
+      // A22 -= L21 U12: the next panel's columns on s, so that the next
+      // panel starts at once; with lookahead the rest on the side stream
+      const int64_t near = lookahead ? std::min<int64_t>(kNB, right) : right;
+      if (near < right) {
+        if ((e = hipEventRecord(side.ready, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(side.s, side.ready, 0)) != hipSuccess) return e;
+      }
+      e = update<T>(dtype, n - k - jb, near, jb, A + (k + jb) + k * lda, lda, a12, lda,
                     A + (k + jb) + (k + jb) * lda, lda, s, prec);
       if (e != hipSuccess) return e;
+      if (near < right) {
+        e = update<T>(dtype, n - k - jb, right - near, jb, A + (k + jb) + k * lda, lda,
+                      a12 + near * lda, lda, A + (k + jb) + (k + jb + near) * lda, lda, side.s,
+                      prec);
+        if (e != hipSuccess) return e;
+        if ((e = hipEventRecord(side.done, side.s)) != hipSuccess) return e;
+        pending = true;
+      }
     }
   }
+  if (pending && (e = hipStreamWaitEvent(s, side.done, 0)) != hipSuccess) return e;
   // the last block's L11^-1 (no update followed it) and every U11^-1, for the solves
   hipLaunchKernelGGL((inv_block_kernel<T, false>), dim3(1), dim3(kNB), 0, s, A, lda, n, np - 1,
                      static_cast<T*>(w.inv));

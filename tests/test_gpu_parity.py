@@ -234,6 +234,21 @@ def test_solve_pivots_on_general_matrix(ctx):
     assert r <= n * 2.0 ** -52
 
 
+def test_solve_pivots_on_general_matrix_many_panels(ctx):
+    """19 panels of 64: each trailing update beyond the next panel's columns
+    runs on a second stream while that panel is factored."""
+    g = inputs.rng(17)
+    n = 1200
+    s = inputs.normal(g, n, n)
+    b = inputs.normal(g, n, 2)
+    ref = gepp.solve(s, b)
+    got = run(ctx, hx.solve(ctx.leaf(dev(s)), ctx.leaf(dev(b))))
+    cond = np.linalg.cond(s)
+    assert rel(got, ref) <= 4 * cond * 2.0 ** -52 * n ** 0.5
+    r = np.linalg.norm(b - s @ got) / (np.linalg.norm(s) * np.linalg.norm(got))
+    assert r <= n * 2.0 ** -52
+
+
 def test_chain_with_inverse(ctx):
     g = inputs.rng(16)
     s = inputs.diag_dominant(g, 40)
