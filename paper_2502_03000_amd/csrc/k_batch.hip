@@ -53,21 +53,6 @@ struct alignas(16) Pub {
   int pos[NW];
 };
 
-// |x| as an unsigned key pair that orders like |x|: the high word of the bit
-// pattern plus one, then the low word (FP64 only). NaN gets (0, 0), which
-// also stands for "no candidate", so it ranks below every number.
-__device__ __forceinline__ void abs_key(float x, unsigned& h, unsigned& l) {
-  const unsigned b = __float_as_uint(x) & 0x7fffffffu;
-  h = b > 0x7f800000u ? 0u : b + 1u;
-  l = 0u;
-}
-__device__ __forceinline__ void abs_key(double x, unsigned& h, unsigned& l) {
-  const unsigned hb = unsigned(__double2hiint(x)) & 0x7fffffffu, lb = unsigned(__double2loint(x));
-  const bool nan = hb > 0x7ff00000u || (hb == 0x7ff00000u && lb != 0u);
-  h = nan ? 0u : hb + 1u;
-  l = nan ? 0u : lb;
-}
-
 // Columns per chunk of the trailing update: two chunks of RPT rows per
 // thread stay in registers (64 VGPRs) beside the panel's G rows.
 template <typename T, int NT>
@@ -288,7 +273,7 @@ __device__ __forceinline__ void panel_factor(gcptr<T> P, int lp, int m, int jb,
     }
     const unsigned mh = wave_max_u32(kh);
     const unsigned ml = sizeof(T) == 8 ? wave_max_u32(kh == mh ? kl : 0u) : 0u;
-    const int bp = wave_min_i32((kh == mh) & (kl == ml) ? kp : 0x7fffffff);
+    const int bp = wave_min_i32(((kh == mh) & (kl == ml)) ? kp : 0x7fffffff);
     if (lane == 0) {
       pub.kh[wave] = mh;
       pub.kl[wave] = ml;

@@ -4,11 +4,13 @@
 //
 // Right-looking blocked algorithm, panel width 64:
 //   panel    one launch factors the n-k x jb panel. Each thread holds one
-//            panel row in registers; per column the workgroups publish their
-//            best pivot candidate (largest |a|, lowest row on ties) with its
-//            row, meet at one grid barrier, read every candidate in one round
-//            trip and all pick the same winner. The participants share one
-//            XCD when there are at most 32.
+//            panel row in registers; per column every workgroup publishes
+//            its best pivot candidate (largest |a|, lowest position on ties)
+//            with the candidate's row as tagged words, reads every
+//            workgroup's header, picks the same winner as all the others and
+//            reads the winner's row. No grid barrier: the tags make each
+//            word self-validating. The participants share one XCD when
+//            there are at most 32.
 //   laswp    the panel's row interchanges, as a gather of the moved rows, on
 //            every column outside the panel and on the row-origin vector.
 //   trsm     U12 = L11^-1 A12 as an in-place product with the explicit
@@ -16,8 +18,9 @@
 //   gemm     A22 -= L21 U12 on the MFMA GEMM.
 // The solves apply the inverses of the diagonal blocks (kept in the
 // workspace) and update the remaining rows with GEMM.
-// Grid barriers spin a bounded number of times; a timeout sets a status bit
-// instead of hanging, and every wave still reaches the end of the kernel.
+// Every wait for another wave's words spins a bounded number of times; a
+// timeout sets a status bit instead of hanging, and every wave still reaches
+// the end of the kernel.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,21 +36,23 @@ namespace {
 
 constexpr int kNB = 64;         // panel width
 constexpr int kPT = 256;        // panel threads per workgroup (one row each)
-constexpr int kSlot = kNB + 3;  // |a|, row, origin, row values
-constexpr int kMaxG = 64;       // panel workgroups (rows up to kMaxG * kPT)
+constexpr int kWaves = kPT / 64;  // waves per panel workgroup
+constexpr int kMaxG = 64;         // panel workgroups (rows up to kMaxG * kPT)
+constexpr int kHdrW = 2;          // header words of a participant's slot
+constexpr int kSlotW = kHdrW + 2 * kNB;  // words per slot (FP64 rows: two per value)
+constexpr unsigned kNoPos = 0xffff;      // position field of "no candidate"
 constexpr unsigned kSpinLimit = 1u << 20;
 constexpr int kStatusSingular = 5;  // HEXLA_E_SINGULAR
 
 struct LuWork {
   void* inv;           // [n_panels][2][kNB][kNB]: L11^-1 and U11^-1 of each diagonal block
-  double* slots;       // [2][G][kSlot]
-  double* diag;        // [2][kNB + 1]
-  unsigned* barrier;   // [n_panels]
+  uint64_t* slots;     // [2][G][kSlotW] tagged words, by column parity
   int32_t* swap_cnt;   // [n_panels]
   int32_t* swap_list;  // [n_panels][2 * kNB][2]   (dst, src)
 };
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+size_t slot_bytes(int64_t gmax) { return size_t(2 * gmax * kSlotW) * sizeof(uint64_t); }
 
 LuWork carve(void* work, int64_t n) {
   const int64_t np = cdiv(n, kNB);
@@ -56,220 +61,243 @@ LuWork carve(void* work, int64_t n) {
   LuWork w;
   w.inv = p;
   p += size_t(np) * 2 * kNB * kNB * sizeof(double);
-  w.slots = reinterpret_cast<double*>(p);
-  p += size_t(2 * gmax * kSlot) * sizeof(double);
-  w.diag = reinterpret_cast<double*>(p);
-  p += size_t(2 * (kNB + 1)) * sizeof(double);
-  w.barrier = reinterpret_cast<unsigned*>(p);
-  p += size_t(np) * sizeof(unsigned);
+  w.slots = reinterpret_cast<uint64_t*>(p);
+  p += slot_bytes(gmax);
   w.swap_cnt = reinterpret_cast<int32_t*>(p);
   p += size_t(np) * sizeof(int32_t);
   w.swap_list = reinterpret_cast<int32_t*>(p);
   return w;
 }
 
-__device__ __forceinline__ void st_agent(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Words other waves read: single-copy atomic 64-bit stores and loads at
+// agent scope. Every word carries the (panel, column) tag in its high bits,
+// so a reader knows from the word alone whether it holds this column's value.
+__device__ __forceinline__ void st_word(uint64_t* p, uint64_t w) {
+  __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ double ld_agent(const double* p) {
-  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ uint64_t ld_word(const uint64_t* p) {
+  return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-
-// Waits until every vector memory operation of this thread has completed
-// (stores acknowledged), so that relaxed agent-scope stores issued before it
-// are visible to any agent-scope load that follows a later signal.
-__device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
-
-// Grid barrier among the G participants; the counter is monotonic within the
-// launch. Each thread's agent-scope stores are complete before the
-// workgroup's arrival is counted. A wait longer than kSpinLimit polls, or an
-// abort raised by another workgroup, makes it return false (for every thread
-// of the workgroup) instead of waiting on.
-__device__ bool grid_barrier(unsigned* counter, unsigned target, int* abort_flag, int* s_flag) {
-  wait_stores();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned spins = 0;
-    int ok = 1;
-    while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > kSpinLimit ||
-          __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-        ok = 0;
-        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        break;
-      }
-    }
-    *s_flag = ok;
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+// Bounded wait: false (and the abort flag raised) after kSpinLimit polls or
+// when another wave has raised it.
+__device__ __forceinline__ bool keep_waiting(unsigned& spins, int32_t* abort_flag) {
+  if (++spins > kSpinLimit ||
+      __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+    __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return false;
   }
-  __syncthreads();
-  return *s_flag != 0;
+  __builtin_amdgcn_s_sleep(1);
+  return true;
 }
 
 // Panel factorisation. Participants are the workgroups with blockIdx a
-// multiple of `stride` (8 places them on one XCD, where the barrier and the
-// exchange stay within one L2); the others return at once. Each thread holds
-// one panel row in registers, kept rotated so that the current column is
-// always v[0]: after step j every row turns left by one, and a row still
-// below the pivot appends its multiplier l_j where column j left, while a
-// finished row appends column j itself. All register indices are static.
-// After jb steps every row is rotated by jb, so v[c] belongs to column
-// (c + jb) mod kNB. Per column: every workgroup publishes its best candidate
-// (largest |a|, lowest row on ties) with the candidate's row and origin,
-// the owner of row j publishes row j, all meet at one barrier, and every
-// workgroup reads all candidates in one round trip and picks the same winner.
+// multiple of `stride` (8 places them on one XCD, where the exchange stays
+// within one L2); the others return at once. Each thread holds one panel row
+// in registers and never hands it to another thread: pos tracks the row's
+// current position, and the interchange of positions j and p at step j only
+// relabels two rows (GEPP's order, kept as positions). A row is kept rotated
+// so that the current column is always v[0]: after step j every row turns
+// left by one, and a row still below the pivot appends its multiplier l_j
+// where column j left, while a finished row appends column j itself; all
+// register indices are static. After jb steps v[c] belongs to column
+// (c + jb) mod kNB.
+// Per column: the waves' best candidates meet in LDS; the wave holding the
+// workgroup's best publishes, as tagged words in the workgroup's slot, the
+// candidate's row (its multiplier part zeroed) and the header (|a| key,
+// position); wave 0 waits until every participant's header carries this
+// column's tag, picks the winner (largest |a|, lowest position), reads the
+// winner's row (waiting on its tags too) and shares it through LDS. Slots
+// alternate with the column's parity: a workgroup overwrites the parity of
+// column j only after every participant has published column j - 1, which
+// each does after reading column j - 2. At the end every row is written at
+// its final position and the moved rows are listed for laswp.
 template <typename T>
 __global__ __launch_bounds__(kPT) void panel_kernel(T* __restrict__ A, int64_t lda, int64_t n,
                                                     int64_t k, int jb, int G, int stride,
-                                                    double* slots, double* diag,
-                                                    unsigned* barrier, int32_t* swap_cnt,
-                                                    int32_t* swap_list, int32_t* status) {
+                                                    uint64_t* slots, unsigned tag0,
+                                                    int32_t* swap_cnt, int32_t* swap_list,
+                                                    int32_t* status) {
   if (blockIdx.x % stride) return;  // not a participant
-  __shared__ double s_abs[kPT / 64];
-  __shared__ int s_row[kPT / 64];
-  __shared__ double s_pub[kNB + 1], s_pubj[kNB + 1];  // rows staged for publishing
-  __shared__ double s_cand[kMaxG * kSlot];
-  __shared__ double s_dia[kNB + 1];
-  __shared__ T s_prow[kNB];  // pivot row, rotated, with its multiplier part zeroed
-  __shared__ int s_win, s_flag, s_ok;
-
+  constexpr bool kF64 = sizeof(T) == 8;
+  __shared__ unsigned s_kh[kWaves], s_kl[kWaves];
+  __shared__ int s_kp[kWaves];
+  __shared__ T s_row[kNB];  // the candidate row, staged by its owner for its wave
+  __shared__ T s_piv[kNB];  // the pivot row
+  __shared__ int s_wp, s_ok;
   const int g = blockIdx.x / stride;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int mp = int(n - k);
   const int r = g * kPT + tid;  // panel row of this thread
   const bool own = r < mp;
-  // a barrier timed out in an earlier panel: the factorisation is void, exit
+  // a wait timed out in an earlier panel: the factorisation is void, exit
   if (__hip_atomic_load(status + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   T v[kNB];
-  int origin = r;  // panel row this content held before the panel
 #pragma unroll
   for (int c = 0; c < kNB; ++c) v[c] = (own && c < jb) ? A[(k + r) + (k + c) * lda] : T(0);
+  int pos = own ? r : int(kNoPos);
   if (tid == 0) s_ok = 1;
 
 #pragma unroll 1
   for (int j = 0; j < jb; ++j) {
-    double* slot_base = slots + size_t(j & 1) * G * kSlot;
-    double* d = diag + (j & 1) * (kNB + 1);
-    // 1. local candidate: largest |a_rj| over rows r >= j, lowest row on ties
-    double ba = -1.0;
-    int bi = 1 << 30;  // no candidate
+    const uint64_t tag = tag0 + unsigned(j);  // < 2^16
+    uint64_t* base = slots + size_t(j & 1) * size_t(G) * kSlotW;
+    // 1. the workgroup's candidate: largest key, lowest position
+    unsigned kh, kl;
+    abs_key(v[0], kh, kl);
+    const bool cand = own & (pos >= j);
+    kh = cand ? kh : 0u;
+    kl = cand ? kl : 0u;
     {
-      double a = -1.0;
-      int idx = 1 << 30;
-      if (own && r >= j && v[0] == v[0]) {  // NaN is never a candidate
-        a = fabs(double(v[0]));
-        idx = r;
-      }
-      wave_argmax(a, idx);
+      const unsigned mh = wave_max_u32(kh);
+      const unsigned ml = kF64 ? wave_max_u32(kh == mh ? kl : 0u) : 0u;
+      const int bp = wave_min_i32(((kh == mh) & (kl == ml) & cand) ? pos : 0x7fffffff);
       if (lane == 0) {
-        s_abs[wave] = a;
-        s_row[wave] = idx;
+        s_kh[wave] = mh;
+        s_kl[wave] = ml;
+        s_kp[wave] = bp;
       }
-      __syncthreads();
+    }
+    __syncthreads();
+    unsigned bh = s_kh[0], bl = s_kl[0];
+    int bp = s_kp[0];
 #pragma unroll
-      for (int q = 0; q < kPT / 64; ++q)
-        if (s_abs[q] > ba || (s_abs[q] == ba && s_row[q] < bi)) {
-          ba = s_abs[q];
-          bi = s_row[q];
+    for (int q = 1; q < kWaves; ++q) {
+      const unsigned h = s_kh[q], l = s_kl[q];
+      const int pp = s_kp[q];
+      const bool take = (h > bh) | ((h == bh) & ((l > bl) | ((l == bl) & (pp < bp))));
+      bh = take ? h : bh;
+      bl = take ? l : bl;
+      bp = take ? pp : bp;
+    }
+    // 2. the wave holding the candidate publishes its row (one value per
+    // lane, the last j positions - its multipliers - zeroed), then the header
+    if (__any(pos == bp)) {
+      if (pos == bp) {
+#pragma unroll
+        for (int c = 0; c < kNB; ++c) s_row[c] = v[c];
+      }
+      wave_fence();
+      const T x = lane < kNB - j ? s_row[lane] : T(0);
+      uint64_t* slot = base + size_t(g) * kSlotW;
+      if constexpr (kF64) {
+        const uint64_t b = uint64_t(__double_as_longlong(double(x)));
+        st_word(slot + kHdrW + 2 * lane, (tag << 32) | (b & 0xffffffffu));
+        st_word(slot + kHdrW + 2 * lane + 1, (tag << 32) | (b >> 32));
+      } else {
+        st_word(slot + kHdrW + lane, (tag << 32) | __float_as_uint(float(x)));
+      }
+      if (lane == 0) {
+        st_word(slot, (tag << 32) | bh);
+        st_word(slot + 1, (tag << 48) | (uint64_t(unsigned(bp)) << 32) | bl);
+      }
+    } else if (bp == 0x7fffffff && wave == 0) {  // no candidate in this workgroup
+      uint64_t* slot = base + size_t(g) * kSlotW;
+      if (lane == 0) {
+        st_word(slot, tag << 32);
+        st_word(slot + 1, (tag << 48) | (uint64_t(kNoPos) << 32));
+      }
+    }
+    // 3. wave 0: every participant's header, the winner, the winner's row
+    if (wave == 0) {
+      unsigned hh = 0u, hl = 0u;
+      int hp = 0x7fffffff;
+      unsigned spins = 0;
+      bool ok = true;
+      for (;;) {
+        bool got = true;
+        if (lane < G) {
+          const uint64_t* sq = base + size_t(lane) * kSlotW;
+          const uint64_t w0 = ld_word(sq), w1 = ld_word(sq + 1);
+          got = ((w0 >> 32) == tag) & ((w1 >> 48) == tag);
+          hh = unsigned(w0);
+          hl = unsigned(w1);
+          const unsigned pp = unsigned(w1 >> 32) & 0xffffu;
+          hp = pp == kNoPos ? 0x7fffffff : int(pp);
         }
-    }
-    // 2. publish the candidate and row j (rotated rows): their owners stage
-    // them in LDS, then one wave stores each with one instruction per field
-    const bool owns_j = j / kPT == g;
-    if (own && r == bi) {
-#pragma unroll
-      for (int c = 0; c < kNB; ++c) s_pub[c] = double(v[c]);
-      s_pub[kNB] = double(origin);
-    }
-    if (own && r == j) {
-#pragma unroll
-      for (int c = 0; c < kNB; ++c) s_pubj[c] = double(v[c]);
-      s_pubj[kNB] = double(origin);
-    }
-    __syncthreads();
-    if (wave == 0) {
-      double* slot = slot_base + size_t(g) * kSlot;
-      st_agent(slot + 3 + lane, s_pub[lane]);
+        if (__all(got)) break;
+        if (!keep_waiting(spins, status + 1)) {
+          ok = false;
+          break;
+        }
+      }
+      int wq = 0x7fffffff, wp = 0x7fffffff;
+      if (ok) {
+        const unsigned wh = wave_max_u32(hh);
+        const unsigned wl = kF64 ? wave_max_u32(hh == wh ? hl : 0u) : 0u;
+        wp = wave_min_i32(((hh == wh) & (hl == wl)) ? hp : 0x7fffffff);
+        wq = wave_min_i32(((hh == wh) & (hl == wl) & (hp == wp)) ? lane : 0x7fffffff);
+        // |pivot| > 0 is a key above (1, 0); otherwise the column is singular
+        if (g == 0 && lane == 0 && !((wh > 1u) | ((wh == 1u) & (wl > 0u)))) {
+          if (atomicCAS(status, 0, kStatusSingular) == 0) status[2] = int(k + j);
+        }
+        if (wq >= G) {  // no participant had a candidate: cannot happen while j < n - k
+          __hip_atomic_store(status + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = false;
+        }
+      }
+      if (ok) {
+        const uint64_t* sw = base + size_t(wq) * kSlotW + kHdrW;
+        T pr = T(0);
+        spins = 0;
+        for (;;) {
+          bool got;
+          if constexpr (kF64) {
+            const uint64_t w0 = ld_word(sw + 2 * lane), w1 = ld_word(sw + 2 * lane + 1);
+            got = ((w0 >> 32) == tag) & ((w1 >> 32) == tag);
+            pr = T(__longlong_as_double(
+                (long long)(((w1 & 0xffffffffu) << 32) | (w0 & 0xffffffffu))));
+          } else {
+            const uint64_t w0 = ld_word(sw + lane);
+            got = (w0 >> 32) == tag;
+            pr = T(__uint_as_float(unsigned(w0)));
+          }
+          if (__all(got)) break;
+          if (!keep_waiting(spins, status + 1)) {
+            ok = false;
+            break;
+          }
+        }
+        s_piv[lane] = pr;
+      }
       if (lane == 0) {
-        st_agent(slot + 0, ba);
-        st_agent(slot + 1, double(bi));
-        st_agent(slot + 2, s_pub[kNB]);
-      }
-    } else if (wave == 1 && owns_j) {
-      st_agent(d + lane, s_pubj[lane]);
-      if (lane == 0) st_agent(d + kNB, s_pubj[kNB]);
-    }
-    if (!grid_barrier(barrier, unsigned(G) * unsigned(j + 1), status + 1, &s_flag)) {
-      if (tid == 0) s_ok = 0;
-      break;  // every thread of the workgroup sees the same flag
-    }
-    // 3. all candidates and row j in one round trip
-    for (int e = tid; e < G * kSlot; e += kPT) s_cand[e] = ld_agent(slot_base + e);
-    if (tid <= kNB) s_dia[tid] = ld_agent(d + tid);
-    __syncthreads();
-    // 4. every workgroup picks the same winner (G <= 64: one lane each)
-    if (wave == 0) {
-      double a = lane < G ? s_cand[lane * kSlot + 0] : -2.0;
-      int idx = lane < G ? int(s_cand[lane * kSlot + 1]) : (1 << 30);
-      wave_argmax(a, idx);
-      int w = idx / kPT;  // the workgroup that published row idx
-      w = a >= 0.0 ? w : -1;  // -1: no comparable candidate
-      if (lane == 0) s_win = w;
-      // the pivot row for the elimination: rotated like every row, with the
-      // multipliers it carries (positions >= kNB - j) zeroed
-      const double* src = w >= 0 ? s_cand + w * kSlot + 3 : s_dia;
-      s_prow[lane] = lane < kNB - j ? T(src[lane]) : T(0);
-    }
-    __syncthreads();
-    const int win = s_win;
-    const int prow = win >= 0 ? int(s_cand[win * kSlot + 1]) : j;
-    const T pivot = s_prow[0];
-    if (g == 0 && tid == 0 && !(pivot != T(0) && win >= 0)) {
-      const int col = int(k + j);
-      if (atomicCAS(status, 0, kStatusSingular) == 0) status[2] = col;
-    }
-    // 5. interchange rows j and prow (whole rotated rows)
-    if (prow != j && own) {
-      if (r == j) {
-        const double* src = s_cand + win * kSlot;
-#pragma unroll
-        for (int c = 0; c < kNB; ++c) v[c] = T(src[3 + c]);
-        origin = int(src[2]);
-      } else if (r == prow) {
-#pragma unroll
-        for (int c = 0; c < kNB; ++c) v[c] = T(s_dia[c]);
-        origin = int(s_dia[kNB]);
+        s_wp = wp;
+        if (!ok) s_ok = 0;
       }
     }
-    // 6. eliminate below the pivot, then rotate
-    const bool active = own && r > j && pivot != T(0);
+    __syncthreads();
+    if (!s_ok) break;  // the same for every thread of the workgroup
+    T prow[kNB];
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) prow[c] = s_piv[c];
+    const int wp = s_wp;
+    const T pivot = prow[0];
+    // 4. interchange positions j and wp, eliminate below the pivot, rotate
+    pos = pos == wp ? j : (pos == j ? wp : pos);
+    const bool active = own & (pos > j) & (pivot != T(0));
     const T l = active ? v[0] / pivot : T(0);
-#pragma unroll
-    for (int c = 1; c < kNB; ++c) v[c] -= l * s_prow[c];
     const T last = active ? l : v[0];
 #pragma unroll
-    for (int c = 0; c < kNB - 1; ++c) v[c] = v[c + 1];
+    for (int c = 0; c < kNB - 1; ++c) v[c] = v[c + 1] - l * prow[c + 1];
     v[kNB - 1] = last;
-    __syncthreads();
   }
 
-  __syncthreads();
-  if (!s_ok) {  // barrier timeout: leave the panel as it is, flag the failure
-    if (tid == 0) atomicOr(status + 1, 1);
-    return;
-  }
+  if (!s_ok) return;  // a wait timed out: status[1] is set, the panel is void
   if (own) {
 #pragma unroll
     for (int c = 0; c < kNB; ++c) {
       const int col = (c + jb) % kNB;  // every row is rotated by jb
-      if (col < jb) A[(k + r) + (k + col) * lda] = v[c];
+      if (col < jb) A[(k + pos) + (k + col) * lda] = v[c];
     }
-    if (origin != r) {
+    if (pos != r) {
       const int e = atomicAdd(swap_cnt, 1);
       if (e < 2 * kNB) {
-        swap_list[2 * e] = int(k + r);
-        swap_list[2 * e + 1] = int(k + origin);
+        swap_list[2 * e] = int(k + pos);
+        swap_list[2 * e + 1] = int(k + r);
       }
     }
   }
@@ -425,7 +453,10 @@ hipError_t factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* rowid,
   const bool lookahead = np >= 3 && cap == hipStreamCaptureStatusNone;
   if (lookahead && (ce = side.open()) != hipSuccess) return ce;
   bool pending = false;  // the side stream holds an update the next interchanges must wait for
-  hipError_t e = fill_i32_launch(reinterpret_cast<int32_t*>(w.barrier), 2 * np, 0, s);
+  // no slot holds a tag of this factorisation yet (tags restart at 1)
+  hipError_t e = fill_i32_launch(reinterpret_cast<int32_t*>(w.slots),
+                                 int64_t(slot_bytes(cdiv(n, kPT)) / sizeof(int32_t)), 0, s);
+  if (e == hipSuccess) e = fill_i32_launch(w.swap_cnt, np, 0, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(iota_kernel, dim3(unsigned(std::min<int64_t>(cdiv(n, 256), 1024))), dim3(256),
                      0, s, rowid, n);
@@ -438,7 +469,7 @@ hipError_t factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* rowid,
     const int stride = G <= 32 ? 8 : 1;
     int32_t* list = w.swap_list + p * (4 * kNB);
     hipLaunchKernelGGL((panel_kernel<T>), dim3(G * stride), dim3(kPT), 0, s, A, lda, n, k, jb, G,
-                       stride, w.slots, w.diag, w.barrier + p, w.swap_cnt + p, list, status);
+                       stride, w.slots, unsigned(p * kNB + 1), w.swap_cnt + p, list, status);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (pending) {  // the interchanges touch the columns the side stream updates
       if ((e = hipStreamWaitEvent(s, side.done, 0)) != hipSuccess) return e;
@@ -542,9 +573,8 @@ size_t lu_workspace_bytes(int, int64_t n) {
   const int64_t np = cdiv(std::max<int64_t>(n, 1), kNB);
   const int64_t gmax = cdiv(std::max<int64_t>(n, 1), kPT);
   size_t b = size_t(np) * 2 * kNB * kNB * sizeof(double);
-  b += size_t(2 * gmax * kSlot) * sizeof(double);
-  b += size_t(2 * (kNB + 1)) * sizeof(double);
-  b += size_t(np) * (sizeof(unsigned) + sizeof(int32_t));
+  b += slot_bytes(gmax);
+  b += size_t(np) * sizeof(int32_t);
   b += size_t(np) * 4 * kNB * sizeof(int32_t);
   return (b + 255) & ~size_t(255);
 }

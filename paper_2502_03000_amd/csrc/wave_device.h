@@ -57,6 +57,21 @@ __device__ __forceinline__ void wave_argmax(T& a, int& i) {
   a = lane63(a);
 }
 
+// |x| as an unsigned key pair that orders like |x|: the high word of the bit
+// pattern plus one, then the low word (FP64 only). NaN gets (0, 0), which
+// also stands for "no candidate", so it ranks below every number.
+__device__ __forceinline__ void abs_key(float x, unsigned& h, unsigned& l) {
+  const unsigned b = __float_as_uint(x) & 0x7fffffffu;
+  h = b > 0x7f800000u ? 0u : b + 1u;
+  l = 0u;
+}
+__device__ __forceinline__ void abs_key(double x, unsigned& h, unsigned& l) {
+  const unsigned hb = unsigned(__double2hiint(x)) & 0x7fffffffu, lb = unsigned(__double2loint(x));
+  const bool nan = hb > 0x7ff00000u || (hb == 0x7ff00000u && lb != 0u);
+  h = nan ? 0u : hb + 1u;
+  l = nan ? 0u : lb;
+}
+
 // Wave-wide max of unsigned values and min of ints, returned to every lane.
 // The DPP source is the operation's identity where a lane has no source
 // (bound_ctrl zero for max, old = INT_MAX for min), so the compiler folds
