@@ -15,7 +15,9 @@
 //            every column outside the panel and on the row-origin vector.
 //   trsm     U12 = L11^-1 A12 as an in-place product with the explicit
 //            inverse of the 64 x 64 unit lower block (MFMA GEMM).
-//   gemm     A22 -= L21 U12 on the MFMA GEMM.
+//   update   A22 -= L21 U12, a rank-64 update: one MFMA kernel that keeps
+//            the whole K range of its A and B tiles in LDS and its C tile in
+//            the accumulators (split-BF16 / FP16 updates use the GEMM).
 // The solves apply the inverses of the diagonal blocks (kept in the
 // workspace) and update the remaining rows with GEMM.
 // Every wait for another wave's words spins a bounded number of times; a
@@ -26,6 +28,7 @@
 #include <algorithm>
 
 #include "ew_device.h"
+#include "gemm_device.h"
 #include "kernels.h"
 #include "wave_device.h"
 
@@ -391,10 +394,105 @@ __global__ void iota_kernel(int32_t* p, int64_t n) {
     p[i] = int32_t(i);
 }
 
-// C (m x ncol) -= A (m x kk) * B (kk x ncol), through GEMM or GEMV.
+// C -= A B for K <= kNB (the panel's rank-K update): A m x K (lda), B K x n
+// (ldb), C m x n (ldc), column-major. One 256-thread workgroup per BT x BT
+// tile of C: the C tile is loaded straight into the accumulators, the whole
+// K range of the A and B tiles goes to LDS once, and the MFMAs add
+// (-B^T) A^T, i.e. the tile is computed transposed (MFMA rows are C's
+// columns). That way the accumulator layout puts 16 consecutive rows of one
+// column of C in each 16-lane group, so C is read and written in whole
+// 64-byte (FP32) or 128-byte (FP64) runs. The traffic is the C tile twice
+// plus the A and B tiles once; with K = 64 the kernel is bound by C.
+template <typename T, int BT>
+__global__ __launch_bounds__(256) void rank_update_kernel(int64_t m, int64_t n, int K,
+                                                          const T* __restrict__ A, int64_t lda,
+                                                          const T* __restrict__ B, int64_t ldb,
+                                                          T* __restrict__ C, int64_t ldc,
+                                                          int tiles_m) {
+  using M = Mfma<T>;
+  using acc_t = typename M::acc_t;
+  constexpr int LD = BT + 1;  // padded LDS rows
+  constexpr int WT = BT / 2;  // a wave's part: WT rows x WT columns
+  constexpr int F = WT / 16;  // 16 x 16 blocks per side of a wave's part
+  __shared__ T sa[kNB][LD];   // A^T: sa[k][row]
+  __shared__ T sb[kNB][LD];   // B: sb[k][col]
+  const int tm = int(blockIdx.x) % tiles_m, tn = int(blockIdx.x) / tiles_m;
+  const int64_t m0 = int64_t(tm) * BT, n0 = int64_t(tn) * BT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1;
+  const int l16 = lane & 15, g = lane >> 4;
+  // 1. the C tile into the accumulators: block (fc, fr) register r holds
+  // column n0 + wc*WT + fc*16 + M::row(lane, r), row m0 + wr*WT + fr*16 + l16
+  acc_t acc[F][F];
+#pragma unroll
+  for (int fc = 0; fc < F; ++fc)
+#pragma unroll
+    for (int fr = 0; fr < F; ++fr)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t col = n0 + wc * WT + fc * 16 + M::row(lane, r);
+        const int64_t row = m0 + wr * WT + fr * 16 + l16;
+        acc[fc][fr][r] = (row < m && col < n) ? C[row + col * ldc] : T(0);
+      }
+  // 2. the A and B tiles, all of K, into LDS (zero past m, n and K)
+  for (int e = tid; e < BT * kNB; e += 256) {
+    const int row = e % BT, k = e / BT;
+    const int64_t gr = m0 + row;
+    sa[k][row] = (k < K && gr < m) ? A[gr + int64_t(k) * lda] : T(0);
+  }
+  for (int e = tid; e < BT * kNB; e += 256) {
+    const int k = e % kNB, col = e / kNB;
+    const int64_t gc = n0 + col;
+    sb[k][col] = (k < K && gc < n) ? B[k + gc * ldb] : T(0);
+  }
+  __syncthreads();
+  // 3. acc += (-B^T) A^T: MFMA operand A[i][k] = -B(k, col i) from lane
+  // i + 16k, operand B[k][j] = A(row j, k) from lane j + 16k
+#pragma unroll 4
+  for (int k0 = 0; k0 < kNB; k0 += 4) {
+    T a[F], b[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      a[f] = -sb[k0 + g][wc * WT + f * 16 + l16];
+      b[f] = sa[k0 + g][wr * WT + f * 16 + l16];
+    }
+#pragma unroll
+    for (int fc = 0; fc < F; ++fc)
+#pragma unroll
+      for (int fr = 0; fr < F; ++fr) acc[fc][fr] = M::mma(a[fc], b[fr], acc[fc][fr]);
+  }
+  // 4. back to C
+#pragma unroll
+  for (int fc = 0; fc < F; ++fc)
+#pragma unroll
+    for (int fr = 0; fr < F; ++fr)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t col = n0 + wc * WT + fc * 16 + M::row(lane, r);
+        const int64_t row = m0 + wr * WT + fr * 16 + l16;
+        if (row < m && col < n) C[row + col * ldc] = acc[fc][fr][r];
+      }
+}
+
+template <typename T>
+hipError_t rank_update(int64_t m, int64_t n, int64_t K, const T* A, int64_t lda, const T* B,
+                       int64_t ldb, T* C, int64_t ldc, hipStream_t s) {
+  constexpr int BT = sizeof(T) == 8 ? 64 : 128;
+  const int64_t tm = cdiv(m, BT), tn = cdiv(n, BT);
+  if (K > kNB || tm * tn > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((rank_update_kernel<T, BT>), dim3(unsigned(tm * tn)), dim3(256), 0, s, m, n,
+                     int(K), A, lda, B, ldb, C, ldc, int(tm));
+  return hipGetLastError();
+}
+
+// C (m x ncol) -= A (m x kk) * B (kk x ncol): GEMV for one column; the
+// factorization's trailing updates (`trailing`) in plain precision take the
+// rank-K kernel; the rest (the solves' narrow updates, split-BF16 and FP16
+// updates) the GEMM in the requested precision.
 template <typename T>
 hipError_t update(int dtype, int64_t m, int64_t ncol, int64_t kk, const T* A, int64_t lda,
-                  const T* B, int64_t ldb, T* C, int64_t ldc, hipStream_t s, int prec = 0) {
+                  const T* B, int64_t ldb, T* C, int64_t ldc, hipStream_t s, int prec = 0,
+                  bool trailing = false) {
   if (m <= 0 || ncol <= 0 || kk <= 0) return hipSuccess;
   if (ncol == 1) {
     EwProgram epi{};
@@ -411,6 +509,8 @@ hipError_t update(int dtype, int64_t m, int64_t ncol, int64_t kk, const T* A, in
     epi.leaf[0].sj = ldc;
     return gemv_launch(dtype, 0, m, kk, -1.0, A, lda, B, 1, C, 1, &epi, s);
   }
+  if (trailing && prec == GEMM_PLAIN && kk <= kNB)
+    return rank_update<T>(m, ncol, kk, A, lda, B, ldb, C, ldc, s);
   GemmConfig cfg = gemm_choose(dtype, prec, 0, m, ncol, kk);
   cfg.split = 1;
   return gemm_launch(dtype, prec, 0, 0, 0, m, ncol, kk, -1.0, A, lda, B, ldb, 1.0, C, ldc,
@@ -502,12 +602,12 @@ hipError_t factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* rowid,
         if ((e = hipStreamWaitEvent(side.s, side.ready, 0)) != hipSuccess) return e;
       }
       e = update<T>(dtype, n - k - jb, near, jb, A + (k + jb) + k * lda, lda, a12, lda,
-                    A + (k + jb) + (k + jb) * lda, lda, s, prec);
+                    A + (k + jb) + (k + jb) * lda, lda, s, prec, true);
       if (e != hipSuccess) return e;
       if (near < right) {
         e = update<T>(dtype, n - k - jb, right - near, jb, A + (k + jb) + k * lda, lda,
                       a12 + near * lda, lda, A + (k + jb) + (k + jb + near) * lda, lda, side.s,
-                      prec);
+                      prec, true);
         if (e != hipSuccess) return e;
         if ((e = hipEventRecord(side.done, side.s)) != hipSuccess) return e;
         pending = true;
