@@ -16,9 +16,12 @@ struct Tile {
   int bm, bn, bk;
 };
 // FP32: 0 = 128x128, 1 = 128x64 (skinny N), 2 = 64x64 (small), then the
-// same shapes with BK = 32 (longer steps: more bytes in flight per step)
-constexpr Tile kTilesF32[] = {{128, 128, 16}, {128, 64, 16}, {64, 64, 16},
-                              {128, 128, 32}, {128, 64, 32}, {64, 64, 32}};
+// same shapes with BK = 32 (longer steps: more bytes in flight per step),
+// then 64x64 with BK = 64 and 128: a split-K chunk of a long, narrow product
+// arrives in one or two steps, so a workgroup waits for memory once or twice
+// instead of once per short step
+constexpr Tile kTilesF32[] = {{128, 128, 16}, {128, 64, 16}, {64, 64, 16}, {128, 128, 32},
+                              {128, 64, 32},  {64, 64, 32},  {64, 64, 64}, {64, 64, 128}};
 // FP64: 0 = 64x64x16, 1 = 128x128x8
 constexpr Tile kTilesF64[] = {{64, 64, 16}, {128, 128, 8}};
 
@@ -42,7 +45,9 @@ GemmFn kernel_for(int dtype, int tile, bool ta, bool tb, bool vec) {
       case 2: return pick<float, 64, 64, 16>(ta, tb, vec);
       case 3: return pick<float, 128, 128, 32>(ta, tb, vec);
       case 4: return pick<float, 128, 64, 32>(ta, tb, vec);
-      default: return pick<float, 64, 64, 32>(ta, tb, vec);
+      case 5: return pick<float, 64, 64, 32>(ta, tb, vec);
+      case 6: return pick<float, 64, 64, 64>(ta, tb, vec);
+      default: return pick<float, 64, 64, 128>(ta, tb, vec);
     }
   }
   return tile == 1 ? pick<double, 128, 128, 8>(ta, tb, vec) : pick<double, 64, 64, 16>(ta, tb, vec);
@@ -54,7 +59,7 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace
 
-int gemm_tile_count(int dtype) { return dtype == 1 ? 6 : 2; }
+int gemm_tile_count(int dtype) { return dtype == 1 ? 8 : 2; }
 
 void gemm_tile_shape(int dtype, int precision, int tile, int* bm, int* bn, int* bk) {
   if (precision != GEMM_PLAIN) {  // split-BF16 family: one 128 x 128 x 32 tile

@@ -51,7 +51,7 @@ std::vector<k::GemmConfig> gemm_candidates(const Step& s) {
     if (!k::gemm_tile_valid(s.dtype, t, s.mode)) continue;
     add(k::GemmConfig{t, 1});
     for (int64_t target : {128, 256, 512, 1024})
-      for (int64_t steps : {2, 4, 8, 16})
+      for (int64_t steps : {1, 2, 4, 8, 16})
         add(k::GemmConfig{t, k::gemm_split_for(s.dtype, t, s.mode, s.m, s.n, s.kk, target, steps)});
   }
   return out;

@@ -321,6 +321,39 @@ def test_autotune_keeps_results_and_fills_table(ctx, tmp_path):
     assert [s["tile"] for s in p2.describe()["steps"]] == [s["tile"] for s in p.describe()["steps"]]
 
 
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("m", [200, 201])
+def test_every_fp32_tile_against_oracle(tmp_path, ta, tb, m):
+    """Each FP32 tile (forced through the tuning table), without and with
+    split-K, on a ragged product (m = 201: unaligned leading dimension, the
+    scalar load path). A context of its own: its table holds one product."""
+    ctx = hx.Context(0)
+    g = inputs.rng(40 + 4 * ta + 2 * tb + m)
+    n, k = 96, 700
+    a = inputs.normal(g, k, m, np.float32) if ta else inputs.normal(g, m, k, np.float32)
+    b = inputs.normal(g, n, k, np.float32) if tb else inputs.normal(g, k, n, np.float32)
+    text = ("trans(A)" if ta else "A") + "*" + ("trans(B)" if tb else "B")
+    ref = oracle.evaluate(text, {"A": a, "B": b})
+    ea, eb = ctx.leaf(dev(a)), ctx.leaf(dev(b))
+    e = (hx.trans(ea) if ta else ea) @ (hx.trans(eb) if tb else eb)
+    p = ctx.plan(e)
+    out, ws = p.output(), p.workspace()
+    p.autotune(out, ws, reps=1)  # learns the product's key for the table
+    path = tmp_path / "tune.txt"
+    ctx.tune_save(str(path))
+    target, key = path.read_text().split()[:2]
+    for tile in range(8):
+        for split in (1, 5):
+            path.write_text(f"{target} {key} {tile} {split}\n")
+            ctx.tune_load(str(path))
+            q = ctx.plan(e)
+            assert q.describe()["steps"][0]["tile"] == tile
+            out, ws = q.output(), q.workspace()
+            q.execute(out, ws)
+            assert ctx.sync().status == hx.OK
+            assert rel(host(out), ref) <= 1e-5, (tile, split)
+
+
 def test_graph_replay_matches_eager(ctx):
     g = inputs.rng(32)
     a, b = inputs.normal(g, 300, 200, np.float32), inputs.normal(g, 200, 100, np.float32)
