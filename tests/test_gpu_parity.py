@@ -343,7 +343,7 @@ def test_every_fp32_tile_against_oracle(tmp_path, ta, tb, m):
     ctx.tune_save(str(path))
     target, key = path.read_text().split()[:2]
     for tile in range(8):
-        for split in (1, 5):
+        for split in (1, 5, 12):
             path.write_text(f"{target} {key} {tile} {split}\n")
             ctx.tune_load(str(path))
             q = ctx.plan(e)
@@ -352,6 +352,54 @@ def test_every_fp32_tile_against_oracle(tmp_path, ta, tb, m):
             q.execute(out, ws)
             assert ctx.sync().status == hx.OK
             assert rel(host(out), ref) <= 1e-5, (tile, split)
+
+
+def _force(ctx, tmp_path, e, tile, split):
+    """Plans `e` (one product) with the given tile and split through the tuning table."""
+    p = ctx.plan(e)
+    out, ws = p.output(), p.workspace()
+    p.autotune(out, ws, reps=1)
+    path = tmp_path / "tune.txt"
+    ctx.tune_save(str(path))
+    target, key = path.read_text().split()[:2]
+    path.write_text(f"{target} {key} {tile} {split}\n")
+    ctx.tune_load(str(path))
+    q = ctx.plan(e)
+    st = q.describe()["steps"][0]
+    assert (st["tile"], st["split"]) == (tile, split)
+    return q
+
+
+@pytest.mark.parametrize("dt,tile", [(np.float32, 2), (np.float32, 4), (np.float64, 0)])
+def test_split_k_repeats_and_replays(tmp_path, dt, tile):
+    """Split-K partials and their fixed-order reduction: repeated executions,
+    graph replays and a workspace full of garbage all give the same bits
+    (m = 300: a ragged last row of tiles)."""
+    ctx = hx.Context(0)
+    g = inputs.rng(77)
+    m, n, k = 300, 130, 2000
+    a, b = inputs.normal(g, m, k, dt), inputs.normal(g, k, n, dt)
+    ref = oracle.evaluate("A*B", {"A": a, "B": b})
+    e = ctx.leaf(dev(a)) @ ctx.leaf(dev(b))
+    q = _force(ctx, tmp_path, e, tile, 3)
+    out, ws = q.output(), q.workspace()
+    ws.fill_(255)  # the partials overwrite whatever the workspace held
+    q.execute(out, ws)
+    assert ctx.sync().status == hx.OK
+    first = out.clone()
+    assert rel(host(first), ref) <= (1e-5 if dt == np.float32 else 1e-13)
+    for _ in range(2):
+        out.zero_()
+        q.execute(out, ws)
+        assert ctx.sync().status == hx.OK
+        assert torch.equal(out, first)
+    q.capture(out, ws)
+    for _ in range(3):
+        out.zero_()
+        torch.cuda.synchronize()
+        q.replay()
+        assert ctx.sync().status == hx.OK
+        assert torch.equal(out, first)
 
 
 def test_graph_replay_matches_eager(ctx):
