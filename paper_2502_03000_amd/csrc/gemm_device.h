@@ -227,20 +227,38 @@ struct GemmTile {
   }
 };
 
+// Work item of this workgroup in a (tile, split) grid of gridDim.x tiles by
+// gridDim.y splits. Workgroups go to the 8 XCDs in turn (dispatch order,
+// x fastest), and each XCD has its own L2; the remap hands each XCD a
+// contiguous run of the split-major order, so the workgroups resident on one
+// XCD work on the same K range of neighbouring tiles and share operand lines
+// in its L2. A bijection of [0, total) for any total; the placement only
+// affects speed.
+__device__ __forceinline__ void xcd_work_item(int& tile, int& z) {
+  const int tiles = int(gridDim.x);
+  const int total = tiles * int(gridDim.y);
+  const int l = int(blockIdx.x) + int(blockIdx.y) * tiles;
+  const int x = l % 8, j = l / 8;
+  const int per = total / 8, rem = total % 8;
+  const int q = x * per + min(x, rem) + j;
+  z = q / tiles;
+  tile = q - z * tiles;
+}
+
 template <typename T, bool TA, bool TB, int BM, int BN, int BK, bool VEC>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   using G = GemmTile<T, TA, TB, BM, BN, BK, VEC>;
   __shared__ __attribute__((aligned(16))) T smem[2 * G::STAGE];
 
-  int tm, tn;
+  int tile, z, tm, tn;
+  xcd_work_item(tile, z);
   if (g.mode == 1) {
-    tri_tile(int(blockIdx.x), tm, tn);
+    tri_tile(tile, tm, tn);
   } else {
-    tm = int(blockIdx.x) % g.tiles_m;
-    tn = int(blockIdx.x) / g.tiles_m;
+    tm = tile % g.tiles_m;
+    tn = tile / g.tiles_m;
   }
   const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
-  const int z = blockIdx.y;
   const int64_t kb = int64_t(z) * g.k_chunk;
   int64_t ke = kb + g.k_chunk;
   if (ke > g.k) ke = g.k;

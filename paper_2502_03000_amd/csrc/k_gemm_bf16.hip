@@ -186,15 +186,15 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(GemmArgs g, int vec) {
   using M = Mfma16<E>;
   typedef typename M::v8 v8;
   __shared__ __attribute__((aligned(16))) E smem[2 * G::STAGE];
-  int tm, tn;
+  int tile, z, tm, tn;
+  xcd_work_item(tile, z);
   if (g.mode == 1) {
-    tri_tile(int(blockIdx.x), tm, tn);
+    tri_tile(tile, tm, tn);
   } else {
-    tm = int(blockIdx.x) % g.tiles_m;
-    tn = int(blockIdx.x) / g.tiles_m;
+    tm = tile % g.tiles_m;
+    tn = tile / g.tiles_m;
   }
   const int64_t m0 = int64_t(tm) * BM, n0 = int64_t(tn) * BN;
-  const int z = blockIdx.y;
   const int64_t kb = int64_t(z) * g.k_chunk;
   int64_t ke = kb + g.k_chunk;
   if (ke > g.k) ke = g.k;
