@@ -348,12 +348,19 @@ __global__ __launch_bounds__(kNB) void inv_block_kernel(const T* __restrict__ A,
   const int64_t p = first_block + blockIdx.x;
   const int64_t k = p * kNB;
   const int jb = int(std::min<int64_t>(kNB, n - k));
-  for (int e = threadIdx.x; e < kNB * kNB; e += kNB) {
-    const int i = e % kNB, j = e / kNB;
-    Ls[i][j] = (i < jb && j < jb) ? A[(k + i) + (k + j) * lda] : T(i == j ? 1 : 0);
+  const int c = threadIdx.x;
+  {
+    // thread c loads row c of every column, all loads in flight at once
+    // (clamped addresses, the identity padding chosen afterwards); a loop
+    // that stored each load before issuing the next waited once per column
+    const T* a = A + (k + min(c, jb - 1)) + k * lda;
+    T r[kNB];
+#pragma unroll
+    for (int j = 0; j < kNB; ++j) r[j] = a[int64_t(min(j, jb - 1)) * lda];
+#pragma unroll
+    for (int j = 0; j < kNB; ++j) Ls[c][j] = (c < jb && j < jb) ? r[j] : T(c == j ? 1 : 0);
   }
   __syncthreads();
-  const int c = threadIdx.x;
   T x[kNB];
   if (!UPPER) {
 #pragma unroll
