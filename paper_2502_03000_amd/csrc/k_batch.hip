@@ -523,9 +523,23 @@ __device__ void batch_solve(gcptr<T> S, int lds, int n, const T* x, T* y, gptr<T
   T* ub = sm.u.ub;  // [i + j * 64]
   for (int r1 = n; r1 > 0; r1 -= 64) {
     const int r0 = max(0, r1 - 64), nb = r1 - r0;
-    for (int e = tid; e < nb * nb; e += NT) {
-      const int i = e % nb, j = e / nb;
-      if (j >= i) ub[i + j * 64] = urow(r0 + i)[unsigned((r0 + j) * ld)];
+    // the block's upper triangle, FP32: four loads in flight at a time
+    // (clamped addresses); FP64 one at a time, since more live registers
+    // cost its variants the second wave per SIMD
+    constexpr int PER = 64 * 64 / NT, GRP = sizeof(T) == 4 ? 4 : 1;
+#pragma unroll 1
+    for (int q0 = 0; q0 < PER; q0 += GRP) {
+      T u[GRP];
+#pragma unroll
+      for (int q = 0; q < GRP; ++q) {
+        const int e = tid + NT * (q0 + q), i = e % 64, j = e / 64;
+        u[q] = urow(r0 + min(i, nb - 1))[unsigned((r0 + min(j, nb - 1)) * ld)];
+      }
+#pragma unroll
+      for (int q = 0; q < GRP; ++q) {
+        const int e = tid + NT * (q0 + q), i = e % 64, j = e / 64;
+        if (j < nb && j >= i) ub[i + j * 64] = u[q];
+      }
     }
     __syncthreads();
     if (wave == 0) {

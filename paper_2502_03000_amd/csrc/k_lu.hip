@@ -441,16 +441,28 @@ __global__ __launch_bounds__(256) void rank_update_kernel(int64_t m, int64_t n, 
         const int64_t row = m0 + wr * WT + fr * 16 + l16;
         acc[fc][fr][r] = (row < m && col < n) ? C[row + col * ldc] : T(0);
       }
-  // 2. the A and B tiles, all of K, into LDS (zero past m, n and K)
-  for (int e = tid; e < BT * kNB; e += 256) {
-    const int row = e % BT, k = e / BT;
-    const int64_t gr = m0 + row;
-    sa[k][row] = (k < K && gr < m) ? A[gr + int64_t(k) * lda] : T(0);
-  }
-  for (int e = tid; e < BT * kNB; e += 256) {
-    const int k = e % kNB, col = e / kNB;
-    const int64_t gc = n0 + col;
-    sb[k][col] = (k < K && gc < n) ? B[k + gc * ldb] : T(0);
+  // 2. the A and B tiles, all of K, into LDS (zero past m, n and K): every
+  // load in flight at once (clamped addresses, zeros chosen afterwards); a
+  // loop that stored each value before the next load waited on each one
+  {
+    constexpr int PER = BT * kNB / 256;
+    T va[PER], vb[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q;
+      const int64_t gr = std::min<int64_t>(m0 + e % BT, m - 1);
+      va[q] = A[gr + int64_t(min(e / BT, K - 1)) * lda];
+      const int64_t gc = std::min<int64_t>(n0 + e / kNB, n - 1);
+      vb[q] = B[min(e % kNB, K - 1) + gc * ldb];
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q;
+      const int row = e % BT, ka = e / BT;
+      sa[ka][row] = (ka < K && m0 + row < m) ? va[q] : T(0);
+      const int kb = e % kNB, col = e / kNB;
+      sb[kb][col] = (kb < K && n0 + col < n) ? vb[q] : T(0);
+    }
   }
   __syncthreads();
   // 3. acc += (-B^T) A^T: MFMA operand A[i][k] = -B(k, col i) from lane
