@@ -143,11 +143,95 @@ __device__ T ew_batch(const BProgram& p, const BOp& op, const BInst* I, T (*slot
   return s0;
 }
 
+// Columns of M a wave takes per step of the FP32 matrix-vector products:
+// their loads are in flight together (one memory round trip per step).
+constexpr int kGemvCols = 4;
+
+// y = alpha * M x, M n x n (ld). Wave w takes columns w + NW u (u <
+// kGemvCols) per step, then steps on by kGemvCols NW; lane l rows l + 64 r
+// (loads at clamped rows, so that none sits behind a branch; rows past n are
+// never written). Per-wave partial sums are added through LDS.
+template <typename T, int NT>
+__device__ void gemv_n(gcptr<T> M, int ld, int n, T alpha, const T* x, T* y, T* red) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  T acc[kR];
+#pragma unroll
+  for (int r = 0; r < kR; ++r) acc[r] = T(0);
+  for (int j = wave; j < n; j += kGemvCols * NW) {
+    T xs[kGemvCols], v[kGemvCols][kR];
+#pragma unroll
+    for (int u = 0; u < kGemvCols; ++u) {
+      const int ju = j + u * NW;
+      xs[u] = ju < n ? x[ju] : T(0);
+      gcptr<T> c = M + unsigned((ju < n ? ju : j) * ld);
+#pragma unroll
+      for (int r = 0; r < kR; ++r) v[u][r] = c[unsigned(min(lane + 64 * r, n - 1))];
+    }
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      T s = v[0][r] * xs[0];
+#pragma unroll
+      for (int u = 1; u < kGemvCols; ++u) s += v[u][r] * xs[u];
+      acc[r] += s;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kR; ++r) {
+    const int i = lane + 64 * r;
+    if (i < n) red[wave * kBMaxN + i] = acc[r];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += NT) {
+    T s = red[i];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) s += red[w * kBMaxN + i];
+    y[i] = alpha * s;
+  }
+}
+
+// y = alpha * M^T x: one wave per output entry (kGemvCols at a time), lanes
+// over the column (loads at clamped rows, x zero past n).
+template <typename T, int NT>
+__device__ void gemv_t(gcptr<T> M, int ld, int n, T alpha, const T* x, T* y) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  for (int j = wave; j < n; j += kGemvCols * NW) {
+    T a[kGemvCols], v[kGemvCols][kR];
+#pragma unroll
+    for (int u = 0; u < kGemvCols; ++u) {
+      const int ju = j + u * NW;
+      gcptr<T> c = M + unsigned((ju < n ? ju : j) * ld);
+#pragma unroll
+      for (int r = 0; r < kR; ++r) v[u][r] = c[unsigned(min(lane + 64 * r, n - 1))];
+    }
+#pragma unroll
+    for (int u = 0; u < kGemvCols; ++u) {
+      a[u] = T(0);
+#pragma unroll
+      for (int r = 0; r < kR; ++r) {
+        const int i = lane + 64 * r;
+        a[u] += v[u][r] * (i < n ? x[i] : T(0));
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) a[u] += __shfl_xor(a[u], off, 64);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int u = 0; u < kGemvCols; ++u)
+        if (j + u * NW < n) y[j + u * NW] = alpha * a[u];
+    }
+  }
+}
+
+// FP64 forms of the two products: column pairs per step, loads behind the
+// row bound (the wider FP32 forms cost the FP64 variants the second wave per
+// SIMD).
 // y = alpha * M x, M n x n (ld). Wave w takes column pairs (w, w + NW),
 // (w + 2 NW, ...); lane l rows l + 64 r; per-wave partial sums are added
 // through LDS.
 template <typename T, int NT>
-__device__ void gemv_n(gcptr<T> M, int ld, int n, T alpha, const T* x, T* y, T* red) {
+__device__ void gemv_n_pairs(gcptr<T> M, int ld, int n, T alpha, const T* x, T* y, T* red) {
   constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, wave = wave_id();
   T acc[kR];
@@ -185,7 +269,7 @@ __device__ void gemv_n(gcptr<T> M, int ld, int n, T alpha, const T* x, T* y, T* 
 // y = alpha * M^T x: one wave per output entry (two at a time), lanes over
 // the column.
 template <typename T, int NT>
-__device__ void gemv_t(gcptr<T> M, int ld, int n, T alpha, const T* x, T* y) {
+__device__ void gemv_t_pairs(gcptr<T> M, int ld, int n, T alpha, const T* x, T* y) {
   constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, wave = wave_id();
   for (int j = wave; j < n; j += 2 * NW) {
@@ -593,10 +677,18 @@ __global__ __launch_bounds__(NT) void batch_kernel(const BProgram* __restrict__ 
       } else if (op.kind == B_GEMV) {
         gcptr<T> M = gcptr<T>(I->leaf[op.leaf]);
         const int ld = int(I->ld[op.leaf]);
-        if (!op.trans)
-          gemv_n<T, NT>(M, ld, n, T(op.alpha), sm.slots[op.src], sm.slots[op.dst], &sm.u.red[0][0]);
-        else
-          gemv_t<T, NT>(M, ld, n, T(op.alpha), sm.slots[op.src], sm.slots[op.dst]);
+        if constexpr (sizeof(T) == 4) {
+          if (!op.trans)
+            gemv_n<T, NT>(M, ld, n, T(op.alpha), sm.slots[op.src], sm.slots[op.dst], &sm.u.red[0][0]);
+          else
+            gemv_t<T, NT>(M, ld, n, T(op.alpha), sm.slots[op.src], sm.slots[op.dst]);
+        } else {
+          if (!op.trans)
+            gemv_n_pairs<T, NT>(M, ld, n, T(op.alpha), sm.slots[op.src], sm.slots[op.dst],
+                                &sm.u.red[0][0]);
+          else
+            gemv_t_pairs<T, NT>(M, ld, n, T(op.alpha), sm.slots[op.src], sm.slots[op.dst]);
+        }
       } else if (op.kind == B_SOLVE) {
         batch_solve<T, PB, NT>(gcptr<T>(I->leaf[op.leaf]), int(I->ld[op.leaf]), n,
                                sm.slots[op.src], sm.slots[op.dst], W, scratch_stride / 2, sm,
