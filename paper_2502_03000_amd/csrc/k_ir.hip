@@ -28,22 +28,53 @@ __global__ __launch_bounds__(256) void cast_kernel(int64_t rows, int64_t cols, c
   }
 }
 
-// Stage 1: each workgroup owns up to 256 rows; partial[block] = max row sum.
+// Infinity norm, stage 1: a workgroup takes 64 rows (one per lane) and one
+// chunk of columns, split between its four waves (eight loads in flight per
+// lane); the waves' row sums are added in LDS in wave order and
+// part[chunk][row] receives the chunk's row sum. Stage 2 adds the chunks of
+// each row in chunk order and keeps the largest row sum of 256 rows; stage 3
+// (max_reduce_kernel) takes the largest of those.
+constexpr int kNormChunks = 32;  // column chunks at most
+
 template <typename T>
-__global__ __launch_bounds__(256) void rowsum_max_kernel(int64_t rows, int64_t cols, const T* __restrict__ a,
-                                                         int64_t lda, double* __restrict__ partial) {
+__global__ __launch_bounds__(256) void rowsum_part_kernel(int64_t rows, int64_t cols,
+                                                          const T* __restrict__ a, int64_t lda,
+                                                          int64_t chunk, double* __restrict__ part) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i = int64_t(blockIdx.x) * 64 + lane;
+  const int64_t ic = i < rows ? i : rows - 1;
+  const int64_t j0 = int64_t(blockIdx.y) * chunk;
+  const int64_t j1 = j0 + chunk < cols ? j0 + chunk : cols;
+  double s = 0.0;
+  for (int64_t j = j0 + wave * 8; j < j1; j += 32) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = a[ic + (j + u < j1 ? j + u : j) * lda];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += j + u < j1 ? fabs(double(v[u])) : 0.0;
+  }
+  red[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && i < rows)
+    part[int64_t(blockIdx.y) * rows + i] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+__global__ __launch_bounds__(256) void rowsum_max_kernel(int64_t rows, int nchunks,
+                                                         const double* __restrict__ part,
+                                                         double* __restrict__ out) {
   __shared__ double red[256];
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   double s = 0.0;
   if (i < rows)
-    for (int64_t j = 0; j < cols; ++j) s += fabs(double(a[i + j * lda]));
+    for (int c = 0; c < nchunks; ++c) s += part[int64_t(c) * rows + i];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w >= 1; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
 __global__ __launch_bounds__(256) void max_reduce_kernel(const double* __restrict__ partial, int64_t n,
@@ -94,20 +125,35 @@ hipError_t cast_launch(int from, int to, int64_t rows, int64_t cols, const void*
   return hipGetLastError();
 }
 
-size_t norm_scratch_elems(int64_t rows) { return size_t(cdiv(std::max<int64_t>(rows, 1), 256)); }
+size_t norm_scratch_elems(int64_t rows) {
+  const int64_t r = std::max<int64_t>(rows, 1);
+  return size_t(kNormChunks * r + cdiv(r, 256));
+}
 
 hipError_t norm_inf_launch(int dtype, int64_t rows, int64_t cols, const void* a, int64_t lda,
                            double* scratch, double* out, hipStream_t s) {
-  const int64_t blocks = cdiv(std::max<int64_t>(rows, 1), 256);
+  if (rows <= 0 || cols <= 0) {
+    hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(256), 0, s, scratch, int64_t(0), out);
+    return hipGetLastError();
+  }
+  // chunks of at least 256 columns, at most kNormChunks of them
+  const int64_t chunk = std::max<int64_t>(256, cdiv(cols, kNormChunks));
+  const int nchunks = int(cdiv(cols, chunk));
+  const dim3 g1(unsigned(cdiv(rows, 64)), unsigned(nchunks));
   if (dtype == 0)
-    hipLaunchKernelGGL((rowsum_max_kernel<double>), dim3(unsigned(blocks)), dim3(256), 0, s, rows,
-                       cols, static_cast<const double*>(a), lda, scratch);
+    hipLaunchKernelGGL((rowsum_part_kernel<double>), g1, dim3(256), 0, s, rows, cols,
+                       static_cast<const double*>(a), lda, chunk, scratch);
   else
-    hipLaunchKernelGGL((rowsum_max_kernel<float>), dim3(unsigned(blocks)), dim3(256), 0, s, rows,
-                       cols, static_cast<const float*>(a), lda, scratch);
+    hipLaunchKernelGGL((rowsum_part_kernel<float>), g1, dim3(256), 0, s, rows, cols,
+                       static_cast<const float*>(a), lda, chunk, scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(256), 0, s, scratch, blocks, out);
+  const int64_t blocks = cdiv(rows, 256);
+  double* bmax = scratch + int64_t(kNormChunks) * rows;
+  hipLaunchKernelGGL(rowsum_max_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, rows, nchunks,
+                     scratch, bmax);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(256), 0, s, bmax, blocks, out);
   return hipGetLastError();
 }
 
