@@ -160,7 +160,8 @@ hexla_status run_ir_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipStrea
   if (e != hipSuccess) return fail(e, "ir: norm S");
   // X0 = LU^-1 B in the low precision
   e = k::cast_launch(0, 1, n, r, addr(B.ref, b), si(B), sj(B), r_low, ldn, st);
-  if (e == hipSuccess) e = k::lu_solve_launch(1, n, r, s_low, ldn, rowid, addr(w.luwork, b), r_low, ldn, d_low, ldn, st);
+  if (e == hipSuccess) e = k::lu_solve_launch(1, n, r, s_low, ldn, rowid, addr(w.luwork, b), r_low, ldn, d_low, ldn,
+                                                ctx->d_status, st);
   if (e == hipSuccess) e = k::cast_launch(1, 0, n, r, d_low, 1, ldn, addr(X.ref, b), X.ld, st);
   if (e != hipSuccess) return fail(e, "ir: first solve");
   const double tol = (w.tol_scale > 0 ? w.tol_scale : 1.0) * std::ldexp(1.0, -53);
@@ -186,7 +187,8 @@ hexla_status run_ir_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipStrea
     if (it >= w.max_iter) break;
     // D = LU^-1 R (low precision), stop when the correction stagnates
     e = k::cast_launch(0, 1, n, r, r64, 1, ldn, r_low, ldn, st);
-    if (e == hipSuccess) e = k::lu_solve_launch(1, n, r, s_low, ldn, rowid, addr(w.luwork, b), r_low, ldn, d_low, ldn, st);
+    if (e == hipSuccess) e = k::lu_solve_launch(1, n, r, s_low, ldn, rowid, addr(w.luwork, b), r_low, ldn, d_low, ldn,
+                                                ctx->d_status, st);
     if (e == hipSuccess) e = k::norm_inf_launch(1, n, r, d_low, ldn, scratch, norms + 3, st);
     if (e == hipSuccess) e = hipMemcpyAsync(h + 3, norms + 3, sizeof(double), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -256,7 +258,7 @@ hexla_status run_steps(hexla_plan* plan, void* out, int64_t ld_out, void* worksp
         const View A = resolve(s.A, b), B = resolve(s.B, b), C = resolve(s.C, b);
         e = k::lu_solve_launch(s.dtype, s.n, s.nrhs, addr(A.ref, b), A.ld,
                                static_cast<const int32_t*>(addr(s.rowid, b)), addr(s.luwork, b),
-                               addr(B.ref, b), B.ld, addr(C.ref, b), C.ld, st);
+                               addr(B.ref, b), B.ld, addr(C.ref, b), C.ld, ctx->d_status, st);
         break;
       }
       case StepKind::IrSolve: {

@@ -108,16 +108,21 @@ hipError_t split_bf16_launch(const float* x, int64_t n, uint16_t* t0, uint16_t* 
 // update_precision: GemmPrecision of the trailing updates (FP32 storage only
 // for the non-plain values).
 // n <= kLuMaxN (larger n: hipErrorInvalidValue). The workspace also keeps the
-// inverses of the 64 x 64 diagonal blocks, which lu_solve_launch applies.
+// inverses of the 64 x 64 diagonal blocks, which lu_solve_launch applies, and
+// (FP32, nrhs > 0) the solve's exchange of solved blocks for nrhs right-hand
+// sides.
 constexpr int64_t kLuMaxN = 16384;
-size_t lu_workspace_bytes(int dtype, int64_t n);
+size_t lu_workspace_bytes(int dtype, int64_t n, int64_t nrhs = 0);
 hipError_t lu_factor_launch(int dtype, int64_t n, void* A, int64_t lda, int32_t* rowid,
                             void* work, int32_t* status, hipStream_t s, int update_precision = 0);
 // X (n x nrhs, ldx) <- U^{-1} L^{-1} B[rowid], B with ldb; work: the
-// factorisation's workspace. X may not alias B.
+// factorisation's workspace, sized for at least nrhs right-hand sides. FP32:
+// two launches per 1024 right-hand sides (forward, backward), a wait that
+// timed out raises status[1]; FP64: a launch pair per 64-row block and
+// direction. X may not alias B.
 hipError_t lu_solve_launch(int dtype, int64_t n, int64_t nrhs, const void* LU, int64_t lda,
-                           const int32_t* rowid, const void* work, const void* B, int64_t ldb,
-                           void* X, int64_t ldx, hipStream_t s);
+                           const int32_t* rowid, void* work, const void* B, int64_t ldb, void* X,
+                           int64_t ldx, int32_t* status, hipStream_t s);
 
 // ------------------------------------------------------ mixed precision
 // b(i, j) = a(i, j) converted between types (0 FP64, 1 FP32); a(i, j) at

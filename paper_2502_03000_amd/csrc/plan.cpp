@@ -1006,7 +1006,7 @@ class Planner {
     IrWork& w = q.ir;
     w.s_low = work(n * n * 4);
     w.rowid = work(n * 4);
-    w.luwork = work(int64_t(k::lu_workspace_bytes(HEXLA_F32, n)));
+    w.luwork = work(int64_t(k::lu_workspace_bytes(HEXLA_F32, n, r)));
     w.r64 = work(n * r * 8);
     w.r_low = work(n * r * 4);
     w.d_low = work(n * r * 4);
@@ -1046,7 +1046,7 @@ class Planner {
     f.A = lu;
     f.n = n;
     f.rowid = work(n * 4);
-    f.luwork = work(int64_t(k::lu_workspace_bytes(dtype_, n)));
+    f.luwork = work(int64_t(k::lu_workspace_bytes(dtype_, n, r)));
     f.flops = 2.0 / 3.0 * double(n) * n * n;
     f.bytes = 2.0 * double(esz_) * double(n) * n;
     steps_.push_back(f);

@@ -221,6 +221,23 @@ def test_solve_and_inverse_rewrite(ctx, n, nrhs):
     assert rel(run(ctx, hx.inv(es) @ eb, planner="naive"), ref) <= 1e-10
 
 
+@pytest.mark.parametrize("n,nrhs", [(513, 1), (513, 3), (1200, 2), (577, 70)])
+def test_blocked_solve_repeats(ctx, n, nrhs):
+    """The one-launch blocked triangular solves exchange solved blocks as
+    tagged 64-bit words: odd panel counts (513: 9 panels, 1200: 19) and a
+    second right-hand-side chunk (70 columns), each solved four times with
+    the deferred status read after every run."""
+    g = inputs.rng(n + 7 * nrhs)
+    s = inputs.diag_dominant(g, n)
+    b = inputs.normal(g, n, nrhs)
+    ref = oracle.evaluate("solve(S,B)", {"S": s, "B": b})
+    es, eb = ctx.leaf(dev(s)), ctx.leaf(dev(b))
+    for e in (hx.solve(es, eb), hx.inv(es) @ eb, hx.solve(es, eb), hx.inv(es) @ eb):
+        out = ctx.evaluate(e)
+        assert ctx.sync().status == hx.OK
+        assert rel(host(out), ref) <= 1e-12
+
+
 def test_solve_pivots_on_general_matrix(ctx):
     g = inputs.rng(15)
     n = 300
