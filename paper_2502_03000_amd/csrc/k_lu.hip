@@ -50,6 +50,8 @@ constexpr unsigned kSpinLimit = 1u << 20;
 constexpr int kStatusSingular = 5;  // HEXLA_E_SINGULAR
 
 constexpr int kSolveChunks = 16;  // right-hand-side chunks of kNB columns per solve launch
+constexpr int kSolveBlocks = 256;  // 64-row blocks at most (n <= kLuMaxN)
+static_assert(int64_t(kSolveBlocks) * kNB >= kLuMaxN, "solve flags");
 
 struct LuWork {
   void* inv;           // [n_panels][2][kNB][kNB]: L11^-1 and U11^-1 of each diagonal block
@@ -57,7 +59,8 @@ struct LuWork {
   int32_t* swap_cnt;   // [n_panels]
   int32_t* swap_list;  // [n_panels][2 * kNB][2]   (dst, src)
   unsigned* tickets;   // [2][kSolveChunks] block tickets of the forward and backward solves
-  uint64_t* xw;        // [chunk][block][kNB * kNB][1 or 2] tagged words of solved blocks
+  uint64_t* flags;     // [kSolveChunks][kSolveBlocks] tag of each solved block
+  uint64_t* xw;        // [chunk][block] solved blocks, kNB * kNB values in 64-bit words
 };
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -81,13 +84,16 @@ LuWork carve(void* work, int64_t n) {
   p = static_cast<char*>(work) + ((size_t(p - static_cast<char*>(work)) + 255) & ~size_t(255));
   w.tickets = reinterpret_cast<unsigned*>(p);
   p += 256;
+  w.flags = reinterpret_cast<uint64_t*>(p);
+  p += size_t(kSolveChunks) * kSolveBlocks * sizeof(uint64_t);
   w.xw = reinterpret_cast<uint64_t*>(p);
   return w;
 }
-// exchange words of one launch of the blocked solve (FP64 values take two)
+// 64-bit exchange words of one launch of the blocked solve (enough for FP64,
+// which takes one word per value; FP32 packs two)
 size_t solve_words(int64_t n, int64_t nrhs) {
   const int64_t chunks = std::min<int64_t>(cdiv(nrhs, kNB), kSolveChunks);
-  return size_t(chunks) * size_t(cdiv(n, kNB)) * kNB * kNB * 2;
+  return size_t(chunks) * size_t(cdiv(n, kNB)) * kNB * kNB;
 }
 
 // Words other waves read: single-copy atomic 64-bit stores and loads at
@@ -408,22 +414,26 @@ __global__ __launch_bounds__(kNB) void inv_block_kernel(const T* __restrict__ A,
 // X_j) over the blocks j solved before it (j < i forward, j > i backward, in
 // solve order). Workgroups take blocks in solve order from a ticket counter,
 // so every block a workgroup waits for belongs to a workgroup that is already
-// running (no deadlock, whatever the residency). A solved block is published
-// as tagged words (tag = tag0 + block; FP64 values as two words), which
-// readers validate word by word; each dependency's block T_ij is loaded
-// before X_j is awaited, and both pass through LDS. Thread (row, g) keeps row
-// `row` of 16 of the chunk's 64 columns (g * 16 ...); padding rows and
-// columns are exact zeros. Every wait is bounded: a timeout raises status[1]
-// and the workgroup exits.
+// running (no deadlock, whatever the residency). A solved block goes to the
+// exchange as device-coherent 64-bit words (two FP32 values or one FP64 value
+// each); once every thread's stores have completed, the block's flag gets its
+// tag (tag0 + block). A reader polls the flag (one thread), then every thread
+// loads the block's words; each dependency's block T_ij is loaded before
+// that, and both pass through LDS. Thread (row, g) keeps row `row` of 16 of
+// the chunk's 64 columns (g * 16 ...); padding rows and columns are exact
+// zeros. Every wait is bounded: a timeout raises status[1] and the
+// workgroup exits.
 template <typename T, bool UPPER>
 __global__ __launch_bounds__(256) void block_solve_kernel(
     const T* __restrict__ LU, int64_t lda, int64_t n, const T* __restrict__ inv, T* __restrict__ X,
-    int64_t ldx, int64_t c_begin, int64_t nrhs, uint64_t* xw, unsigned* tickets, unsigned tag0,
-    int32_t* status) {
+    int64_t ldx, int64_t c_begin, int64_t nrhs, uint64_t* xw, uint64_t* flags, unsigned* tickets,
+    unsigned tag0, int32_t* status) {
   constexpr bool kF64 = sizeof(T) == 8;
-  constexpr int W = kF64 ? 2 : 1;           // exchange words per value
-  constexpr int XP = kF64 ? 2 : 4;          // keeps rows of xs 16-byte aligned
-  constexpr int PER = kNB * kNB / 256;      // block elements per thread
+  constexpr int VPW = kF64 ? 1 : 2;        // values per exchange word
+  constexpr int WPB = kNB * kNB / VPW;     // words per block
+  constexpr int WPT = WPB / 256;           // words per thread
+  constexpr int XP = kF64 ? 2 : 4;         // keeps rows of xs 16-byte aligned
+  constexpr int PER = kNB * kNB / 256;     // block elements per thread
   __shared__ __attribute__((aligned(16))) T xs[kNB][kNB + XP];  // X_j by [row k][column]
   __shared__ T ts[kNB][kNB + 1];                                 // T_ij by [row][column k]
   __shared__ int s_t, s_ok;
@@ -431,7 +441,8 @@ __global__ __launch_bounds__(256) void block_solve_kernel(
   const int ch = blockIdx.y;
   const int64_t c0 = c_begin + int64_t(ch) * kNB;
   const int rc = int(std::min<int64_t>(kNB, nrhs - c0));
-  uint64_t* xch = xw + size_t(ch) * size_t(nb) * kNB * kNB * W;
+  uint64_t* xch = xw + size_t(ch) * size_t(nb) * WPB;
+  uint64_t* fch = flags + size_t(ch) * kSolveBlocks;
   const int tid = threadIdx.x, row = tid & 63, g = tid >> 6;
   if (tid == 0) s_ok = 1;
   for (;;) {
@@ -465,46 +476,39 @@ __global__ __launch_bounds__(256) void block_solve_kernel(
         const int e = tid + 256 * q, i = e % kNB, k = e / kNB;
         lv[q] = LU[(r0 + min(i, ib - 1)) + (j0 + min(k, jbj - 1)) * lda];
       }
-      // X_j: element (k, c) = word e = k + 64 c (W words each); all of the
-      // thread's words in flight at once, polled again until every tag is
-      // this block's
-      const uint64_t tag = tag0 + unsigned(bj);
-      const uint64_t* src = xch + size_t(bj) * kNB * kNB * W;
-      uint64_t wv[PER * W];
-      bool ok = true;
-      unsigned spins = 0;
-      for (;;) {
-#pragma unroll
-        for (int q = 0; q < PER; ++q)
-#pragma unroll
-          for (int h = 0; h < W; ++h) wv[q * W + h] = ld_word(src + (tid + 256 * q) * W + h);
-        bool got = true;
-#pragma unroll
-        for (int u = 0; u < PER * W; ++u) got &= (wv[u] >> 32) == tag;
-        if (got) break;
-        if (!keep_waiting(spins, status + 1)) {
-          ok = false;
-          break;
-        }
+      if (tid == 0) {
+        const uint64_t tag = tag0 + unsigned(bj);
+        unsigned spins = 0;
+        while (ld_word(fch + bj) != tag)
+          if (!keep_waiting(spins, status + 1)) {
+            s_ok = 0;
+            break;
+          }
       }
-      T xv[PER];
+      __syncthreads();
+      if (!s_ok) break;
+      // X_j: word w holds row w % 64 of column w / 64 (FP64) or of columns
+      // 2 (w / 64) and the next (FP32, low half first)
+      const uint64_t* src = xch + size_t(bj) * WPB;
+      uint64_t wv[WPT];
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        if constexpr (kF64)
-          xv[q] = T(__longlong_as_double(
-              (long long)(((wv[2 * q + 1] & 0xffffffffu) << 32) | (wv[2 * q] & 0xffffffffu))));
-        else
-          xv[q] = T(__uint_as_float(unsigned(wv[q])));
-      }
+      for (int q = 0; q < WPT; ++q) wv[q] = ld_word(src + tid + 256 * q);
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const int e = tid + 256 * q, i = e % kNB, k = e / kNB;
         ts[i][k] = (i < ib && k < jbj) ? lv[q] : T(0);
-        xs[i][k] = xv[q];  // here i is the row k' = e % 64 of X_j, k its column
       }
-      if (!ok) s_ok = 0;
+#pragma unroll
+      for (int q = 0; q < WPT; ++q) {
+        const int w = tid + 256 * q, r = w % kNB, cw = w / kNB;
+        if constexpr (kF64) {
+          xs[r][cw] = T(__longlong_as_double((long long)wv[q]));
+        } else {
+          xs[r][2 * cw] = T(__uint_as_float(unsigned(wv[q])));
+          xs[r][2 * cw + 1] = T(__uint_as_float(unsigned(wv[q] >> 32)));
+        }
+      }
       __syncthreads();
-      if (!s_ok) break;
 #pragma unroll 4
       for (int k = 0; k < kNB; ++k) {
         const T a = ts[row][k];
@@ -532,20 +536,21 @@ __global__ __launch_bounds__(256) void block_solve_kernel(
 #pragma unroll
       for (int q = 0; q < 16; ++q) x[q] += a * xs[k][g * 16 + q];
     }
-    uint64_t* dst = xch + size_t(bi) * kNB * kNB * W;
-    const uint64_t tag = tag0 + unsigned(bi);
+    uint64_t* dst = xch + size_t(bi) * WPB;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int c = g * 16 + q, e = row + c * kNB;
+      const int c = g * 16 + q;
       if (row < ib && c < rc) X[(r0 + row) + (c0 + c) * ldx] = x[q];
       if constexpr (kF64) {
-        const uint64_t b = uint64_t(__double_as_longlong(double(x[q])));
-        st_word(dst + 2 * e, (tag << 32) | (b & 0xffffffffu));
-        st_word(dst + 2 * e + 1, (tag << 32) | (b >> 32));
-      } else {
-        st_word(dst + e, (tag << 32) | __float_as_uint(float(x[q])));
+        st_word(dst + row + c * kNB, uint64_t(__double_as_longlong(double(x[q]))));
+      } else if (q % 2 == 0) {
+        st_word(dst + row + (c / 2) * kNB,
+                (uint64_t(__float_as_uint(float(x[q + 1]))) << 32) | __float_as_uint(float(x[q])));
       }
     }
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's block words have completed
+    __syncthreads();
+    if (tid == 0) st_word(fch + bi, tag0 + unsigned(bi));
     __syncthreads();  // ts, xs and s_t are reused
   }
 }
@@ -870,14 +875,14 @@ hipError_t solve_typed(int64_t n, int64_t nrhs, const T* LU, int64_t lda, const 
     // fresh tickets and no stale tags (forward tags 1..nb, backward nb+1..2nb)
     e = fill_i32_launch(reinterpret_cast<int32_t*>(w.tickets), 2 * kSolveChunks, 0, s);
     if (e == hipSuccess)
-      e = fill_i32_launch(reinterpret_cast<int32_t*>(w.xw), int64_t(solve_words(n, cols)) * 2, 0, s);
+      e = fill_i32_launch(reinterpret_cast<int32_t*>(w.flags), 2 * kSolveChunks * kSolveBlocks, 0, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((block_solve_kernel<T, false>), dim3(grid, chunks), dim3(256), 0, s, LU, lda,
-                       n, inv, X, ldx, cb, nrhs, w.xw, w.tickets, 1u, status);
+                       n, inv, X, ldx, cb, nrhs, w.xw, w.flags, w.tickets, 1u, status);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL((block_solve_kernel<T, true>), dim3(grid, chunks), dim3(256), 0, s, LU, lda,
-                       n, inv, X, ldx, cb, nrhs, w.xw, w.tickets + kSolveChunks, unsigned(nb + 1),
-                       status);
+                       n, inv, X, ldx, cb, nrhs, w.xw, w.flags, w.tickets + kSolveChunks,
+                       unsigned(nb + 1), status);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -894,6 +899,7 @@ size_t lu_workspace_bytes(int dtype, int64_t n, int64_t nrhs) {
   b += size_t(np) * 4 * kNB * sizeof(int32_t);
   b = (b + 255) & ~size_t(255);
   b += 256;  // tickets
+  b += size_t(kSolveChunks) * kSolveBlocks * sizeof(uint64_t);  // block flags
   // the FP32 solve's exchange (the FP64 solve launches per block step)
   if (dtype == 1 && nrhs > 0) b += solve_words(std::max<int64_t>(n, 1), nrhs) * sizeof(uint64_t);
   return (b + 255) & ~size_t(255);
