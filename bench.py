@@ -45,6 +45,8 @@ def parse():
                          "syrk: trans(X)*X, X 65536x2048, plain FP64/FP32 vs split-BF16")
     ap.add_argument("--forms", default="", help="comma-separated subset of forms (syrk, solve)")
     ap.add_argument("--no-tune", action="store_true", help="skip product autotuning")
+    ap.add_argument("--serial", action="store_true",
+                    help="expr workload, eager: both jobs on one stream, one after the other")
     ap.add_argument("--launch", default="eager", choices=["eager", "graph"],
                     help="expr workload: launch each plan's kernels on the stream (eager, the "
                          "default: the host queues ahead of the GPU) or replay a HIP graph of them")
@@ -593,9 +595,22 @@ def main():
         p2.capture(out2, ws2)
         run1, run2 = p1.replay, p2.replay
 
-    def step():
-        run1()
-        run2()
+    main = torch.cuda.current_stream()
+    if args.launch == "eager" and not args.serial:
+        # the two jobs are independent plans: the chain's launches go to a
+        # second stream (default priority) so that the latency-bound products
+        # run beside the HBM-bound element-wise pass
+        side = torch.cuda.Stream()
+
+        def step():
+            ctx.set_stream(side.cuda_stream)
+            run1()
+            ctx.set_stream(main.cuda_stream)
+            run2()
+    else:
+        def step():
+            run1()
+            run2()
 
     if args.copy_probe:  # a plain copy of 1 GiB: reference for HBM byte counters
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -678,7 +693,9 @@ def main():
                                f"0.5*exp(-(A%A))+B/C over {args.n}x{args.n}",
                    "chain_dims": list(inputs.FP32_CHAIN_DIMS), "elementwise_n": args.n,
                    "planner": "dp", "form": "plain fp32",
-                   "launch": "eager" if args.launch == "eager" else "hip graph replay",
+                   "launch": ("hip graph replay" if args.launch == "graph" else
+                              "eager, one stream" if args.serial else
+                              "eager, chain and element-wise on two streams"),
                    "autotuned": not args.no_tune},
         "roofline": ew_kernel,
         "jobs": {
