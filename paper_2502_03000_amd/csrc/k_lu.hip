@@ -149,6 +149,9 @@ __global__ __launch_bounds__(kPT) void panel_kernel(T* __restrict__ A, int64_t l
                                                     int32_t* swap_cnt, int32_t* swap_list,
                                                     int32_t* status) {
   if (blockIdx.x % stride) return;  // not a participant
+  // the panel is the critical path and shares CUs with the trailing update
+  // of the previous panel: its waves go first at instruction issue
+  __builtin_amdgcn_s_setprio(3);
   constexpr bool kF64 = sizeof(T) == 8;
   __shared__ unsigned s_kh[kWaves], s_kl[kWaves];
   __shared__ int s_kp[kWaves];
@@ -864,28 +867,29 @@ hipError_t solve_typed(int64_t n, int64_t nrhs, const T* LU, int64_t lda, const 
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
+  } else {
+    if (reinterpret_cast<uintptr_t>(w.xw) % 8 != 0) return hipErrorInvalidValue;
+    const T* inv = static_cast<const T*>(w.inv);
+    const int64_t nb = cdiv(n, kNB);
+    const unsigned grid = unsigned(std::min<int64_t>(nb, 256));
+    for (int64_t cb = 0; cb < nrhs; cb += int64_t(kSolveChunks) * kNB) {
+      const int64_t cols = std::min<int64_t>(nrhs - cb, int64_t(kSolveChunks) * kNB);
+      const unsigned chunks = unsigned(cdiv(cols, kNB));
+      // fresh tickets and flags (forward tags 1..nb, backward nb+1..2nb)
+      e = fill_i32_launch(reinterpret_cast<int32_t*>(w.tickets), 2 * kSolveChunks, 0, s);
+      if (e == hipSuccess)
+        e = fill_i32_launch(reinterpret_cast<int32_t*>(w.flags), 2 * kSolveChunks * kSolveBlocks, 0, s);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((block_solve_kernel<T, false>), dim3(grid, chunks), dim3(256), 0, s, LU,
+                         lda, n, inv, X, ldx, cb, nrhs, w.xw, w.flags, w.tickets, 1u, status);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL((block_solve_kernel<T, true>), dim3(grid, chunks), dim3(256), 0, s, LU,
+                         lda, n, inv, X, ldx, cb, nrhs, w.xw, w.flags, w.tickets + kSolveChunks,
+                         unsigned(nb + 1), status);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
-  if (reinterpret_cast<uintptr_t>(w.xw) % 8 != 0) return hipErrorInvalidValue;
-  const T* inv = static_cast<const T*>(w.inv);
-  const int64_t nb = cdiv(n, kNB);
-  const unsigned grid = unsigned(std::min<int64_t>(nb, 256));
-  for (int64_t cb = 0; cb < nrhs; cb += int64_t(kSolveChunks) * kNB) {
-    const int64_t cols = std::min<int64_t>(nrhs - cb, int64_t(kSolveChunks) * kNB);
-    const unsigned chunks = unsigned(cdiv(cols, kNB));
-    // fresh tickets and no stale tags (forward tags 1..nb, backward nb+1..2nb)
-    e = fill_i32_launch(reinterpret_cast<int32_t*>(w.tickets), 2 * kSolveChunks, 0, s);
-    if (e == hipSuccess)
-      e = fill_i32_launch(reinterpret_cast<int32_t*>(w.flags), 2 * kSolveChunks * kSolveBlocks, 0, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((block_solve_kernel<T, false>), dim3(grid, chunks), dim3(256), 0, s, LU, lda,
-                       n, inv, X, ldx, cb, nrhs, w.xw, w.flags, w.tickets, 1u, status);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL((block_solve_kernel<T, true>), dim3(grid, chunks), dim3(256), 0, s, LU, lda,
-                       n, inv, X, ldx, cb, nrhs, w.xw, w.flags, w.tickets + kSolveChunks,
-                       unsigned(nb + 1), status);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  return hipSuccess;
 }
 
 }  // namespace
