@@ -146,7 +146,7 @@ def bench_syrk(args, ctx, hx, torch, inputs):
         ex = ctx.leaf(leaf)
         p = ctx.plan(hx.trans(ex) @ ex, product_precision=prec)
         out, ws = p.output(), p.workspace()
-        if prec == "plain" and not args.no_tune:
+        if not args.no_tune:
             p.autotune(out, ws, reps=2)
         ms = time_plan(torch, p, out, ws, max(args.steps, 3))
         got = out.double().cpu().numpy()

@@ -46,7 +46,10 @@ std::vector<k::GemmConfig> gemm_candidates(const Step& s) {
     out.push_back(c);
   };
   add(k::gemm_choose(s.dtype, s.precision, s.mode, s.m, s.n, s.kk));
-  if (s.precision != 0) return out;
+  if (s.precision != 0) {  // the split-BF16 / FP16 family has one tile: split-K counts
+    for (int split : {1, 2, 4, 8, 16}) add(k::GemmConfig{0, split});
+    return out;
+  }
   for (int t = 0; t < k::gemm_tile_count(s.dtype); ++t) {
     if (!k::gemm_tile_valid(s.dtype, t, s.mode)) continue;
     add(k::GemmConfig{t, 1});

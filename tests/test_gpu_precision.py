@@ -83,6 +83,39 @@ def test_split_gemm_against_oracle(ctx, ta, tb, mnk):
     assert rel(got6, ref) <= 2e-6
 
 
+@pytest.mark.parametrize("prec,tol", [("bf16x3", 2e-5), ("bf16x6", 2e-6)])
+@pytest.mark.parametrize("syrk", [True, False])
+def test_split_family_every_split(tmp_path, prec, tol, syrk):
+    """The autotuner's split-K candidates of the split-BF16 family, each
+    forced through the tuning table (split 1 writes C directly, mirrored for
+    the symmetric product; the others reduce partials), on ragged shapes.
+    A context of its own: its table holds one product."""
+    ctx = hx.Context(0)
+    g = inputs.rng(62 + syrk)
+    x = inputs.normal(g, 700, 150, np.float32)
+    y = inputs.normal(g, 700, 90, np.float32)
+    ex, ey = ctx.leaf(dev(x)), ctx.leaf(dev(y))
+    if syrk:
+        e, ref = hx.trans(ex) @ ex, oracle.evaluate("trans(X)*X", {"X": x})
+    else:
+        e, ref = hx.trans(ex) @ ey, oracle.evaluate("trans(X)*Y", {"X": x, "Y": y})
+    p = ctx.plan(e, product_precision=prec)
+    out, ws = p.output(), p.workspace()
+    p.autotune(out, ws, reps=1)
+    path = tmp_path / "tune.txt"
+    ctx.tune_save(str(path))
+    target, key = path.read_text().split()[:2]
+    for split in (1, 2, 4, 8, 16, 32):
+        path.write_text(f"{target} {key} 0 {split}\n")
+        ctx.tune_load(str(path))
+        q = ctx.plan(e, product_precision=prec)
+        assert q.describe()["steps"][0]["split"] == split
+        out, ws = q.output(), q.workspace()
+        q.execute(out, ws)
+        assert ctx.sync().status == hx.OK
+        assert rel(host(out), ref) <= tol, split
+
+
 # ------------------------------------------------ mixed-precision solves
 
 @pytest.mark.parametrize("form,cond", [("ir_fp32", 1e3), ("ir_bf16x3", 1e3), ("ir_fp16", 1e2)])
