@@ -185,3 +185,15 @@ def test_row_vector_result_uses_gemv(ctx):
     p = ctx.plan(a @ x)
     assert kernels(p) == ["gemv_t"]
     assert p.shape == (1, 70)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus 2 exits with a message before it
+    touches a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
