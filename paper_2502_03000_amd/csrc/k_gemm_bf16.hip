@@ -54,7 +54,16 @@ struct Mfma16<_Float16> {
 };
 
 constexpr int BM = 128, BN = 128, BK = 32;
-constexpr int LDK = BK + 8;  // bf16 row stride in LDS (80 bytes: conflict-free 16-byte reads)
+constexpr int LDK = BK;  // bf16 row stride in LDS (64 bytes), 16-byte chunks swizzled
+
+// LDS position of element k of row `row` in a term's [row][k] tile: the
+// 16-byte chunk k / 8 is XORed with bits 2-3 of the row, so that the term
+// stores (8 bytes per lane, four consecutive rows per 32 lanes) fill the 64
+// banks once and the MFMA fragment reads (16 bytes per lane, 16 consecutive
+// rows at one chunk) touch 16 distinct 4-bank groups.
+__device__ __forceinline__ int lds_off(int row, int k) {
+  return row * LDK + (((k >> 3) ^ ((row >> 2) & 3)) << 3) + (k & 7);
+}
 
 template <int TERMS, typename E = __bf16>
 __device__ __forceinline__ void split_terms(float x, E (&t)[TERMS]) {
@@ -144,14 +153,14 @@ struct SplitTile {
           v4 v;
 #pragma unroll
           for (int q = 0; q < 4; ++q) v[q] = t[q][s];
-          *reinterpret_cast<v4*>(sa + s * A_ELEMS + row * LDK + kk) = v;
+          *reinterpret_cast<v4*>(sa + s * A_ELEMS + lds_off(row, kk)) = v;
         }
       } else {
         const int kk = e / (BM / 4), row = (e % (BM / 4)) * 4;
 #pragma unroll
         for (int s = 0; s < TERMS; ++s)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) sa[s * A_ELEMS + (row + q) * LDK + kk] = t[q][s];
+          for (int q = 0; q < 4; ++q) sa[s * A_ELEMS + lds_off(row + q, kk)] = t[q][s];
       }
     }
 #pragma unroll
@@ -167,14 +176,14 @@ struct SplitTile {
           v4 v;
 #pragma unroll
           for (int q = 0; q < 4; ++q) v[q] = t[q][s];
-          *reinterpret_cast<v4*>(sb + s * B_ELEMS + col * LDK + kk) = v;
+          *reinterpret_cast<v4*>(sb + s * B_ELEMS + lds_off(col, kk)) = v;
         }
       } else {
         const int kk = e / (BN / 4), col = (e % (BN / 4)) * 4;
 #pragma unroll
         for (int s = 0; s < TERMS; ++s)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) sb[s * B_ELEMS + (col + q) * LDK + kk] = t[q][s];
+          for (int q = 0; q < 4; ++q) sb[s * B_ELEMS + lds_off(col + q, kk)] = t[q][s];
       }
     }
   }
@@ -228,9 +237,9 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(GemmArgs g, int vec) {
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         a[s][f] = *reinterpret_cast<const v8*>(sa + s * G::A_ELEMS +
-                                               (wm * 64 + f * 16 + l16) * LDK + grp * 8);
+                                               lds_off(wm * 64 + f * 16 + l16, grp * 8));
         b[s][f] = *reinterpret_cast<const v8*>(sb + s * G::B_ELEMS +
-                                               (wn * 64 + f * 16 + l16) * LDK + grp * 8);
+                                               lds_off(wn * 64 + f * 16 + l16, grp * 8));
       }
 #pragma unroll
     for (int fm = 0; fm < 4; ++fm)
