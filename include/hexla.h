@@ -133,7 +133,7 @@ typedef enum hexla_planner {
   HEXLA_PLANNER_GREEDY = 1,  /* Sec. II rule: smallest-result pair first, leftmost on ties */
   HEXLA_PLANNER_NAIVE = 2,   /* Sec. III "naive": left to right, no rewrites     */
   HEXLA_PLANNER_LEARNED = 3  /* predicted-time DP with the context's cost model,
-                                judged by the DP (see hexla_ctx_set_model)      */
+                                checked by the DP (see hexla_ctx_set_model)     */
 } hexla_planner;
 
 typedef enum hexla_product_precision {
@@ -363,7 +363,7 @@ hexla_status hexla_batch_destroy(hexla_batch* batch);
  * With a model set on the context, HEXLA_PLANNER_LEARNED plans each chain by
  * a DP over predicted times (each product at its predicted-fastest
  * configuration; one inference launch per chain, on the context's stream,
- * waited for by hexla_plan_create). The multiply-add DP is the judge: the
+ * waited for by hexla_plan_create). The multiply-add DP has the last word: the
  * learned order is kept only when its multiply-adds are at most twice the
  * DP's and its predicted time is below the predicted time of the DP order;
  * otherwise the DP order is used. Configurations in the context's tuning

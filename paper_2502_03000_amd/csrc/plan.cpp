@@ -775,7 +775,7 @@ class Planner {
   // The learned planner: every product (lo, s, hi) a bracketing of the chain
   // can contain is priced at its predicted-fastest configuration (one
   // inference launch for all of them), a DP minimises the predicted time,
-  // and the multiply-add DP judges: its order is used unless the learned
+  // and the multiply-add DP decides: its order is used unless the learned
   // order costs at most twice its multiply-adds and is predicted faster.
   // The chosen configurations are kept for product().
   int order_learned(const std::vector<int64_t>& d, const std::vector<char>& sym,

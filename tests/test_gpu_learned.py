@@ -155,7 +155,7 @@ def time_plan(p, reps=3):
 
 def test_learned_planner_end_to_end(tmp_path):
     """Trains on a shape sweep disjoint from the evaluation chains, then plans
-    random chains with and without the model: results agree, the DP judge
+    random chains with and without the model: results agree, the DP check
     holds, and the time gained is reported."""
     ctx = hx.Context(0)
     log = tmp_path / "sweep.jsonl"
