@@ -155,7 +155,8 @@ def bench_syrk(args, ctx, hx, torch, inputs):
             "form": name, "ms": ms, "tflops_algorithmic": flops / (ms * 1e-3) / 1e12,
             "max_rel_err_sampled": float(np.max(np.abs(samp - exact) / np.abs(exact).max())),
             "rel_err_vs_closed_form": float(np.linalg.norm(got - closed) / np.linalg.norm(closed)),
-            "kernels": [f"{st['kernel']} split{st.get('split', 1)}" for st in p.describe()["steps"]],
+            "kernels": [f"{st['kernel']} tile{st.get('tile', 0)} split{st.get('split', 1)}"
+                        for st in p.describe()["steps"]],
         })
         del p, out, ws
         torch.cuda.empty_cache()

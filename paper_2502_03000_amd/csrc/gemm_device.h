@@ -245,8 +245,10 @@ __device__ __forceinline__ void xcd_work_item(int& tile, int& z) {
   tile = q - z * tiles;
 }
 
-template <typename T, bool TA, bool TB, int BM, int BN, int BK, bool VEC>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+// WPE: waves per SIMD the register allocation must allow (2 caps a wave at
+// 256 registers, so two workgroups of a small-LDS tile share a CU)
+template <typename T, bool TA, bool TB, int BM, int BN, int BK, bool VEC, int WPE = 1>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void gemm_kernel(GemmArgs g) {
   using G = GemmTile<T, TA, TB, BM, BN, BK, VEC>;
   __shared__ __attribute__((aligned(16))) T smem[2 * G::STAGE];
 

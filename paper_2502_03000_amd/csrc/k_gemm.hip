@@ -22,19 +22,21 @@ struct Tile {
 // instead of once per short step
 constexpr Tile kTilesF32[] = {{128, 128, 16}, {128, 64, 16}, {64, 64, 16}, {128, 128, 32},
                               {128, 64, 32},  {64, 64, 32},  {64, 64, 64}, {64, 64, 128}};
-// FP64: 0 = 64x64x16, 1 = 128x128x8
-constexpr Tile kTilesF64[] = {{64, 64, 16}, {128, 128, 8}};
+// FP64: 0 = 64x64x16, 1 = 128x128x8, 2 = 128x128x8 held to 256 registers per
+// wave (two workgroups per CU instead of one), 3 = 128x128x16 (one wave per
+// SIMD; a longer step hides more of each step's load latency)
+constexpr Tile kTilesF64[] = {{64, 64, 16}, {128, 128, 8}, {128, 128, 8}, {128, 128, 16}};
 
 typedef void (*GemmFn)(GemmArgs);
 
-template <typename T, int BM, int BN, int BK>
+template <typename T, int BM, int BN, int BK, int WPE = 1>
 GemmFn pick(bool ta, bool tb, bool vec) {
   if (vec) {
-    if (ta) return tb ? gemm_kernel<T, true, true, BM, BN, BK, true> : gemm_kernel<T, true, false, BM, BN, BK, true>;
-    return tb ? gemm_kernel<T, false, true, BM, BN, BK, true> : gemm_kernel<T, false, false, BM, BN, BK, true>;
+    if (ta) return tb ? gemm_kernel<T, true, true, BM, BN, BK, true, WPE> : gemm_kernel<T, true, false, BM, BN, BK, true, WPE>;
+    return tb ? gemm_kernel<T, false, true, BM, BN, BK, true, WPE> : gemm_kernel<T, false, false, BM, BN, BK, true, WPE>;
   }
-  if (ta) return tb ? gemm_kernel<T, true, true, BM, BN, BK, false> : gemm_kernel<T, true, false, BM, BN, BK, false>;
-  return tb ? gemm_kernel<T, false, true, BM, BN, BK, false> : gemm_kernel<T, false, false, BM, BN, BK, false>;
+  if (ta) return tb ? gemm_kernel<T, true, true, BM, BN, BK, false, WPE> : gemm_kernel<T, true, false, BM, BN, BK, false, WPE>;
+  return tb ? gemm_kernel<T, false, true, BM, BN, BK, false, WPE> : gemm_kernel<T, false, false, BM, BN, BK, false, WPE>;
 }
 
 GemmFn kernel_for(int dtype, int tile, bool ta, bool tb, bool vec) {
@@ -50,7 +52,12 @@ GemmFn kernel_for(int dtype, int tile, bool ta, bool tb, bool vec) {
       default: return pick<float, 64, 64, 128>(ta, tb, vec);
     }
   }
-  return tile == 1 ? pick<double, 128, 128, 8>(ta, tb, vec) : pick<double, 64, 64, 16>(ta, tb, vec);
+  switch (tile) {
+    case 1: return pick<double, 128, 128, 8>(ta, tb, vec);
+    case 2: return pick<double, 128, 128, 8, 2>(ta, tb, vec);
+    case 3: return pick<double, 128, 128, 16>(ta, tb, vec);
+    default: return pick<double, 64, 64, 16>(ta, tb, vec);
+  }
 }
 
 Tile tile_of(int dtype, int tile) { return dtype == 1 ? kTilesF32[tile] : kTilesF64[tile]; }
@@ -59,7 +66,7 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace
 
-int gemm_tile_count(int dtype) { return dtype == 1 ? 8 : 2; }
+int gemm_tile_count(int dtype) { return dtype == 1 ? 8 : 4; }
 
 void gemm_tile_shape(int dtype, int precision, int tile, int* bm, int* bn, int* bk) {
   if (precision != GEMM_PLAIN) {  // split-BF16 family: one 128 x 128 x 32 tile
@@ -115,7 +122,7 @@ GemmConfig gemm_choose(int dtype, int precision, int mode, int64_t m, int64_t n,
     else if (n <= 64) c.tile = 4;
     else c.tile = (m * n >= 1024 * 1024) ? 3 : 5;
   } else {
-    c.tile = (m * n >= int64_t(2048) * 2048) ? 1 : 0;
+    c.tile = (m * n >= int64_t(2048) * 2048) ? 2 : 0;
   }
   c.split = gemm_split_for(dtype, c.tile, mode, m, n, k, 256, 8);
   return c;

@@ -81,6 +81,7 @@ GemmConfig gemm_choose(int dtype, int precision, int mode, int64_t m, int64_t n,
 int gemm_tile_count(int dtype);
 void gemm_tile_shape(int dtype, int precision, int tile, int* bm, int* bn, int* bk);
 bool gemm_tile_valid(int dtype, int tile, int mode);
+int64_t gemm_tiles_for(int dtype, int tile, int mode, int64_t m, int64_t n);  // output tiles
 int gemm_split_for(int dtype, int tile, int mode, int64_t m, int64_t n, int64_t k, int64_t target,
                    int64_t min_steps);
 size_t gemm_partial_bytes(int dtype, const GemmConfig& cfg, int64_t m, int64_t n);

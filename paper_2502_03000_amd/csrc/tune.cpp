@@ -56,6 +56,14 @@ std::vector<k::GemmConfig> gemm_candidates(const Step& s) {
     for (int64_t target : {128, 256, 512, 1024})
       for (int64_t steps : {1, 2, 4, 8, 16})
         add(k::GemmConfig{t, k::gemm_split_for(s.dtype, t, s.mode, s.m, s.n, s.kk, target, steps)});
+    // the largest split whose workgroups fit 512, 1024 or 2048 slots (2, 4 or
+    // 8 per CU): whole rounds of workgroups, no short last round
+    const int64_t tiles = k::gemm_tiles_for(s.dtype, t, s.mode, s.m, s.n);
+    for (int64_t slots : {512, 1024, 2048}) {
+      const int64_t split = slots / tiles;
+      if (split >= 2)
+        add(k::GemmConfig{t, k::gemm_split_for(s.dtype, t, s.mode, s.m, s.n, s.kk, split * tiles, 1)});
+    }
   }
   return out;
 }

@@ -371,6 +371,38 @@ def test_every_fp32_tile_against_oracle(tmp_path, ta, tb, m):
             assert rel(host(out), ref) <= 1e-5, (tile, split)
 
 
+@pytest.mark.parametrize("sym", [False, True])
+def test_every_fp64_tile_against_oracle(tmp_path, sym):
+    """Each FP64 tile (forced through the tuning table), without and with
+    split-K, on a ragged general product and on a ragged trans(A)*A (the
+    symmetric-product mode: lower-triangle tiles, mirrored)."""
+    ctx = hx.Context(0)
+    g = inputs.rng(90 + sym)
+    m, n, k = 201, 130, 700
+    if sym:
+        a = inputs.normal(g, k, n, np.float64)
+        text, leaves = "trans(A)*A", {"A": a}
+        ea = ctx.leaf(dev(a))
+        e = hx.trans(ea) @ ea
+    else:
+        a, b = inputs.normal(g, m, k, np.float64), inputs.normal(g, k, n, np.float64)
+        text, leaves = "A*B", {"A": a, "B": b}
+        e = ctx.leaf(dev(a)) @ ctx.leaf(dev(b))
+    ref = oracle.evaluate(text, leaves)
+    for tile in range(4):
+        for split in (1, 5):
+            q = _force(ctx, tmp_path, e, tile, split)
+            if sym:
+                assert q.describe()["steps"][0]["kernel"] == "syrk"
+            out, ws = q.output(), q.workspace()
+            q.execute(out, ws)
+            assert ctx.sync().status == hx.OK
+            got = host(out)
+            assert rel(got, ref) <= 1e-13, (tile, split)
+            if sym:
+                assert np.array_equal(got, got.T), (tile, split)
+
+
 def _force(ctx, tmp_path, e, tile, split):
     """Plans `e` (one product) with the given tile and split through the tuning table."""
     p = ctx.plan(e)
