@@ -48,6 +48,9 @@ std::vector<k::GemmConfig> gemm_candidates(const Step& s) {
   add(k::gemm_choose(s.dtype, s.precision, s.mode, s.m, s.n, s.kk));
   if (s.precision != 0) {  // the split-BF16 / FP16 family has one tile: split-K counts
     for (int split : {1, 2, 4, 8, 16}) add(k::GemmConfig{0, split});
+    const int64_t tiles = k::gemm_tiles_for(s.dtype, 0, s.mode, s.m, s.n);  // 128 x 128 tiles
+    for (int64_t slots : {512, 1024, 2048})
+      if (slots / tiles >= 2 && slots / tiles <= 64) add(k::GemmConfig{0, int(slots / tiles)});
     return out;
   }
   for (int t = 0; t < k::gemm_tile_count(s.dtype); ++t) {
