@@ -670,7 +670,9 @@ __global__ __launch_bounds__(256) void rank_update_kernel(int64_t m, int64_t n, 
 template <typename T>
 hipError_t rank_update(int64_t m, int64_t n, int64_t K, const T* A, int64_t lda, const T* B,
                        int64_t ldb, T* C, int64_t ldc, hipStream_t s) {
-  constexpr int BT = sizeof(T) == 8 ? 64 : 128;
+  // 64 x 64 tiles in both types: the FP32 128 x 128 tile needed 325
+  // registers (one wave per SIMD); at 64 x 64 three waves fit
+  constexpr int BT = 64;
   const int64_t tm = cdiv(m, BT), tn = cdiv(n, BT);
   if (K > kNB || tm * tn > INT32_MAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL((rank_update_kernel<T, BT>), dim3(unsigned(tm * tn)), dim3(256), 0, s, m, n,
