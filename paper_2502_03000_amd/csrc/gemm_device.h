@@ -32,6 +32,8 @@ struct GemmArgs {
   int32_t tiles_m, tiles_n;
   int32_t mode;      // 0 full, 1 lower-triangle tiles + mirror (square tiles)
   int32_t split;
+  int32_t ct;        // split-BF16 family, split 1, mode 0: the kernel computes
+                     // C^T (m x n here) and stores element (i, j) at C[j + i*ldc]
 };
 
 template <typename T>

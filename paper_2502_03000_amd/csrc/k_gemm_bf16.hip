@@ -286,9 +286,10 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(GemmArgs g, int vec) {
             if (i > j) C[j + i * g.ldc] = out;
           }
         } else {
+          const int64_t at = g.ct ? j + i * g.ldc : i + j * g.ldc;
           float out = alpha * v;
-          if (beta != 0.f) out += beta * C[i + j * g.ldc];
-          C[i + j * g.ldc] = out;
+          if (beta != 0.f) out += beta * C[at];
+          C[at] = out;
         }
       }
 }
@@ -341,7 +342,21 @@ hipError_t gemm_split_launch(int dtype, int precision, int mode, int ta, int tb,
                              const void* B, int64_t ldb, double beta, void* C, int64_t ldc,
                              void* partial, const GemmConfig& cfg, hipStream_t s) {
   if (dtype != 1) return hipErrorNotSupported;  // FP32 storage only
+  // Without split-K a full product is computed transposed, C^T = op(B)^T op(A)^T:
+  // the accumulator layout then gives each 16-lane group 16 consecutive rows
+  // of one column of C, so C is read and written in 64-byte runs (C-bound
+  // products such as the LU's rank-64 updates gain most).
+  const bool ct = mode == 0 && cfg.split <= 1;
+  if (ct) {
+    std::swap(m, n);
+    std::swap(A, B);
+    std::swap(lda, ldb);
+    const int t = ta;
+    ta = !tb;
+    tb = !t;
+  }
   GemmArgs g{};
+  g.ct = ct ? 1 : 0;
   g.m = m; g.n = n; g.k = k;
   g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
   g.alpha = alpha; g.beta = beta; g.partial = partial;
