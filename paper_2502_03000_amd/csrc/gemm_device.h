@@ -297,6 +297,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
   const T alpha = T(g.alpha), beta = T(g.beta);
   T* C = static_cast<T*>(g.C);
   T* P = static_cast<T*>(g.partial);
+  if constexpr (sizeof(T) == 4) {
+    // FP32 split-K partials: a lane's four registers are four consecutive
+    // rows of one column, written as one 16-byte store (m % 4 == 0 keeps
+    // every such store inside the column and 16-byte aligned)
+    if (g.split > 1 && (g.m & 3) == 0 && (reinterpret_cast<uintptr_t>(P) & 15) == 0) {
+#pragma unroll
+      for (int fm = 0; fm < G::FM; ++fm)
+#pragma unroll
+        for (int fn = 0; fn < G::FN; ++fn) {
+          const int64_t i = m0 + wm * G::WM + fm * 16 + Mfma<T>::row(lane, 0);
+          const int64_t j = n0 + wn * G::WN + fn * 16 + (lane & 15);
+          if (i >= g.m || j >= g.n) continue;
+          *reinterpret_cast<typename G::acc_t*>(P + int64_t(z) * g.m * g.n + i + j * g.m) =
+              acc[fm][fn];
+        }
+      return;
+    }
+  }
 #pragma unroll
   for (int fm = 0; fm < G::FM; ++fm)
 #pragma unroll
