@@ -266,6 +266,20 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(GemmArgs g, int vec) {
   const float alpha = float(g.alpha), beta = float(g.beta);
   float* C = static_cast<float*>(g.C);
   float* P = static_cast<float*>(g.partial);
+  if (g.split > 1 && (g.m & 3) == 0 && (reinterpret_cast<uintptr_t>(P) & 15) == 0) {
+    // split-K partials: a lane's four registers are four consecutive rows
+    // of one column, one 16-byte store (in bounds and aligned as m % 4 == 0)
+#pragma unroll
+    for (int fm = 0; fm < 4; ++fm)
+#pragma unroll
+      for (int fn = 0; fn < 4; ++fn) {
+        const int64_t i = m0 + wm * 64 + fm * 16 + 4 * grp;
+        const int64_t j = n0 + wn * 64 + fn * 16 + l16;
+        if (i >= g.m || j >= g.n) continue;
+        *reinterpret_cast<accv*>(P + int64_t(z) * g.m * g.n + i + j * g.m) = acc[fm][fn];
+      }
+    return;
+  }
 #pragma unroll
   for (int fm = 0; fm < 4; ++fm)
 #pragma unroll
