@@ -85,15 +85,18 @@ def test_split_gemm_against_oracle(ctx, ta, tb, mnk):
 
 @pytest.mark.parametrize("prec,tol", [("bf16x3", 2e-5), ("bf16x6", 2e-6)])
 @pytest.mark.parametrize("syrk", [True, False])
-def test_split_family_every_split(tmp_path, prec, tol, syrk):
+@pytest.mark.parametrize("cols", [(150, 90), (152, 88)])
+def test_split_family_every_split(tmp_path, prec, tol, syrk, cols):
     """The autotuner's split-K candidates of the split-BF16 family, each
-    forced through the tuning table (split 1 writes C directly, mirrored for
-    the symmetric product; the others reduce partials), on ragged shapes.
-    A context of its own: its table holds one product."""
+    forced through the tuning table (split 1 writes C directly: mirrored for
+    the symmetric product, through the transposed product otherwise; the
+    others reduce partials, written as 16-byte stores when the row count is
+    a multiple of 4), on ragged shapes. A context of its own: its table
+    holds one product."""
     ctx = hx.Context(0)
     g = inputs.rng(62 + syrk)
-    x = inputs.normal(g, 700, 150, np.float32)
-    y = inputs.normal(g, 700, 90, np.float32)
+    x = inputs.normal(g, 700, cols[0], np.float32)
+    y = inputs.normal(g, 700, cols[1], np.float32)
     ex, ey = ctx.leaf(dev(x)), ctx.leaf(dev(y))
     if syrk:
         e, ref = hx.trans(ex) @ ex, oracle.evaluate("trans(X)*X", {"X": x})
