@@ -129,7 +129,7 @@ def test_product_features():
     g = hx.product_features(hx.F64, 0, 1, 1, 0, 512, 512, 100, 0, 1)
     assert g[6] == 1 and g[8] == 1 and g[29] == 0 and 0 < g[25] <= 1
     with pytest.raises(hx.HexlaError):
-        hx.product_features(hx.F64, 0, 0, 0, 0, 16, 16, 16, 5, 1)  # FP64 has 2 tiles
+        hx.product_features(hx.F64, 0, 0, 0, 0, 16, 16, 16, 4, 1)  # FP64 has 4 tiles
 
 
 def test_learned_planner_without_model_is_dp():
