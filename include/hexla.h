@@ -142,21 +142,30 @@ typedef enum hexla_product_precision {
   HEXLA_PRODUCT_BF16X6 = 2   /* FP32 products as 6 BF16 MFMA products (3-term split) */
 } hexla_product_precision;
 
-/* Mixed-precision forms apply to FP64 systems: the LU is computed on an FP32
- * copy (partial pivoting on the FP32 values), the residual R = B - S X and the
- * update X += D in FP64, with D solved on the low-precision factors, until
- * ||R||inf <= ir_tol_scale * 2^-53 * ||S||inf * ||X||inf (ir_tol_scale 0:
- * 1), the correction stagnates (||D|| > 0.5 ||D_prev||) or ir_max_iter is
- * reached (deferred HEXLA_E_NO_CONVERGENCE). The refinement loop reads a
- * small status block after every step, so hexla_execute of such a plan
- * returns only when the solve is done and the plan cannot be captured.
- * A correction larger than the previous one is dropped (divergence); one
- * larger than half the previous one is applied and ends the loop. */
+/* Mixed-precision forms apply to FP64 systems (iterative refinement with a
+ * low-precision factorisation; the paper names reduced-precision types as
+ * future work, Sec. IV). The LU is stored in FP32 and its panels are factored
+ * in FP32 (IR_FP32) or in FP64, pivots chosen on FP64 values and the panel
+ * rounded to FP32 when stored (IR_FP16, IR_BF16X3); the trailing updates run
+ * in the form's product precision with FP32 accumulation. The residual
+ * R = B - S X and the update X += D are FP64, D solved on the low-precision
+ * factors. The loop stops when ||R||inf <= ir_tol_scale * 2^-53 * ||S||inf *
+ * ||X||inf (ir_tol_scale 0: 1; converged), when ir_max_iter is reached, when
+ * a correction is larger than the previous one (it is dropped) or when it is
+ * larger than half the previous one (it is applied: stagnation). A stagnated
+ * solve whose last residual's backward error ||R||/(||S|| ||X||) exceeds
+ * n * 2^-53, a diverging one and a capped one raise the deferred
+ * HEXLA_E_NO_CONVERGENCE; hexla_sync reports the iterations and that
+ * backward error. The loop reads a small status block after every step, so
+ * hexla_execute of such a plan returns only when the solve is done and the
+ * plan cannot be captured. */
 typedef enum hexla_solve_precision {
   HEXLA_SOLVE_PLAIN = 0,     /* LU and substitution in the storage type          */
-  HEXLA_SOLVE_IR_FP32 = 1,   /* FP32 LU, FP32 trailing updates                   */
-  HEXLA_SOLVE_IR_FP16 = 2,   /* FP32 LU, FP16-MFMA trailing updates (FP32 accumulation) */
-  HEXLA_SOLVE_IR_BF16X3 = 3  /* FP32 LU, split-BF16 (x3) MFMA trailing updates   */
+  HEXLA_SOLVE_IR_FP32 = 1,   /* FP32 LU (FP32 panels), FP32 trailing updates      */
+  HEXLA_SOLVE_IR_FP16 = 2,   /* FP32 LU, FP64 panels, FP16-MFMA trailing updates
+                                (FP32 accumulation)                              */
+  HEXLA_SOLVE_IR_BF16X3 = 3  /* FP32 LU, FP64 panels, split-BF16 (x3) MFMA
+                                trailing updates                                 */
 } hexla_solve_precision;
 
 typedef struct hexla_plan_opts {
@@ -221,11 +230,14 @@ typedef struct hexla_report {
   int32_t status;             /* deferred hexla_status of the work since the last sync */
   int32_t ir_iterations;      /* refinement iterations of the last refined solve */
   int64_t singular_column;    /* first zero-pivot column (or -1)                 */
+  double ir_backward_error;   /* ||R||inf / (||S||inf ||X||inf) of the last
+                                 residual that refined solve formed            */
 } hexla_report;
 
 /* Waits for the context's stream, then reports (and clears) the deferred
  * status: HEXLA_E_SINGULAR (exact zero pivot; the result is unspecified),
- * HEXLA_E_NO_CONVERGENCE (refinement cap reached). `report` may be NULL. The
+ * HEXLA_E_NO_CONVERGENCE (a refined solve hit its cap, its correction grew,
+ * or it stagnated with a backward error above n * 2^-53). `report` may be NULL. The
  * return value is HEXLA_E_DEVICE on a HIP error, else HEXLA_OK. */
 hexla_status hexla_sync(hexla_ctx* ctx, hexla_report* report);
 

@@ -10,7 +10,8 @@ type of Fig. 2 and the ``double`` element type of Fig. 3).
 Modules
 -------
 parse     recursive-descent parser for the expression language
-evaluate  plain evaluation of a parsed expression (definitions, no rewrites)
+evaluate  plain evaluation of a parsed expression (definitions, no rewrites),
+          and the componentwise error scale of its result
 chain     parenthesisation enumeration, cost counts, the paper's greedy rule
 gepp      Gaussian elimination with partial pivoting, substitution, inverse
 bf16      bfloat16 round-to-nearest-even and hi/lo splitting
@@ -18,8 +19,8 @@ refine    mixed-precision iterative refinement, step by step
 mlp       small ReLU network: forward, backward, MSE, Adam
 """
 from .parse import parse, OracleSyntaxError
-from .evaluate import evaluate, OracleDimError
+from .evaluate import evaluate, magnitude, OracleDimError
 from .gepp import SingularMatrix
 
-__all__ = ["parse", "evaluate", "OracleSyntaxError", "OracleDimError",
+__all__ = ["parse", "evaluate", "magnitude", "OracleSyntaxError", "OracleDimError",
            "SingularMatrix"]

@@ -15,6 +15,11 @@ choice here is a reading):
       stop (stagnated) if ||D||_inf > 0.5 * ||D_prev||_inf
   until the iteration cap.
 
+Each residual's backward error ||R||_inf / (||S||_inf ||X||_inf) is kept. The
+result is accepted when the loop converged, or when it stagnated and the
+backward error of the last residual formed is at most n * 2^-53 (the level of
+a backward-stable FP64 solve); a diverging or capped loop is not accepted.
+
 ``solve_low`` solves with the low-precision factors; the oracle's default
 factorises in float32 with partial pivoting (``gepp.lu_partial_pivot`` with
 dtype float32) and substitutes in float64 on the float32 factors.
@@ -48,16 +53,19 @@ def refine(s, b, solve_low=None, cap: int = 30) -> dict:
     if solve_low is None:
         solve_low = low_precision_solver(s)
     n = s.shape[0]
-    tol = 2.0 ** -53 * norm_inf(s)
+    u = 2.0 ** -53
+    s_norm = norm_inf(s)
     x = solve_low(b)
-    history = []
+    history, berr = [], []
     d_prev = None
     status = "cap"
     for it in range(cap + 1):
         r = b - s @ x
         rn = norm_inf(r)
         history.append(rn)
-        if rn <= tol * norm_inf(x):
+        scale = s_norm * norm_inf(x)
+        berr.append(rn / scale if scale > 0 else (np.inf if rn > 0 else 0.0))
+        if rn <= u * scale:
             status = "converged"
             break
         if it == cap:
@@ -72,5 +80,6 @@ def refine(s, b, solve_low=None, cap: int = 30) -> dict:
             status = "stagnated"
             break
         d_prev = dn
+    accepted = status == "converged" or (status == "stagnated" and berr[-1] <= n * u)
     return {"x": x, "iterations": len(history) - 1, "residuals": history,
-            "status": status}
+            "backward_errors": berr, "status": status, "accepted": accepted}

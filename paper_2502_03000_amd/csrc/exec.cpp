@@ -135,9 +135,15 @@ GemmBind bind_gemm(const Step& s, void* out, int64_t ld_out, void* workspace) {
   return g;
 }
 
-// Mixed-precision solve of an FP64 system (see hexla_solve_precision): FP32
-// LU, first solve, then FP64 residual / low-precision correction steps. The
-// loop reads the norms after each step (one small device-to-host copy).
+// Mixed-precision solve of an FP64 system (see hexla_solve_precision): LU in
+// the low precision (FP32 storage; FP64 panels for the FP16 and split-BF16
+// update forms), first solve, then FP64 residual / low-precision correction
+// steps. The loop reads the norms after each step (one small device-to-host
+// copy). Outcome: converged (OK); the correction grew (it is dropped) or the
+// cap was reached (deferred HEXLA_E_NO_CONVERGENCE); the correction shrank
+// by less than half (it is applied and the loop ends): OK when the backward
+// error ||R||/(||S|| ||X||) of the last residual formed is at most n * 2^-53,
+// else HEXLA_E_NO_CONVERGENCE.
 hexla_status run_ir_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipStream_t st) {
   const IrWork& w = s.ir;
   const int64_t n = s.n, r = s.nrhs;
@@ -153,22 +159,24 @@ hexla_status run_ir_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipStrea
   auto fail = [&](hipError_t e, const char* what) { return device_err(ctx, e, what); };
   hipError_t e = k::cast_launch(0, 1, n, n, addr(S.ref, b), si(S), sj(S), s_low, ldn, st);
   if (e != hipSuccess) return fail(e, "ir: cast S");
-  e = k::lu_factor_launch(1, n, s_low, ldn, rowid, addr(w.luwork, b), ctx->d_status, st,
-                          w.update_precision);
-  if (e != hipSuccess) return fail(e, "ir: lu");
+  // ||S||inf of the (rounded) copy, before it is factored in place
   e = k::norm_inf_launch(1, n, n, s_low, ldn, scratch, norms + 0, st);
   if (e != hipSuccess) return fail(e, "ir: norm S");
+  e = k::lu_factor_launch(1, n, s_low, ldn, rowid, addr(w.luwork, b), ctx->d_status, st,
+                          w.update_precision, w.panel_fp64);
+  if (e != hipSuccess) return fail(e, "ir: lu");
   // X0 = LU^-1 B in the low precision
   e = k::cast_launch(0, 1, n, r, addr(B.ref, b), si(B), sj(B), r_low, ldn, st);
   if (e == hipSuccess) e = k::lu_solve_launch(1, n, r, s_low, ldn, rowid, addr(w.luwork, b), r_low, ldn, d_low, ldn,
                                                 ctx->d_status, st);
   if (e == hipSuccess) e = k::cast_launch(1, 0, n, r, d_low, 1, ldn, addr(X.ref, b), X.ld, st);
   if (e != hipSuccess) return fail(e, "ir: first solve");
-  const double tol = (w.tol_scale > 0 ? w.tol_scale : 1.0) * std::ldexp(1.0, -53);
+  const double u = std::ldexp(1.0, -53);
+  const double tol = (w.tol_scale > 0 ? w.tol_scale : 1.0) * u;
   double h[4] = {0, 0, 0, 0};
-  double d_prev = -1.0;
+  double d_prev = -1.0, berr = 0.0;
   int it = 0;
-  bool converged = false;
+  enum { kConverged, kCap, kDiverging, kStagnated } outcome = kCap;
   for (;; ++it) {
     // R = B - S X (FP64)
     e = k::cast_launch(0, 0, n, r, addr(B.ref, b), si(B), sj(B), r64, ldn, st);
@@ -180,8 +188,10 @@ hexla_status run_ir_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipStrea
     if (e == hipSuccess) e = hipMemcpyAsync(h, norms, 3 * sizeof(double), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(e, "ir: residual");
-    if (h[1] <= tol * h[0] * h[2]) {
-      converged = true;
+    const double scale = h[0] * h[2];
+    berr = scale > 0.0 ? h[1] / scale : (h[1] > 0.0 ? HUGE_VAL : 0.0);
+    if (h[1] <= tol * scale) {
+      outcome = kConverged;
       break;
     }
     if (it >= w.max_iter) break;
@@ -194,17 +204,23 @@ hexla_status run_ir_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipStrea
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(e, "ir: correction");
     // a growing correction is dropped; a slowly shrinking one is the last
-    if (d_prev >= 0.0 && h[3] > d_prev) break;
+    if (d_prev >= 0.0 && h[3] > d_prev) {
+      outcome = kDiverging;
+      break;
+    }
     e = k::add_mixed_launch(1, n, r, static_cast<double*>(addr(X.ref, b)), X.ld, d_low, ldn, st);
     if (e != hipSuccess) return fail(e, "ir: update");
     if (d_prev >= 0.0 && h[3] > 0.5 * d_prev) {
       ++it;
+      outcome = kStagnated;
       break;
     }
     d_prev = h[3];
   }
   ctx->host_ir_iterations = it;
-  if (!converged && it >= w.max_iter && ctx->host_status == 0) ctx->host_status = HEXLA_E_NO_CONVERGENCE;
+  ctx->host_ir_berr = berr;
+  const bool accepted = outcome == kConverged || (outcome == kStagnated && berr <= double(n) * u);
+  if (!accepted && ctx->host_status == 0) ctx->host_status = HEXLA_E_NO_CONVERGENCE;
   return HEXLA_OK;
 }
 
@@ -314,6 +330,7 @@ hexla_status hexla_sync(hexla_ctx* ctx, hexla_report* report) {
   if (e != hipSuccess) return device_err(ctx, e, "hexla_sync");
   r.status = h[0] ? h[0] : ctx->host_status;
   r.ir_iterations = ctx->host_ir_iterations;
+  r.ir_backward_error = ctx->host_ir_berr;
   ctx->host_status = 0;
   if (h[0] == HEXLA_E_SINGULAR) r.singular_column = h[2];
   if (h[1]) {

@@ -84,6 +84,7 @@ struct IrWork {
   Ref partial;   // split-K partials of the residual product
   k::GemmConfig res_cfg{};
   int update_precision = 0;  // k::GemmPrecision of the LU's trailing updates
+  bool panel_fp64 = false;   // panels factored in FP64 (pivots on FP64 values)
   int max_iter = 30;
   double tol_scale = 0.0;    // 0: sqrt(n)
 };
@@ -123,6 +124,7 @@ struct hexla_ctx {
   std::map<std::string, hexla::k::GemmConfig> tuned;  // autotuned product configurations
   int32_t host_status = 0;         // deferred status raised by host-driven loops
   int32_t host_ir_iterations = 0;  // iterations of the last refined solve
+  double host_ir_berr = 0.0;       // its backward error ||R||/(||S|| ||X||), last residual
   hexla_model* model = nullptr;    // cost model of the learned planner (borrowed)
   std::string timing_log;          // autotune timings are appended here when set
   // objects made from this context; destroying the context detaches them

@@ -142,7 +142,10 @@ __device__ __forceinline__ bool keep_waiting(unsigned& spins, int32_t* abort_fla
 // column j only after every participant has published column j - 1, which
 // each does after reading column j - 2. At the end every row is written at
 // its final position and the moved rows are listed for laswp.
-template <typename T>
+// T is the storage type, C the type the panel is factored in: a float
+// matrix may be factored with FP64 panels (pivots chosen on FP64 values,
+// the eliminated panel rounded to float when it is stored).
+template <typename T, typename C = T>
 __global__ __launch_bounds__(kPT) void panel_kernel(T* __restrict__ A, int64_t lda, int64_t n,
                                                     int64_t k, int jb, int G, int stride,
                                                     uint64_t* slots, unsigned tag0,
@@ -152,11 +155,11 @@ __global__ __launch_bounds__(kPT) void panel_kernel(T* __restrict__ A, int64_t l
   // the panel is the critical path and shares CUs with the trailing update
   // of the previous panel: its waves go first at instruction issue
   __builtin_amdgcn_s_setprio(3);
-  constexpr bool kF64 = sizeof(T) == 8;
+  constexpr bool kF64 = sizeof(C) == 8;
   __shared__ unsigned s_kh[kWaves], s_kl[kWaves];
   __shared__ int s_kp[kWaves];
-  __shared__ T s_row[kNB];  // the candidate row, staged by its owner for its wave
-  __shared__ T s_piv[kNB];  // the pivot row
+  __shared__ C s_row[kNB];  // the candidate row, staged by its owner for its wave
+  __shared__ C s_piv[kNB];  // the pivot row
   __shared__ int s_wp, s_ok;
   const int g = blockIdx.x / stride;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -166,9 +169,9 @@ __global__ __launch_bounds__(kPT) void panel_kernel(T* __restrict__ A, int64_t l
   const bool own = r < mp;
   // a wait timed out in an earlier panel: the factorisation is void, exit
   if (__hip_atomic_load(status + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
-  T v[kNB];
+  C v[kNB];
 #pragma unroll
-  for (int c = 0; c < kNB; ++c) v[c] = (own && c < jb) ? A[(k + r) + (k + c) * lda] : T(0);
+  for (int c = 0; c < kNB; ++c) v[c] = (own && c < jb) ? C(A[(k + r) + (k + c) * lda]) : C(0);
   int pos = own ? r : int(kNoPos);
   if (tid == 0) s_ok = 1;
 
@@ -212,7 +215,7 @@ __global__ __launch_bounds__(kPT) void panel_kernel(T* __restrict__ A, int64_t l
         for (int c = 0; c < kNB; ++c) s_row[c] = v[c];
       }
       wave_fence();
-      const T x = lane < kNB - j ? s_row[lane] : T(0);
+      const C x = lane < kNB - j ? s_row[lane] : C(0);
       uint64_t* slot = base + size_t(g) * kSlotW;
       if constexpr (kF64) {
         const uint64_t b = uint64_t(__double_as_longlong(double(x)));
@@ -272,19 +275,19 @@ __global__ __launch_bounds__(kPT) void panel_kernel(T* __restrict__ A, int64_t l
       }
       if (ok) {
         const uint64_t* sw = base + size_t(wq) * kSlotW + kHdrW;
-        T pr = T(0);
+        C pr = C(0);
         spins = 0;
         for (;;) {
           bool got;
           if constexpr (kF64) {
             const uint64_t w0 = ld_word(sw + 2 * lane), w1 = ld_word(sw + 2 * lane + 1);
             got = ((w0 >> 32) == tag) & ((w1 >> 32) == tag);
-            pr = T(__longlong_as_double(
+            pr = C(__longlong_as_double(
                 (long long)(((w1 & 0xffffffffu) << 32) | (w0 & 0xffffffffu))));
           } else {
             const uint64_t w0 = ld_word(sw + lane);
             got = (w0 >> 32) == tag;
-            pr = T(__uint_as_float(unsigned(w0)));
+            pr = C(__uint_as_float(unsigned(w0)));
           }
           if (__all(got)) break;
           if (!keep_waiting(spins, status + 1)) {
@@ -301,16 +304,16 @@ __global__ __launch_bounds__(kPT) void panel_kernel(T* __restrict__ A, int64_t l
     }
     __syncthreads();
     if (!s_ok) break;  // the same for every thread of the workgroup
-    T prow[kNB];
+    C prow[kNB];
 #pragma unroll
     for (int c = 0; c < kNB; ++c) prow[c] = s_piv[c];
     const int wp = s_wp;
-    const T pivot = prow[0];
+    const C pivot = prow[0];
     // 4. interchange positions j and wp, eliminate below the pivot, rotate
     pos = pos == wp ? j : (pos == j ? wp : pos);
-    const bool active = own & (pos > j) & (pivot != T(0));
-    const T l = active ? v[0] / pivot : T(0);
-    const T last = active ? l : v[0];
+    const bool active = own & (pos > j) & (pivot != C(0));
+    const C l = active ? v[0] / pivot : C(0);
+    const C last = active ? l : v[0];
 #pragma unroll
     for (int c = 0; c < kNB - 1; ++c) v[c] = v[c + 1] - l * prow[c + 1];
     v[kNB - 1] = last;
@@ -321,7 +324,7 @@ __global__ __launch_bounds__(kPT) void panel_kernel(T* __restrict__ A, int64_t l
 #pragma unroll
     for (int c = 0; c < kNB; ++c) {
       const int col = (c + jb) % kNB;  // every row is rotated by jb
-      if (col < jb) A[(k + pos) + (k + col) * lda] = v[c];
+      if (col < jb) A[(k + pos) + (k + col) * lda] = T(v[c]);
     }
     if (pos != r) {
       const int e = atomicAdd(swap_cnt, 1);
@@ -734,7 +737,7 @@ struct SideStream {
 
 template <typename T>
 hipError_t factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* rowid, void* work,
-                        int32_t* status, hipStream_t s, int prec) {
+                        int32_t* status, hipStream_t s, int prec, bool panel_fp64) {
   if (n == 0) return hipSuccess;
   if (n > kLuMaxN) return hipErrorInvalidValue;
   const int64_t np = cdiv(n, kNB);
@@ -763,8 +766,13 @@ hipError_t factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* rowid,
     // up to 32 participants share one XCD (every 8th workgroup id)
     const int stride = G <= 32 ? 8 : 1;
     int32_t* list = w.swap_list + p * (4 * kNB);
-    hipLaunchKernelGGL((panel_kernel<T>), dim3(G * stride), dim3(kPT), 0, s, A, lda, n, k, jb, G,
-                       stride, w.slots, unsigned(p * kNB + 1), w.swap_cnt + p, list, status);
+    if (panel_fp64)
+      hipLaunchKernelGGL((panel_kernel<T, double>), dim3(G * stride), dim3(kPT), 0, s, A, lda, n, k,
+                         jb, G, stride, w.slots, unsigned(p * kNB + 1), w.swap_cnt + p, list,
+                         status);
+    else
+      hipLaunchKernelGGL((panel_kernel<T, T>), dim3(G * stride), dim3(kPT), 0, s, A, lda, n, k, jb,
+                         G, stride, w.slots, unsigned(p * kNB + 1), w.swap_cnt + p, list, status);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (pending) {  // the interchanges touch the columns the side stream updates
       if ((e = hipStreamWaitEvent(s, side.done, 0)) != hipSuccess) return e;
@@ -912,11 +920,13 @@ size_t lu_workspace_bytes(int dtype, int64_t n, int64_t nrhs) {
 }
 
 hipError_t lu_factor_launch(int dtype, int64_t n, void* A, int64_t lda, int32_t* rowid,
-                            void* work, int32_t* status, hipStream_t s, int update_precision) {
+                            void* work, int32_t* status, hipStream_t s, int update_precision,
+                            bool panel_fp64) {
   return dtype == 0
-             ? factor_typed<double>(0, n, static_cast<double*>(A), lda, rowid, work, status, s, 0)
+             ? factor_typed<double>(0, n, static_cast<double*>(A), lda, rowid, work, status, s, 0,
+                                    false)
              : factor_typed<float>(1, n, static_cast<float*>(A), lda, rowid, work, status, s,
-                                   update_precision);
+                                   update_precision, panel_fp64);
 }
 
 hipError_t lu_solve_launch(int dtype, int64_t n, int64_t nrhs, const void* LU, int64_t lda,

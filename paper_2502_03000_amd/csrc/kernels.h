@@ -107,7 +107,9 @@ hipError_t split_bf16_launch(const float* x, int64_t n, uint16_t* t0, uint16_t* 
 // position (row i of L U is row rowid[i] of A). status[0] gets HEXLA_E_SINGULAR
 // and status[2..3] the first zero-pivot column on an exact zero pivot.
 // update_precision: GemmPrecision of the trailing updates (FP32 storage only
-// for the non-plain values).
+// for the non-plain values). panel_fp64 (FP32 storage only): each panel is
+// factored in FP64 (pivot search and elimination on FP64 values) and rounded
+// to FP32 when it is stored.
 // n <= kLuMaxN (larger n: hipErrorInvalidValue). The workspace also keeps the
 // inverses of the 64 x 64 diagonal blocks, which lu_solve_launch applies, and
 // (FP32, nrhs > 0) the solve's exchange of solved blocks for nrhs right-hand
@@ -115,7 +117,8 @@ hipError_t split_bf16_launch(const float* x, int64_t n, uint16_t* t0, uint16_t* 
 constexpr int64_t kLuMaxN = 16384;
 size_t lu_workspace_bytes(int dtype, int64_t n, int64_t nrhs = 0);
 hipError_t lu_factor_launch(int dtype, int64_t n, void* A, int64_t lda, int32_t* rowid,
-                            void* work, int32_t* status, hipStream_t s, int update_precision = 0);
+                            void* work, int32_t* status, hipStream_t s, int update_precision = 0,
+                            bool panel_fp64 = false);
 // X (n x nrhs, ldx) <- U^{-1} L^{-1} B[rowid], B with ldb; work: the
 // factorisation's workspace, sized for at least nrhs right-hand sides. FP32:
 // two launches per 1024 right-hand sides (forward, backward), a wait that

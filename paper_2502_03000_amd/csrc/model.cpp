@@ -30,10 +30,9 @@ struct hexla_model {
   float* v = nullptr;
   int64_t step = 0;
   float y_mean = 0.f, y_std = 1.f;  // target standardisation (log microseconds)
-  // inference scratch (grown on demand)
+  // inference buffers, kPredictCap samples, allocated with the model
   float* x_buf = nullptr;
   float* y_buf = nullptr;
-  int64_t cap = 0;
   ~hexla_model() {
     for (float* p : {params, m, v, x_buf, y_buf})
       if (p) (void)hipFree(p);
@@ -43,6 +42,10 @@ struct hexla_model {
 namespace hexla {
 
 namespace {
+
+// Candidates predicted per inference launch (a chain of eight factors with
+// every tile and split-K candidate needs a few thousand).
+constexpr int64_t kPredictCap = 16384;
 
 constexpr int F = k::kMlpFeatures;
 constexpr int P = k::kMlpParams;
@@ -130,23 +133,20 @@ bool model_predict_us(hexla_model* md, const std::vector<float>& x, std::vector<
   if (count == 0) return true;
   hipStream_t s = md->ctx->stream;
   hipError_t e = enter_device(md->ctx->device);
-  if (e == hipSuccess && count > md->cap) {
-    if (md->x_buf) (void)hipFree(md->x_buf);
-    if (md->y_buf) (void)hipFree(md->y_buf);
-    md->x_buf = md->y_buf = nullptr;
-    md->cap = 0;
-    const int64_t cap = std::max<int64_t>(count, 4096);
-    e = hipMalloc(reinterpret_cast<void**>(&md->x_buf), size_t(cap) * F * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&md->y_buf), size_t(cap) * sizeof(float));
-    if (e == hipSuccess) md->cap = cap;
+  // The inference buffers were sized when the model was created: planning
+  // allocates no device memory; a long candidate list runs in chunks.
+  for (int64_t at = 0; at < count && e == hipSuccess; at += kPredictCap) {
+    const int64_t c = std::min<int64_t>(kPredictCap, count - at);
+    e = hipMemcpyAsync(md->x_buf, x.data() + size_t(at) * F, size_t(c) * F * sizeof(float),
+                       hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = k::mlp_predict_launch(md->params, md->x_buf, c, md->y_std, md->y_mean, md->y_buf, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(us.data() + at, md->y_buf, size_t(c) * sizeof(float),
+                         hipMemcpyDeviceToHost, s);
+    // the next chunk overwrites x_buf: wait for this one (and for the result)
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
   }
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(md->x_buf, x.data(), x.size() * sizeof(float), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess)
-    e = k::mlp_predict_launch(md->params, md->x_buf, count, md->y_std, md->y_mean, md->y_buf, s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(us.data(), md->y_buf, size_t(count) * sizeof(float), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     if (err) *err = std::string("model inference: ") + hipGetErrorString(e);
     return false;
@@ -194,6 +194,10 @@ hexla_status hexla_model_create(hexla_ctx* ctx, uint64_t seed, hexla_model** out
   hipError_t e = enter_device(ctx->device);
   for (float** p : {&md->params, &md->m, &md->v})
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(p), P * sizeof(float));
+  if (e == hipSuccess)
+    e = hipMalloc(reinterpret_cast<void**>(&md->x_buf), size_t(kPredictCap) * F * sizeof(float));
+  if (e == hipSuccess)
+    e = hipMalloc(reinterpret_cast<void**>(&md->y_buf), size_t(kPredictCap) * sizeof(float));
   if (e == hipSuccess) e = hipMemcpy(md->params, h.data(), P * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(md->m, 0, P * sizeof(float));
   if (e == hipSuccess) e = hipMemset(md->v, 0, P * sizeof(float));

@@ -1018,6 +1018,8 @@ class Planner {
     w.update_precision = o_.solve_precision == HEXLA_SOLVE_IR_FP16   ? k::GEMM_F16
                          : o_.solve_precision == HEXLA_SOLVE_IR_BF16X3 ? k::GEMM_BF16X3
                                                                        : k::GEMM_PLAIN;
+    w.panel_fp64 = o_.solve_precision == HEXLA_SOLVE_IR_FP16 ||
+                   o_.solve_precision == HEXLA_SOLVE_IR_BF16X3;
     w.max_iter = o_.ir_max_iter;
     w.tol_scale = o_.ir_tol_scale;
     q.name = o_.solve_precision == HEXLA_SOLVE_IR_FP16     ? "lu_solve_ir_fp16"

@@ -66,7 +66,7 @@ class TrainOpts(C.Structure):
 
 class Report(C.Structure):
     _fields_ = [("status", C.c_int32), ("ir_iterations", C.c_int32),
-                ("singular_column", C.c_int64)]
+                ("singular_column", C.c_int64), ("ir_backward_error", C.c_double)]
 
 
 def _load():
@@ -214,8 +214,10 @@ def solve(a, b): return a.ctx.binary(OP_SOLVE, a, a._lift(b))
 
 
 class Plan:
-    def __init__(self, ctx, handle):
-        self.ctx, self.handle = ctx, handle
+    def __init__(self, ctx, handle, keep=()):
+        # the tensors the plan's leaves borrow stay alive as long as the plan,
+        # even after the context's nodes are cleared
+        self.ctx, self.handle, self._keep = ctx, handle, list(keep)
         info = PlanInfo()
         ctx._check(lib.hexla_plan_get_info(handle, C.byref(info)))
         self.info = info
@@ -577,7 +579,7 @@ class Context:
         o.codegen = 1 if codegen else 0
         h = C.c_void_p()
         self._check(lib.hexla_plan_create(self.handle, root.node, C.byref(o), C.byref(h)))
-        return Plan(self, h.value)
+        return Plan(self, h.value, keep=self._keep)
 
     def template_leaf(self, t, kind, dtype) -> Expr:
         """A leaf of a batch template: t x t ("matrix") or t x 1 ("vector").

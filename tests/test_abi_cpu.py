@@ -197,3 +197,23 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_plan_keeps_borrowed_tensors_alive_after_clear(ctx):
+    """A plan holds the tensors its leaves borrow: clearing the context's
+    nodes and dropping every other reference leaves them allocated."""
+    import gc
+    import weakref
+
+    import torch
+    a = torch.ones(64, 32, dtype=torch.float64)
+    b = torch.ones(32, 16, dtype=torch.float64)
+    refs = [weakref.ref(a), weakref.ref(b)]
+    p = ctx.plan(ctx.leaf(a) @ ctx.leaf(b))
+    ctx.clear()
+    del a, b
+    gc.collect()
+    assert all(r() is not None for r in refs)
+    del p
+    gc.collect()
+    assert all(r() is None for r in refs)

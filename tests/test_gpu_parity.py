@@ -1,8 +1,13 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
 Tolerances: normwise relative Frobenius error against the oracle, 1e-12 for
-FP64 storage and 1e-5 for FP32 storage; bitwise equality where the arithmetic
-is exact (small-integer inputs) or the result is a copy (mirrored triangle).
+FP64 storage and 1e-5 for FP32 storage, and beside it the componentwise error
+scaled by the oracle's magnitude of the computation (|op(A)| |op(B)| for a
+product) within K unit roundoffs, K the roundings on the longest path (k for
+a length-k sum, one per element-wise operation, two for exp and division);
+bitwise equality where the arithmetic is exact (small-integer inputs) or the
+result is a copy (mirrored triangle). Solves: normwise error and the backward
+error.
 """
 import numpy as np
 import pytest
@@ -12,6 +17,7 @@ import inputs
 import oracle
 from oracle import gepp
 from paper_2502_03000_amd import hexla as hx
+from parity import assert_close
 
 pytestmark = pytest.mark.gpu
 
@@ -64,7 +70,8 @@ def test_small_chain_expression_fp64(ctx, planner):
     y = hx.trans(L["A"]) @ L["B"] @ L["C"] @ L["v"] + 0.5 * (L["d"] % L["e"])
     got = run(ctx, y, planner=planner)
     assert got.shape == (300, 1)
-    assert rel(got, ref) <= 1e-12
+    mag = oracle.magnitude(inputs.SMALL_CHAIN_EXPR, env)
+    assert_close(got, ref, mag, np.float64, 400 + 600 + 200 + 8, what=planner)
 
 
 # ------------------------------------------------------------- element-wise
@@ -82,7 +89,7 @@ def test_elementwise_expression(ctx, dt, shape, codegen):
     got = run(ctx, e, codegen=codegen)
     assert got.shape == shape
     if got.size:
-        assert rel(got, ref) <= TOL[dt]
+        assert_close(got, ref, oracle.magnitude(inputs.ELEMENTWISE_EXPR, env), dt, 8)
 
 
 def test_generated_and_interpreted_kernels_agree(ctx):
@@ -94,7 +101,9 @@ def test_generated_and_interpreted_kernels_agree(ctx):
     ref = oracle.evaluate("(A - 2*B) % (C + A) / C - exp(B/4) + 1.5", env)
     a = run(ctx, e, codegen=True)
     b = run(ctx, e, codegen=False)
-    assert rel(a, ref) <= 1e-6 and rel(b, ref) <= 1e-6
+    mag = oracle.magnitude("(A - 2*B) % (C + A) / C - exp(B/4) + 1.5", env)
+    assert_close(a, ref, mag, np.float32, 12, norm_tol=1e-6, what="generated")
+    assert_close(b, ref, mag, np.float32, 12, norm_tol=1e-6, what="interpreted")
     assert np.max(np.abs(a - b)) <= 4 * np.finfo(np.float32).eps * np.max(np.abs(ref))
 
 
@@ -111,8 +120,10 @@ def test_elementwise_strided_and_transposed_views(ctx, dt):
     ex = ctx.leaf(tx)
     ey = ctx.leaf(ty_rowmajor)    # binds as trans of a 40 x 50 column-major leaf
     got = run(ctx, 0.4 * ex + 0.6 * ey - hx.trans(ctx.leaf(dev(y, td))))
-    ref = 0.4 * x.astype(np.float64) + 0.6 * y.T.astype(np.float64) - y.T.astype(np.float64)
-    assert rel(got, ref) <= TOL[dt]
+    env = {"X": x, "Y": y}
+    ref = oracle.evaluate("0.4*X + 0.6*trans(Y) - trans(Y)", env)
+    mag = oracle.magnitude("0.4*X + 0.6*trans(Y) - trans(Y)", env)
+    assert_close(got, ref, mag, dt, 5)
 
 
 def test_paper_fusion_example_in_place(ctx):
@@ -123,7 +134,8 @@ def test_paper_fusion_example_in_place(ctx):
     e = 0.4 * ctx.leaf(tx) + 0.6 * ctx.leaf(ty)
     ctx.evaluate(e, out=tx)  # Z = X written over X: element-wise, so allowed
     torch.cuda.synchronize()
-    assert rel(host(tx), ref) <= 1e-15
+    assert_close(host(tx), ref, oracle.magnitude("0.4*X + 0.6*Y", {"X": x, "Y": yv}),
+                 np.float64, 3, norm_tol=1e-15)
 
 
 # ----------------------------------------------------------------- products
@@ -145,7 +157,7 @@ def test_gemm_against_oracle(ctx, dt, ta, tb, mnk):
     ea, eb = ctx.leaf(dev(a)), ctx.leaf(dev(b))
     got = run(ctx, (hx.trans(ea) if ta else ea) @ (hx.trans(eb) if tb else eb))
     assert got.shape == (m, n)
-    assert rel(got, ref) <= TOL[dt]
+    assert_close(got, ref, oracle.magnitude(expr, {"A": a, "B": b}), dt, k + 2)
 
 
 @pytest.mark.parametrize("dt", [np.float32, np.float64])
@@ -174,7 +186,8 @@ def test_fp32_chain_scaled(ctx):
         x = ctx.leaf(dev(m))
         e = x if e is None else e @ x
     got = run(ctx, e)
-    assert rel(got, ref) <= 1e-5
+    mag = oracle.magnitude("*".join(names), dict(zip(names, mats)))
+    assert_close(got, ref, mag, np.float32, sum(dims[1:-1]) + len(mats))
 
 
 @pytest.mark.parametrize("dt", [np.float32, np.float64])
@@ -188,10 +201,11 @@ def test_syrk_against_oracle(ctx, dt, shape):
     assert [s["kernel"] for s in p.describe()["steps"]] == (["syrk"] if shape[1] > 1 else ["gemv_t"])
     got = run(ctx, hx.trans(ex) @ ex)
     assert np.array_equal(got, got.T)
-    assert rel(got, ref) <= TOL[dt] * (10 if dt == np.float32 else 1)
-    got2 = run(ctx, ex @ hx.trans(ex)) if shape[0] <= 1000 else None
-    if got2 is not None:
-        assert rel(got2, oracle.evaluate("X*trans(X)", {"X": x})) <= TOL[dt] * 10
+    assert_close(got, ref, oracle.magnitude("trans(X)*X", {"X": x}), dt, shape[0] + 2, what="X'X")
+    got2 = run(ctx, ex @ hx.trans(ex))
+    assert np.array_equal(got2, got2.T)
+    assert_close(got2, oracle.evaluate("X*trans(X)", {"X": x}),
+                 oracle.magnitude("X*trans(X)", {"X": x}), dt, shape[1] + 2, what="XX'")
 
 
 def test_syrk_equals_gemm_on_integers(ctx):
@@ -328,7 +342,8 @@ def test_autotune_keeps_results_and_fills_table(ctx, tmp_path):
     p.autotune(out, ws, reps=2)
     p.execute(out, ws)
     assert ctx.sync().status == hx.OK
-    assert rel(host(out), ref) <= 1e-5
+    mag = oracle.magnitude("*".join(names), dict(zip(names, mats)))
+    assert_close(host(out), ref, mag, np.float32, sum(dims[1:-1]) + len(mats))
     path = tmp_path / "tune.txt"
     ctx.tune_save(str(path))
     lines = path.read_text().splitlines()
@@ -351,6 +366,7 @@ def test_every_fp32_tile_against_oracle(tmp_path, ta, tb, m):
     b = inputs.normal(g, n, k, np.float32) if tb else inputs.normal(g, k, n, np.float32)
     text = ("trans(A)" if ta else "A") + "*" + ("trans(B)" if tb else "B")
     ref = oracle.evaluate(text, {"A": a, "B": b})
+    mag = oracle.magnitude(text, {"A": a, "B": b})
     ea, eb = ctx.leaf(dev(a)), ctx.leaf(dev(b))
     e = (hx.trans(ea) if ta else ea) @ (hx.trans(eb) if tb else eb)
     p = ctx.plan(e)
@@ -368,7 +384,7 @@ def test_every_fp32_tile_against_oracle(tmp_path, ta, tb, m):
             out, ws = q.output(), q.workspace()
             q.execute(out, ws)
             assert ctx.sync().status == hx.OK
-            assert rel(host(out), ref) <= 1e-5, (tile, split)
+            assert_close(host(out), ref, mag, np.float32, k + 2, what=f"tile {tile} split {split}")
 
 
 @pytest.mark.parametrize("sym", [False, True])
@@ -389,6 +405,7 @@ def test_every_fp64_tile_against_oracle(tmp_path, sym):
         text, leaves = "A*B", {"A": a, "B": b}
         e = ctx.leaf(dev(a)) @ ctx.leaf(dev(b))
     ref = oracle.evaluate(text, leaves)
+    mag = oracle.magnitude(text, leaves)
     for tile in range(4):
         for split in (1, 5):
             q = _force(ctx, tmp_path, e, tile, split)
@@ -398,7 +415,8 @@ def test_every_fp64_tile_against_oracle(tmp_path, sym):
             q.execute(out, ws)
             assert ctx.sync().status == hx.OK
             got = host(out)
-            assert rel(got, ref) <= 1e-13, (tile, split)
+            assert_close(got, ref, mag, np.float64, k + 2, norm_tol=1e-13,
+                         what=f"tile {tile} split {split}")
             if sym:
                 assert np.array_equal(got, got.T), (tile, split)
 
@@ -429,6 +447,7 @@ def test_split_k_repeats_and_replays(tmp_path, dt, tile):
     m, n, k = 300, 130, 2000
     a, b = inputs.normal(g, m, k, dt), inputs.normal(g, k, n, dt)
     ref = oracle.evaluate("A*B", {"A": a, "B": b})
+    mag = oracle.magnitude("A*B", {"A": a, "B": b})
     e = ctx.leaf(dev(a)) @ ctx.leaf(dev(b))
     q = _force(ctx, tmp_path, e, tile, 3)
     out, ws = q.output(), q.workspace()
@@ -436,7 +455,7 @@ def test_split_k_repeats_and_replays(tmp_path, dt, tile):
     q.execute(out, ws)
     assert ctx.sync().status == hx.OK
     first = out.clone()
-    assert rel(host(first), ref) <= (1e-5 if dt == np.float32 else 1e-13)
+    assert_close(host(first), ref, mag, dt, k + 2)
     for _ in range(2):
         out.zero_()
         q.execute(out, ws)

@@ -58,7 +58,8 @@ def test_refinement_converges_to_fp64_solution():
     b = inputs.normal(g, 96, 3)
     out = refine.refine(x0, b)
     ref = np.linalg.solve(x0, b)
-    assert out["status"] in ("converged", "stagnated")
+    assert out["status"] in ("converged", "stagnated") and out["accepted"]
+    assert out["backward_errors"][-1] <= 96 * 2.0 ** -53
     assert np.linalg.norm(out["x"] - ref) / np.linalg.norm(ref) < 1e-12
     r = out["residuals"]
     assert all(r[i + 1] < r[i] for i in range(len(r) - 1))
@@ -108,3 +109,55 @@ def test_adam_first_step_moves_by_lr_times_sign():
     assert np.allclose(new[0][0], [[1.0 - 1e-2, -2.0 + 1e-2]], atol=1e-9)
     assert np.allclose(new[0][1], [0.5 - 1e-2], atol=1e-7)
     assert state["t"] == 1
+
+
+def test_adam_second_step_by_hand():
+    # one scalar parameter p0 = 1, gradients 3 then 1, lr 0.01, betas 0.9 / 0.999:
+    #   step 1: m = 0.3, v = 0.009; bias-corrected 3 / sqrt(9) = 1 -> p1 = 0.99
+    #   step 2: m = 0.9*0.3 + 0.1*1 = 0.37, v = 0.999*0.009 + 0.001*1 = 0.009991
+    #           mhat = 0.37 / 0.19, vhat = 0.009991 / 0.001999
+    #           p2 = 0.99 - 0.01 * 1.9473684210 / 2.2356652 = 0.9812893605
+    p = [(np.array([[1.0]]), np.array([0.0]))]
+    state = {}
+    p = mlp.adam_step(p, [(np.array([[3.0]]), np.array([0.0]))], state, lr=1e-2)
+    assert p[0][0][0, 0] == pytest.approx(0.99, abs=1e-9)
+    p = mlp.adam_step(p, [(np.array([[1.0]]), np.array([0.0]))], state, lr=1e-2)
+    assert p[0][0][0, 0] == pytest.approx(0.9812893605, abs=1e-9)
+    assert state["t"] == 2
+    # a zero gradient leaves the bias at zero through both steps
+    assert p[0][1][0] == 0.0
+
+
+def _scaled_exact_solver(s, factor):
+    # a "low-precision" solve that returns factor times the exact correction:
+    # the error of X is multiplied by (1 - factor) at every step
+    return lambda r: factor * np.linalg.solve(s, r)
+
+
+@pytest.mark.parametrize("factor,status,accepted", [
+    (0.75, "converged", True),    # error x (-0.25) per step: corrections shrink 4x
+    (1.6, "stagnated", False),    # error x (-0.6): the second correction is 0.6x the first
+    (2.5, "diverging", False),    # error x (-1.5): the second correction grows
+])
+def test_refinement_outcomes_in_closed_form(factor, status, accepted):
+    g = inputs.rng(26)
+    s = inputs.diag_dominant(g, 40)
+    b = inputs.normal(g, 40, 2)
+    out = refine.refine(s, b, solve_low=_scaled_exact_solver(s, factor))
+    assert out["status"] == status
+    assert out["accepted"] is accepted
+    assert len(out["backward_errors"]) == len(out["residuals"])
+    if status == "diverging":
+        # the growing correction was dropped: X is the first corrected iterate
+        x = np.linalg.solve(s, b)
+        x1 = factor * x + factor * (x - factor * x)
+        assert np.allclose(out["x"], x1, rtol=1e-12, atol=1e-12)
+        assert out["iterations"] == 1
+
+
+def test_refinement_cap_is_not_accepted():
+    g = inputs.rng(27)
+    s = inputs.diag_dominant(g, 30)
+    b = inputs.normal(g, 30, 1)
+    out = refine.refine(s, b, solve_low=_scaled_exact_solver(s, 0.75), cap=1)
+    assert out["status"] == "cap" and out["accepted"] is False and out["iterations"] == 1
