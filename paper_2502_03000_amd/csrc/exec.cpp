@@ -163,7 +163,7 @@ hexla_status run_ir_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipStrea
   e = k::norm_inf_launch(1, n, n, s_low, ldn, scratch, norms + 0, st);
   if (e != hipSuccess) return fail(e, "ir: norm S");
   e = k::lu_factor_launch(1, n, s_low, ldn, rowid, addr(w.luwork, b), ctx->d_status, st,
-                          w.update_precision, w.panel_fp64);
+                          &ctx->side, w.update_precision, w.panel_fp64);
   if (e != hipSuccess) return fail(e, "ir: lu");
   // X0 = LU^-1 B in the low precision
   e = k::cast_launch(0, 1, n, r, addr(B.ref, b), si(B), sj(B), r_low, ldn, st);
@@ -267,7 +267,7 @@ hexla_status run_steps(hexla_plan* plan, void* out, int64_t ld_out, void* worksp
         const View A = resolve(s.A, b);
         e = k::lu_factor_launch(s.dtype, s.n, addr(A.ref, b), A.ld,
                                 static_cast<int32_t*>(addr(s.rowid, b)), addr(s.luwork, b),
-                                ctx->d_status, st);
+                                ctx->d_status, st, &ctx->side);
         break;
       }
       case StepKind::LuSolve: {

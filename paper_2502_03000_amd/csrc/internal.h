@@ -121,6 +121,7 @@ struct hexla_ctx {
   std::vector<hexla::Node> nodes;
   std::string err;
   int32_t* d_status = nullptr;  // [0] status, [1] timeout, [2] singular column, [3] ir iterations
+  hexla::k::Lookahead side;     // the LU's second stream and events (made with the context)
   std::map<std::string, hexla::k::GemmConfig> tuned;  // autotuned product configurations
   int32_t host_status = 0;         // deferred status raised by host-driven loops
   int32_t host_ir_iterations = 0;  // iterations of the last refined solve

@@ -55,9 +55,14 @@ hexla_status hexla_ctx_create(int device, void* stream, hexla_ctx** out) {
     hipError_t e = hipSetDevice(device);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ctx->d_status), 256);
     if (e == hipSuccess) e = hipMemset(ctx->d_status, 0, 256);
+    // the LU's lookahead stream (default priority, like the caller's) and
+    // events are made once here, so that executing a plan creates nothing
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->side.s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->side.ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->side.done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
-      delete ctx;
+      hexla_ctx_destroy(ctx);
       return HEXLA_E_DEVICE;
     }
   }
@@ -70,9 +75,13 @@ hexla_status hexla_ctx_destroy(hexla_ctx* ctx) {
   for (hexla_plan* p : ctx->plans) p->ctx = nullptr;
   for (hexla_batch* b : ctx->batches) hexla::detach_batch(b);
   for (hexla_model* md : ctx->models) hexla::detach_model(md);
-  if (ctx->d_status) {
+  if (ctx->device >= 0) {
     (void)hipSetDevice(ctx->device);
-    (void)hipFree(ctx->d_status);
+    if (ctx->side.s) (void)hipStreamSynchronize(ctx->side.s);
+    if (ctx->side.done) (void)hipEventDestroy(ctx->side.done);
+    if (ctx->side.ready) (void)hipEventDestroy(ctx->side.ready);
+    if (ctx->side.s) (void)hipStreamDestroy(ctx->side.s);
+    if (ctx->d_status) (void)hipFree(ctx->d_status);
   }
   delete ctx;
   return HEXLA_OK;

@@ -715,41 +715,20 @@ hipError_t update(int dtype, int64_t m, int64_t ncol, int64_t kk, const T* A, in
                      nullptr, cfg, s);
 }
 
-// A second stream for the lookahead: the trailing update beyond the next
-// panel's columns runs there while the next panel is factored. Default
-// priority, like the caller's stream; released when the factorization has
-// been issued (its work completes first).
-struct SideStream {
-  hipStream_t s = nullptr;
-  hipEvent_t ready = nullptr, done = nullptr;
-  hipError_t open() {
-    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
-    return e;
-  }
-  ~SideStream() {
-    if (done) (void)hipEventDestroy(done);
-    if (ready) (void)hipEventDestroy(ready);
-    if (s) (void)hipStreamDestroy(s);
-  }
-};
-
 template <typename T>
 hipError_t factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* rowid, void* work,
-                        int32_t* status, hipStream_t s, int prec, bool panel_fp64) {
+                        int32_t* status, hipStream_t s, int prec, bool panel_fp64,
+                        const Lookahead* side) {
   if (n == 0) return hipSuccess;
   if (n > kLuMaxN) return hipErrorInvalidValue;
   const int64_t np = cdiv(n, kNB);
   LuWork w = carve(work, n);
-  // Lookahead from three panels on, outside graph capture (a captured
-  // sequence stays on one stream).
+  // Lookahead from three panels on, on the caller's second stream, outside
+  // graph capture (a captured sequence stays on one stream).
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   hipError_t ce = hipStreamIsCapturing(s, &cap);
   if (ce != hipSuccess) return ce;
-  SideStream side;
-  const bool lookahead = np >= 3 && cap == hipStreamCaptureStatusNone;
-  if (lookahead && (ce = side.open()) != hipSuccess) return ce;
+  const bool lookahead = side && side->s && np >= 3 && cap == hipStreamCaptureStatusNone;
   bool pending = false;  // the side stream holds an update the next interchanges must wait for
   // no slot holds a tag of this factorisation yet (tags restart at 1)
   hipError_t e = fill_i32_launch(reinterpret_cast<int32_t*>(w.slots),
@@ -775,7 +754,7 @@ hipError_t factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* rowid,
                          G, stride, w.slots, unsigned(p * kNB + 1), w.swap_cnt + p, list, status);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (pending) {  // the interchanges touch the columns the side stream updates
-      if ((e = hipStreamWaitEvent(s, side.done, 0)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(s, side->done, 0)) != hipSuccess) return e;
       pending = false;
     }
     const int64_t cols = n - jb + 1;
@@ -801,23 +780,23 @@ hipError_t factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* rowid,
       // panel starts at once; with lookahead the rest on the side stream
       const int64_t near = lookahead ? std::min<int64_t>(kNB, right) : right;
       if (near < right) {
-        if ((e = hipEventRecord(side.ready, s)) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(side.s, side.ready, 0)) != hipSuccess) return e;
+        if ((e = hipEventRecord(side->ready, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(side->s, side->ready, 0)) != hipSuccess) return e;
       }
       e = update<T>(dtype, n - k - jb, near, jb, A + (k + jb) + k * lda, lda, a12, lda,
                     A + (k + jb) + (k + jb) * lda, lda, s, prec, true);
       if (e != hipSuccess) return e;
       if (near < right) {
         e = update<T>(dtype, n - k - jb, right - near, jb, A + (k + jb) + k * lda, lda,
-                      a12 + near * lda, lda, A + (k + jb) + (k + jb + near) * lda, lda, side.s,
+                      a12 + near * lda, lda, A + (k + jb) + (k + jb + near) * lda, lda, side->s,
                       prec, true);
         if (e != hipSuccess) return e;
-        if ((e = hipEventRecord(side.done, side.s)) != hipSuccess) return e;
+        if ((e = hipEventRecord(side->done, side->s)) != hipSuccess) return e;
         pending = true;
       }
     }
   }
-  if (pending && (e = hipStreamWaitEvent(s, side.done, 0)) != hipSuccess) return e;
+  if (pending && (e = hipStreamWaitEvent(s, side->done, 0)) != hipSuccess) return e;
   // the last block's L11^-1 (no update followed it) and every U11^-1, for the solves
   hipLaunchKernelGGL((inv_block_kernel<T, false>), dim3(1), dim3(kNB), 0, s, A, lda, n, np - 1,
                      static_cast<T*>(w.inv));
@@ -920,13 +899,13 @@ size_t lu_workspace_bytes(int dtype, int64_t n, int64_t nrhs) {
 }
 
 hipError_t lu_factor_launch(int dtype, int64_t n, void* A, int64_t lda, int32_t* rowid,
-                            void* work, int32_t* status, hipStream_t s, int update_precision,
-                            bool panel_fp64) {
+                            void* work, int32_t* status, hipStream_t s, const Lookahead* side,
+                            int update_precision, bool panel_fp64) {
   return dtype == 0
              ? factor_typed<double>(0, n, static_cast<double*>(A), lda, rowid, work, status, s, 0,
-                                    false)
+                                    false, side)
              : factor_typed<float>(1, n, static_cast<float*>(A), lda, rowid, work, status, s,
-                                   update_precision, panel_fp64);
+                                   update_precision, panel_fp64, side);
 }
 
 hipError_t lu_solve_launch(int dtype, int64_t n, int64_t nrhs, const void* LU, int64_t lda,

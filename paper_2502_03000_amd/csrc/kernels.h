@@ -115,10 +115,18 @@ hipError_t split_bf16_launch(const float* x, int64_t n, uint16_t* t0, uint16_t* 
 // (FP32, nrhs > 0) the solve's exchange of solved blocks for nrhs right-hand
 // sides.
 constexpr int64_t kLuMaxN = 16384;
+// A second stream, default priority like the caller's, and two events, owned
+// by the caller: the trailing update beyond the next panel's columns runs
+// there while the next panel is factored (the factorisation makes the
+// caller's stream wait for it before it returns).
+struct Lookahead {
+  hipStream_t s = nullptr;
+  hipEvent_t ready = nullptr, done = nullptr;
+};
 size_t lu_workspace_bytes(int dtype, int64_t n, int64_t nrhs = 0);
 hipError_t lu_factor_launch(int dtype, int64_t n, void* A, int64_t lda, int32_t* rowid,
-                            void* work, int32_t* status, hipStream_t s, int update_precision = 0,
-                            bool panel_fp64 = false);
+                            void* work, int32_t* status, hipStream_t s, const Lookahead* side,
+                            int update_precision = 0, bool panel_fp64 = false);
 // X (n x nrhs, ldx) <- U^{-1} L^{-1} B[rowid], B with ldb; work: the
 // factorisation's workspace, sized for at least nrhs right-hand sides. FP32:
 // two launches per 1024 right-hand sides (forward, backward), a wait that
