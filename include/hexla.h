@@ -226,6 +226,20 @@ hexla_status hexla_plan_destroy(hexla_plan* plan);
 hexla_status hexla_execute(hexla_plan* plan, void* out, int64_t ld_out, void* workspace,
                            size_t workspace_bytes);
 
+/* Evaluates the plan like hexla_execute, with its intermediates in a static
+ * device array of the library instead of a caller-provided workspace: for
+ * callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation). No device memory
+ * is allocated or freed by this call. The array holds
+ * hexla_static_scratch_bytes() bytes (64 MiB) on each device, kept until the
+ * process ends; a plan whose workspace_bytes exceeds it is rejected with
+ * HEXLA_E_INVALID_ARG. All calls on one device share that device's array:
+ * calls that overlap in time on one device (two streams or threads) race.
+ * `out` and ld_out, ownership, aliasing rules and errors are those of
+ * hexla_execute. */
+hexla_status hexla_execute_static(hexla_plan* plan, void* out, int64_t ld_out);
+hexla_status hexla_static_scratch_bytes(size_t* bytes);
+
 typedef struct hexla_report {
   int32_t status;             /* deferred hexla_status of the work since the last sync */
   int32_t ir_iterations;      /* refinement iterations of the last refined solve */

@@ -95,6 +95,8 @@ def _load():
         "hexla_plan_describe": [vp, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)],
         "hexla_plan_destroy": [vp],
         "hexla_execute": [vp, vp, i64, vp, C.c_size_t],
+        "hexla_execute_static": [vp, vp, i64],
+        "hexla_static_scratch_bytes": [C.POINTER(C.c_size_t)],
         "hexla_sync": [vp, C.POINTER(Report)],
         "hexla_plan_autotune": [vp, vp, i64, vp, C.c_size_t, i32],
         "hexla_tune_save": [vp, C.c_char_p],
@@ -207,6 +209,15 @@ class Expr:
         return self.ctx.shape(self)
 
 
+def static_scratch_bytes() -> int:
+    """Bytes of the static device scratch that Plan.execute_static uses."""
+    n = C.c_size_t(0)
+    st = lib.hexla_static_scratch_bytes(C.byref(n))
+    if st != OK:
+        raise HexlaError(st, "static_scratch_bytes")
+    return int(n.value)
+
+
 def trans(x): return x.ctx.unary(OP_TRANS, x)
 def inv(x): return x.ctx.unary(OP_INV, x)
 def exp(x): return x.ctx.unary(OP_EXP, x)
@@ -252,6 +263,12 @@ class Plan:
             wptr = _addr(workspace)
             wbytes = workspace.numel() * workspace.element_size() if hasattr(workspace, "numel") else self.workspace_bytes
         self.ctx._check(lib.hexla_execute(self.handle, optr, ld, wptr or None, wbytes))
+
+    def execute_static(self, out, ld_out=None):
+        """Launches the plan with its intermediates in the library's static
+        device scratch (no workspace, no allocation; asynchronous)."""
+        optr, ld = _ptr_ld(out, ld_out)
+        self.ctx._check(lib.hexla_execute_static(self.handle, optr, ld))
 
     def _bufs(self, out, workspace, ld_out):
         optr, ld = _ptr_ld(out, ld_out)
