@@ -8,6 +8,13 @@ Every operator is evaluated by its definition, with no rewrites and no fusion:
     the matrix product (AB)_ij = sum_k A_ik B_kj, sizes checked first (the
     conformance checks of Sec. II);
   * ``trans`` is the plain transpose (real data);
+  * ``diag(X)``: d_i = X_ii, i < min(m, n), a column vector;
+    ``diagmat(v)`` of a vector: the n x n matrix with D_ii = v_i, zeros
+    elsewhere; ``diagmat(X)`` of a matrix: X_ij where i == j, else 0;
+    ``trace(X)``: sum_i X_ii as a 1 x 1 matrix (expressions (3)-(5), (7) of
+    Sec. III); on a number each is the number itself;
+  * ``col(X, j)``, ``row(X, i)``, ``submat(X, r0, c0, rows, cols)``: the
+    submatrix (0-based), expression (2);
   * ``inv(S) * Y`` is S^{-1} Y, computed by elimination (``gepp.solve``),
     ``solve(S, Y)`` likewise; a bare ``inv(S)`` (or ``X * inv(S)``) forms the
     inverse by Gauss-Jordan elimination, or every ``inv`` does when
@@ -68,6 +75,42 @@ def _product(mats):
         return run(t[0]) @ run(t[1])
 
     return run(best[0])
+
+
+def _diagonal_function(name, x):
+    if _is_scalar(x):
+        return x
+    m, n = x.shape
+    if name == "diag":
+        return np.array([[x[i, i]] for i in range(min(m, n))], dtype=np.float64).reshape(-1, 1)
+    if name == "trace":
+        return np.array([[sum(x[i, i] for i in range(min(m, n)))]], dtype=np.float64)
+    if m == 1 or n == 1:  # diagmat of a vector
+        v = x.reshape(-1)
+        d = np.zeros((v.size, v.size))
+        for i in range(v.size):
+            d[i, i] = v[i]
+        return d
+    d = np.zeros((m, n))
+    for i in range(min(m, n)):
+        d[i, i] = x[i, i]
+    return d
+
+
+def _submatrix(name, x, idx):
+    if _is_scalar(x) or not all(_is_scalar(i) and float(i).is_integer() for i in idx):
+        raise OracleDimError(f"{name}: a matrix and integer indices are required")
+    idx = [int(i) for i in idx]
+    m, n = x.shape
+    if name == "col":
+        r0, c0, rows, cols = 0, idx[0], m, 1
+    elif name == "row":
+        r0, c0, rows, cols = idx[0], 0, 1, n
+    else:
+        r0, c0, rows, cols = idx
+    if min(r0, c0, rows, cols) < 0 or r0 + rows > m or c0 + cols > n:
+        raise OracleDimError(f"{name}: indices out of range for {x.shape}")
+    return np.ascontiguousarray(x[r0:r0 + rows, c0:c0 + cols])
 
 
 class _Evaluator:
@@ -149,6 +192,10 @@ class _Evaluator:
                 return float(np.exp(v)) if _is_scalar(v) else np.exp(v)
             if name == "inv":
                 return self.chain(node)
+            if name in ("diag", "diagmat", "trace"):
+                return _diagonal_function(name, self.value(args[0]))
+            if name in ("col", "row", "submat"):
+                return _submatrix(name, self.value(args[0]), [self.value(a) for a in args[1:]])
             if name == "solve":
                 s, b = self.value(args[0]), self.value(args[1])
                 if s.shape[0] != s.shape[1]:
@@ -186,6 +233,8 @@ class _MagnitudeEvaluator(_Evaluator):
       a / b                     (M(a) + |a / b| M(b)) / |b|
       exp(a)                    exp(a) (1 + M(a))
       a * b (matrix product)    M(a) M(b) (matrix product of the magnitudes)
+      diag, diagmat, trace,     the same function of M(a)
+      submatrices
     so a product's magnitude is |op(A)| |op(B)|, the scale of the classical
     componentwise bound |fl(AB) - AB| <= k u |A| |B|. Solves and inverses have
     no such scale here (their error is measured normwise and by the backward
@@ -245,6 +294,15 @@ class _MagnitudeEvaluator(_Evaluator):
                 v, m = self.vm(args[0])
                 e = np.exp(v)
                 return e, e * (1.0 + m)
+            if name in ("diag", "diagmat", "trace"):
+                # the same function of the magnitude: a diagonal entry keeps
+                # its scale, a trace's error is bounded by the sum of them
+                v, m = self.vm(args[0])
+                return _diagonal_function(name, v), _diagonal_function(name, m)
+            if name in ("col", "row", "submat"):
+                v, m = self.vm(args[0])
+                idx = [self.value(a) for a in args[1:]]
+                return _submatrix(name, v, idx), _submatrix(name, m, idx)
             raise ValueError(f"magnitude: {name} has no componentwise scale")
         raise ValueError(f"unknown node {node!r}")
 

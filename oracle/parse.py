@@ -6,6 +6,12 @@ scalar multiple when one side is a number), ``+``/``-`` are element-wise,
 ``%`` is the element-wise (Schur) product and ``/`` element-wise division,
 ``trans(X)`` / ``X.t()`` transpose, ``inv(X)`` the inverse, ``solve(A,B)`` the
 solution of A X = B and ``exp(X)`` the element-wise exponential.
+``diag(X)`` is the main diagonal as a column vector, ``diagmat(X)`` the
+diagonal matrix of a vector (or a matrix's diagonal part), ``trace(X)`` the
+sum of the diagonal (the functions of Sec. III's expressions (3)-(5), (7)).
+``col(X, j)``, ``row(X, i)`` and ``submat(X, r0, c0, rows, cols)`` are
+submatrices with 0-based integer indices (expression (2): the paper's first
+column A(:,1) is col(A, 0), its second row B(2,:) is row(B, 1)).
 
 ``*``, ``%`` and ``/`` share one precedence level and group left to right, as
 the C++ operators they overload do; ``+`` and ``-`` bind looser; unary minus
@@ -19,7 +25,8 @@ from __future__ import annotations
 
 import re
 
-FUNCTIONS = {"trans": 1, "inv": 1, "exp": 1, "solve": 2}
+FUNCTIONS = {"trans": 1, "inv": 1, "exp": 1, "solve": 2, "diag": 1, "diagmat": 1, "trace": 1,
+             "col": 2, "row": 2, "submat": 5}
 
 _TOKEN = re.compile(
     r"\s*(?:(?P<num>(?:\d+\.\d*|\.\d+|\d+)(?:[eE][+-]?\d+)?)"

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import inputs
+import oracle
 from oracle import chain, evaluate, gepp, parse
 from oracle.evaluate import OracleDimError
 from oracle.parse import OracleSyntaxError
@@ -262,3 +263,67 @@ def test_gram_invariants_and_closed_form():
     assert np.allclose(np.sort(np.linalg.eigvalsh(g))[::-1], sv ** 2, rtol=1e-8, atol=1e-13)
     h = evaluate("X*trans(X)", {"X": x[:20, :]})
     assert np.allclose(h, loops_product(x[:20, :], x[:20, :].T.copy()), atol=1e-13)
+
+
+# --------------------------------------- diagonals, traces and submatrices
+
+def test_diagonal_functions_by_hand():
+    x = np.array([[1.0, 2.0, 3.0], [4.0, 5.0, 6.0], [7.0, 8.0, 10.0]])
+    env = {"X": x, "W": x[:2, :], "v": np.array([[2.0], [-1.0], [0.5]])}
+    assert oracle.evaluate("diag(X)", env).ravel().tolist() == [1.0, 5.0, 10.0]
+    assert oracle.evaluate("diag(W)", env).ravel().tolist() == [1.0, 5.0]  # 2 x 3: two entries
+    assert oracle.evaluate("trace(X)", env).tolist() == [[16.0]]
+    assert oracle.evaluate("diagmat(X)", env).tolist() == [[1, 0, 0], [0, 5, 0], [0, 0, 10]]
+    assert oracle.evaluate("diagmat(v)", env).tolist() == [[2, 0, 0], [0, -1, 0], [0, 0, 0.5]]
+    assert oracle.evaluate("diagmat(trans(v))", env).tolist() == [[2, 0, 0], [0, -1, 0], [0, 0, 0.5]]
+    # expression (3): diagmat(v) * X scales the rows of X
+    assert oracle.evaluate("diagmat(v)*X", env).tolist() == [[2, 4, 6], [-4, -5, -6], [3.5, 4, 5]]
+    # expression (7): a^T diagmat(B) c = sum_i a_i B_ii c_i = 1*1*2 + 1*5*(-1) + 1*10*0.5 = 2
+    env["a"] = np.ones((3, 1))
+    assert oracle.evaluate("trans(a)*diagmat(X)*v", env).tolist() == [[2.0]]
+
+
+def test_paper_view_expression_by_hand():
+    # expression (2): C = A(:,1) + B(2,:)^T, the first column of A plus the
+    # transposed second row of B
+    a = np.array([[1.0, 2.0], [3.0, 4.0]])
+    b = np.array([[5.0, 6.0], [7.0, 8.0]])
+    got = oracle.evaluate("col(A, 0) + trans(row(B, 1))", {"A": a, "B": b})
+    assert got.tolist() == [[8.0], [11.0]]
+    assert oracle.evaluate("submat(A, 1, 0, 1, 2)", {"A": a}).tolist() == [[3.0, 4.0]]
+    with pytest.raises(oracle.OracleDimError):
+        oracle.evaluate("col(A, 2)", {"A": a})
+
+
+def test_trace_and_diagonal_identities():
+    g = inputs.rng(33)
+    a, b = inputs.normal(g, 5, 7), inputs.normal(g, 7, 5)
+    env = {"A": a, "B": b, "u": inputs.normal(g, 5, 1), "w": inputs.normal(g, 5, 1),
+           "S": inputs.normal(g, 5, 5), "one": np.ones((5, 1))}
+    tab = oracle.evaluate("trace(A*B)", env)[0, 0]
+    # trace(AB) = trace(BA) = sum(A % B^T) (the Frobenius inner product)
+    assert tab == pytest.approx(oracle.evaluate("trace(B*A)", env)[0, 0], rel=1e-12)
+    assert tab == pytest.approx(float(np.sum(oracle.evaluate("A % trans(B)", env))), rel=1e-12)
+    # diag(AB) = row sums of A % B^T
+    assert np.allclose(oracle.evaluate("diag(A*B)", env),
+                       oracle.evaluate("(A % trans(B))*ones", dict(env, ones=np.ones((7, 1)))),
+                       rtol=1e-12, atol=1e-12)
+    # diagmat(AB) keeps exactly the diagonal of AB
+    dm = oracle.evaluate("diagmat(A*B)", env)
+    assert np.array_equal(np.diag(np.diag(dm)), dm)
+    assert np.allclose(np.diag(dm), oracle.evaluate("diag(A*B)", env).ravel(), rtol=1e-12)
+    # u^T diagmat(S) w = u^T (diag(S) % w); diagmat(u) * S = (u * one^T) % S
+    assert oracle.evaluate("trans(u)*diagmat(S)*w", env)[0, 0] == pytest.approx(
+        oracle.evaluate("trans(u)*(diag(S) % w)", env)[0, 0], rel=1e-12)
+    assert np.allclose(oracle.evaluate("diagmat(u)*S", env),
+                       oracle.evaluate("(u*trans(one)) % S", env), rtol=1e-14, atol=0)
+
+
+def test_magnitude_of_diagonal_functions():
+    a = np.array([[1.0, -2.0], [3.0, 4.0]])
+    b = np.array([[-1.0, 1.0], [2.0, -3.0]])
+    env = {"A": a, "B": b}
+    # |A||B| = [[5, 7], [11, 15]]: its diagonal and trace
+    assert oracle.magnitude("diag(A*B)", env).ravel().tolist() == [5.0, 15.0]
+    assert oracle.magnitude("trace(A*B)", env).tolist() == [[20.0]]
+    assert oracle.magnitude("col(A, 1)", env).ravel().tolist() == [2.0, 4.0]
