@@ -70,6 +70,15 @@ typedef enum hexla_op {
   HEXLA_OP_NEG = 2,    /* element-wise negation                                */
   HEXLA_OP_EXP = 3,    /* element-wise exponential                             */
   HEXLA_OP_INV = 4,    /* inverse marker (Op<.., op_inv>, Sec. II)             */
+  HEXLA_OP_DIAG = 5,   /* main diagonal as a column vector, min(m,n) x 1
+                          (diag(A*B) of expression (4), Sec. III)              */
+  HEXLA_OP_DIAGMAT = 6,/* diagonal matrix: a vector v (n x 1 or 1 x n) gives
+                          the n x n matrix with v on its diagonal; a matrix
+                          keeps its diagonal, zeros elsewhere (expressions
+                          (3), (4), (7))                                      */
+  HEXLA_OP_TRACE = 7,  /* sum of the main diagonal, a 1 x 1 result
+                          (expression (5))                                    */
+  HEXLA_OP_SUBMAT = 8, /* submatrix view (made by hexla_submatrix only)       */
   /* binary */
   HEXLA_OP_TIMES = 16, /* matrix product, or scaling when one side is a scalar */
   HEXLA_OP_PLUS = 17,  /* element-wise sum (Glue<.., glue_plus>, Sec. II)      */
@@ -122,6 +131,14 @@ hexla_status hexla_unary(hexla_ctx* ctx, hexla_op op, hexla_node a, hexla_node* 
  * when the operands' storage types differ. */
 hexla_status hexla_binary(hexla_ctx* ctx, hexla_op op, hexla_node a, hexla_node b,
                           hexla_node* out);
+/* Submatrix view (expression (2) of Sec. III: columns and rows accessed in
+ * place): rows [r0, r0 + rows) and columns [c0, c0 + cols) of `a` (0-based;
+ * a column A(:, j) is (0, j, m, 1), a row B(i, :) is (i, 0, 1, n)). A view of
+ * a leaf borrows the leaf's storage with its leading dimension; a view of
+ * any other node views its evaluated value. Errors: HEXLA_E_DIM (the range
+ * leaves the operand), HEXLA_E_INVALID_ARG (negative sizes, scalar). */
+hexla_status hexla_submatrix(hexla_ctx* ctx, hexla_node a, int64_t r0, int64_t c0,
+                             int64_t rows, int64_t cols, hexla_node* out);
 /* Shape of a node (a scalar is 1 x 1 with *is_scalar = 1). */
 hexla_status hexla_node_shape(const hexla_ctx* ctx, hexla_node n, int64_t* rows,
                               int64_t* cols, int32_t* is_scalar);

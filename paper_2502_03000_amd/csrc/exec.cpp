@@ -34,8 +34,8 @@ View resolve(View v, const Bind& b) {
   return v;
 }
 
-int64_t si(const View& v) { return v.trans ? v.ld : 1; }
-int64_t sj(const View& v) { return v.trans ? 1 : v.ld; }
+int64_t si(const View& v) { return v.strided ? v.str_i : (v.trans ? v.ld : 1); }
+int64_t sj(const View& v) { return v.strided ? v.str_j : (v.trans ? 1 : v.ld); }
 
 k::EwProgram make_prog(const EwHost& h, int64_t rows, int64_t cols, const Bind& b) {
   k::EwProgram p{};
@@ -280,6 +280,21 @@ hexla_status run_steps(hexla_plan* plan, void* out, int64_t ld_out, void* worksp
       case StepKind::IrSolve: {
         const hexla_status hs = run_ir_solve(ctx, s, b, st);
         if (hs != HEXLA_OK) return hs;
+        break;
+      }
+      case StepKind::DiagProd: {
+        const View A = resolve(s.A, b), B = resolve(s.B, b), o = resolve(s.out, b);
+        // incd 0: onto the diagonal of the output matrix
+        const int64_t incd = s.incd ? s.incd : o.ld + 1;
+        e = k::diagprod_launch(s.dtype, A.trans ? 1 : 0, B.trans ? 1 : 0, s.m, s.kk, s.alpha,
+                               addr(A.ref, b), A.ld, addr(B.ref, b), B.ld, addr(o.ref, b), incd,
+                               s.sum, addr(s.partial, b), st);
+        break;
+      }
+      case StepKind::EwSum: {
+        const View o = resolve(s.out, b);
+        const k::EwProgram p = make_prog(s.ew, s.m, s.n, b);
+        e = k::ew_sum_launch(s.dtype, p, s.alpha, addr(o.ref, b), addr(s.partial, b), st);
         break;
       }
       default:

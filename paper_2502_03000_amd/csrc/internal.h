@@ -28,6 +28,7 @@ struct Node {
   double value = 0.0;
   int64_t rows = 0, cols = 0;
   bool scalar = false;
+  int64_t r0 = 0, c0 = 0;  // submatrix view: first row and column in the operand
 };
 
 enum class Buf : uint8_t { None, Leaf, Work, Out };
@@ -42,12 +43,17 @@ struct Ref {
 
 // A rows x cols view; element (i, j) lives at storage (j, i) when trans.
 // ld == -1 means "the leading dimension hexla_execute receives" (output).
+// A strided view (a matrix's diagonal, a vector broadcast along rows or
+// columns) holds element (i, j) at element offset i * str_i + j * str_j, and
+// `span` elements of storage; it is read only by element-wise programs.
 struct View {
   Ref ref;
   int64_t rows = 0, cols = 0, ld = 1;
   bool trans = false;
   bool is_leaf = false;       // a borrowed leaf (not a temporary)
   const void* leaf_ptr = nullptr;
+  bool strided = false;
+  int64_t str_i = 0, str_j = 0, span = 0;
 };
 
 // Storage range of a borrowed leaf, for the aliasing checks at execute time.
@@ -69,7 +75,7 @@ struct EwHost {
   bool ident = false;
 };
 
-enum class StepKind : uint8_t { Ew, Gemv, Gemm, LuFactor, LuSolve, IrSolve, Fill };
+enum class StepKind : uint8_t { Ew, Gemv, Gemm, LuFactor, LuSolve, IrSolve, Fill, DiagProd, EwSum };
 
 // Workspace of a mixed-precision solve (low-precision LU + FP64 refinement).
 struct IrWork {
@@ -106,6 +112,11 @@ struct Step {
   int64_t m = 0, n = 0, kk = 0, nrhs = 0;
   Ref rowid, luwork;
   IrWork ir;
+  // DiagProd: out (a vector with element stride incd, or 1 x 1 when sum)
+  // gets alpha * diag(op(A) op(B)) or its sum; m = diagonal length, kk the
+  // contraction. EwSum: out (1 x 1) = alpha * the sum of `ew` over m x n.
+  int64_t incd = 1;
+  bool sum = false;
   double flops = 0.0, bytes = 0.0;
   // Ew: kernel generated for this program (null: interpreter)
   std::string cg_src;

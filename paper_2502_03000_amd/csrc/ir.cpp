@@ -3,6 +3,7 @@
 // (the conformance checks of Sec. II); nothing is evaluated here.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cstring>
 #include <string>
 
@@ -157,6 +158,21 @@ hexla_status hexla_unary(hexla_ctx* ctx, hexla_op op, hexla_node a, hexla_node* 
       n.rows = x.rows;
       n.cols = x.cols;
       break;
+    case HEXLA_OP_DIAG:  // the main diagonal, min(m, n) x 1 (a scalar stays one)
+      n.rows = x.scalar ? 1 : std::min(x.rows, x.cols);
+      n.cols = 1;
+      break;
+    case HEXLA_OP_DIAGMAT:  // a vector spreads onto a square diagonal
+      if (!x.scalar && (x.rows == 1 || x.cols == 1)) {
+        n.rows = n.cols = std::max(x.rows, x.cols);
+      } else {
+        n.rows = x.rows;
+        n.cols = x.cols;
+      }
+      break;
+    case HEXLA_OP_TRACE:
+      n.rows = n.cols = 1;
+      break;
     default:
       return set_err(ctx, HEXLA_E_INVALID_ARG, "unary: unknown op");
   }
@@ -219,6 +235,31 @@ hexla_status hexla_binary(hexla_ctx* ctx, hexla_op op, hexla_node a, hexla_node 
   } else {
     return set_err(ctx, HEXLA_E_INVALID_ARG, "binary: unknown op");
   }
+  return hexla::push(ctx, n, out);
+}
+
+hexla_status hexla_submatrix(hexla_ctx* ctx, hexla_node a, int64_t r0, int64_t c0, int64_t rows,
+                             int64_t cols, hexla_node* out) {
+  if (!ctx || !out) return HEXLA_E_INVALID_ARG;
+  if (!hexla::valid_node(ctx, a)) return set_err(ctx, HEXLA_E_INVALID_ARG, "submatrix: bad node");
+  const Node& x = ctx->nodes[a];
+  if (x.scalar) return set_err(ctx, HEXLA_E_INVALID_ARG, "submatrix: scalar operand");
+  if (r0 < 0 || c0 < 0 || rows < 0 || cols < 0)
+    return set_err(ctx, HEXLA_E_INVALID_ARG, "submatrix: negative index or size");
+  if (r0 + rows > x.rows || c0 + cols > x.cols)
+    return set_err(ctx, HEXLA_E_DIM,
+                   "submatrix: rows " + std::to_string(r0) + "+" + std::to_string(rows) +
+                       ", columns " + std::to_string(c0) + "+" + std::to_string(cols) + " of " +
+                       hexla::shape(x));
+  Node n;
+  n.kind = hexla::NK_UNARY;
+  n.op = HEXLA_OP_SUBMAT;
+  n.a = a;
+  n.dtype = x.dtype;
+  n.rows = rows;
+  n.cols = cols;
+  n.r0 = r0;
+  n.c0 = c0;
   return hexla::push(ctx, n, out);
 }
 

@@ -101,6 +101,21 @@ hipError_t gemm_launch(int dtype, int precision, int mode, int ta, int tb, int64
 hipError_t split_bf16_launch(const float* x, int64_t n, uint16_t* t0, uint16_t* t1, uint16_t* t2,
                              int terms, hipStream_t s);
 
+// ---------------------------------------------------------------- diagonals
+// d[i * incd] = alpha * sum_k op(A)(i, k) op(B)(k, i) for i < nd (op(A) is
+// nd x kk or wider, op(B) kk x nd or wider; ta / tb: transposed operands),
+// or with sum: d[0] = alpha * sum_i of the same. `partial` (device,
+// diagprod_partial_bytes) holds the split-contraction partial sums.
+size_t diagprod_partial_bytes(int dtype, int64_t nd, int64_t kk, bool sum);
+hipError_t diagprod_launch(int dtype, int ta, int tb, int64_t nd, int64_t kk, double alpha,
+                           const void* A, int64_t lda, const void* B, int64_t ldb, void* d,
+                           int64_t incd, bool sum, void* partial, hipStream_t s);
+// out[0] = alpha * sum of the program over its p.rows x p.cols elements (any
+// leaf strides); `partial`: ew_sum_partial_bytes(count) bytes.
+size_t ew_sum_partial_bytes(int dtype, int64_t count);
+hipError_t ew_sum_launch(int dtype, const EwProgram& p, double alpha, void* out, void* partial,
+                         hipStream_t s);
+
 // ---------------------------------------------------------------------- LU
 // In-place LU with partial pivoting of the n x n column-major matrix A (lda),
 // A = P^T L U. rowid (n ints) receives the original row held at each final

@@ -37,7 +37,8 @@ bool is_ew_binary(int op) {
 }
 
 struct Factor {
-  int kind = 0;  // 0 view, 1 inverse marker (node = S), 2 expression to materialize
+  int kind = 0;  // 0 view, 1 inverse marker (node = S), 2 expression to materialize,
+                 // 3 diagonal matrix (node = diagmat's argument)
   uint32_t node = 0;
   bool trans = false;
   View v;
@@ -45,13 +46,15 @@ struct Factor {
 
 // Element-wise tree node.
 struct ENode {
-  int kind = 0;  // 0 op, 1 view, 2 const, 3 pending (product/solve/inverse), 4 extra
+  int kind = 0;  // 0 op, 1 view, 2 const, 3 pending (product/solve/inverse), 4 extra,
+                 // 5 identity matrix
   int op = 0;    // k::EwOp of an op node (binary or NEG/EXP)
   int a = -1, b = -1;
   View v;
   double c = 0.0;
   uint32_t node = 0;
   bool trans = false;
+  bool diag = false;  // pending: its main diagonal (a column vector) is wanted
   int64_t rows = 0, cols = 0;
 };
 
@@ -78,8 +81,74 @@ bool same_storage(const View& a, const View& b) {
 View transposed(const View& v) {
   View t = v;
   std::swap(t.rows, t.cols);
-  t.trans = !v.trans;
+  if (v.strided) std::swap(t.str_i, t.str_j);
+  else t.trans = !v.trans;
   return t;
+}
+
+// Element strides of a view whose leading dimension is known (leaves and
+// temporaries; the output's is bound only at execute time).
+int64_t vsi(const View& v) { return v.strided ? v.str_i : (v.trans ? v.ld : 1); }
+int64_t vsj(const View& v) { return v.strided ? v.str_j : (v.trans ? 1 : v.ld); }
+int64_t extent(const View& v) {
+  if (v.strided) return v.span;
+  const int64_t rs = v.trans ? v.cols : v.rows, cs = v.trans ? v.rows : v.cols;
+  return rs * cs > 0 ? (cs - 1) * v.ld + rs : 0;
+}
+
+// The main diagonal of v as a min(rows, cols) x 1 strided view.
+View diag_view(const View& v) {
+  View d = v;
+  d.strided = true;
+  d.str_i = vsi(v) + vsj(v);
+  d.str_j = 0;
+  d.span = extent(v);
+  d.rows = std::min(v.rows, v.cols);
+  d.cols = 1;
+  d.trans = false;
+  return d;
+}
+
+// A column vector v (n x 1, strided or not) repeated across `cols` columns.
+View bcast_cols(const View& v, int64_t cols) {
+  View b = v;
+  b.strided = true;
+  b.str_i = vsi(v);
+  b.str_j = 0;
+  b.span = extent(v);
+  b.cols = cols;
+  b.trans = false;
+  return b;
+}
+
+// The same column vector repeated down `rows` rows as a rows x n matrix
+// (element (i, j) = v_j).
+View bcast_rows(const View& v, int64_t rows) {
+  View b = v;
+  b.strided = true;
+  b.str_i = 0;
+  b.str_j = vsi(v);
+  b.span = extent(v);
+  b.cols = v.rows;
+  b.rows = rows;
+  b.trans = false;
+  return b;
+}
+
+// Rows [r0, r0 + rows) and columns [c0, c0 + cols) of v, in place.
+View sub_view(const View& v, int64_t r0, int64_t c0, int64_t rows, int64_t cols, size_t esz) {
+  View s = v;
+  const int64_t off = r0 * vsi(v) + c0 * vsj(v);
+  if (s.ref.buf == Buf::Leaf) {
+    s.ref.ptr = static_cast<const char*>(v.ref.ptr) + off * int64_t(esz);
+    s.leaf_ptr = s.ref.ptr;
+  } else {
+    s.ref.off = v.ref.off + off * int64_t(esz);
+  }
+  s.rows = rows;
+  s.cols = cols;
+  if (v.strided) s.span = std::max<int64_t>(0, v.span - off);
+  return s;
 }
 
 class Planner {
@@ -129,6 +198,7 @@ class Planner {
   std::map<std::string, k::GemmConfig> learned_cfg_;  // predicted-fastest configurations
   std::vector<std::string> learned_notes_;           // the learned planner's decisions
   hexla_status status_ = HEXLA_OK;
+  bool diag_mode_ = false;  // build_ew builds the diagonal of its node
 
   const Node& N(uint32_t i) const { return ctx_->nodes[i]; }
 
@@ -174,7 +244,15 @@ class Planner {
 
   static bool same_view(const View& a, const View& b) {
     return a.ref.buf == b.ref.buf && a.ref.off == b.ref.off && a.ref.ptr == b.ref.ptr &&
-           a.rows == b.rows && a.cols == b.cols && a.ld == b.ld && a.trans == b.trans;
+           a.rows == b.rows && a.cols == b.cols && a.ld == b.ld && a.trans == b.trans &&
+           a.strided == b.strided && a.str_i == b.str_i && a.str_j == b.str_j;
+  }
+
+  // A view products and solves can read: strided views (diagonals,
+  // broadcasts) are copied into a temporary first.
+  View dense(const View& v) {
+    if (!v.strided || status_ != HEXLA_OK) return v;
+    return emit_ew(add_view(v), nullptr, v.rows, v.cols, true);
   }
 
   // ------------------------------------------------------------- scalars
@@ -228,6 +306,14 @@ class Planner {
       out.push_back(f);
       return;
     }
+    if (x.kind == NK_UNARY && x.op == HEXLA_OP_DIAGMAT) {
+      f.kind = 3;
+      f.node = x.a;
+      f.v.rows = t ? x.cols : x.rows;
+      f.v.cols = t ? x.rows : x.cols;
+      out.push_back(f);
+      return;
+    }
     if (x.kind == NK_LEAF) {
       f.kind = 0;
       f.node = n;
@@ -247,7 +333,7 @@ class Planner {
     double alpha = 1.0;
     flatten(n, false, f, alpha);
     if (f.size() >= 2) return true;
-    return f.size() == 1 && f[0].kind == 1;
+    return f.size() == 1 && (f[0].kind == 1 || f[0].kind == 3);
   }
 
   // The final product of this chain is a matrix-vector product.
@@ -259,7 +345,7 @@ class Planner {
     flatten(n, t, f, alpha);
     if (f.size() < 2) return false;
     for (const Factor& q : f)
-      if (q.kind == 1) return false;
+      if (q.kind == 1 || q.kind == 3) return false;
     const int64_t rows = t ? x.cols : x.rows, cols = t ? x.rows : x.cols;
     return rows == 1 || cols == 1;
   }
@@ -283,9 +369,27 @@ class Planner {
       case NK_UNARY:
         if (x.op == HEXLA_OP_TRANS) return materialize(x.a, !t, dest);
         if (x.op == HEXLA_OP_INV) {
-          View s = materialize(x.a, t, nullptr);
+          View s = dense(materialize(x.a, t, nullptr));
           return explicit_inverse(s, dest);
         }
+        if (x.op == HEXLA_OP_SUBMAT) {
+          // a view of the operand's storage (a leaf, or its evaluated value)
+          View base = materialize(x.a, false, nullptr);
+          if (status_ != HEXLA_OK) return View{};
+          View sv = sub_view(base, x.r0, x.c0, x.rows, x.cols, esz_);
+          if (t) sv = transposed(sv);
+          if (!dest) return sv;
+          return emit_ew(add_view(sv), dest, sv.rows, sv.cols);
+        }
+        if (x.op == HEXLA_OP_DIAG) {
+          View d = diag_value(x.a, t ? nullptr : dest);
+          if (!t) return d;
+          View dt = transposed(d);
+          if (!dest) return dt;
+          return emit_ew(add_view(dt), dest, dt.rows, dt.cols);
+        }
+        if (x.op == HEXLA_OP_TRACE) return trace_value(x.a, dest);
+        if (x.op == HEXLA_OP_DIAGMAT) return diagmat_value(x.a, t, dest);
         return emit_ew(build_ew(n, t), dest, t ? x.cols : x.rows, t ? x.rows : x.cols);
       default:
         break;
@@ -297,8 +401,8 @@ class Planner {
     if (is_ew_binary(x.op))
       return emit_ew(build_ew(n, t), dest, t ? x.cols : x.rows, t ? x.rows : x.cols);
     if (x.op == HEXLA_OP_SOLVE) {
-      View s = materialize(x.a, false, nullptr);
-      View b = materialize(x.b, false, nullptr);
+      View s = dense(materialize(x.a, false, nullptr));
+      View b = dense(materialize(x.b, false, nullptr));
       if (!t) {
         View xo = dest ? *dest : temp(s.cols, b.cols);
         solve(s, b, xo);
@@ -344,16 +448,36 @@ class Planner {
     return add_node(e);
   }
 
+  int add_ident(int64_t rows, int64_t cols) {
+    ENode e;
+    e.kind = 5;
+    e.rows = rows;
+    e.cols = cols;
+    return add_node(e);
+  }
+
+  // Element-wise tree of node n (transposed when t). In diagonal mode
+  // (diag_mode_) the tree computes the main diagonal of n's value as a
+  // column vector: element-wise operations commute with taking the
+  // diagonal, so every operand is replaced by its diagonal.
   int build_ew(uint32_t n, bool t) {
     const Node& x = N(n);
     if (x.scalar) return add_const(scalar_value(n));
-    const int64_t rows = t ? x.cols : x.rows, cols = t ? x.rows : x.cols;
-    if (x.kind == NK_LEAF) return add_view(leaf_view(n, t));
+    int64_t rows = t ? x.cols : x.rows, cols = t ? x.rows : x.cols;
+    if (diag_mode_) {
+      rows = std::min(rows, cols);
+      cols = 1;
+    }
+    if (x.kind == NK_LEAF) {
+      const View v = leaf_view(n, t);
+      return add_view(diag_mode_ ? diag_view(v) : v);
+    }
     auto pending = [&]() {
       ENode e;
       e.kind = 3;
       e.node = n;
       e.trans = t;
+      e.diag = diag_mode_;
       e.rows = rows;
       e.cols = cols;
       return add_node(e);
@@ -363,6 +487,10 @@ class Planner {
         case HEXLA_OP_TRANS: return build_ew(x.a, !t);
         case HEXLA_OP_NEG: return add_op(k::EW_NEG, build_ew(x.a, t), -1, rows, cols);
         case HEXLA_OP_EXP: return add_op(k::EW_EXP, build_ew(x.a, t), -1, rows, cols);
+        case HEXLA_OP_DIAG:
+          if (t || diag_mode_) return pending();
+          return with_diag(x.a);
+        case HEXLA_OP_DIAGMAT: return diagmat_ew(n, t);
         default: return pending();
       }
     }
@@ -376,13 +504,49 @@ class Planner {
         std::vector<Factor> f;
         double alpha = 1.0;
         flatten(n, t, f, alpha);
-        const int inner = f[0].kind == 0 ? add_view(f[0].v) : build_ew(f[0].node, f[0].trans);
+        const int inner = f[0].kind == 0 ? add_view(diag_mode_ ? diag_view(f[0].v) : f[0].v)
+                                         : build_ew(f[0].node, f[0].trans);
         if (alpha == 1.0) return inner;
         return add_op(k::EW_MUL, inner, add_const(alpha), rows, cols);
       }
       default:
         return pending();
     }
+  }
+
+  // The diagonal of node a as an element-wise tree (a column vector).
+  int with_diag(uint32_t a) {
+    const bool prev = diag_mode_;
+    diag_mode_ = true;
+    const int r = build_ew(a, false);
+    diag_mode_ = prev;
+    return r;
+  }
+  int without_diag(uint32_t a, bool t) {
+    const bool prev = diag_mode_;
+    diag_mode_ = false;
+    const int r = build_ew(a, t);
+    diag_mode_ = prev;
+    return r;
+  }
+
+  static bool is_vector(const Node& y) { return !y.scalar && (y.rows == 1 || y.cols == 1); }
+
+  // diagmat(z) inside an element-wise tree: the identity's mask times the
+  // broadcast diagonal values (a vector argument) or times the matrix.
+  int diagmat_ew(uint32_t n, bool t) {
+    const Node& x = N(n);
+    const Node& z = N(x.a);
+    if (diag_mode_) {  // diag(diagmat(v)) = v, diag(diagmat(M)) = diag(M)
+      if (is_vector(z)) return without_diag(x.a, z.rows == 1 && z.cols != 1);
+      return build_ew(x.a, t);
+    }
+    const int64_t rows = t ? x.cols : x.rows, cols = t ? x.rows : x.cols;
+    if (is_vector(z)) {
+      const View dv = diag_vector(x.a);
+      return add_op(k::EW_MUL, add_ident(rows, cols), add_view(bcast_cols(dv, cols)), rows, cols);
+    }
+    return add_op(k::EW_MUL, add_ident(rows, cols), build_ew(x.a, t), rows, cols);
   }
 
   void collect(int e, int kind, std::vector<int>& out) const {
@@ -398,28 +562,47 @@ class Planner {
     return dest ? *dest : temp(rows, cols);
   }
 
-  View emit_ew(int root, const View* dest, int64_t rows, int64_t cols) {
+  // The value of a pending subtree (its diagonal when marked so).
+  View pending_value(int p) {
+    const ENode& e = E_[p];
+    if (!e.diag) return materialize(e.node, e.trans, nullptr);
+    return diag_value(e.node, nullptr);
+  }
+
+  // copy: a lone view is copied into a temporary (or dest) instead of
+  // being returned as it is.
+  View emit_ew(int root, const View* dest, int64_t rows, int64_t cols, bool copy = false) {
     if (status_ != HEXLA_OK) return View{};
-    if (E_[root].kind == 1 && !dest) return E_[root].v;
-    if (E_[root].kind == 3) return materialize(E_[root].node, E_[root].trans, dest);
+    if (E_[root].kind == 1 && !dest && !copy) return E_[root].v;
+    if (E_[root].kind == 3 && !E_[root].diag) return materialize(E_[root].node, E_[root].trans, dest);
     std::vector<int> pend;
     collect(root, 3, pend);
     int epi = -1;
     if (o_.fuse && o_.planner != HEXLA_PLANNER_NAIVE && E_[root].kind == 0) {
       for (int p : pend)
-        if (gemv_final(E_[p].node, E_[p].trans)) {
+        if (!E_[p].diag && gemv_final(E_[p].node, E_[p].trans)) {
           epi = p;
           break;
         }
     }
     for (int p : pend) {
       if (p == epi) continue;
-      View v = materialize(E_[p].node, E_[p].trans, nullptr);
+      View v = pending_value(p);
       E_[p].kind = 1;
       E_[p].v = v;
     }
     if (status_ != HEXLA_OK) return View{};
-    if (!o_.fuse || o_.planner == HEXLA_PLANNER_NAIVE) return emit_unfused(root, dest);
+    if (E_[root].kind == 1 && !dest && !copy) return E_[root].v;
+    if (!o_.fuse || o_.planner == HEXLA_PLANNER_NAIVE) {
+      if (E_[root].kind == 1 && !dest) {  // copy a lone view
+        EwHost p;
+        if (!compile(root, p, false)) return View{};
+        View o = temp(rows, cols);
+        push_ew(p, o);
+        return o;
+      }
+      return emit_unfused(root, dest);
+    }
     if (epi >= 0) {
       E_[epi].kind = 4;
       EwHost prog;
@@ -431,6 +614,183 @@ class Planner {
     View o = out_or_temp(dest, rows, cols);
     push_ew(prog, o);
     return o;
+  }
+
+  // One pass that multiplies and sums: dest (1 x 1) = alpha * the sum of
+  // the program `root` over its rows x cols elements.
+  View emit_sum(int root, int64_t rows, int64_t cols, double alpha, const View* dest) {
+    if (status_ != HEXLA_OK) return View{};
+    std::vector<int> pend;
+    collect(root, 3, pend);
+    for (int p : pend) {
+      View v = pending_value(p);
+      E_[p].kind = 1;
+      E_[p].v = v;
+    }
+    EwHost prog;
+    if (status_ != HEXLA_OK || !compile(root, prog, false)) return View{};
+    Step st;
+    st.kind = StepKind::EwSum;
+    st.dtype = dtype_;
+    st.name = "sum";
+    st.ew = prog;
+    st.m = rows;
+    st.n = cols;
+    st.alpha = alpha;
+    st.sum = true;
+    st.out = out_or_temp(dest, 1, 1);
+    const size_t pb = k::ew_sum_partial_bytes(dtype_, rows * cols);
+    if (pb) st.partial = work(int64_t(pb));
+    const double elems = double(rows) * double(cols);
+    st.flops = elems * (prog.n_arith + 1);
+    st.bytes = elems * double(esz_) * double(prog.leaves.size()) + double(esz_);
+    steps_.push_back(st);
+    return st.out;
+  }
+
+  // --------------------------------------------------------- diagonals
+  // Only the diagonal of a product (expressions (4), (5) of Sec. III):
+  // d_i = sum_k L_ik R_ki with L, R the chain's factors on either side of
+  // the split with the fewest multiply-adds (sub-chains by the DP), and
+  // with `sum` its trace. diag_of_dest: write d onto the diagonal of dest
+  // (stride ld + 1) instead of into a vector.
+  static bool plain_chain(const std::vector<Factor>& f) {
+    if (f.size() < 2) return false;
+    for (const Factor& q : f)
+      if (q.kind == 1 || q.kind == 3) return false;
+    return true;
+  }
+
+  View diag_product(std::vector<Factor> f, double alpha, const View* dest, bool sum,
+                    bool diag_of_dest = false) {
+    for (Factor& q : f)
+      if (q.kind == 2) {
+        q.v = materialize(q.node, q.trans, nullptr);
+        q.kind = 0;
+      }
+    if (status_ != HEXLA_OK) return View{};
+    const int L = int(f.size());
+    std::vector<int64_t> d(L + 1);
+    d[0] = f[0].v.rows;
+    for (int i = 0; i < L; ++i) d[i + 1] = f[i].v.cols;
+    const int64_t nd = std::min(d[0], d[L]);
+    const std::vector<char> sym(L, 0);
+    const auto cost = dp_table(d, sym);
+    int best = 1;
+    i128 bc = -1;
+    for (int p = 1; p < L; ++p) {
+      const i128 c = cost[0][p - 1] + cost[p][L - 1] + i128(nd) * d[p];
+      if (bc < 0 || c < bc) {
+        bc = c;
+        best = p;
+      }
+    }
+    std::vector<Factor> lf(f.begin(), f.begin() + best), rf(f.begin() + best, f.end());
+    View left = best == 1 ? lf[0].v : chain_views(lf, 1.0, nullptr, nullptr);
+    View right = best == L - 1 ? rf[0].v : chain_views(rf, 1.0, nullptr, nullptr);
+    left = dense(left);
+    right = dense(right);
+    if (status_ != HEXLA_OK) return View{};
+    macs_ += double(nd) * double(d[best]);
+    Step st;
+    st.kind = StepKind::DiagProd;
+    st.dtype = dtype_;
+    st.name = sum ? "trace_product" : "diag_product";
+    st.A = left;
+    st.B = right;
+    st.m = nd;
+    st.kk = d[best];
+    st.alpha = alpha;
+    st.sum = sum;
+    st.out = dest ? *dest : temp(sum ? 1 : nd, 1);
+    st.incd = diag_of_dest ? 0 : 1;
+    const size_t pb = k::diagprod_partial_bytes(dtype_, nd, d[best], sum);
+    if (pb) st.partial = work(int64_t(pb));
+    st.flops = 2.0 * double(nd) * double(d[best]);
+    st.bytes = (2.0 * double(nd) * double(d[best]) + (sum ? 1.0 : double(nd))) * double(esz_);
+    steps_.push_back(st);
+    return st.out;
+  }
+
+  // The main diagonal of node a's value, as a column vector (a view when
+  // it can be one).
+  View diag_value(uint32_t a, const View* dest) {
+    const Node& y = N(a);
+    const int64_t nd = y.scalar ? 1 : std::min(y.rows, y.cols);
+    const bool naive = o_.planner == HEXLA_PLANNER_NAIVE;
+    if (!y.scalar && !naive && is_chain(a)) {
+      std::vector<Factor> f;
+      double alpha = 1.0;
+      flatten(a, false, f, alpha);
+      if (plain_chain(f)) return diag_product(f, alpha, dest, false);
+    }
+    if (!y.scalar && (naive || is_chain(a))) {
+      // the full value, then its diagonal (the naive evaluation)
+      const View d = diag_view(materialize(a, false, nullptr));
+      if (!dest) return d;
+      return emit_ew(add_view(d), dest, nd, 1);
+    }
+    return emit_ew(with_diag(a), dest, nd, 1);
+  }
+
+  // trace(a): a product's trace by the diagonal product; otherwise one pass
+  // summing the diagonal of the (element-wise) value.
+  View trace_value(uint32_t a, const View* dest) {
+    const Node& y = N(a);
+    const bool naive = o_.planner == HEXLA_PLANNER_NAIVE;
+    if (!y.scalar && !naive && is_chain(a)) {
+      std::vector<Factor> f;
+      double alpha = 1.0;
+      flatten(a, false, f, alpha);
+      if (plain_chain(f)) return diag_product(f, alpha, dest, true);
+    }
+    const int64_t nd = y.scalar ? 1 : std::min(y.rows, y.cols);
+    int r;
+    if (y.scalar) r = add_const(scalar_value(a));
+    else if (naive || is_chain(a)) r = add_view(diag_view(materialize(a, false, nullptr)));
+    else r = with_diag(a);
+    return emit_sum(r, nd, 1, 1.0, dest);
+  }
+
+  // The diagonal values of diagmat(z) as an n x 1 view: the vector itself,
+  // or the diagonal of the matrix.
+  View diag_vector(uint32_t z) {
+    const Node& y = N(z);
+    if (is_vector(y)) {
+      const int r = without_diag(z, y.rows == 1 && y.cols != 1);
+      return emit_ew(r, nullptr, std::max(y.rows, y.cols), 1);
+    }
+    return diag_value(z, nullptr);
+  }
+
+  // diagmat(a) as a value: expression (4) (the diagonal of a product written
+  // onto zeros) or one element-wise pass.
+  View diagmat_value(uint32_t a, bool t, const View* dest) {
+    const Node& y = N(a);
+    const bool vec = is_vector(y);
+    const int64_t n = std::max(y.rows, y.cols);
+    const int64_t rows = vec ? n : (t ? y.cols : y.rows), cols = vec ? n : (t ? y.rows : y.cols);
+    if (!vec && !y.scalar && o_.planner != HEXLA_PLANNER_NAIVE && is_chain(a)) {
+      std::vector<Factor> f;
+      double alpha = 1.0;
+      flatten(a, false, f, alpha);
+      if (plain_chain(f)) {
+        View o = out_or_temp(dest, rows, cols);
+        EwHost zero;
+        if (!compile(add_const(0.0), zero, false)) return View{};
+        push_ew(zero, o);
+        diag_product(f, alpha, &o, false, true);
+        return o;
+      }
+    }
+    int r;
+    if (vec) {
+      const View dv = diag_vector(a);
+      r = add_op(k::EW_MUL, add_ident(rows, cols), add_view(bcast_cols(dv, cols)), rows, cols);
+    } else {
+      r = add_op(k::EW_MUL, add_ident(rows, cols), without_diag(a, t), rows, cols);
+    }
+    return emit_ew(r, dest, rows, cols);
   }
 
   // One kernel and one temporary per operation (the eager evaluation the
@@ -520,6 +880,7 @@ class Planner {
     if (n.kind == 1) return emit(g, k::EW_LEAF, leaf_slot(g, n.v));
     if (n.kind == 2) return emit(g, k::EW_CONST, const_slot(g, n.c));
     if (n.kind == 4) return emit(g, k::EW_EXTRA, 0);
+    if (n.kind == 5) return emit(g, k::EW_IDENT, 0);
     if (n.b < 0) {
       gen(g, n.a);
       return emit(g, n.op, 0);
@@ -635,20 +996,103 @@ class Planner {
     std::vector<Factor> f;
     double alpha = 1.0;
     flatten(n, t, f, alpha);
+    bool diag = false;
+    for (const Factor& q : f) diag = diag || q.kind == 3;
+    if (diag) return chain_with_diagonals(f, alpha, dest);
     for (Factor& q : f)
       if (q.kind == 2) {
-        q.v = materialize(q.node, q.trans, nullptr);
+        q.v = dense(materialize(q.node, q.trans, nullptr));
         q.kind = 0;
       }
     if (status_ != HEXLA_OK) return View{};
     return chain_views(f, alpha, dest, epi);
   }
 
+  // A chain with diagonal factors diagmat(z) (expressions (3) and (7) of
+  // Sec. III). Only z's diagonal values are read:
+  //   * a row vector, diagonal factors and a column vector: one pass that
+  //     multiplies and sums, x^T diag(d1) ... y = sum_i x_i d1_i ... y_i;
+  //   * otherwise each square diagonal factor scales the rows of the factor
+  //     on its right (or the columns of the one on its left, at the end), as
+  //     one element-wise pass; a chain left with one factor is that pass,
+  //     written to the destination.
+  // The naive planner builds each diagonal matrix instead (the paper's naive
+  // evaluation, a temporary dense matrix and a general product).
+  View chain_with_diagonals(std::vector<Factor> f, double alpha, const View* dest) {
+    const bool naive = o_.planner == HEXLA_PLANNER_NAIVE;
+    bool inverse = false;
+    for (const Factor& q : f) inverse = inverse || q.kind == 1;
+    for (Factor& q : f)
+      if (q.kind == 3 && (naive || inverse || q.v.rows != q.v.cols)) {
+        q.v = diagmat_value(q.node, q.trans, nullptr);
+        q.kind = 0;
+      }
+    for (Factor& q : f)
+      if (q.kind == 2) {
+        q.v = dense(materialize(q.node, q.trans, nullptr));
+        q.kind = 0;
+      }
+    if (status_ != HEXLA_OK) return View{};
+    bool any = false;
+    for (const Factor& q : f) any = any || q.kind == 3;
+    if (!any) return chain_views(f, alpha, dest, nullptr);
+    const int L = int(f.size());
+    // x^T diag(d1) ... diag(dk) y
+    bool dot = L >= 3 && f[0].kind == 0 && f[L - 1].kind == 0 && f[0].v.rows == 1 &&
+               f[L - 1].v.cols == 1;
+    for (int i = 1; i + 1 < L && dot; ++i) dot = f[i].kind == 3;
+    if (dot) {
+      const int64_t n = f[0].v.cols;
+      int r = add_view(transposed(f[0].v));
+      for (int i = 1; i + 1 < L; ++i)
+        r = add_op(k::EW_MUL, r, add_view(diag_vector(f[i].node)), n, 1);
+      r = add_op(k::EW_MUL, r, add_view(f[L - 1].v), n, 1);
+      return emit_sum(r, n, 1, alpha, dest);
+    }
+    // fold the diagonals into their neighbours
+    std::vector<int> roots;         // element-wise tree of each remaining factor
+    std::vector<Factor> g;
+    std::vector<View> pend;         // diagonal vectors waiting for a right neighbour
+    for (const Factor& q : f) {
+      if (q.kind == 3) {
+        pend.push_back(diag_vector(q.node));
+        continue;
+      }
+      int r = add_view(q.v);
+      for (const View& d : pend)
+        r = add_op(k::EW_MUL, add_view(bcast_cols(d, q.v.cols)), r, q.v.rows, q.v.cols);
+      pend.clear();
+      roots.push_back(r);
+      g.push_back(q);
+    }
+    if (status_ != HEXLA_OK) return View{};
+    if (g.empty()) {  // only diagonal factors: diagmat of the product of their diagonals
+      const int64_t n = f[0].v.rows;
+      int r = add_ident(n, n);
+      for (const View& d : pend) r = add_op(k::EW_MUL, r, add_view(bcast_cols(d, n)), n, n);
+      if (alpha != 1.0) r = add_op(k::EW_MUL, r, add_const(alpha), n, n);
+      return emit_ew(r, dest, n, n);
+    }
+    for (const View& d : pend) {  // diagonals at the end scale the last factor's columns
+      const View& v = g.back().v;
+      roots.back() = add_op(k::EW_MUL, roots.back(), add_view(bcast_rows(d, v.rows)), v.rows, v.cols);
+    }
+    if (g.size() == 1) {
+      int r = roots[0];
+      if (alpha != 1.0) r = add_op(k::EW_MUL, r, add_const(alpha), g[0].v.rows, g[0].v.cols);
+      return emit_ew(r, dest, g[0].v.rows, g[0].v.cols);
+    }
+    for (size_t i = 0; i < g.size(); ++i)
+      if (E_[roots[i]].kind != 1) g[i].v = emit_ew(roots[i], nullptr, g[i].v.rows, g[i].v.cols);
+    if (status_ != HEXLA_OK) return View{};
+    return chain_views(g, alpha, dest, nullptr);
+  }
+
   View chain_views(std::vector<Factor> f, double alpha, const View* dest, const EwHost* epi) {
     const bool naive = o_.planner == HEXLA_PLANNER_NAIVE;
     for (size_t p = 0; p < f.size(); ++p) {
       if (f[p].kind != 1) continue;
-      View s = materialize(f[p].node, f[p].trans, nullptr);
+      View s = dense(materialize(f[p].node, f[p].trans, nullptr));
       if (status_ != HEXLA_OK) return View{};
       if (naive || p + 1 == f.size()) {
         f[p].v = explicit_inverse(s, nullptr);
@@ -741,6 +1185,24 @@ class Planner {
     int t = mk_leaf(tree, 0);
     for (int i = 1; i < L; ++i) t = mk_pair(tree, t, mk_leaf(tree, i));
     return t;
+  }
+
+  // Minimum multiply-adds of every sub-chain lo..hi (O(L^3)).
+  std::vector<std::vector<i128>> dp_table(const std::vector<int64_t>& d,
+                                          const std::vector<char>& sym) const {
+    const int L = int(d.size()) - 1;
+    std::vector<std::vector<i128>> cost(L, std::vector<i128>(L, 0));
+    for (int len = 2; len <= L; ++len)
+      for (int lo = 0; lo + len - 1 < L; ++lo) {
+        const int hi = lo + len - 1;
+        i128 best = -1;
+        for (int s = lo; s < hi; ++s) {
+          const i128 c = cost[lo][s] + cost[s + 1][hi] + pair_cost(d, lo, s, hi, sym);
+          if (best < 0 || c < best) best = c;
+        }
+        cost[lo][hi] = best;
+      }
+    return cost;
   }
 
   // Exact minimum over all bracketings (O(L^3)); ties keep the first split.
@@ -1102,7 +1564,9 @@ std::string source_hash(const std::string& src) {
 void json_view(std::ostringstream& js, const char* name, const View& v) {
   js << "\"" << name << "\":{\"rows\":" << v.rows << ",\"cols\":" << v.cols
      << ",\"trans\":" << (v.trans ? "true" : "false") << ",\"buf\":\""
-     << (v.ref.buf == Buf::Leaf ? "leaf" : v.ref.buf == Buf::Work ? "work" : "out") << "\"}";
+     << (v.ref.buf == Buf::Leaf ? "leaf" : v.ref.buf == Buf::Work ? "work" : "out") << "\"";
+  if (v.strided) js << ",\"strides\":[" << v.str_i << "," << v.str_j << "]";
+  js << "}";
 }
 
 }  // namespace
@@ -1145,6 +1609,16 @@ std::string describe(const hexla_plan* p) {
       case StepKind::LuSolve:
         js << ",\"n\":" << s.n << ",\"nrhs\":" << s.nrhs;
         break;
+      case StepKind::DiagProd:
+        js << ",\"n\":" << s.m << ",\"k\":" << s.kk << ",\"alpha\":" << s.alpha << ",";
+        json_view(js, "A", s.A);
+        js << ",";
+        json_view(js, "B", s.B);
+        break;
+      case StepKind::EwSum:
+        js << ",\"elements\":" << s.m * s.n << ",\"leaves\":" << s.ew.leaves.size()
+           << ",\"alpha\":" << s.alpha;
+        break;
       default:
         break;
     }
@@ -1162,6 +1636,15 @@ std::string describe(const hexla_plan* p) {
 
 void leaf_range(const View& v, size_t esz, std::vector<Range>& out) {
   if (v.ref.buf != Buf::Leaf || !v.ref.ptr) return;
+  if (v.strided) {  // a diagonal or broadcast: the storage it spans
+    if (v.span <= 0) return;
+    Range r;
+    r.ptr = v.ref.ptr;
+    r.bytes = uint64_t(v.span) * esz;
+    r.ld = 0;
+    out.push_back(r);
+    return;
+  }
   const int64_t rs = v.trans ? v.cols : v.rows, cs = v.trans ? v.rows : v.cols;
   if (rs == 0 || cs == 0) return;
   Range r;
@@ -1210,6 +1693,9 @@ hexla_status hexla_plan_create(hexla_ctx* ctx, hexla_node root, const hexla_plan
   for (const hexla::Step& s : p->steps) {
     if (s.kind == hexla::StepKind::Ew) {
       for (const hexla::View& v : s.ew.leaves) hexla::leaf_range(v, esz, p->ew_leaf_ranges);
+    } else if (s.kind == hexla::StepKind::EwSum) {
+      // a sum writes one value: the output must not overlap what it reads
+      for (const hexla::View& v : s.ew.leaves) hexla::leaf_range(v, esz, p->leaf_ranges);
     } else {
       hexla::leaf_range(s.A, esz, p->leaf_ranges);
       hexla::leaf_range(s.B, esz, p->leaf_ranges);

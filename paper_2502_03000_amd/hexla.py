@@ -25,7 +25,7 @@ OK, E_INVALID_ARG, E_DIM, E_DTYPE, E_NOT_SQUARE, E_SINGULAR, E_NO_CONVERGENCE, \
 STATUS_NAMES = ["OK", "E_INVALID_ARG", "E_DIM", "E_DTYPE", "E_NOT_SQUARE", "E_SINGULAR",
                 "E_NO_CONVERGENCE", "E_UNSUPPORTED", "E_DEVICE"]
 F64, F32 = 0, 1
-OP_TRANS, OP_NEG, OP_EXP, OP_INV = 1, 2, 3, 4
+OP_TRANS, OP_NEG, OP_EXP, OP_INV, OP_DIAG, OP_DIAGMAT, OP_TRACE = 1, 2, 3, 4, 5, 6, 7
 OP_TIMES, OP_PLUS, OP_MINUS, OP_SCHUR, OP_DIV, OP_SOLVE = 16, 17, 18, 19, 20, 21
 PLANNERS = {"dp": 0, "greedy": 1, "naive": 2, "learned": 3}
 PRODUCT_PRECISION = {"plain": 0, "bf16x3": 1, "bf16x6": 2}
@@ -88,6 +88,7 @@ def _load():
         "hexla_scalar": [vp, C.c_double, C.POINTER(u32)],
         "hexla_unary": [vp, C.c_int, u32, C.POINTER(u32)],
         "hexla_binary": [vp, C.c_int, u32, u32, C.POINTER(u32)],
+        "hexla_submatrix": [vp, u32, i64, i64, i64, i64, C.POINTER(u32)],
         "hexla_node_shape": [vp, u32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)],
         "hexla_plan_opts_default": [C.POINTER(PlanOpts)],
         "hexla_plan_create": [vp, u32, C.POINTER(PlanOpts), C.POINTER(vp)],
@@ -204,6 +205,18 @@ class Expr:
     def t(self):
         return self.ctx.unary(OP_TRANS, self)
 
+    def submat(self, r0, c0, rows, cols):
+        """Rows [r0, r0+rows) and columns [c0, c0+cols), 0-based, in place."""
+        return self.ctx.submatrix(self, r0, c0, rows, cols)
+
+    def col(self, j):
+        """Column j (0-based) as an m x 1 view."""
+        return self.submat(0, j, self.shape[0], 1)
+
+    def row(self, i):
+        """Row i (0-based) as a 1 x n view."""
+        return self.submat(i, 0, 1, self.shape[1])
+
     @property
     def shape(self):
         return self.ctx.shape(self)
@@ -221,6 +234,9 @@ def static_scratch_bytes() -> int:
 def trans(x): return x.ctx.unary(OP_TRANS, x)
 def inv(x): return x.ctx.unary(OP_INV, x)
 def exp(x): return x.ctx.unary(OP_EXP, x)
+def diag(x): return x.ctx.unary(OP_DIAG, x)
+def diagmat(x): return x.ctx.unary(OP_DIAGMAT, x)
+def trace(x): return x.ctx.unary(OP_TRACE, x)
 def solve(a, b): return a.ctx.binary(OP_SOLVE, a, a._lift(b))
 
 
@@ -574,6 +590,11 @@ class Context:
     def binary(self, op, a, b) -> Expr:
         n = C.c_uint32()
         self._check(lib.hexla_binary(self.handle, op, a.node, b.node, C.byref(n)))
+        return Expr(self, n.value)
+
+    def submatrix(self, a, r0, c0, rows, cols) -> Expr:
+        n = C.c_uint32()
+        self._check(lib.hexla_submatrix(self.handle, a.node, r0, c0, rows, cols, C.byref(n)))
         return Expr(self, n.value)
 
     def shape(self, e):

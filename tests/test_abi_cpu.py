@@ -217,3 +217,53 @@ def test_plan_keeps_borrowed_tensors_alive_after_clear(ctx):
     del p
     gc.collect()
     assert all(r() is None for r in refs)
+
+
+# ------------------------------- diagonals, traces and views (dry-run plans)
+
+def test_diagonal_rewrites_plan_no_full_product(ctx):
+    a, b = leaf(ctx, 300, 500), leaf(ctx, 500, 300)
+    s, v, w = leaf(ctx, 300, 300), leaf(ctx, 300, 1), leaf(ctx, 300, 1)
+    assert kernels(ctx.plan(hx.diag(a @ b))) == ["diag_product"]
+    assert ctx.plan(hx.diag(a @ b)).shape == (300, 1)
+    assert kernels(ctx.plan(hx.trace(a @ b))) == ["trace_product"]
+    assert ctx.plan(hx.trace(a @ b)).shape == (1, 1)
+    # expression (4): zeros, then the product's diagonal written onto them
+    assert kernels(ctx.plan(hx.diagmat(a @ b))) == ["elementwise", "diag_product"]
+    # expression (3): one element-wise pass scaling rows (matrix or vector diagonal)
+    assert kernels(ctx.plan(hx.diagmat(s) @ a)) == ["elementwise"]
+    assert kernels(ctx.plan(hx.diagmat(v) @ a)) == ["elementwise"]
+    assert kernels(ctx.plan(b @ hx.diagmat(s))) == ["elementwise"]
+    # expression (7): one multiply-and-sum pass
+    p = ctx.plan(hx.trans(v) @ hx.diagmat(s) @ w)
+    assert kernels(p) == ["sum"] and p.shape == (1, 1)
+    # the naive planner forms the full product or the dense diagonal matrix
+    assert "gemm" in kernels(ctx.plan(hx.diag(a @ b), planner="naive"))
+    assert "gemm" in kernels(ctx.plan(hx.diagmat(s) @ a, planner="naive"))
+    # traces and diagonals of element-wise values read only the diagonals
+    p = ctx.plan(hx.trace(s + 2.0 * s))
+    assert kernels(p) == ["sum"]
+    assert kernels(ctx.plan(hx.diag(s % s) + v)) == ["elementwise"]
+    # four factors: the split with the fewest multiply-adds, each side by the
+    # DP: (A (B C)) and D, 3e6 + 3e6 + 300 * 20 (the diagonal of a 300 x 20
+    # by 20 x 300 product) against 6.15e6 for A and (B C) D
+    c = leaf(ctx, 300, 20)
+    d = leaf(ctx, 20, 300)
+    p = ctx.plan(hx.diag(a @ b @ c @ d))
+    assert kernels(p) == ["gemm", "gemm", "diag_product"]
+    assert p.describe()["chain_macs"] == 500 * 300 * 20 + 300 * 500 * 20 + 300 * 20
+
+
+def test_submatrix_views(ctx):
+    a, b = leaf(ctx, 40, 30), leaf(ctx, 20, 40)
+    e = a.col(0) + hx.trans(b.row(1))
+    assert e.shape == (40, 1)
+    assert kernels(ctx.plan(e)) == ["elementwise"]
+    # a view of a leaf feeds a product without a copy
+    x = leaf(ctx, 30, 1)
+    assert kernels(ctx.plan(a.submat(5, 0, 20, 30) @ x)) == ["gemv_n"]
+    with pytest.raises(hx.HexlaError) as ei:
+        a.submat(30, 0, 20, 1)
+    assert ei.value.status == hx.E_DIM
+    with pytest.raises(hx.HexlaError):
+        a.col(30)
