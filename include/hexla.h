@@ -149,8 +149,12 @@ typedef enum hexla_planner {
   HEXLA_PLANNER_DP = 0,      /* exact minimum multiply-adds over all bracketings */
   HEXLA_PLANNER_GREEDY = 1,  /* Sec. II rule: smallest-result pair first, leftmost on ties */
   HEXLA_PLANNER_NAIVE = 2,   /* Sec. III "naive": left to right, no rewrites     */
-  HEXLA_PLANNER_LEARNED = 3  /* predicted-time DP with the context's cost model,
+  HEXLA_PLANNER_LEARNED = 3, /* predicted-time DP with the context's cost model,
                                 checked by the DP (see hexla_ctx_set_model)     */
+  HEXLA_PLANNER_ROOFLINE = 4 /* exact minimum over all bracketings of the summed
+                                roofline times max(flops / peak, bytes / 8 TB/s)
+                                of the products (peak: the MFMA rate of the
+                                product precision); not in the paper        */
 } hexla_planner;
 
 typedef enum hexla_product_precision {

@@ -104,3 +104,36 @@ def catalan(n: int) -> int:
     if n <= 1:
         return 1
     return sum(catalan(i) * catalan(n - 1 - i) for i in range(n))
+
+
+def roofline_time(tree, dims, esz, peak_flops, bandwidth, sym_pairs=frozenset()) -> float:
+    """Seconds to evaluate ``tree`` on a machine where each product takes
+    the longer of its flops at ``peak_flops`` and its bytes at ``bandwidth``
+    (the roofline): 2 flops per multiply-add, each operand read once and the
+    result written once, ``esz`` bytes per element. A symmetric pair (see
+    ``tree_cost``) does n(n+1) k flops and reads its one operand once. Not in
+    the paper: the cost model of a planner variant beside the multiply-add
+    count."""
+    if isinstance(tree, int):
+        return 0.0
+    (a, _), (_, b) = span(tree[0]), span(tree[1])
+    k = span(tree[0])[1]
+    rows, inner, cols = dims[a], dims[k + 1], dims[b + 1]
+    if isinstance(tree[0], int) and isinstance(tree[1], int) and (tree[0], tree[1]) in sym_pairs:
+        flops = rows * (rows + 1) * inner
+        elems = rows * inner + rows * cols
+    else:
+        flops = 2 * rows * inner * cols
+        elems = rows * inner + inner * cols + rows * cols
+    here = max(flops / peak_flops, elems * esz / bandwidth)
+    return (here + roofline_time(tree[0], dims, esz, peak_flops, bandwidth, sym_pairs)
+            + roofline_time(tree[1], dims, esz, peak_flops, bandwidth, sym_pairs))
+
+
+def brute_force_min_time(dims, esz, peak_flops, bandwidth, sym_pairs=frozenset()) -> tuple:
+    """(min roofline time, the trees within 1e-12 of it) over every bracketing."""
+    n = len(dims) - 1
+    times = [(roofline_time(t, dims, esz, peak_flops, bandwidth, sym_pairs), t)
+             for t in trees(0, n - 1)]
+    best = min(c for c, _ in times)
+    return best, [t for c, t in times if c <= best * (1 + 1e-12)]

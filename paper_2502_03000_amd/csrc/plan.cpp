@@ -68,6 +68,7 @@ const char* planner_name(int p) {
     case HEXLA_PLANNER_GREEDY: return "greedy";
     case HEXLA_PLANNER_NAIVE: return "naive";
     case HEXLA_PLANNER_LEARNED: return "learned";
+    case HEXLA_PLANNER_ROOFLINE: return "roofline";
     default: return "dp";
   }
 }
@@ -1143,6 +1144,7 @@ class Planner {
     if (o_.planner == HEXLA_PLANNER_GREEDY) root = order_greedy(dims, tree);
     else if (naive) root = order_left(L, tree);
     else if (o_.planner == HEXLA_PLANNER_LEARNED && ctx_->model) root = order_learned(dims, sym, f, tree);
+    else if (o_.planner == HEXLA_PLANNER_ROOFLINE) root = order_roofline(dims, sym, tree);
     else root = order_dp(dims, sym, tree);
     if (status_ != HEXLA_OK) return View{};
     macs_ += double(tree_cost(root, tree, dims, sym));
@@ -1203,6 +1205,56 @@ class Planner {
         cost[lo][hi] = best;
       }
     return cost;
+  }
+
+  // Roofline time of one product: the longer of its flops at the MFMA peak
+  // of the product precision and its bytes (operands read once, result
+  // written once) at 8 TB/s; a symmetric pair reads its operand once.
+  double pair_time(const std::vector<int64_t>& d, int lo, int split, int hi,
+                   const std::vector<char>& sym) const {
+    double peak = dtype_ == HEXLA_F64 ? 78.6e12 : 157.3e12;
+    if (dtype_ == HEXLA_F32 && o_.product_precision == HEXLA_PRODUCT_BF16X3) peak = 2.5e15 / 3.0;
+    if (dtype_ == HEXLA_F32 && o_.product_precision == HEXLA_PRODUCT_BF16X6) peak = 2.5e15 / 6.0;
+    const double r = double(d[lo]), k = double(d[split + 1]), c = double(d[hi + 1]);
+    double flops, elems;
+    if (hi == lo + 1 && sym[lo]) {
+      flops = r * (r + 1.0) * k;
+      elems = r * k + r * c;
+    } else {
+      flops = 2.0 * r * k * c;
+      elems = r * k + k * c + r * c;
+    }
+    return std::max(flops / peak, elems * double(esz_) / 8e12);
+  }
+
+  // Exact minimum of the summed roofline times over all bracketings;
+  // ties keep the first split.
+  int order_roofline(const std::vector<int64_t>& d, const std::vector<char>& sym,
+                     std::vector<TNode>& tree) {
+    const int L = int(d.size()) - 1;
+    std::vector<std::vector<double>> cost(L, std::vector<double>(L, 0.0));
+    std::vector<std::vector<int>> arg(L, std::vector<int>(L, -1));
+    for (int len = 2; len <= L; ++len)
+      for (int lo = 0; lo + len - 1 < L; ++lo) {
+        const int hi = lo + len - 1;
+        double best = -1.0;
+        for (int s = lo; s < hi; ++s) {
+          const double c = cost[lo][s] + cost[s + 1][hi] + pair_time(d, lo, s, hi, sym);
+          if (best < 0.0 || c < best) {
+            best = c;
+            arg[lo][hi] = s;
+          }
+        }
+        cost[lo][hi] = best;
+      }
+    std::function<int(int, int)> build = [&](int lo, int hi) -> int {
+      if (lo == hi) return mk_leaf(tree, lo);
+      const int s = arg[lo][hi];
+      const int l = build(lo, s);
+      const int r = build(s + 1, hi);
+      return mk_pair(tree, l, r);
+    };
+    return build(0, L - 1);
   }
 
   // Exact minimum over all bracketings (O(L^3)); ties keep the first split.
@@ -1669,7 +1721,7 @@ hexla_status hexla_plan_create(hexla_ctx* ctx, hexla_node root, const hexla_plan
   hexla_plan_opts o;
   hexla_plan_opts_default(&o);
   if (opts) o = *opts;
-  if (o.planner < 0 || o.planner > HEXLA_PLANNER_LEARNED || o.product_precision < 0 ||
+  if (o.planner < 0 || o.planner > HEXLA_PLANNER_ROOFLINE || o.product_precision < 0 ||
       o.product_precision > HEXLA_PRODUCT_BF16X6 || o.solve_precision < 0 ||
       o.solve_precision > HEXLA_SOLVE_IR_BF16X3)
     return set_err(ctx, HEXLA_E_INVALID_ARG, "plan: bad options");

@@ -267,3 +267,40 @@ def test_submatrix_views(ctx):
     assert ei.value.status == hx.E_DIM
     with pytest.raises(hx.HexlaError):
         a.col(30)
+
+
+def _plan_roofline_time(plan, esz, peak):
+    t = 0.0
+    for s in plan.describe()["steps"]:
+        m, n, k = s["m"], s["n"], s["k"]
+        t += max(2.0 * m * n * k / peak, (m * k + k * n + m * n) * esz / 8e12)
+    return t
+
+
+@pytest.mark.parametrize("dtype,esz,peak", [(hx.F32, 4, 157.3e12), (hx.F64, 8, 78.6e12)])
+def test_roofline_planner_matches_brute_force(ctx, dtype, esz, peak):
+    """The roofline planner's bracketing has the oracle's brute-force
+    minimum of summed roofline times (chains of 3-6 factors, dims
+    log-uniform in [1, 8192])."""
+    for dims in inputs.random_chain_dims(seed=77, count=40, lmin=3, lmax=6, lo=1, hi=8192):
+        e = None
+        for a, b in zip(dims[:-1], dims[1:]):
+            x = leaf(ctx, a, b, dtype)
+            e = x if e is None else e @ x
+        p = ctx.plan(e, planner="roofline")
+        want, _ = chain.brute_force_min_time(list(dims), esz, peak, 8e12)
+        assert _plan_roofline_time(p, esz, peak) == pytest.approx(want, rel=1e-9), dims
+        # never fewer multiply-adds than the DP's minimum
+        assert p.describe()["chain_macs"] >= chain.brute_force_min(list(dims))[0]
+
+
+def test_roofline_planner_golden_order(ctx):
+    dims = [1, 4, 8192, 4]
+    e = None
+    for a, b in zip(dims[:-1], dims[1:]):
+        x = leaf(ctx, a, b, hx.F32)
+        e = x if e is None else e @ x
+    first = ctx.plan(e, planner="roofline").describe()["steps"][0]
+    assert (first["m"], first["k"], first["n"]) == (4, 8192, 4)
+    assert ctx.plan(e).describe()["chain_macs"] == 65536
+    assert ctx.plan(e, planner="roofline").describe()["chain_macs"] == 131088

@@ -62,7 +62,7 @@ def run(ctx, expr, **opts):
 
 # ------------------------------------------------------------- small chain
 
-@pytest.mark.parametrize("planner", ["dp", "greedy", "naive"])
+@pytest.mark.parametrize("planner", ["dp", "greedy", "naive", "roofline"])
 def test_small_chain_expression_fp64(ctx, planner):
     env = inputs.small_chain_expr(1000)
     ref = oracle.evaluate(inputs.SMALL_CHAIN_EXPR, env)
@@ -171,7 +171,7 @@ def test_small_integer_chain_is_exact(ctx, dt):
     for m in mats:
         x = ctx.leaf(dev(m))
         e = x if e is None else e @ x
-    for planner in ("dp", "greedy", "naive"):
+    for planner in ("dp", "greedy", "naive", "roofline"):
         got = run(ctx, e, planner=planner)
         assert np.array_equal(got, ref), planner
 

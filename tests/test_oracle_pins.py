@@ -327,3 +327,22 @@ def test_magnitude_of_diagonal_functions():
     assert oracle.magnitude("diag(A*B)", env).ravel().tolist() == [5.0, 15.0]
     assert oracle.magnitude("trace(A*B)", env).tolist() == [[20.0]]
     assert oracle.magnitude("col(A, 1)", env).ravel().tolist() == [2.0, 4.0]
+
+
+def test_roofline_time_by_hand_and_golden_order():
+    # one product 2 x 3 by 3 x 4: 48 flops, 6 + 12 + 8 = 26 elements
+    assert chain.roofline_time((0, 1), [2, 3, 4], 4, 48.0, 26 * 4.0) == 1.0
+    assert chain.roofline_time((0, 1), [2, 3, 4], 4, 24.0, 1e9) == 2.0   # flop-bound
+    assert chain.roofline_time((0, 1), [2, 3, 4], 8, 1e9, 26 * 4.0) == 2.0  # byte-bound at 8 B
+    # [1, 4, 8192, 4] in FP32 at 157.3 TFLOP/s and 8 TB/s: the fewest
+    # multiply-adds first make a 1 x 8192 row (65,536 MACs); the roofline
+    # order forms the 4 x 4 product of the two large factors first (131,088
+    # MACs) and moves (65,552 + 24) * 4 = 262,304 bytes instead of
+    # (40,964 + 40,964) * 4 = 327,712
+    dims = [1, 4, 8192, 4]
+    assert chain.brute_force_min(dims)[1] == [((0, 1), 2)]
+    t, best = chain.brute_force_min_time(dims, 4, 157.3e12, 8e12)
+    assert best == [(0, (1, 2))]
+    assert t == pytest.approx(262304 / 8e12, rel=1e-12)
+    assert chain.roofline_time(((0, 1), 2), dims, 4, 157.3e12, 8e12) == pytest.approx(327712 / 8e12,
+                                                                                     rel=1e-12)
