@@ -199,10 +199,15 @@ typedef struct hexla_plan_opts {
   int32_t ir_max_iter;        /* refinement cap (default 30; 0: none; < 0: 30)   */
   double ir_tol_scale;        /* stop when ||R||inf <= scale*2^-53*||S||inf*||X||inf;
                                  0 = 1                                           */
+  int32_t solve_structure;    /* 0: solve() examines the system matrix when the
+                                 plan runs and picks a solver for its structure
+                                 (hexla_solver; default); 1: LU always. Plain
+                                 precision only; a plan that examines cannot be
+                                 captured                                        */
   int32_t codegen;            /* 1: element-wise passes run as kernels generated
                                  for the expression (hipRTC, default); 0: the
                                  program interpreter kernel                     */
-  int32_t reserved[7];
+  int32_t reserved[6];
 } hexla_plan_opts;
 
 /* Fills the defaults: DP, plain precision, fusion on, SYRK on, cap 30,
@@ -261,12 +266,31 @@ hexla_status hexla_execute(hexla_plan* plan, void* out, int64_t ld_out, void* wo
 hexla_status hexla_execute_static(hexla_plan* plan, void* out, int64_t ld_out);
 hexla_status hexla_static_scratch_bytes(size_t* bytes);
 
+/* Solvers a structure-aware solve chooses (expression (10) of Sec. III: the
+ * matrix is analysed and a tailored solver used): S diagonal -> division;
+ * lower / upper triangular -> block substitution; tridiagonal -> elimination
+ * with partial pivoting between adjacent rows; symmetric with a positive
+ * diagonal, or S = X X^T known from the expression (the solve of Sec. IV's
+ * call trace) -> Cholesky, falling back to LU if a pivot is not positive;
+ * anything else -> LU with partial pivoting. */
+typedef enum hexla_solver {
+  HEXLA_SOLVER_LU = 0,
+  HEXLA_SOLVER_CHOLESKY = 1,
+  HEXLA_SOLVER_LOWER = 2,
+  HEXLA_SOLVER_UPPER = 3,
+  HEXLA_SOLVER_TRIDIAGONAL = 4,
+  HEXLA_SOLVER_DIAGONAL = 5
+} hexla_solver;
+
 typedef struct hexla_report {
   int32_t status;             /* deferred hexla_status of the work since the last sync */
   int32_t ir_iterations;      /* refinement iterations of the last refined solve */
   int64_t singular_column;    /* first zero-pivot column (or -1)                 */
   double ir_backward_error;   /* ||R||inf / (||S||inf ||X||inf) of the last
                                  residual that refined solve formed            */
+  int32_t solver;             /* hexla_solver of the last structure-aware solve,
+                                 -1 if none ran since the last sync             */
+  int32_t reserved;
 } hexla_report;
 
 /* Waits for the context's stream, then reports (and clears) the deferred

@@ -224,6 +224,129 @@ hexla_status run_ir_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipStrea
   return HEXLA_OK;
 }
 
+// Structure-aware solve (see hexla_solver): copy S into the working matrix,
+// read its structure (one pass and one wait for four integers) unless the
+// planner knows S = X X^T, then run the solver that structure allows. A
+// Cholesky whose pivot is not positive falls back to LU on a fresh copy.
+hexla_status run_struct_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipStream_t st) {
+  const int64_t n = s.n, r = s.nrhs;
+  ctx->host_solver = -1;
+  if (n == 0 || r == 0) return HEXLA_OK;
+  const View B = resolve(s.B, b), X = resolve(s.C, b), W = resolve(s.out, b);
+  void* wm = addr(W.ref, b);
+  const int64_t ldw = std::max<int64_t>(n, 1);
+  int32_t* info = static_cast<int32_t*>(addr(s.info, b));
+  void* inv = addr(s.inv, b);
+  void* ybuf = addr(s.ybuf, b);
+  void* xo = addr(X.ref, b);
+  const size_t esz = dtype_size(s.dtype);
+  auto fail = [&](hipError_t e, const char* what) { return device_err(ctx, e, what); };
+  auto copy_s = [&]() {
+    const k::EwProgram p = make_prog(s.ew, n, n, b);
+    return k::ew_launch(s.dtype, p, wm, 1, ldw, st);
+  };
+  auto copy_b = [&](void* dst, int64_t ldd) {
+    return hipMemcpy2DAsync(dst, size_t(ldd) * esz, addr(B.ref, b), size_t(B.ld) * esz,
+                            size_t(n) * esz, size_t(r), hipMemcpyDeviceToDevice, st);
+  };
+  auto read_info = [&](int32_t* h) {
+    hipError_t e = hipMemcpyAsync(h, info, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
+  };
+  auto singular = [&]() {
+    if (ctx->host_status == 0) ctx->host_status = HEXLA_E_SINGULAR;
+  };
+  int32_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  hipError_t e = copy_s();
+  if (e != hipSuccess) return fail(e, "solve: copy");
+  int solver = HEXLA_SOLVER_CHOLESKY;
+  if (!s.spd_known) {
+    e = k::structure_launch(s.dtype, n, wm, ldw, info, st);
+    if (e == hipSuccess) e = read_info(h);
+    if (e != hipSuccess) return fail(e, "solve: structure");
+    const int kl = h[0], ku = h[1];
+    if (kl == 0 && ku == 0) solver = HEXLA_SOLVER_DIAGONAL;
+    else if (kl == 0) solver = HEXLA_SOLVER_UPPER;
+    else if (ku == 0) solver = HEXLA_SOLVER_LOWER;
+    else if (kl <= 1 && ku <= 1) solver = HEXLA_SOLVER_TRIDIAGONAL;
+    else if (!h[2] && !h[3]) solver = HEXLA_SOLVER_CHOLESKY;
+    else solver = HEXLA_SOLVER_LU;
+    // a triangular or diagonal matrix with a zero on its diagonal is singular
+    if (solver >= HEXLA_SOLVER_LOWER && solver != HEXLA_SOLVER_TRIDIAGONAL && h[5]) singular();
+  } else {
+    e = k::fill_i32_launch(info, 8, 0, st);
+    if (e != hipSuccess) return fail(e, "solve: clear");
+  }
+  if (solver == HEXLA_SOLVER_CHOLESKY) {
+    e = k::chol_factor_launch(s.dtype, n, wm, ldw, inv, addr(s.partial, b), info, st);
+    if (e == hipSuccess) e = read_info(h);
+    if (e != hipSuccess) return fail(e, "solve: cholesky");
+    if (h[4]) {  // not positive definite: LU on a fresh copy
+      solver = HEXLA_SOLVER_LU;
+      e = copy_s();
+      if (e != hipSuccess) return fail(e, "solve: copy");
+    } else {
+      e = copy_b(xo, X.ld);
+      if (e == hipSuccess)
+        e = k::tri_solve_launch(s.dtype, 0, n, r, wm, ldw, inv, xo, X.ld, ybuf, xo, X.ld, st);
+      if (e != hipSuccess) return fail(e, "solve: cholesky substitution");
+    }
+  }
+  switch (solver) {
+    case HEXLA_SOLVER_DIAGONAL: {  // X = B ./ diag(S), the diagonal broadcast along rows
+      k::EwProgram p{};
+      p.n_instr = 3;
+      p.op[0] = k::EW_LEAF;
+      p.arg[0] = 0;
+      p.op[1] = k::EW_LEAF;
+      p.arg[1] = 1;
+      p.op[2] = k::EW_DIV;
+      p.n_leaf = 2;
+      p.rows = n;
+      p.cols = r;
+      p.leaf[0].ptr = addr(B.ref, b);
+      p.leaf[0].si = 1;
+      p.leaf[0].sj = B.ld;
+      p.leaf[1].ptr = wm;
+      p.leaf[1].si = ldw + 1;
+      p.leaf[1].sj = 0;
+      e = k::ew_launch(s.dtype, p, xo, 1, X.ld, st);
+      break;
+    }
+    case HEXLA_SOLVER_LOWER:
+    case HEXLA_SOLVER_UPPER: {
+      const bool lower = solver == HEXLA_SOLVER_LOWER;
+      e = k::trinv_launch(s.dtype, lower, n, wm, ldw, inv, info, st);
+      if (e == hipSuccess) e = copy_b(lower ? xo : ybuf, lower ? X.ld : ldw);
+      if (e == hipSuccess)
+        e = lower ? k::tri_solve_launch(s.dtype, 1, n, r, wm, ldw, inv, xo, X.ld, ybuf, xo, X.ld, st)
+                  : k::tri_solve_launch(s.dtype, 2, n, r, wm, ldw, inv, ybuf, ldw, nullptr, xo, X.ld,
+                                        st);
+      break;
+    }
+    case HEXLA_SOLVER_TRIDIAGONAL:
+      e = copy_b(xo, X.ld);
+      if (e == hipSuccess)
+        e = k::gtsv_launch(s.dtype, n, r, wm, ldw, xo, X.ld, addr(s.coef, b), info, st);
+      if (e == hipSuccess) e = read_info(h);
+      if (e == hipSuccess && h[5]) singular();
+      break;
+    case HEXLA_SOLVER_LU:
+      e = k::lu_factor_launch(s.dtype, n, wm, ldw, static_cast<int32_t*>(addr(s.rowid, b)),
+                              addr(s.luwork, b), ctx->d_status, st, &ctx->side);
+      if (e == hipSuccess)
+        e = k::lu_solve_launch(s.dtype, n, r, wm, ldw, static_cast<const int32_t*>(addr(s.rowid, b)),
+                               addr(s.luwork, b), addr(B.ref, b), B.ld, xo, X.ld, ctx->d_status, st);
+      break;
+    default:
+      break;
+  }
+  if (e != hipSuccess) return fail(e, "solve");
+  ctx->host_solver = solver;
+  return HEXLA_OK;
+}
+
 hexla_status run_steps(hexla_plan* plan, void* out, int64_t ld_out, void* workspace,
                        hipStream_t st) {
   hexla_ctx* ctx = plan->ctx;
@@ -282,6 +405,11 @@ hexla_status run_steps(hexla_plan* plan, void* out, int64_t ld_out, void* worksp
         if (hs != HEXLA_OK) return hs;
         break;
       }
+      case StepKind::StructSolve: {
+        const hexla_status hs = run_struct_solve(ctx, s, b, st);
+        if (hs != HEXLA_OK) return hs;
+        break;
+      }
       case StepKind::DiagProd: {
         const View A = resolve(s.A, b), B = resolve(s.B, b), o = resolve(s.out, b);
         // incd 0: onto the diagonal of the output matrix
@@ -332,6 +460,7 @@ hexla_status hexla_sync(hexla_ctx* ctx, hexla_report* report) {
   if (!ctx) return HEXLA_E_INVALID_ARG;
   hexla_report r{};
   r.singular_column = -1;
+  r.solver = -1;
   if (ctx->device < 0) {
     if (report) *report = r;
     return HEXLA_OK;
@@ -346,6 +475,8 @@ hexla_status hexla_sync(hexla_ctx* ctx, hexla_report* report) {
   r.status = h[0] ? h[0] : ctx->host_status;
   r.ir_iterations = ctx->host_ir_iterations;
   r.ir_backward_error = ctx->host_ir_berr;
+  r.solver = ctx->host_solver;
+  ctx->host_solver = -1;
   ctx->host_status = 0;
   if (h[0] == HEXLA_E_SINGULAR) r.singular_column = h[2];
   if (h[1]) {

@@ -75,7 +75,8 @@ struct EwHost {
   bool ident = false;
 };
 
-enum class StepKind : uint8_t { Ew, Gemv, Gemm, LuFactor, LuSolve, IrSolve, Fill, DiagProd, EwSum };
+enum class StepKind : uint8_t { Ew, Gemv, Gemm, LuFactor, LuSolve, IrSolve, Fill, DiagProd, EwSum,
+                                StructSolve };
 
 // Workspace of a mixed-precision solve (low-precision LU + FP64 refinement).
 struct IrWork {
@@ -117,6 +118,11 @@ struct Step {
   // contraction. EwSum: out (1 x 1) = alpha * the sum of `ew` over m x n.
   int64_t incd = 1;
   bool sum = false;
+  // StructSolve: S (A) copied by `ew` into the working matrix `out`, the
+  // solver chosen at execute time from the structure of S (or Cholesky when
+  // the planner knows S = X X^T); B, C: right-hand sides and solution.
+  bool spd_known = false;
+  Ref inv, ybuf, coef, info;
   double flops = 0.0, bytes = 0.0;
   // Ew: kernel generated for this program (null: interpreter)
   std::string cg_src;
@@ -137,6 +143,7 @@ struct hexla_ctx {
   int32_t host_status = 0;         // deferred status raised by host-driven loops
   int32_t host_ir_iterations = 0;  // iterations of the last refined solve
   double host_ir_berr = 0.0;       // its backward error ||R||/(||S|| ||X||), last residual
+  int32_t host_solver = -1;        // solver of the last structure-aware solve (hexla_solver)
   hexla_model* model = nullptr;    // cost model of the learned planner (borrowed)
   std::string timing_log;          // autotune timings are appended here when set
   // objects made from this context; destroying the context detaches them

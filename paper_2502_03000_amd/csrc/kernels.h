@@ -116,6 +116,38 @@ size_t ew_sum_partial_bytes(int dtype, int64_t count);
 hipError_t ew_sum_launch(int dtype, const EwProgram& p, double alpha, void* out, void* partial,
                          hipStream_t s);
 
+// ------------------------------------------------------ structured solves
+// info (8 ints, cleared here): [0] lower bandwidth, [1] upper bandwidth,
+// [2] 1 if S != S^T, [3] 1 if a diagonal entry is not > 0, [5] 1 if a
+// diagonal entry is zero. One pass over the n x n matrix S (lds).
+hipError_t structure_launch(int dtype, int64_t n, const void* S, int64_t lds, int32_t* info,
+                            hipStream_t s);
+// Bytes of the inverse diagonal blocks (64 x 64 each) of an n x n factor.
+size_t struct_inv_bytes(int dtype, int64_t n);
+// In-place Cholesky A = L L^T (lower triangle of A, lda), blocks of 64; the
+// inverse of each diagonal block of L goes to inv; W: n x 64 scratch.
+// A pivot that is not > 0 sets info[4] (A is then not positive definite and
+// its contents are unspecified).
+hipError_t chol_factor_launch(int dtype, int64_t n, void* A, int64_t lda, void* inv, void* W,
+                              int32_t* info, hipStream_t s);
+// Inverses of the 64 x 64 diagonal blocks of a triangular S (lower or upper,
+// non-unit) into inv; a zero diagonal entry sets info[6].
+hipError_t trinv_launch(int dtype, bool lower, int64_t n, const void* S, int64_t lds, void* inv,
+                        int32_t* info, hipStream_t s);
+// Block substitution with the inverse diagonal blocks in inv:
+//   which 0: L L^T X = B (L: the lower triangle of M), which 1: L X = B,
+//   which 2: U X = B (U: the upper triangle of M).
+// B (ldb) holds the right-hand sides and is overwritten; Y: n x nrhs
+// scratch (ld n); X (ldx) receives the solution and must not alias B or Y.
+hipError_t tri_solve_launch(int dtype, int which, int64_t n, int64_t nrhs, const void* M,
+                            int64_t ldm, const void* inv, void* B, int64_t ldb, void* Y,
+                            void* X, int64_t ldx, hipStream_t s);
+// Tridiagonal part of S with partial pivoting; X (ldx) holds the right-hand
+// sides and receives the solution; coef: 3 n scratch; a zero pivot sets
+// info[5].
+hipError_t gtsv_launch(int dtype, int64_t n, int64_t nrhs, const void* S, int64_t lds, void* X,
+                       int64_t ldx, void* coef, int32_t* info, hipStream_t s);
+
 // ---------------------------------------------------------------------- LU
 // In-place LU with partial pivoting of the n x n column-major matrix A (lda),
 // A = P^T L U. rowid (n ints) receives the original row held at each final

@@ -402,15 +402,16 @@ class Planner {
     if (is_ew_binary(x.op))
       return emit_ew(build_ew(n, t), dest, t ? x.cols : x.rows, t ? x.rows : x.cols);
     if (x.op == HEXLA_OP_SOLVE) {
+      const bool spd = gram_product(x.a);
       View s = dense(materialize(x.a, false, nullptr));
       View b = dense(materialize(x.b, false, nullptr));
       if (!t) {
         View xo = dest ? *dest : temp(s.cols, b.cols);
-        solve(s, b, xo);
+        solve(s, b, xo, spd);
         return xo;
       }
       View xo = temp(s.cols, b.cols);
-      solve(s, b, xo);
+      solve(s, b, xo, spd);
       View tv = transposed(xo);
       if (!dest) return tv;
       return emit_ew(add_view(tv), dest, tv.rows, tv.cols);
@@ -1107,7 +1108,7 @@ class Planner {
       if (status_ != HEXLA_OK) return View{};
       const bool direct = p == 0 && dest && !epi;
       View xo = direct ? *dest : temp(s.cols, rhs.cols);
-      solve(s, rhs, xo);
+      solve(s, dense(rhs), xo, gram_product(f[p].node));
       f.resize(p);
       Factor q;
       q.kind = 0;
@@ -1545,15 +1546,61 @@ class Planner {
     steps_.push_back(q);
   }
 
-  void solve(const View& s, const View& b, const View& x) {
+  // A product X X^T or X^T X of one stored matrix (the symmetric rank-k
+  // update of Sec. II) with a positive scale: symmetric positive
+  // semidefinite by construction (definite when X has full rank).
+  bool gram_product(uint32_t n) const {
+    if (!o_.syrk) return false;
+    const Node& x = N(n);
+    if (x.scalar || x.kind != NK_BINARY || x.op != HEXLA_OP_TIMES) return false;
+    std::vector<Factor> f;
+    double alpha = 1.0;
+    flatten(n, false, f, alpha);
+    return f.size() == 2 && f[0].kind == 0 && f[1].kind == 0 && alpha > 0.0 &&
+           same_storage(f[0].v, f[1].v) && f[0].v.trans != f[1].v.trans;
+  }
+
+  void solve(const View& s, const View& b, const View& x, bool spd = false) {
     if (s.rows > k::kLuMaxN)
       return (void)fail(HEXLA_E_UNSUPPORTED,
                         "solve: n > " + std::to_string(k::kLuMaxN) + " is not supported");
     if (dtype_ == HEXLA_F64 && o_.solve_precision != HEXLA_SOLVE_PLAIN) return refined_solve(s, b, x);
     const int64_t n = s.rows, r = b.cols;
+    if (b.trans || x.trans) {
+      fail(HEXLA_E_UNSUPPORTED, "internal: transposed solve operand");
+      return;
+    }
     View lu = temp(n, n);
     EwHost copy;
     if (!compile(add_view(s), copy, false)) return;
+    if (o_.solve_structure == 0 && o_.planner != HEXLA_PLANNER_NAIVE) {
+      // the solver is chosen when the plan runs, from the matrix itself
+      Step q;
+      q.kind = StepKind::StructSolve;
+      q.dtype = dtype_;
+      q.name = spd ? "solve_spd" : "solve_structured";
+      q.A = s;
+      q.out = lu;
+      q.ew = copy;
+      q.B = b;
+      q.C = x;
+      q.n = n;
+      q.nrhs = r;
+      q.spd_known = spd;
+      q.rowid = work(n * 4);
+      q.luwork = work(int64_t(k::lu_workspace_bytes(dtype_, n, r)));
+      q.inv = work(int64_t(k::struct_inv_bytes(dtype_, n)));
+      q.ybuf = work(n * r * int64_t(esz_));
+      q.coef = work(3 * n * int64_t(esz_));
+      q.partial = work(n * 64 * int64_t(esz_));
+      q.info = work(8 * 4);
+      // the general case's work (LU and substitution); the structured
+      // solvers do less
+      q.flops = 2.0 / 3.0 * double(n) * n * n + 2.0 * double(n) * n * r;
+      q.bytes = double(esz_) * (3.0 * double(n) * n + 2.0 * double(n) * r);
+      steps_.push_back(q);
+      return;
+    }
     push_ew(copy, lu);
     Step f;
     f.kind = StepKind::LuFactor;
@@ -1579,10 +1626,6 @@ class Planner {
     q.luwork = f.luwork;  // the inverses of the diagonal blocks
     q.flops = 2.0 * double(n) * n * r;
     q.bytes = double(esz_) * (double(n) * n + 2.0 * double(n) * r);
-    if (b.trans || x.trans) {
-      fail(HEXLA_E_UNSUPPORTED, "internal: transposed solve operand");
-      return;
-    }
     steps_.push_back(q);
   }
 

@@ -177,6 +177,10 @@ hexla_status hexla_plan_capture(hexla_plan* plan, void* out, int64_t ld_out, voi
   for (const Step& s : plan->steps)
     if (s.kind == StepKind::IrSolve)
       return set_err(ctx, HEXLA_E_UNSUPPORTED, "capture: a refined solve reads status on the host");
+    else if (s.kind == StepKind::StructSolve)
+      return set_err(ctx, HEXLA_E_UNSUPPORTED,
+                     "capture: a structure-aware solve reads the matrix's structure on the host "
+                     "(plan with solve_structure = 1 to capture an LU solve)");
   hipError_t e = enter_device(ctx->device);
   hipStream_t cs = nullptr;  // capture needs a stream other than the null stream
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);

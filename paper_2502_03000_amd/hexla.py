@@ -30,6 +30,8 @@ OP_TIMES, OP_PLUS, OP_MINUS, OP_SCHUR, OP_DIV, OP_SOLVE = 16, 17, 18, 19, 20, 21
 PLANNERS = {"dp": 0, "greedy": 1, "naive": 2, "learned": 3, "roofline": 4}
 PRODUCT_PRECISION = {"plain": 0, "bf16x3": 1, "bf16x6": 2}
 SOLVE_PRECISION = {"plain": 0, "ir_fp32": 1, "ir_fp16": 2, "ir_bf16x3": 3}
+SOLVE_STRUCTURE = {"auto": 0, "general": 1}
+SOLVERS = {0: "lu", 1: "cholesky", 2: "lower", 3: "upper", 4: "tridiagonal", 5: "diagonal"}
 
 
 class HexlaError(RuntimeError):
@@ -43,7 +45,8 @@ class PlanOpts(C.Structure):
     _fields_ = [("planner", C.c_int32), ("product_precision", C.c_int32),
                 ("solve_precision", C.c_int32), ("fuse", C.c_int32), ("syrk", C.c_int32),
                 ("ir_max_iter", C.c_int32), ("ir_tol_scale", C.c_double),
-                ("codegen", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("solve_structure", C.c_int32), ("codegen", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
 
 
 class PlanInfo(C.Structure):
@@ -66,7 +69,8 @@ class TrainOpts(C.Structure):
 
 class Report(C.Structure):
     _fields_ = [("status", C.c_int32), ("ir_iterations", C.c_int32),
-                ("singular_column", C.c_int64), ("ir_backward_error", C.c_double)]
+                ("singular_column", C.c_int64), ("ir_backward_error", C.c_double),
+                ("solver", C.c_int32), ("reserved", C.c_int32)]
 
 
 def _load():
@@ -604,7 +608,8 @@ class Context:
 
     # ------------------------------------------------------------- planning
     def plan(self, root, planner="dp", product_precision="plain", solve_precision="plain",
-             fuse=True, syrk=True, ir_max_iter=30, ir_tol_scale=0.0, codegen=True) -> Plan:
+             fuse=True, syrk=True, ir_max_iter=30, ir_tol_scale=0.0, codegen=True,
+             solve_structure="auto") -> Plan:
         o = PlanOpts()
         lib.hexla_plan_opts_default(C.byref(o))
         o.planner = PLANNERS[planner]
@@ -615,6 +620,7 @@ class Context:
         o.ir_max_iter = ir_max_iter
         o.ir_tol_scale = ir_tol_scale
         o.codegen = 1 if codegen else 0
+        o.solve_structure = SOLVE_STRUCTURE[solve_structure]
         h = C.c_void_p()
         self._check(lib.hexla_plan_create(self.handle, root.node, C.byref(o), C.byref(h)))
         return Plan(self, h.value, keep=self._keep)

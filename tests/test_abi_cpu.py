@@ -108,16 +108,31 @@ def test_symmetric_product_detected_by_identity(ctx):
 
 def test_inverse_times_matrix_becomes_solve(ctx):
     s, b = leaf(ctx, 50, 50), leaf(ctx, 50, 3)
-    k = kernels(ctx.plan(hx.inv(s) @ b))
+    # by default the solver is chosen from the matrix when the plan runs
+    assert kernels(ctx.plan(hx.inv(s) @ b)) == ["solve_structured"]
+    k = kernels(ctx.plan(hx.inv(s) @ b, solve_structure="general"))
     assert "lu_factor" in k and "lu_solve" in k
     assert k.count("elementwise") == 1  # the working copy of S only
     naive = kernels(ctx.plan(hx.inv(s) @ b, planner="naive"))
     assert naive.count("elementwise") == 2  # copy of S and the identity
     assert naive[-1] == "gemm"
-    p1 = ctx.plan(hx.inv(s) @ b)
-    p2 = ctx.plan(hx.solve(s, b))
-    assert kernels(p1) == kernels(p2)
-    assert p1.info.flops == pytest.approx(2 / 3 * 50 ** 3 + 2 * 50 ** 2 * 3)
+    for opt in ("auto", "general"):
+        p1 = ctx.plan(hx.inv(s) @ b, solve_structure=opt)
+        p2 = ctx.plan(hx.solve(s, b), solve_structure=opt)
+        assert kernels(p1) == kernels(p2)
+        assert p1.info.flops == pytest.approx(2 / 3 * 50 ** 3 + 2 * 50 ** 2 * 3)
+
+
+def test_solve_of_gram_product_plans_cholesky(ctx):
+    """solve(A*A.t(), b), the call trace of Sec. IV: the symmetric product
+    runs as SYRK and the planner knows the system is positive
+    (semi)definite."""
+    a, b = leaf(ctx, 300, 40), leaf(ctx, 300, 2)
+    k = kernels(ctx.plan(hx.solve(a @ hx.trans(a), b)))
+    assert k == ["syrk", "solve_spd"]
+    c = leaf(ctx, 40, 300)
+    assert kernels(ctx.plan(hx.solve(a @ c, b))) == ["gemm", "solve_structured"]
+    assert kernels(ctx.plan(hx.inv(hx.trans(c) @ c) @ b)) == ["syrk", "solve_spd"]
 
 
 def test_elementwise_fusion(ctx):
