@@ -6,9 +6,12 @@ Workload (one step): the FP32-at-scale pair of expressions
   job 2  0.5*exp(-(A%A)) + B/C over 16384 x 16384, A,B ~ N(0,1), C ~ U[1,2]
          (one fused element-wise pass)
 Inputs are generated once, resident in HBM before timing. The value is the
-whole step's algorithmic GFLOP/s. Prints one JSON line.
+whole step's algorithmic GFLOP/s; the same step in plain FP64 gives the
+speedup of the chosen form, and every other configuration (the small FP64
+expression, the symmetric product and solve forms, the batched form, the
+learned planner) is summarized under "jobs". Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--quick]
 """
 from __future__ import annotations
 
@@ -40,16 +43,19 @@ def parse():
     ap.add_argument("--chains", type=int, default=2000, help="random chains (learned workload)")
     ap.add_argument("--sweep", type=int, default=600, help="training shapes (learned workload)")
     ap.add_argument("--workload", default="expr",
-                    choices=["expr", "syrk", "solve", "batched", "learned"],
-                    help="expr: the FP32 chain + fused element-wise step (default); "
-                         "syrk: trans(X)*X, X 65536x2048, plain FP64/FP32 vs split-BF16")
+                    choices=["expr", "small", "syrk", "solve", "batched", "learned", "diag",
+                             "struct"],
+                    help="expr: the FP32 chain + fused element-wise step, its plain-FP64 "
+                         "leg and a summary of every other configuration (default); the "
+                         "others print that configuration's own line")
+    ap.add_argument("--quick", action="store_true",
+                    help="expr workload: the FP32 step alone (no FP64 leg, no other jobs)")
+    ap.add_argument("--reps", type=int, default=100, help="runs per median")
+    ap.add_argument("--overlap", action="store_true",
+                    help="expr workload: the chain's launches on a second stream beside the "
+                         "element-wise pass")
     ap.add_argument("--forms", default="", help="comma-separated subset of forms (syrk, solve)")
     ap.add_argument("--no-tune", action="store_true", help="skip product autotuning")
-    ap.add_argument("--serial", action="store_true",
-                    help="expr workload, eager: both jobs on one stream, one after the other")
-    ap.add_argument("--launch", default="eager", choices=["eager", "graph"],
-                    help="expr workload: launch each plan's kernels on the stream (eager, the "
-                         "default: the host queues ahead of the GPU) or replay a HIP graph of them")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -177,7 +183,7 @@ def bench_syrk(args, ctx, hx, torch, inputs):
         "fp64_frac_of_peak": by["fp64"]["tflops_algorithmic"] / FP64_PEAK_TFLOPS,
         "forms": forms,
     }
-    print(json.dumps(res), flush=True)
+    return res
 
 
 def bench_solve(args, ctx, hx, torch, inputs):
@@ -215,8 +221,7 @@ def bench_solve(args, ctx, hx, torch, inputs):
         del p, out, ws
     by = {f["form"]: f for f in forms}
     if "plain" not in by:
-        print(json.dumps({"forms": forms}), flush=True)
-        return
+        return {"forms": forms}
     best = min((f for f in forms if f["form"] != "plain" and f["rel_err_vs_closed_form"] <= 1e-12),
                key=lambda f: f["ms"], default=by["plain"])
     res = {
@@ -233,7 +238,7 @@ def bench_solve(args, ctx, hx, torch, inputs):
         "speedup_vs_plain_fp64": by["plain"]["ms"] / best["ms"],
         "forms": forms,
     }
-    print(json.dumps(res), flush=True)
+    return res
 
 
 def bench_learned(args, ctx, hx, torch, inputs):
@@ -305,36 +310,62 @@ def bench_learned(args, ctx, hx, torch, inputs):
         return e0.elapsed_time(e1) / reps, out
 
     rows = []
-    t_dp = t_ln = fl_dp = fl_ln = 0.0
+    fl = {"dp": 0.0, "learned": 0.0, "roofline": 0.0}
     n_learned = 0
     sample = set(inputs.rng(12).choice(len(chains), 8, replace=False).tolist())
     err = 0.0
     t1 = time.perf_counter()
     for i, dims in enumerate(chains):
-        pd = build(dims, "dp")
-        a, _ = timed(pd)
-        pl = build(dims, "learned")
-        b, out = timed(pl)
-        note = pl.describe()["learned"][0]
-        n_learned += note["chosen"] == "learned"
-        t_dp += a
-        t_ln += b
-        fl_dp += pd.info.flops
-        fl_ln += pl.info.flops
-        if i in sample:  # rows of the product against FP64 row-vector products
-            got = out.cpu().numpy().astype(np.float64)
-            mats, off = [], 0
-            for r, c in zip(dims[:-1], dims[1:]):
-                mats.append(pool[off:off + r * c].view(c, r).t().cpu().numpy().astype(np.float64))
-                off += r * c
-            for rr in inputs.rng(i).integers(0, dims[0], 2):
-                v = mats[0][rr:rr + 1]
-                for m in mats[1:]:
-                    v = v @ m
-                err = max(err, float(np.linalg.norm(got[rr] - v[0]) / np.linalg.norm(v[0])))
+        row = {}
+        for planner in ("dp", "learned", "roofline"):
+            torch.cuda.synchronize()
+            tp = time.perf_counter()
+            pl = build(dims, planner)
+            plan_ms = (time.perf_counter() - tp) * 1e3
+            ex_ms, out = timed(pl)
+            row[planner] = (plan_ms, ex_ms)
+            fl[planner] += pl.info.flops
+            if planner == "learned":
+                n_learned += pl.describe()["learned"][0]["chosen"] == "learned"
+                if i in sample:  # rows of the product against FP64 row-vector products
+                    got = out.cpu().numpy().astype(np.float64)
+                    mats, off = [], 0
+                    for r, c in zip(dims[:-1], dims[1:]):
+                        mats.append(pool[off:off + r * c].view(c, r).t().cpu().numpy().astype(np.float64))
+                        off += r * c
+                    for rr in inputs.rng(i).integers(0, dims[0], 2):
+                        v = mats[0][rr:rr + 1]
+                        for m in mats[1:]:
+                            v = v @ m
+                        err = max(err, float(np.linalg.norm(got[rr] - v[0]) / np.linalg.norm(v[0])))
+            del pl, out
+        rows.append(row)
         ctx.clear()
-        del pd, pl, out
     eval_s = time.perf_counter() - t1
+
+    def stats(name):
+        plan = np.array([r[name][0] for r in rows])
+        ex = np.array([r[name][1] for r in rows])
+        return plan, ex
+
+    pd_, ed = stats("dp")
+    summary = {}
+    for name in ("dp", "learned", "roofline"):
+        pp, ee = stats(name)
+        summary[name] = {"plan_ms_total": float(pp.sum()), "exec_ms_total": float(ee.sum()),
+                         "end_to_end_ms_total": float((pp + ee).sum()), "gflop": fl[name] / 1e9}
+        if name != "dp":
+            summary[name].update({
+                "exec_geomean_speedup_vs_dp": float(np.exp(np.mean(np.log(ed / ee)))),
+                "exec_win_rate_vs_dp": float(np.mean(ee < ed)),
+                "exec_speedup_total_vs_dp": float(ed.sum() / ee.sum()),
+                "end_to_end_geomean_speedup_vs_dp": float(np.exp(np.mean(np.log((pd_ + ed) / (pp + ee))))),
+                "end_to_end_win_rate_vs_dp": float(np.mean(pp + ee < pd_ + ed)),
+                "end_to_end_speedup_total_vs_dp": float((pd_ + ed).sum() / (pp + ee).sum())})
+    summary["learned"]["chains_learned_order"] = n_learned
+    t_ln = summary["learned"]["exec_ms_total"]
+    t_dp = summary["dp"]["exec_ms_total"]
+    fl_ln = fl["learned"]
     tflops = fl_ln / (t_ln * 1e-3) / 1e12
     res = {
         "metric": METRIC, "value": fl_ln / (t_ln * 1e-3) / 1e9, "unit": "GFLOP/s",
@@ -342,15 +373,17 @@ def bench_learned(args, ctx, hx, torch, inputs):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded)",
         "config": {"workload": f"{len(chains)} random FP32 chains, length 3-8, dims log-uniform "
-                               "in [16, 8192], N(0,1); learned planner vs FLOP DP",
+                               "in [16, 8192], N(0,1); learned planner vs FLOP DP vs roofline DP",
                    "training_records": len(recs), "training_loss_std_mse": loss,
-                   "sweep_s": sweep_s, "train_s": train_s, "eval_s": eval_s},
+                   "sweep_s": sweep_s, "train_s": train_s, "eval_s": eval_s,
+                   "timing": "execution: graph replay, mean of 3; planning: host wall time of "
+                             "hexla_plan_create (the learned planner's inference launch and its "
+                             "wait included); end to end: planning + one execution"},
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": FP32_MFMA_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / FP32_MFMA_PEAK_TFLOPS, "traffic": None,
                      "note": "all products of all chains, learned plans"},
         "speedup_vs_dp": t_dp / t_ln,
-        "dp": {"total_ms": t_dp, "gflop": fl_dp / 1e9},
-        "learned": {"total_ms": t_ln, "gflop": fl_ln / 1e9, "chains_learned_order": n_learned},
+        "dp": summary["dp"], "learned": summary["learned"], "roofline_planner": summary["roofline"],
         "max_rel_err_sampled_rows": err,
     }
     if not args.no_cpu_baseline:  # the oracle on whole chains, in order, for about 10 s
@@ -372,7 +405,7 @@ def bench_learned(args, ctx, hx, torch, inputs):
                                "kind": "oracle",
                                "sample": f"the first {done} of the {len(chains)} chains, in the "
                                          f"oracle's cheapest order ({el:.1f} s, float64 numpy)"}
-    print(json.dumps(res), flush=True)
+    return res
 
 
 def _threads():
@@ -538,7 +571,296 @@ def bench_batched(args, ctx, hx, torch, inputs):
                                "kind": "oracle",
                                "sample": f"{done} random instances of the {args.count} "
                                          f"({el:.1f} s, float64 numpy)"}
-    print(json.dumps(res), flush=True)
+    return res
+
+
+def bench_diag(args, ctx, hx, torch, inputs):
+    """The diagonal rewrites of expressions (3)-(5), (7) and the view of
+    expression (2) at sizes where HBM decides, each against the naive
+    evaluation (full product / dense diagonal matrix / temporaries): FP64,
+    n = 8192 (A, B 8192^2 N(0,1); vectors of 2^25 for expression (7))."""
+    import oracle
+    n = 8192
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1006)
+    a = torch.randn((n, n), generator=gen, device="cuda", dtype=torch.float64).t()
+    b = torch.randn((n, n), generator=gen, device="cuda", dtype=torch.float64).t()
+    nv = 1 << 25
+    x, w, y = (torch.randn(nv, generator=gen, device="cuda", dtype=torch.float64) for _ in range(3))
+    ea, eb = ctx.leaf(a), ctx.leaf(b)
+    ex, ew_, ey = ctx.leaf(x), ctx.leaf(w), ctx.leaf(y)
+    cases = [
+        ("diag(A*B)", hx.diag(ea @ eb), 2.0 * n * n * 8),
+        ("trace(A*B)", hx.trace(ea @ eb), 2.0 * n * n * 8),
+        ("diagmat(A*B)", hx.diagmat(ea @ eb), (2.0 * n * n + n * n) * 8),
+        ("diagmat(A)*B", hx.diagmat(ea) @ eb, (n + 2.0 * n * n) * 8),
+        ("trans(x)*diagmat(w)*y", hx.trans(ex) @ hx.diagmat(ew_) @ ey, 3.0 * nv * 8),
+        ("A(:,1) + B(2,:)^T", ea.col(0) + hx.trans(eb.row(1)), 3.0 * n * 8),
+    ]
+    ah = b_h = None
+    forms = []
+    reps = max(args.reps // 4, 10)
+    for text, e, nbytes in cases:
+        row = {"expression": text, "algorithmic_bytes": nbytes}
+        for planner in ("dp", "naive"):
+            if planner == "naive" and text.startswith("trans(x)"):
+                continue  # the naive form builds a 2^25 x 2^25 diagonal matrix
+            p = ctx.plan(e, planner=planner)
+            o, ws = p.output(), p.workspace()
+            run = lambda: p.execute(o, ws)  # noqa: E731
+            run()
+            ctx.sync()
+            ms = median_ms(torch, run, reps)
+            row[planner] = {"ms": ms, "kernels": [st["kernel"] for st in p.describe()["steps"]]}
+            if planner == "dp":
+                row["gbs"] = nbytes / (ms * 1e-3) / 1e9
+                row["frac_hbm"] = row["gbs"] / HBM_PEAK_GBS
+                out_dp = o
+            del p, ws
+        if "naive" in row:
+            row["speedup_vs_naive"] = row["naive"]["ms"] / row["dp"]["ms"]
+        # error against the FP64 oracle on a slice the oracle computes exactly
+        g = inputs.rng(7)
+        if text in ("diag(A*B)", "trace(A*B)", "diagmat(A*B)"):
+            if ah is None:
+                ah, b_h = a.cpu().numpy(), b.cpu().numpy()
+            idx = np.sort(g.choice(n, 16, replace=False))
+            ref = np.array([ah[i, :] @ b_h[:, i] for i in idx])
+            if text == "trace(A*B)":
+                ref_t = oracle.evaluate("trace(A*B)", {"A": ah, "B": b_h})[0, 0]
+                got = out_dp.cpu().numpy()[0, 0]
+                row["rel_err_vs_fp64"] = abs(got - ref_t) / abs(ref_t)
+            else:
+                d = out_dp.cpu().numpy()
+                got = d[idx, 0] if text == "diag(A*B)" else d[idx, idx]
+                row["rel_err_vs_fp64"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        forms.append(row)
+        del out_dp
+    best = forms[0]
+    return {"metric": METRIC, "value": best["gbs"], "unit": "GB/s", "ms_per_step": best["dp"]["ms"],
+            "dtype": "f64",
+            "config": {"workload": f"diagonal rewrites and views, FP64, n = {n}"},
+            "roofline": {"bound": "hbm", "achieved": best["gbs"], "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": best["gbs"] / HBM_PEAK_GBS,
+                         "kernel": "diag_product of diag(A*B)"},
+            "forms": forms}
+
+
+def bench_struct(args, ctx, hx, torch, inputs):
+    """Structure-aware solves at n = 8192, B 8192 x 64, FP64: each matrix
+    solved with the structure analysis (auto) and with the general LU
+    (general); backward error ||B - S X|| / (||S|| ||X||) of each."""
+    n, r = 8192, 64
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1007)
+    g = torch.randn((n, n), generator=gen, device="cuda", dtype=torch.float64)
+    mats = {
+        "spd": (g @ g.t() / n + torch.eye(n, device="cuda", dtype=torch.float64)),
+        "lower": torch.tril(g / n ** 0.5) + 2.0 * torch.eye(n, device="cuda", dtype=torch.float64),
+        "tridiagonal": (torch.diag(torch.rand(n, generator=gen, device="cuda", dtype=torch.float64) * 0.6 - 0.3)
+                        + torch.diag(1.0 + 0.2 * torch.randn(n - 1, generator=gen, device="cuda",
+                                                              dtype=torch.float64), -1)
+                        + torch.diag(-1.0 + 0.2 * torch.randn(n - 1, generator=gen, device="cuda",
+                                                               dtype=torch.float64), 1)),
+    }
+    del g
+    bmat = torch.randn((r, n), generator=gen, device="cuda", dtype=torch.float64).t()
+    forms = []
+    for kind, m in mats.items():
+        s_dev = m.t().contiguous().t()  # column-major
+        es, eb = ctx.leaf(s_dev), ctx.leaf(bmat)
+        row = {"matrix": kind}
+        for opt in ("auto", "general"):
+            p = ctx.plan(hx.solve(es, eb), solve_structure=opt)
+            o, ws = p.output(), p.workspace()
+            p.execute(o, ws)
+            rep = ctx.sync()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                p.execute(o, ws)
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t0) * 1e3)
+            rep = ctx.sync()
+            res_ = bmat - s_dev @ o
+            berr = float(torch.linalg.norm(res_) / (torch.linalg.norm(s_dev) * torch.linalg.norm(o)))
+            row[opt] = {"ms": float(np.median(ts)), "status": int(rep.status),
+                        "solver": hx.SOLVERS.get(int(rep.solver), "lu"), "backward_error": berr}
+            del p, o, ws
+        row["speedup_vs_lu"] = row["general"]["ms"] / row["auto"]["ms"]
+        forms.append(row)
+        ctx.clear()
+    spd = forms[0]
+    flops = n ** 3 / 3.0 + 2.0 * n * n * r
+    return {"metric": METRIC, "value": flops / (spd["auto"]["ms"] * 1e-3) / 1e9, "unit": "GFLOP/s",
+            "ms_per_step": spd["auto"]["ms"], "dtype": "f64",
+            "config": {"workload": f"structure-aware solve(S,B), S {n}x{n} (spd, lower, "
+                                   f"tridiagonal), B {n}x{r}, FP64"},
+            "roofline": {"bound": "mfma", "achieved": flops / (spd["auto"]["ms"] * 1e-3) / 1e12,
+                         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": flops / (spd["auto"]["ms"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                         "kernel": "whole Cholesky solve, n^3/3 + 2 n^2 nrhs flops"},
+            "forms": forms}
+
+
+def median_ms(torch, fn, reps, stream=None):
+    """Median over reps of one call of fn, each bracketed by HIP events on
+    the launch stream (a GPU-side spin first, so that the events see kernel
+    time, not the host's launch rate)."""
+    st = stream or torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda._sleep(200_000)
+        ev0.record(st)
+        fn()
+        ev1.record(st)
+        ev1.synchronize()
+        ts.append(ev0.elapsed_time(ev1))
+    return float(np.median(ts))
+
+
+def cold_ms(torch, fn, flush):
+    """One call of fn right after 512 MB of unrelated writes (the caches hold
+    none of its operands)."""
+    flush.add_(1.0)
+    return median_ms(torch, fn, 1)
+
+
+def host_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+def expr_jobs(args, ctx, hx, torch, inputs, dt, tune=True):
+    """The two jobs of the FP32-at-scale workload in storage type dt (FP32,
+    or FP64 for the plain-FP64 leg): plans, per-job median and cold times,
+    sampled errors against the FP64 oracle."""
+    import oracle
+    dev = "cuda:0"
+    chain_np = inputs.fp32_chain(seed=1001)
+    chain_t = [torch.from_numpy(np.ascontiguousarray(m.T)).to(dev).to(dt).t() for m in chain_np]
+    ew = inputs.fp32_elementwise_device(seed=1001, n=args.n, device=dev)
+    if dt != torch.float32:
+        ew = {k: v.t().contiguous().to(dt).t() for k, v in ew.items()}
+    torch.cuda.synchronize()
+    e1 = None
+    for t in chain_t:
+        x = ctx.leaf(t)
+        e1 = x if e1 is None else e1 @ x
+    t0 = time.perf_counter()
+    p1 = ctx.plan(e1)
+    A, B, Cm = (ctx.leaf(ew[k]) for k in ("A", "B", "C"))
+    p2 = ctx.plan(0.5 * hx.exp(-(A % A)) + B / Cm)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    out1, out2 = p1.output(dev), p2.output(dev)
+    ws1, ws2 = p1.workspace(dev), p2.workspace(dev)
+    if tune and not args.no_tune:
+        p1.autotune(out1, ws1)
+    run1 = lambda: p1.execute(out1, ws1)  # noqa: E731
+    run2 = lambda: p2.execute(out2, ws2)  # noqa: E731
+    for _ in range(3):
+        run1()
+        run2()
+    if ctx.sync().status != hx.OK:
+        raise SystemExit("deferred error in the expression jobs")
+    reps = max(args.reps, 1)
+    flush = torch.empty(1 << 27, dtype=torch.float32, device=dev)
+    ms_chain, ms_ew = median_ms(torch, run1, reps), median_ms(torch, run2, reps)
+    cold_chain, cold_ew = cold_ms(torch, run1, flush), cold_ms(torch, run2, flush)
+    del flush
+    # sampled parity against the FP64 oracle: rows of the chain, columns of job 2
+    g = inputs.rng(99)
+    rows = sorted(set([0, chain_np[0].shape[0] - 1] + g.integers(0, chain_np[0].shape[0], 6).tolist()))
+    names = [f"M{i}" for i in range(len(chain_np))]
+    env = dict(zip(names, chain_np), M0=np.asfortranarray(chain_np[0][rows, :]))
+    ref = oracle.evaluate("*".join(names), env)
+    got = out1.cpu().numpy().astype(np.float64)[rows]
+    err_chain = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    cols = sorted(set([0, args.n - 1] + g.integers(0, args.n, 6).tolist()))
+    idx = torch.tensor(cols, device=dev)
+    sub = {k: v.index_select(1, idx).cpu().numpy().astype(np.float64) for k, v in ew.items()}
+    ref = oracle.evaluate("0.5*exp(-(A%A)) + B/C", sub)
+    got = out2.index_select(1, idx).cpu().numpy().astype(np.float64)
+    err_ew = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    d1, d2 = p1.describe(), p2.describe()
+    res = {"p1": p1, "p2": p2, "run1": run1, "run2": run2, "d1": d1, "d2": d2,
+           "chain_np": chain_np, "ew": ew, "plan_ms": plan_ms,
+           "chain": {"ms_median": ms_chain, "ms_cold": cold_chain, "gflop": p1.info.flops / 1e9,
+                     "tflops": p1.info.flops / (ms_chain * 1e-3) / 1e12,
+                     "kernels": [f"{s['kernel']} {s['m']}x{s['n']}x{s['k']} tile{s.get('tile')} "
+                                 f"split{s.get('split', 1)}" for s in d1["steps"]],
+                     "rel_err_vs_fp64_sampled_rows": err_chain},
+           "elementwise": {"ms_median": ms_ew, "ms_cold": cold_ew, "gbytes": d2["bytes"] / 1e9,
+                           "gbs": d2["bytes"] / (ms_ew * 1e-3) / 1e9,
+                           "rel_err_vs_fp64_sampled_cols": err_ew}}
+    return res
+
+
+def summarize(job, key_ms="ms_per_step"):
+    """The few figures of a workload's own line that its job entry keeps."""
+    out = {k: job[k] for k in ("value", "unit", key_ms) if k in job}
+    for k in ("speedup_vs_plain_fp64", "speedup_vs_dp", "dtype"):
+        if k in job:
+            out[k] = job[k]
+    if "roofline" in job:
+        out["roofline"] = {k: job["roofline"][k] for k in ("bound", "achieved", "peak", "unit", "frac")}
+    out["workload"] = job.get("config", {}).get("workload")
+    for k in ("forms", "dp", "learned", "roofline_planner", "end_to_end"):
+        if k in job:
+            out[k] = job[k]
+    return out
+
+
+def bench_small(args, ctx, hx, torch, inputs):
+    """The plain FP64 expression trans(A)*B*C*v + 0.5*(d % e) at its own size:
+    planned into three matrix-vector products with the element-wise part as
+    the last one's epilogue. Its work is 3.85 MB and 0.96 MFLOP, so launch
+    latency decides its time: the median of eager executions (three queued
+    launches), of graph replays, and of the left-to-right (naive) plan."""
+    import oracle
+    env = inputs.small_chain_expr(1000)
+    t = {k: torch.from_numpy(np.ascontiguousarray(v.T)).cuda().t() for k, v in env.items()}
+    L = {k: ctx.leaf(v) for k, v in t.items()}
+    y = hx.trans(L["A"]) @ L["B"] @ L["C"] @ L["v"] + 0.5 * (L["d"] % L["e"])
+    ref = oracle.evaluate(inputs.SMALL_CHAIN_EXPR, env)
+    out = {}
+    for planner in ("dp", "naive"):
+        p = ctx.plan(y, planner=planner)
+        o, ws = p.output(), p.workspace()
+        run = lambda: p.execute(o, ws)  # noqa: E731
+        run()
+        ctx.sync()
+        ms = median_ms(torch, run, max(args.reps, 100))
+        p.capture(o, ws)
+        ms_graph = median_ms(torch, p.replay, max(args.reps, 100))
+        err = float(np.linalg.norm(o.cpu().numpy() - ref) / np.linalg.norm(ref))
+        d = p.describe()
+        out[planner] = {"ms_eager": ms, "ms_graph": ms_graph, "launches": len(d["steps"]),
+                        "gflop": d["flops"] / 1e9, "mbytes": d["bytes"] / 1e6,
+                        "gbs_eager": d["bytes"] / (ms * 1e-3) / 1e9,
+                        "rel_err_vs_fp64": err, "kernels": [s["kernel"] for s in d["steps"]]}
+        del p, o, ws
+    dp = out["dp"]
+    ideal_us = out["dp"]["mbytes"] * 1e6 / (HBM_PEAK_GBS * 1e9) * 1e6
+    return {"metric": METRIC, "value": out["dp"]["gflop"] / (dp["ms_eager"] * 1e-3),
+            "unit": "GFLOP/s", "ms_per_step": dp["ms_eager"], "dtype": "f64",
+            "config": {"workload": "trans(A)*B*C*v + 0.5*(d%e), FP64, A 400x300, B 400x600, "
+                                   "C 600x200, v 200x1, d,e 300x1"},
+            "roofline": {"bound": "hbm", "achieved": dp["gbs_eager"], "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": dp["gbs_eager"] / HBM_PEAK_GBS},
+            "ideal_us_at_hbm_peak": ideal_us,
+            "launch_overhead_us": dp["ms_eager"] * 1e3 - ideal_us,
+            "speedup_vs_naive_order": out["naive"]["ms_eager"] / dp["ms_eager"],
+            "forms": [dict(planner=k, **v) for k, v in out.items()]}
 
 
 def main():
@@ -555,58 +877,26 @@ def main():
     dev = "cuda:0"
     torch.cuda.set_device(0)
     ctx = hx.Context(0)
-    if args.workload == "syrk":
-        return bench_syrk(args, ctx, hx, torch, inputs)
-    if args.workload == "solve":
-        return bench_solve(args, ctx, hx, torch, inputs)
-    if args.workload == "batched":
-        return bench_batched(args, ctx, hx, torch, inputs)
-    if args.workload == "learned":
-        return bench_learned(args, ctx, hx, torch, inputs)
+    single = {"small": bench_small, "syrk": bench_syrk, "solve": bench_solve,
+              "batched": bench_batched, "learned": bench_learned, "diag": bench_diag,
+              "struct": bench_struct}
+    if args.workload in single:
+        print(json.dumps(single[args.workload](args, ctx, hx, torch, inputs)), flush=True)
+        return
 
-    # ---- inputs resident in HBM
-    chain_np = inputs.fp32_chain(seed=1001)
-    chain_t = [torch.from_numpy(np.ascontiguousarray(m.T)).to(dev).t() for m in chain_np]
-    ew = inputs.fp32_elementwise_device(seed=1001, n=args.n, device=dev)
-    torch.cuda.synchronize()
-
-    # ---- plans (host-side, once)
-    t0 = time.perf_counter()
-    e1 = None
-    for t in chain_t:
-        x = ctx.leaf(t)
-        e1 = x if e1 is None else e1 @ x
-    p1 = ctx.plan(e1)
-    A, B, Cm = (ctx.leaf(ew[k]) for k in ("A", "B", "C"))
-    p2 = ctx.plan(0.5 * hx.exp(-(A % A)) + B / Cm)
-    plan_ms = (time.perf_counter() - t0) * 1e3
-    out1, out2 = p1.output(dev), p2.output(dev)
-    ws1, ws2 = p1.workspace(dev), p2.workspace(dev)
-    if not args.no_tune:  # tile / split-K choice of the chain's products, measured
-        p1.autotune(out1, ws1)
-    d1, d2 = p1.describe(), p2.describe()
-    if args.launch == "eager":  # the host stays ahead: launches queue behind running work
-        def run1():
-            p1.execute(out1, ws1)
-
-        def run2():
-            p2.execute(out2, ws2)
-    else:  # each plan's launches recorded once into a HIP graph, then replayed
-        p1.capture(out1, ws1)
-        p2.capture(out2, ws2)
-        run1, run2 = p1.replay, p2.replay
-
-    main = torch.cuda.current_stream()
-    if args.launch == "eager" and not args.serial:
-        # the two jobs are independent plans: the chain's launches go to a
-        # second stream (default priority) so that the latency-bound products
-        # run beside the HBM-bound element-wise pass
+    # ---- the headline step: the FP32 chain job, then the element-wise job
+    j32 = expr_jobs(args, ctx, hx, torch, inputs, torch.float32)
+    run1, run2 = j32["run1"], j32["run2"]
+    main_stream = torch.cuda.current_stream()
+    if args.overlap:
+        # the two jobs are independent plans: the chain's launches on a second
+        # stream (default priority) beside the element-wise pass
         side = torch.cuda.Stream()
 
         def step():
             ctx.set_stream(side.cuda_stream)
             run1()
-            ctx.set_stream(main.cuda_stream)
+            ctx.set_stream(main_stream.cuda_stream)
             run2()
     else:
         def step():
@@ -634,53 +924,45 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed / args.steps * 1e3
+    p1, p2, d2 = j32["p1"], j32["p2"], j32["d2"]
     flops_step = p1.info.flops + p2.info.flops
+    chain_np, ew = j32["chain_np"], j32["ew"]
 
-    # ---- per-job kernel times with HIP events on the launch stream
-    stream = torch.cuda.current_stream()
-
-    def time_job(fn, reps):
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        # a GPU-side spin first, so that every launch is queued before ev0 and
-        # the events see kernel time, not the host's launch rate
-        torch.cuda._sleep(50_000_000)
-        ev0.record(stream)
-        for _ in range(reps):
-            fn()
-        ev1.record(stream)
-        ev1.synchronize()
-        return ev0.elapsed_time(ev1) / reps
-
-    reps = max(args.steps, 5)
-    ms_chain = time_job(run1, reps)
-    ms_ew = time_job(run2, reps)
-
-    # ---- sampled parity against the FP64 oracle (rows of the chain, elements of job 2)
-    import oracle
-    g = inputs.rng(99)
-    rows = g.integers(0, chain_np[0].shape[0], 8)
-    y1 = out1.cpu().numpy().astype(np.float64)
-    err_chain = 0.0
-    for i in rows:
-        v = chain_np[0][i:i + 1, :].astype(np.float64)
-        for m in chain_np[1:]:
-            v = v @ m.astype(np.float64)
-        err_chain = max(err_chain, np.linalg.norm(y1[i] - v[0]) / np.linalg.norm(v[0]))
-    cols = g.integers(0, args.n, 4)
-    err_ew = 0.0
-    for j in cols:
-        env = {k: ew[k][:, j:j + 1].cpu().numpy() for k in ("A", "B", "C")}
-        ref = oracle.evaluate("0.5*exp(-(A%A)) + B/C", env)
-        got = out2[:, j:j + 1].cpu().numpy().astype(np.float64)
-        err_ew = max(err_ew, np.linalg.norm(got - ref) / np.linalg.norm(ref))
-
-    ew_bytes = d2["bytes"]
-    ew_kernel = {"bound": "hbm", "achieved": ew_bytes / (ms_ew * 1e-3) / 1e9,
+    ew_ms = j32["elementwise"]["ms_median"]
+    ew_kernel = {"bound": "hbm", "achieved": d2["bytes"] / (ew_ms * 1e-3) / 1e9,
                  "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     ew_kernel["frac"] = ew_kernel["achieved"] / HBM_PEAK_GBS
     ew_kernel["traffic"] = profiled_traffic(d2["steps"][0].get("source_hash", "")) \
         if args.n == 16384 else None
-    chain_tflops = p1.info.flops / (ms_chain * 1e-3) / 1e12
+    ew_kernel["kernel"] = "generated element-wise pass, median of per-launch HIP event times"
+    chain32 = {k: v for k, v in j32["chain"].items()}
+    chain32["frac_fp32_mfma_peak"] = chain32["tflops"] / FP32_MFMA_PEAK_TFLOPS
+    jobs = {"chain_fp32": chain32, "elementwise_fp32": j32["elementwise"]}
+    cpu_inputs = None
+    if not args.no_cpu_baseline:
+        ncol = max(1, args.n // 2)
+        cpu_inputs = (chain_np, {k: ew[k][:, :ncol].cpu().numpy() for k in ("A", "B", "C")},
+                      d2["flops"] / float(args.n) ** 2)
+    del j32, run1, run2, step
+    p1 = p2 = None
+    ctx.clear()
+    torch.cuda.empty_cache()
+
+    # ---- the same workload in plain FP64 (the metric's comparison)
+    speedup = None
+    if not args.quick:
+        j64 = expr_jobs(args, ctx, hx, torch, inputs, torch.float64, tune=True)
+        ms64 = j64["chain"]["ms_median"] + j64["elementwise"]["ms_median"]
+        ms32 = jobs["chain_fp32"]["ms_median"] + jobs["elementwise_fp32"]["ms_median"]
+        speedup = ms64 / ms32
+        c64 = dict(j64["chain"])
+        c64["frac_fp64_mfma_peak"] = c64["tflops"] / FP64_PEAK_TFLOPS
+        jobs["chain_fp64"] = c64
+        jobs["elementwise_fp64"] = j64["elementwise"]
+        jobs["step_fp64_vs_fp32"] = {"ms_fp64": ms64, "ms_fp32": ms32, "speedup": speedup}
+        del j64
+        ctx.clear()
+        torch.cuda.empty_cache()
 
     res = {
         "metric": METRIC,
@@ -690,30 +972,37 @@ def main():
         "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic (seeded)",
-        "config": {"workload": "fp32 chain 8192x1024x8192x512x4096x64 (DP order) + fused "
+        "config": {"workload": "fp32 chain 8192x1024x8192x512x4096x64 (DP order) then fused "
                                f"0.5*exp(-(A%A))+B/C over {args.n}x{args.n}",
                    "chain_dims": list(inputs.FP32_CHAIN_DIMS), "elementwise_n": args.n,
                    "planner": "dp", "form": "plain fp32",
-                   "launch": ("hip graph replay" if args.launch == "graph" else
-                              "eager, one stream" if args.serial else
-                              "eager, chain and element-wise on two streams"),
-                   "autotuned": not args.no_tune},
+                   "launch": ("eager, the chain and the element-wise pass on two streams"
+                              if args.overlap else "eager, one stream, one job after the other"),
+                   "autotuned": not args.no_tune,
+                   "timing": f"value: {args.steps} whole steps between two synchronisations; "
+                             f"jobs: median of {args.reps} event-timed runs and one run after "
+                             "a 512 MB flush (cold)"},
+        "speedup_vs_plain_fp64": speedup,
         "roofline": ew_kernel,
-        "jobs": {
-            "chain": {"ms": ms_chain, "gflop": p1.info.flops / 1e9, "tflops": chain_tflops,
-                      "frac_fp32_mfma_peak": chain_tflops / FP32_MFMA_PEAK_TFLOPS,
-                      "kernels": [f"{s['kernel']} {s['m']}x{s['n']}x{s['k']} tile{s.get('tile')} "
-                                  f"split{s.get('split', 1)}" for s in d1["steps"]],
-                      "max_rel_err_sampled_rows": err_chain},
-            "elementwise": {"ms": ms_ew, "gbytes": ew_bytes / 1e9,
-                            "gbs": ew_kernel["achieved"], "max_rel_err_sampled_cols": err_ew},
-        },
-        "plan_ms": plan_ms,
+        "jobs": jobs,
+        "host": host_info(),
     }
-    if not args.no_cpu_baseline:
-        ncol = max(1, args.n // 2)
-        ew_host = {k: ew[k][:, :ncol].cpu().numpy() for k in ("A", "B", "C")}
-        res["cpu_baseline"] = cpu_baseline(chain_np, ew_host, d2["flops"] / float(args.n) ** 2)
+    # ---- the other configurations, each in its own form, summarized
+    if not args.quick:
+        for name, fn in [("small_fp64_expression", bench_small), ("syrk_65536x2048", bench_syrk),
+                         ("solve_8192", bench_solve), ("batched_10000", bench_batched),
+                         ("learned_2000_chains", bench_learned), ("diagonal_rewrites", bench_diag),
+                         ("structured_solves", bench_struct)]:
+            t1 = time.perf_counter()
+            jr = fn(args, ctx, hx, torch, inputs)
+            jr_s = summarize(jr)
+            jr_s["wall_s"] = time.perf_counter() - t1
+            res["jobs"][name] = jr_s
+            ctx.clear()
+            torch.cuda.empty_cache()
+    if cpu_inputs is not None:
+        res["cpu_baseline"] = cpu_baseline(*cpu_inputs)
+        res["cpu_baseline"].update(host_info())
     print(json.dumps(res), flush=True)
 
 

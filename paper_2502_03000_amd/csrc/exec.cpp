@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstring>
 #include <string>
 #include <algorithm>
 #include <vector>
@@ -224,6 +225,19 @@ hexla_status run_ir_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipStrea
   return HEXLA_OK;
 }
 
+// Symmetric for the solver's purpose: S_ij and S_ji differ by at most
+// n u max |S| (u the unit roundoff of the storage type), the size of the
+// rounding differences between the two triangles of a product X X^T formed
+// by a general GEMM; the Cholesky factorisation reads the lower triangle.
+bool symmetric(const int32_t* h, int64_t n, int dtype) {
+  if (!h[2]) return true;
+  double amax, dmax;
+  std::memcpy(&amax, h + 8, sizeof(double));
+  std::memcpy(&dmax, h + 10, sizeof(double));
+  const double u = std::ldexp(1.0, dtype == HEXLA_F64 ? -53 : -24);
+  return dmax <= double(n) * u * amax;
+}
+
 // Structure-aware solve (see hexla_solver): copy S into the working matrix,
 // read its structure (one pass and one wait for four integers) unless the
 // planner knows S = X X^T, then run the solver that structure allows. A
@@ -250,14 +264,14 @@ hexla_status run_struct_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipS
                             size_t(n) * esz, size_t(r), hipMemcpyDeviceToDevice, st);
   };
   auto read_info = [&](int32_t* h) {
-    hipError_t e = hipMemcpyAsync(h, info, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    hipError_t e = hipMemcpyAsync(h, info, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     return e;
   };
   auto singular = [&]() {
     if (ctx->host_status == 0) ctx->host_status = HEXLA_E_SINGULAR;
   };
-  int32_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  alignas(8) int32_t h[16] = {};
   hipError_t e = copy_s();
   if (e != hipSuccess) return fail(e, "solve: copy");
   int solver = HEXLA_SOLVER_CHOLESKY;
@@ -270,12 +284,12 @@ hexla_status run_struct_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipS
     else if (kl == 0) solver = HEXLA_SOLVER_UPPER;
     else if (ku == 0) solver = HEXLA_SOLVER_LOWER;
     else if (kl <= 1 && ku <= 1) solver = HEXLA_SOLVER_TRIDIAGONAL;
-    else if (!h[2] && !h[3]) solver = HEXLA_SOLVER_CHOLESKY;
+    else if (!h[3] && symmetric(h, n, s.dtype)) solver = HEXLA_SOLVER_CHOLESKY;
     else solver = HEXLA_SOLVER_LU;
     // a triangular or diagonal matrix with a zero on its diagonal is singular
     if (solver >= HEXLA_SOLVER_LOWER && solver != HEXLA_SOLVER_TRIDIAGONAL && h[5]) singular();
   } else {
-    e = k::fill_i32_launch(info, 8, 0, st);
+    e = k::fill_i32_launch(info, 16, 0, st);
     if (e != hipSuccess) return fail(e, "solve: clear");
   }
   if (solver == HEXLA_SOLVER_CHOLESKY) {

@@ -207,6 +207,12 @@ std::vector<k::GemmConfig> gemm_candidates(const Step& s);
 // learned cost model (model.cpp)
 void product_features(int dtype, int precision, int mode, int ta, int tb, int64_t m, int64_t n,
                       int64_t kk, int tile, int split, float* out);
+void product_features_many(int dtype, int precision, int mode, int ta, int tb, int64_t m,
+                           int64_t n, int64_t kk, const k::GemmConfig* cfg, int count, float* out);
+// the configurations the learned planner prices for one product: per tile,
+// no split-K and the split counts that fill whole rounds of 512, 1024 and
+// 2048 workgroup slots, plus the default choice
+std::vector<k::GemmConfig> learned_candidates(const Step& s);
 bool model_predict_us(hexla_model* md, const std::vector<float>& x, std::vector<float>& us,
                       std::string* err);
 hexla_status set_err(const hexla_ctx* ctx, hexla_status st, const std::string& msg);

@@ -37,14 +37,19 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // ------------------------------------------------------------ structure
 
 // info[0] = lower bandwidth, info[1] = upper bandwidth, info[2] = 1 if some
-// S_ij != S_ji, info[3] = 1 if some diagonal entry is not > 0, info[5] = 1
-// if some diagonal entry is zero. Tile t enumerates the pairs I >= J.
+// S_ij != S_ji or is NaN, info[3] = 1 if some diagonal entry is not > 0,
+// info[5] = 1 if some diagonal entry is zero; the 64-bit words at info + 8
+// and info + 10 get max |S_ij| and max |S_ij - S_ji| (as FP64 bit patterns,
+// which order like the values for non-negative numbers). A product X X^T
+// formed by a general GEMM is symmetric only up to its summation order, so
+// the caller compares the two maxima. Tile t enumerates the pairs I >= J.
 template <typename T>
 __global__ __launch_bounds__(256) void structure_kernel(int64_t n, const T* __restrict__ S,
                                                         int64_t lds, int32_t* info) {
   __shared__ T sa[kB][kB + 1];
   __shared__ T sm[kB][kB + 1];
   __shared__ int s_red[4][4];
+  __shared__ double s_max[4][2];
   const int64_t t = blockIdx.x;
   int64_t I = int64_t((sqrt(8.0 * double(t) + 1.0) - 1.0) * 0.5);
   while ((I + 1) * (I + 2) / 2 <= t) ++I;
@@ -63,6 +68,7 @@ __global__ __launch_bounds__(256) void structure_kernel(int64_t n, const T* __re
   }
   __syncthreads();
   int kl = 0, ku = 0, asym = 0, nonpos = 0, zero = 0;
+  double amax = 0.0, dmax = 0.0;
 #pragma unroll 4
   for (int q = 0; q < 16; ++q) {
     const int c = cq + 4 * q;
@@ -78,7 +84,12 @@ __global__ __launch_bounds__(256) void structure_kernel(int64_t n, const T* __re
         if (j > i) kl = max(kl, int(std::min<int64_t>(j - i, 0x7fffffff)));
         if (i > j) ku = max(ku, int(std::min<int64_t>(i - j, 0x7fffffff)));
       }
-      if (!(a == b)) asym = 1;  // NaN compares unequal: not symmetric
+      if (!(a == b)) asym = 1;  // NaN compares unequal
+      const double da = fmax(fabs(double(a)), fabs(double(b)));
+      const double dd = fabs(double(a) - double(b));
+      amax = da > amax ? da : amax;  // a NaN never replaces the maximum ...
+      dmax = dd > dmax ? dd : dmax;
+      if (a != a || b != b) dmax = __builtin_inf();  // ... but makes S unsymmetric
       if (i == j) {
         if (!(a > T(0))) nonpos = 1;
         if (a == T(0)) zero = 1;
@@ -88,6 +99,8 @@ __global__ __launch_bounds__(256) void structure_kernel(int64_t n, const T* __re
   // workgroup maxima, then one atomic per workgroup and field
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int off = 32; off > 0; off >>= 1) {
+    amax = fmax(amax, __shfl_xor(amax, off));
+    dmax = fmax(dmax, __shfl_xor(dmax, off));
     kl = max(kl, __shfl_xor(kl, off));
     ku = max(ku, __shfl_xor(ku, off));
     asym |= __shfl_xor(asym, off);
@@ -95,6 +108,8 @@ __global__ __launch_bounds__(256) void structure_kernel(int64_t n, const T* __re
     zero |= __shfl_xor(zero, off);
   }
   if (lane == 0) {
+    s_max[w][0] = amax;
+    s_max[w][1] = dmax;
     s_red[w][0] = kl;
     s_red[w][1] = ku;
     s_red[w][2] = asym;
@@ -109,6 +124,14 @@ __global__ __launch_bounds__(256) void structure_kernel(int64_t n, const T* __re
       a2 |= s_red[q][2];
       a3 |= s_red[q][3];
     }
+    double m0 = 0.0, m1 = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      m0 = fmax(m0, s_max[q][0]);
+      m1 = fmax(m1, s_max[q][1]);
+    }
+    unsigned long long* words = reinterpret_cast<unsigned long long*>(info + 8);
+    if (m0 > 0.0) atomicMax(words, static_cast<unsigned long long>(__double_as_longlong(m0)));
+    if (m1 > 0.0) atomicMax(words + 1, static_cast<unsigned long long>(__double_as_longlong(m1)));
     if (a0) atomicMax(info + 0, a0);
     if (a1) atomicMax(info + 1, a1);
     if (a2) atomicOr(info + 2, 1);
@@ -414,7 +437,7 @@ size_t struct_inv_bytes(int dtype, int64_t n) {
 
 hipError_t structure_launch(int dtype, int64_t n, const void* S, int64_t lds, int32_t* info,
                             hipStream_t s) {
-  hipError_t e = fill_i32_launch(info, 8, 0, s);
+  hipError_t e = fill_i32_launch(info, 16, 0, s);
   if (e != hipSuccess || n <= 0) return e;
   const int64_t nb = cdiv(n, kB);
   const unsigned tiles = unsigned(nb * (nb + 1) / 2);

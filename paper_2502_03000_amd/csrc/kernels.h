@@ -117,9 +117,10 @@ hipError_t ew_sum_launch(int dtype, const EwProgram& p, double alpha, void* out,
                          hipStream_t s);
 
 // ------------------------------------------------------ structured solves
-// info (8 ints, cleared here): [0] lower bandwidth, [1] upper bandwidth,
-// [2] 1 if S != S^T, [3] 1 if a diagonal entry is not > 0, [5] 1 if a
-// diagonal entry is zero. One pass over the n x n matrix S (lds).
+// info (16 ints, 8-byte aligned, cleared here): [0] lower bandwidth, [1]
+// upper bandwidth, [2] 1 if S != S^T bitwise, [3] 1 if a diagonal entry is
+// not > 0, [5] 1 if a diagonal entry is zero, 64-bit words at [8] max |S_ij|
+// and [10] max |S_ij - S_ji| (FP64 values). One pass over the n x n S (lds).
 hipError_t structure_launch(int dtype, int64_t n, const void* S, int64_t lds, int32_t* info,
                             hipStream_t s);
 // Bytes of the inverse diagonal blocks (64 x 64 each) of an n x n factor.

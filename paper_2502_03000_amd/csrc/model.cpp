@@ -30,12 +30,17 @@ struct hexla_model {
   float* v = nullptr;
   int64_t step = 0;
   float y_mean = 0.f, y_std = 1.f;  // target standardisation (log microseconds)
-  // inference buffers, kPredictCap samples, allocated with the model
+  // inference buffers, kPredictCap samples, allocated with the model: on
+  // the device, and pinned host staging for the copies
   float* x_buf = nullptr;
   float* y_buf = nullptr;
+  float* x_host = nullptr;
+  float* y_host = nullptr;
   ~hexla_model() {
     for (float* p : {params, m, v, x_buf, y_buf})
       if (p) (void)hipFree(p);
+    for (float* p : {x_host, y_host})
+      if (p) (void)hipHostFree(p);
   }
 };
 
@@ -126,6 +131,67 @@ void product_features(int dtype, int precision, int mode, int ta, int tb, int64_
   f[31] = lg(M * N) / 26.f;
 }
 
+// The features of one product for several configurations at once: the
+// same values as product_features, with the parts that do not depend on the
+// configuration computed once.
+void product_features_many(int dtype, int precision, int mode, int ta, int tb, int64_t m,
+                           int64_t n, int64_t kk, const k::GemmConfig* cfg, int count, float* out) {
+  if (count <= 0) return;
+  const double es = dtype == HEXLA_F64 ? 8.0 : 4.0;
+  const double M = double(m), N = double(n), K = double(kk);
+  const double bytes = es * (M * K + K * N + M * N);
+  const double flops = mode == 1 ? N * (N + 1) * K : 2.0 * M * N * K;
+  float base[F];
+  std::fill(base, base + F, 0.f);
+  base[0] = lg(M) / 13.f;
+  base[1] = lg(N) / 13.f;
+  base[2] = lg(K) / 13.f;
+  base[3] = lg(M * N * K) / 39.f;
+  base[6] = dtype == HEXLA_F64 ? 1.f : 0.f;
+  base[7] = dtype == HEXLA_F32 ? 1.f : 0.f;
+  base[8] = mode == 1 ? 1.f : 0.f;
+  base[9] = ta ? 1.f : 0.f;
+  base[10] = tb ? 1.f : 0.f;
+  base[11] = float(precision) / 3.f;
+  base[27] = lg(bytes) / 40.f;
+  base[28] = lg(flops / bytes) / 12.f;
+  base[31] = lg(M * N) / 26.f;
+  int last_tile = -2, bm = 64, bn = 64, bk = 16;
+  float fbm = 0.f, fbn = 0.f, fbk = 0.f;
+  double tm = 0.0, tn = 0.0, tiles = 0.0;
+  for (int c = 0; c < count; ++c) {
+    float* f = out + size_t(c) * F;
+    std::copy(base, base + F, f);
+    const int tile = cfg[c].tile;
+    if (tile != last_tile) {
+      bm = 64, bn = 64, bk = 16;
+      if (tile >= 0) k::gemm_tile_shape(dtype, precision, tile, &bm, &bn, &bk);
+      fbm = lg(bm) / 8.f;
+      fbn = lg(bn) / 8.f;
+      fbk = lg(bk) / 6.f;
+      tm = std::ceil(M / bm);
+      tn = std::ceil(N / bn);
+      tiles = mode == 1 ? tn * (tn + 1) / 2 : tm * tn;
+      last_tile = tile;
+    }
+    const int split = std::max(cfg[c].split, 1);
+    const double wgs = tiles * split;
+    const double kchunk = std::ceil(K / split);
+    f[4] = lg(kchunk) / 13.f;
+    f[5] = lg(split) / 10.f;
+    if (tile >= 0 && tile < 8) f[12 + tile] = 1.f;
+    f[20] = fbm;
+    f[21] = fbn;
+    f[22] = fbk;
+    f[23] = lg(wgs) / 20.f;
+    f[24] = float(std::min(wgs / 256.0, 4.0) / 4.0);
+    f[25] = float((M * N) / (tm * bm * tn * bn));
+    f[26] = float(K / (std::ceil(kchunk / bk) * bk * split));
+    f[29] = split > 1 ? 1.f : 0.f;
+    f[30] = split > 1 ? lg(double(split) * M * N * es) / 36.f : 0.f;
+  }
+}
+
 bool model_predict_us(hexla_model* md, const std::vector<float>& x, std::vector<float>& us,
                       std::string* err) {
   const int64_t count = int64_t(x.size()) / F;
@@ -137,15 +203,17 @@ bool model_predict_us(hexla_model* md, const std::vector<float>& x, std::vector<
   // allocates no device memory; a long candidate list runs in chunks.
   for (int64_t at = 0; at < count && e == hipSuccess; at += kPredictCap) {
     const int64_t c = std::min<int64_t>(kPredictCap, count - at);
-    e = hipMemcpyAsync(md->x_buf, x.data() + size_t(at) * F, size_t(c) * F * sizeof(float),
+    std::memcpy(md->x_host, x.data() + size_t(at) * F, size_t(c) * F * sizeof(float));
+    e = hipMemcpyAsync(md->x_buf, md->x_host, size_t(c) * F * sizeof(float),
                        hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
       e = k::mlp_predict_launch(md->params, md->x_buf, c, md->y_std, md->y_mean, md->y_buf, s);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(us.data() + at, md->y_buf, size_t(c) * sizeof(float),
+      e = hipMemcpyAsync(md->y_host, md->y_buf, size_t(c) * sizeof(float),
                          hipMemcpyDeviceToHost, s);
-    // the next chunk overwrites x_buf: wait for this one (and for the result)
+    // the next chunk overwrites the staging buffers: wait for this one
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) std::memcpy(us.data() + at, md->y_host, size_t(c) * sizeof(float));
   }
   if (e != hipSuccess) {
     if (err) *err = std::string("model inference: ") + hipGetErrorString(e);
@@ -198,6 +266,12 @@ hexla_status hexla_model_create(hexla_ctx* ctx, uint64_t seed, hexla_model** out
     e = hipMalloc(reinterpret_cast<void**>(&md->x_buf), size_t(kPredictCap) * F * sizeof(float));
   if (e == hipSuccess)
     e = hipMalloc(reinterpret_cast<void**>(&md->y_buf), size_t(kPredictCap) * sizeof(float));
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&md->x_host), size_t(kPredictCap) * F * sizeof(float),
+                      hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&md->y_host), size_t(kPredictCap) * sizeof(float),
+                      hipHostMallocDefault);
   if (e == hipSuccess) e = hipMemcpy(md->params, h.data(), P * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(md->m, 0, P * sizeof(float));
   if (e == hipSuccess) e = hipMemset(md->v, 0, P * sizeof(float));

@@ -1308,10 +1308,21 @@ class Planner {
     std::vector<int> index(size_t(L) * L * L, -1);
     std::vector<Prod> prods;
     std::vector<float> feats;
+    // a product no bracketing within twice the fewest multiply-adds can
+    // contain (its own and its operands' cheapest costs exceed that) is
+    // never kept by the check below: it is not priced
+    const auto macs = dp_table(d, sym);
+    const i128 limit = 2 * macs[0][L - 1];
     for (int lo = 0; lo < L; ++lo)
       for (int hi = lo + 1; hi < L; ++hi)
         for (int s = lo; s < hi; ++s) {
           Prod p;
+          if (macs[lo][s] + macs[s + 1][hi] + pair_cost(d, lo, s, hi, sym) > limit) {
+            p.us = 1e30;
+            index[at(lo, s, hi)] = int(prods.size());
+            prods.push_back(std::move(p));
+            continue;
+          }
           p.st.dtype = dtype_;
           p.st.precision = dtype_ == HEXLA_F32 ? o_.product_precision : 0;
           p.st.mode = (hi == lo + 1 && sym[lo] && o_.syrk) ? 1 : 0;
@@ -1325,14 +1336,13 @@ class Planner {
                                                  double(p.st.kk) * p.st.n + double(p.st.m) * p.st.n);
             p.us = 4.0 + bytes / 4.0e6;
           } else {
-            p.cands = gemm_candidates(p.st);
+            p.cands = learned_candidates(p.st);
             p.first = feats.size() / k::kMlpFeatures;
             p.count = p.cands.size();
-            for (const k::GemmConfig& c : p.cands) {
-              feats.resize(feats.size() + k::kMlpFeatures);
-              product_features(dtype_, p.st.precision, p.st.mode, p.ta, p.tb, p.st.m, p.st.n,
-                               p.st.kk, c.tile, c.split, &feats[feats.size() - k::kMlpFeatures]);
-            }
+            feats.resize(feats.size() + p.count * k::kMlpFeatures);
+            product_features_many(dtype_, p.st.precision, p.st.mode, p.ta, p.tb, p.st.m, p.st.n,
+                                  p.st.kk, p.cands.data(), int(p.count),
+                                  &feats[p.first * k::kMlpFeatures]);
           }
           index[at(lo, s, hi)] = int(prods.size());
           prods.push_back(std::move(p));
@@ -1593,7 +1603,7 @@ class Planner {
       q.ybuf = work(n * r * int64_t(esz_));
       q.coef = work(3 * n * int64_t(esz_));
       q.partial = work(n * 64 * int64_t(esz_));
-      q.info = work(8 * 4);
+      q.info = work(16 * 4);
       // the general case's work (LU and substitution); the structured
       // solvers do less
       q.flops = 2.0 / 3.0 * double(n) * n * n + 2.0 * double(n) * n * r;

@@ -71,6 +71,33 @@ std::vector<k::GemmConfig> gemm_candidates(const Step& s) {
   return out;
 }
 
+std::vector<k::GemmConfig> learned_candidates(const Step& s) {
+  std::vector<k::GemmConfig> out;
+  out.reserve(48);
+  auto add = [&](k::GemmConfig c) {
+    for (const k::GemmConfig& q : out)
+      if (q.tile == c.tile && q.split == c.split) return;
+    if (k::gemm_partial_bytes(s.dtype, c, s.m, s.n) > kMaxCandidatePartial) return;
+    out.push_back(c);
+  };
+  add(k::gemm_choose(s.dtype, s.precision, s.mode, s.m, s.n, s.kk));
+  if (s.precision != 0) {
+    for (int split : {1, 2, 4, 8, 16}) add(k::GemmConfig{0, split});
+    return out;
+  }
+  for (int t = 0; t < k::gemm_tile_count(s.dtype); ++t) {
+    if (!k::gemm_tile_valid(s.dtype, t, s.mode)) continue;
+    add(k::GemmConfig{t, 1});
+    const int64_t tiles = k::gemm_tiles_for(s.dtype, t, s.mode, s.m, s.n);
+    for (int64_t slots : {512, 1024, 2048}) {
+      const int64_t split = slots / tiles;
+      if (split >= 2)
+        add(k::GemmConfig{t, k::gemm_split_for(s.dtype, t, s.mode, s.m, s.n, s.kk, split * tiles, 1)});
+    }
+  }
+  return out;
+}
+
 size_t gemm_max_partial(const Step& s) {
   size_t b = 0;
   for (const k::GemmConfig& c : gemm_candidates(s))
