@@ -250,8 +250,6 @@ hexla_status run_struct_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipS
   void* wm = addr(W.ref, b);
   const int64_t ldw = std::max<int64_t>(n, 1);
   int32_t* info = static_cast<int32_t*>(addr(s.info, b));
-  void* inv = addr(s.inv, b);
-  void* ybuf = addr(s.ybuf, b);
   void* xo = addr(X.ref, b);
   const size_t esz = dtype_size(s.dtype);
   auto fail = [&](hipError_t e, const char* what) { return device_err(ctx, e, what); };
@@ -293,7 +291,7 @@ hexla_status run_struct_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipS
     if (e != hipSuccess) return fail(e, "solve: clear");
   }
   if (solver == HEXLA_SOLVER_CHOLESKY) {
-    e = k::chol_factor_launch(s.dtype, n, wm, ldw, inv, addr(s.partial, b), info, st);
+    e = k::chol_factor_launch(s.dtype, n, wm, ldw, info, st, &ctx->side);
     if (e == hipSuccess) e = read_info(h);
     if (e != hipSuccess) return fail(e, "solve: cholesky");
     if (h[4]) {  // not positive definite: LU on a fresh copy
@@ -303,7 +301,7 @@ hexla_status run_struct_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipS
     } else {
       e = copy_b(xo, X.ld);
       if (e == hipSuccess)
-        e = k::tri_solve_launch(s.dtype, 0, n, r, wm, ldw, inv, xo, X.ld, ybuf, xo, X.ld, st);
+        e = k::tri_solve_launch(s.dtype, 0, n, r, wm, ldw, xo, X.ld, addr(s.coef, b), st);
       if (e != hipSuccess) return fail(e, "solve: cholesky substitution");
     }
   }
@@ -329,16 +327,12 @@ hexla_status run_struct_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipS
       break;
     }
     case HEXLA_SOLVER_LOWER:
-    case HEXLA_SOLVER_UPPER: {
-      const bool lower = solver == HEXLA_SOLVER_LOWER;
-      e = k::trinv_launch(s.dtype, lower, n, wm, ldw, inv, info, st);
-      if (e == hipSuccess) e = copy_b(lower ? xo : ybuf, lower ? X.ld : ldw);
+    case HEXLA_SOLVER_UPPER:
+      e = copy_b(xo, X.ld);
       if (e == hipSuccess)
-        e = lower ? k::tri_solve_launch(s.dtype, 1, n, r, wm, ldw, inv, xo, X.ld, ybuf, xo, X.ld, st)
-                  : k::tri_solve_launch(s.dtype, 2, n, r, wm, ldw, inv, ybuf, ldw, nullptr, xo, X.ld,
-                                        st);
+        e = k::tri_solve_launch(s.dtype, solver == HEXLA_SOLVER_LOWER ? 1 : 2, n, r, wm, ldw, xo,
+                                X.ld, addr(s.coef, b), st);
       break;
-    }
     case HEXLA_SOLVER_TRIDIAGONAL:
       e = copy_b(xo, X.ld);
       if (e == hipSuccess)

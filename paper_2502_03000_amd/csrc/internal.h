@@ -122,7 +122,7 @@ struct Step {
   // solver chosen at execute time from the structure of S (or Cholesky when
   // the planner knows S = X X^T); B, C: right-hand sides and solution.
   bool spd_known = false;
-  Ref inv, ybuf, coef, info;
+  Ref coef, info;
   double flops = 0.0, bytes = 0.0;
   // Ew: kernel generated for this program (null: interpreter)
   std::string cg_src;

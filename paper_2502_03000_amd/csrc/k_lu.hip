@@ -587,7 +587,10 @@ __global__ void iota_kernel(int32_t* p, int64_t n) {
 // column of C in each 16-lane group, so C is read and written in whole
 // 64-byte (FP32) or 128-byte (FP64) runs. The traffic is the C tile twice
 // plus the A and B tiles once; with K = 64 the kernel is bound by C.
-template <typename T, int BT>
+// BTRANS: B is given as its transpose, an n x K matrix (element (k, j) at
+// B[j + k ldb]). LOWER: only the tiles on or below the diagonal of a square
+// C (tile column <= tile row), workgroup t taking the t-th such tile.
+template <typename T, int BT, bool BTRANS = false, bool LOWER = false>
 __global__ __launch_bounds__(256) void rank_update_kernel(int64_t m, int64_t n, int K,
                                                           const T* __restrict__ A, int64_t lda,
                                                           const T* __restrict__ B, int64_t ldb,
@@ -600,7 +603,15 @@ __global__ __launch_bounds__(256) void rank_update_kernel(int64_t m, int64_t n, 
   constexpr int F = WT / 16;  // 16 x 16 blocks per side of a wave's part
   __shared__ T sa[kNB][LD];   // A^T: sa[k][row]
   __shared__ T sb[kNB][LD];   // B: sb[k][col]
-  const int tm = int(blockIdx.x) % tiles_m, tn = int(blockIdx.x) / tiles_m;
+  int tm = int(blockIdx.x) % tiles_m, tn = int(blockIdx.x) / tiles_m;
+  if (LOWER) {  // t = tm (tm + 1) / 2 + tn, tn <= tm
+    const int64_t t = blockIdx.x;
+    int64_t I = int64_t((sqrt(8.0 * double(t) + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    while (I * (I + 1) / 2 > t) --I;
+    tm = int(I);
+    tn = int(t - I * (I + 1) / 2);
+  }
   const int64_t m0 = int64_t(tm) * BT, n0 = int64_t(tn) * BT;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave & 1, wc = wave >> 1;
@@ -629,15 +640,20 @@ __global__ __launch_bounds__(256) void rank_update_kernel(int64_t m, int64_t n, 
       const int e = tid + 256 * q;
       const int64_t gr = std::min<int64_t>(m0 + e % BT, m - 1);
       va[q] = A[gr + int64_t(min(e / BT, K - 1)) * lda];
-      const int64_t gc = std::min<int64_t>(n0 + e / kNB, n - 1);
-      vb[q] = B[min(e % kNB, K - 1) + gc * ldb];
+      if (BTRANS) {  // along the columns of C, like A along its rows
+        const int64_t gc = std::min<int64_t>(n0 + e % BT, n - 1);
+        vb[q] = B[gc + int64_t(min(e / BT, K - 1)) * ldb];
+      } else {
+        const int64_t gc = std::min<int64_t>(n0 + e / kNB, n - 1);
+        vb[q] = B[min(e % kNB, K - 1) + gc * ldb];
+      }
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int e = tid + 256 * q;
       const int row = e % BT, ka = e / BT;
       sa[ka][row] = (ka < K && m0 + row < m) ? va[q] : T(0);
-      const int kb = e % kNB, col = e / kNB;
+      const int kb = BTRANS ? e / BT : e % kNB, col = BTRANS ? e % BT : e / kNB;
       sb[kb][col] = (kb < K && n0 + col < n) ? vb[q] : T(0);
     }
   }
@@ -668,6 +684,28 @@ __global__ __launch_bounds__(256) void rank_update_kernel(int64_t m, int64_t n, 
         const int64_t row = m0 + wr * WT + fr * 16 + l16;
         if (row < m && col < n) C[row + col * ldc] = acc[fc][fr][r];
       }
+}
+
+template <typename T>
+hipError_t syrk_lower_update(int64_t n, int64_t K, const T* W, int64_t ldw, T* C, int64_t ldc,
+                             hipStream_t s) {
+  constexpr int BT = 64;
+  const int64_t tn = cdiv(n, BT);
+  if (K > kNB || tn * (tn + 1) / 2 > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((rank_update_kernel<T, BT, true, true>), dim3(unsigned(tn * (tn + 1) / 2)),
+                     dim3(256), 0, s, n, n, int(K), W, ldw, W, ldw, C, ldc, int(tn));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t rank_update_bt(int64_t m, int64_t n, int64_t K, const T* A, int64_t lda, const T* Bt,
+                          int64_t ldbt, T* C, int64_t ldc, hipStream_t s) {
+  constexpr int BT = 64;
+  const int64_t tm = cdiv(m, BT), tn = cdiv(n, BT);
+  if (K > kNB || tm * tn > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((rank_update_kernel<T, BT, true, false>), dim3(unsigned(tm * tn)), dim3(256),
+                     0, s, m, n, int(K), A, lda, Bt, ldbt, C, ldc, int(tm));
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -896,6 +934,27 @@ size_t lu_workspace_bytes(int dtype, int64_t n, int64_t nrhs) {
   // the FP32 solve's exchange (the FP64 solve launches per block step)
   if (dtype == 1 && nrhs > 0) b += solve_words(std::max<int64_t>(n, 1), nrhs) * sizeof(uint64_t);
   return (b + 255) & ~size_t(255);
+}
+
+hipError_t rank_update_bt_launch(int dtype, int64_t m, int64_t n, int64_t K, const void* A,
+                                 int64_t lda, const void* Bt, int64_t ldbt, void* C, int64_t ldc,
+                                 hipStream_t s) {
+  if (m <= 0 || n <= 0 || K <= 0) return hipSuccess;
+  return dtype == 0 ? rank_update_bt<double>(m, n, K, static_cast<const double*>(A), lda,
+                                             static_cast<const double*>(Bt), ldbt,
+                                             static_cast<double*>(C), ldc, s)
+                    : rank_update_bt<float>(m, n, K, static_cast<const float*>(A), lda,
+                                            static_cast<const float*>(Bt), ldbt,
+                                            static_cast<float*>(C), ldc, s);
+}
+
+hipError_t syrk_lower_update_launch(int dtype, int64_t n, int64_t K, const void* W, int64_t ldw,
+                                   void* C, int64_t ldc, hipStream_t s) {
+  if (n <= 0 || K <= 0) return hipSuccess;
+  return dtype == 0 ? syrk_lower_update<double>(n, K, static_cast<const double*>(W), ldw,
+                                                static_cast<double*>(C), ldc, s)
+                    : syrk_lower_update<float>(n, K, static_cast<const float*>(W), ldw,
+                                               static_cast<float*>(C), ldc, s);
 }
 
 hipError_t lu_factor_launch(int dtype, int64_t n, void* A, int64_t lda, int32_t* rowid,

@@ -8,14 +8,18 @@
 //               its transpose, whether its diagonal is positive, and zero
 //               diagonal entries;
 //   Cholesky    right-looking, 64-column blocks: each diagonal block is
-//               factored by one wave with its rows in registers, which also
-//               inverts the block's factor; the block column below is
-//               L21 = A21 L11^-T (a product with that inverse) and the
-//               trailing matrix takes a symmetric rank-64 update (the SYRK
-//               tile map). No pivoting, so no per-column exchange between
+//               factored by one wave (a row per lane, in registers); the
+//               block column below is L21 = A21 L11^-T, one row per lane
+//               (forward substitution along the row, in place), and the
+//               trailing matrix's lower tiles take the rank-64 update
+//               L21 L21^T. No pivoting, so no per-column exchange between
 //               workgroups;
-//   triangular  per 64-row block: the inverse of the diagonal block applied,
-//               then a product updating the rows still to solve;
+//   triangular  the inverses of all 64 x 64 diagonal blocks in one launch
+//               (substitution against the identity, one column per lane),
+//               then per block one launch: the block's solution as the
+//               product with its inverse and, in the same workgroups, the
+//               update of the rows still to solve (Cholesky: forward with L,
+//               backward with L^T), all on the MFMAs;
 //   tridiagonal Gaussian elimination with partial pivoting between adjacent
 //               rows (a fill-in of one extra superdiagonal), one lane per
 //               right-hand side.
@@ -23,6 +27,7 @@
 
 #include <algorithm>
 
+#include "gemm_device.h"
 #include "kernels.h"
 
 namespace hexla {
@@ -142,174 +147,356 @@ __global__ __launch_bounds__(256) void structure_kernel(int64_t n, const T* __re
 
 // ------------------------------------------------ 64 x 64 triangular blocks
 
-// Inverse of the lower-triangular (non-unit) 64 x 64 matrix in sL (rows past
-// jb hold the identity): thread i computes column i of X = L^-1 by forward
-// substitution, X written to inv (column-major, ld 64).
-template <typename T>
-__device__ void invert_lower_block(T (*sL)[kB + 1], T (*sX)[kB + 1], T* inv) {
-  const int i = threadIdx.x;
-  for (int c = 0; c < kB; ++c) {
-    T x;
-    if (c < i) {
-      x = T(0);
-    } else if (c == i) {
-      x = T(1) / sL[c][c];
-    } else {
-      T s = T(0);
-      for (int k = i; k < c; ++k) s += sL[c][k] * sX[k][i];
-      x = -s / sL[c][c];
-    }
-    sX[c][i] = x;  // only this thread reads column i of sX
-    inv[c + i * kB] = x;
-  }
-}
+// The kernels below hold one 64-element row or column per lane in registers,
+// with every index fixed at compile time (fully unrolled loops). A ragged
+// last block (jb < 64) is handled by clamped addresses, never by per-element
+// conditions around loads or stores: those make the compiler keep all 64
+// values live across each branch and spill them.
 
-// Cholesky of the diagonal block at (k0, k0) (jb <= 64 rows): thread i
-// holds row i with the current column rotated into v[0]. The factor L11 is
-// written over the block's lower triangle and L11^-1 to inv. A pivot that is
-// not > 0 sets info[4] (the block is then not factored further).
+// Cholesky of the diagonal block at (k0, k0) (jb <= 64 rows; rows and
+// columns past jb are the identity) by one wave, lane r holding row r of the
+// block: per column j the pivot (lane j's entry, read by all through LDS),
+// its square root, the column of multipliers published through LDS, then
+// each lane's rank-1 update of its row. Only entries on or below the
+// diagonal feed later columns. L11 is written over the block's lower
+// triangle; a pivot that is not > 0 sets info[4] and the block is then not
+// stored.
 template <typename T>
-__global__ __launch_bounds__(kB) void potrf_block_kernel(T* __restrict__ A, int64_t lda,
-                                                         int64_t k0, int jb, T* inv,
-                                                         int32_t* info) {
-  __shared__ T col[kB];
-  __shared__ T sL[kB][kB + 1];
-  __shared__ T sX[kB][kB + 1];
-  __shared__ int s_bad;
-  const int i = threadIdx.x;
-  const bool own = i < jb;
-  T v[kB];
+__global__ __launch_bounds__(64) void potrf_block_kernel(T* __restrict__ A, int64_t lda,
+                                                         int64_t k0, int jb, int32_t* info) {
+  __shared__ T piv[kB];      // column j before scaling: the pivot is piv[j]
+  __shared__ T colj[2][kB];  // column j of L (two buffers: no reuse before two barriers)
+  const int r = threadIdx.x;
+  const int rr = std::min(r, jb - 1);
+  T a[kB];
 #pragma unroll
   for (int c = 0; c < kB; ++c) {
-    const bool in = own && c < jb;
-    v[c] = in ? A[(k0 + i) + (k0 + c) * lda] : (i == c ? T(1) : T(0));
+    const T x = A[(k0 + rr) + (k0 + std::min(c, jb - 1)) * lda];
+    a[c] = (r < jb && c < jb) ? (c <= r ? x : T(0)) : (r == c ? T(1) : T(0));
   }
-  if (i == 0) s_bad = 0;
-  __syncthreads();
-#pragma unroll 1
+  bool bad = false;
+#pragma unroll
   for (int j = 0; j < kB; ++j) {
-    if (i == j) col[0] = v[0];
+    piv[r] = a[j];
     __syncthreads();
-    const T d = col[0];
+    const T d = piv[j];
     const bool ok = d > T(0);
-    if (!ok && i == 0) s_bad = 1;
+    bad = bad || !ok;
     const T ljj = ok ? sqrt(d) : T(1);
-    const T lij = i > j ? v[0] / ljj : (i == j ? ljj : T(0));
+    const T l = r == j ? ljj : a[j] / ljj;
+    a[j] = l;
+    colj[j & 1][r] = l;
     __syncthreads();
-    col[i] = lij;
-    sL[i][j] = lij;
-    __syncthreads();
-    // trailing columns k = j + c: a_ik -= l_ij l_kj for rows i > j
 #pragma unroll
-    for (int c = 1; c < kB; ++c) {
-      const int kk = j + c < kB ? j + c : kB - 1;
-      const T lkj = j + c < kB ? col[kk] : T(0);
-      v[c] -= lij * lkj;
-    }
-#pragma unroll
-    for (int c = 0; c < kB - 1; ++c) v[c] = v[c + 1];
-    v[kB - 1] = T(0);
+    for (int c = j + 1; c < kB; ++c) a[c] -= l * colj[j & 1][c];
   }
-  __syncthreads();
-  if (s_bad) {
-    if (i == 0) info[4] = 1;
+  if (bad) {
+    if (r == 0) info[4] = 1;
     return;
   }
-  if (own) {
-    for (int c = 0; c <= i && c < jb; ++c) A[(k0 + i) + (k0 + c) * lda] = sL[i][c];
+  if (r < jb) {
+#pragma unroll
+    for (int c = kB - 1; c >= 0; --c) A[(k0 + r) + (k0 + std::min(c, r)) * lda] = a[c];
   }
-  invert_lower_block<T>(sL, sX, inv);
 }
 
-// Inverses of the 64 x 64 diagonal blocks of a triangular matrix (non-unit;
-// LOWER or upper), one block per workgroup: inv[p] = (S_pp)^-1, stored
-// column-major with ld 64. An upper block is inverted as the transpose of
-// its (lower) transpose. A zero diagonal entry sets info[6].
-template <typename T, bool LOWER>
-__global__ __launch_bounds__(kB) void trinv_block_kernel(const T* __restrict__ S, int64_t lds,
-                                                         int64_t n, T* inv, int32_t* info) {
-  __shared__ T sL[kB][kB + 1];
-  __shared__ T sX[kB][kB + 1];
-  __shared__ T sT[kB * kB];
-  const int64_t p = blockIdx.x, k0 = p * kB;
-  const int jb = int(std::min<int64_t>(kB, n - k0));
-  const int i = threadIdx.x;
-  // row i of L: for a lower block S[k0 + i][k0 + c]; for an upper block the
-  // transpose, S[k0 + c][k0 + i] (read down column i: coalesced by c... the
-  // loads run along each thread's own column)
-  bool zero = false;
-  for (int c = 0; c < kB; ++c) {
-    T x;
-    if (i < jb && c < jb) x = LOWER ? S[(k0 + i) + (k0 + c) * lds] : S[(k0 + c) + (k0 + i) * lds];
-    else x = i == c ? T(1) : T(0);
-    if (c > i) x = T(0);
-    if (c == i && x == T(0)) zero = true;
-    sL[i][c] = x;
+// The block column under a factored diagonal block: each lane takes one row
+// a of A21 (m rows) and solves w L11^T = a in place (forward substitution
+// along the row, w_c = (a_c - sum_{k<c} w_k l_ck) / l_cc, four partial sums),
+// with L11 (lower, from the diagonal block) in LDS and the row in registers.
+template <typename T>
+__global__ __launch_bounds__(64) void trsm_rows_kernel(T* __restrict__ A, int64_t lda, int64_t k0,
+                                                       int jb, int64_t m) {
+  __shared__ T L[kB][kB + 1];
+  const int t = threadIdx.x;
+#pragma unroll  // all 64 loads in flight at once
+  for (int c = 0; c < kB; ++c) {  // column c of the block, coalesced down the rows
+    const T x = A[(k0 + std::min(t, jb - 1)) + (k0 + std::min(c, jb - 1)) * lda];
+    L[t][c] = (t < jb && c < jb && c <= t) ? x : (t == c ? T(1) : T(0));
   }
-  if (zero) info[6] = 1;
   __syncthreads();
-  T* out = inv + p * kB * kB;
-  if (LOWER) {
-    invert_lower_block<T>(sL, sX, out);
-  } else {
-    invert_lower_block<T>(sL, sX, sT);  // (U^T)^-1 ...
-    __syncthreads();
-    for (int c = 0; c < kB; ++c) out[c + i * kB] = sT[i + c * kB];  // ... transposed
+  const int64_t i = int64_t(blockIdx.x) * kB + t;
+  T* row = A + (k0 + jb + std::min<int64_t>(i, m - 1)) + k0 * lda;
+  T w[kB];
+#pragma unroll
+  for (int c = 0; c < kB; ++c) w[c] = row[int64_t(std::min(c, jb - 1)) * lda];
+#pragma unroll
+  for (int c = 0; c < kB; ++c) {
+    T s[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int k = 0; k < c; ++k) s[k & 3] += w[k] * L[c][k];
+    w[c] = (w[c] - ((s[0] + s[1]) + (s[2] + s[3]))) / L[c][c];
   }
+  if (i < m) {
+#pragma unroll
+    for (int c = kB - 1; c >= 0; --c) row[int64_t(std::min(c, jb - 1)) * lda] = w[c];
+  }
+}
+
+// Inverses of the diagonal 64 x 64 blocks of the lower (UPPER: upper)
+// triangle of the n x n M, one workgroup per block, all blocks at once: lane
+// j solves T x = e_j by substitution (x in registers, the triangle in LDS)
+// for column j of the inverse. inv + 4096 p receives block p's inverse,
+// column-major with ld 64; rows and columns past the block's size are those
+// of the identity.
+template <typename T, bool UPPER>
+__global__ __launch_bounds__(64) void trtri_blocks_kernel(const T* __restrict__ M, int64_t ldm,
+                                                          int64_t n, T* __restrict__ inv) {
+  __shared__ T L[kB][kB + 1];  // L[r][c] = M(r0 + r, r0 + c) on the stored triangle
+  const int64_t r0 = int64_t(blockIdx.x) * kB;
+  const int jb = int(std::min<int64_t>(kB, n - r0));
+  const int t = threadIdx.x;
+#pragma unroll  // all 64 loads in flight at once
+  for (int c = 0; c < kB; ++c) {  // column c of the block, coalesced down the rows
+    const bool tri = UPPER ? c >= t : c <= t;
+    const T x = M[(r0 + std::min(t, jb - 1)) + (r0 + std::min(c, jb - 1)) * ldm];
+    L[t][c] = (t < jb && c < jb && tri) ? x : (t == c ? T(1) : T(0));
+  }
+  __syncthreads();
+  T x[kB];
+#pragma unroll
+  for (int c = 0; c < kB; ++c) x[c] = c == t ? T(1) : T(0);
+  if (!UPPER) {
+#pragma unroll
+    for (int c = 0; c < kB; ++c) {
+      T s[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int k = 0; k < c; ++k) s[k & 3] += L[c][k] * x[k];
+      x[c] = (x[c] - ((s[0] + s[1]) + (s[2] + s[3]))) / L[c][c];
+    }
+  } else {
+#pragma unroll
+    for (int c = kB - 1; c >= 0; --c) {
+      T s[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int k = c + 1; k < kB; ++k) s[k & 3] += L[c][k] * x[k];
+      x[c] = (x[c] - ((s[0] + s[1]) + (s[2] + s[3]))) / L[c][c];
+    }
+  }
+  T* out = inv + int64_t(blockIdx.x) * kB * kB + t * kB;
+#pragma unroll
+  for (int c = 0; c < kB; ++c) out[c] = x[c];
+}
+
+// One step of a block triangular solve with the inverted diagonal block
+// (blocks of 64 rows, diagonal block p at rows r0 .. r0 + jb): with X_p the
+// block's rows of the right-hand sides X,
+//   Y_p = D X_p,  D = T_pp^-1 (MODE 0: T = L, MODE 2: T = U) or L_pp^-T
+//                 (MODE 1, the transposed solve with the lower L),
+// written to Y by the workgroups of tile row 0; every other workgroup
+// recomputes Y_p for its 64 columns and updates one 64 x 64 tile of the rows
+// still to solve in place: X_i -= A_i Y_p, with A_i = L(i, p) below the block
+// (MODE 0), L(p, i)^T (MODE 1) or U(i, p) (MODE 2) above it. No workgroup
+// writes rows another one reads. Both products are computed transposed on
+// the MFMAs (rows of the MFMA result are columns of Y and of the tile), so
+// 16 consecutive lanes hold 16 consecutive rows of one column for the global
+// stores.
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void trsm_step_kernel(const T* __restrict__ M, int64_t ldm,
+                                                        int64_t n, int64_t r0, int jb,
+                                                        const T* __restrict__ inv, T* X,
+                                                        int64_t ldx, T* __restrict__ Y,
+                                                        int64_t ldy, int64_t nrhs, int tiles_m) {
+  using Mf = Mfma<T>;
+  using acc_t = typename Mf::acc_t;
+  constexpr int LD = kB + 1, WT = kB / 2, F = WT / 16;
+  __shared__ T sI[kB][LD];  // sI[k][j] = D(j, k)
+  __shared__ T sX[kB][LD];  // sX[k][j] = X_p(k, j), then Y_p(k, j)
+  __shared__ T sA[kB][LD];  // sA[k][i] = A_tile(i, k)
+  const int tm = int(blockIdx.x) % tiles_m, tn = int(blockIdx.x) / tiles_m;
+  const int64_t n0 = int64_t(tn) * kB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1, l16 = lane & 15, g = lane >> 4;
+  const int64_t u0 = MODE == 0 ? r0 + jb : 0;        // first row still to solve
+  const int64_t ue = MODE == 0 ? n : r0;             // one past the last
+  const int64_t m0 = u0 + int64_t(tm - 1) * kB;      // this tile's first row (tm >= 1)
+  const int64_t mlast = std::max<int64_t>(ue - 1, 0);
+  // 1. D, X_p and the A tile into LDS: every load issued first (clamped
+  // addresses), the zeros past jb, nrhs and the rows chosen when storing
+  constexpr int PER = kB * kB / 256;
+  T vi[PER], vx[PER], va[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = tid + 256 * q, a = e & (kB - 1), c = e / kB;
+    vi[q] = inv[a + kB * c];  // inverse block element (a, c)
+    vx[q] = X[(r0 + std::min(a, jb - 1)) + std::min<int64_t>(n0 + c, nrhs - 1) * ldx];
+    if (tm > 0)
+      va[q] = MODE == 1 ? M[(r0 + std::min(a, jb - 1)) + std::min<int64_t>(m0 + c, mlast) * ldm]
+                        : M[std::min<int64_t>(m0 + a, mlast) + (r0 + std::min(c, jb - 1)) * ldm];
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = tid + 256 * q, a = e & (kB - 1), c = e / kB;
+    const bool in = a < jb && c < jb;
+    if (MODE == 1) sI[a][c] = in ? vi[q] : T(0);  // D(c, a) = inverse(a, c)
+    else sI[c][a] = in ? vi[q] : T(0);            // D(a, c) = inverse(a, c)
+    sX[a][c] = (a < jb && n0 + c < nrhs) ? vx[q] : T(0);
+    if (tm > 0) {
+      if (MODE == 1) sA[a][c] = (a < jb && m0 + c < ue) ? va[q] : T(0);  // A(c, a) = L(r0+a, m0+c)
+      else sA[c][a] = (c < jb && m0 + a < ue) ? va[q] : T(0);            // A(a, c)
+    }
+  }
+  __syncthreads();
+  // 2. Y_p^T = X_p^T D^T: operand A[i][k] = X_p(k, column i), operand
+  // B[k][j] = D(row j, k); acc[fc][fr] register r holds Y_p(row wr*WT +
+  // fr*16 + l16, column wc*WT + fc*16 + Mf::row(lane, r))
+  acc_t acc[F][F];
+#pragma unroll
+  for (int fc = 0; fc < F; ++fc)
+#pragma unroll
+    for (int fr = 0; fr < F; ++fr) acc[fc][fr] = acc_t{};
+#pragma unroll 4
+  for (int k0 = 0; k0 < kB; k0 += 4) {
+    T x[F], d[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      x[f] = sX[k0 + g][wc * WT + f * 16 + l16];
+      d[f] = sI[k0 + g][wr * WT + f * 16 + l16];
+    }
+#pragma unroll
+    for (int fc = 0; fc < F; ++fc)
+#pragma unroll
+      for (int fr = 0; fr < F; ++fr) acc[fc][fr] = Mf::mma(x[fc], d[fr], acc[fc][fr]);
+  }
+  if (tm == 0) {  // the solved block
+#pragma unroll
+    for (int fc = 0; fc < F; ++fc)
+#pragma unroll
+      for (int fr = 0; fr < F; ++fr)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = wr * WT + fr * 16 + l16;
+          const int64_t col = n0 + wc * WT + fc * 16 + Mf::row(lane, r);
+          if (row < jb && col < nrhs) Y[(r0 + row) + col * ldy] = acc[fc][fr][r];
+        }
+    return;
+  }
+  __syncthreads();  // every read of X_p done
+#pragma unroll
+  for (int fc = 0; fc < F; ++fc)
+#pragma unroll
+    for (int fr = 0; fr < F; ++fr)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        sX[wr * WT + fr * 16 + l16][wc * WT + fc * 16 + Mf::row(lane, r)] = acc[fc][fr][r];
+  // 3. the tile, transposed like Y_p: register r of acc[fc][fr] holds
+  // X(m0 + wr*WT + fr*16 + l16, n0 + wc*WT + fc*16 + Mf::row(lane, r))
+#pragma unroll
+  for (int fc = 0; fc < F; ++fc)
+#pragma unroll
+    for (int fr = 0; fr < F; ++fr)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = m0 + wr * WT + fr * 16 + l16;
+        const int64_t col = n0 + wc * WT + fc * 16 + Mf::row(lane, r);
+        acc[fc][fr][r] = X[std::min<int64_t>(row, mlast) + std::min<int64_t>(col, nrhs - 1) * ldx];
+      }
+  __syncthreads();
+  // X_tile^T -= Y_p^T A^T: operand A[i][k] = -Y_p(k, column i), operand
+  // B[k][j] = A(row j, k)
+#pragma unroll 4
+  for (int k0 = 0; k0 < kB; k0 += 4) {
+    T y[F], a[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      y[f] = -sX[k0 + g][wc * WT + f * 16 + l16];
+      a[f] = sA[k0 + g][wr * WT + f * 16 + l16];
+    }
+#pragma unroll
+    for (int fc = 0; fc < F; ++fc)
+#pragma unroll
+      for (int fr = 0; fr < F; ++fr) acc[fc][fr] = Mf::mma(y[fc], a[fr], acc[fc][fr]);
+  }
+#pragma unroll
+  for (int fc = 0; fc < F; ++fc)
+#pragma unroll
+    for (int fr = 0; fr < F; ++fr)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = m0 + wr * WT + fr * 16 + l16;
+        const int64_t col = n0 + wc * WT + fc * 16 + Mf::row(lane, r);
+        if (row < ue && col < nrhs) X[row + col * ldx] = acc[fc][fr][r];
+      }
 }
 
 // ------------------------------------------------------------ tridiagonal
 
-// Forward elimination with partial pivoting of the tridiagonal part of S
-// (sub l_i = S[i][i-1], diagonal d_i, super u_i = S[i][i+1]) applied to the
-// right-hand sides in X (lane r: column col0 + r). The final upper
-// triangular rows (d', u', w': the diagonal, the superdiagonal and the fill
-// two to the right) go to coef[3 i ..]; workgroup 0 writes them, the others
-// compute the same values. A zero pivot sets info[5].
+// The three diagonals of S into contiguous arrays: sub[i] = S[i+1][i],
+// dia[i] = S[i][i], sup[i] = S[i][i+1] (the last sub and sup are zero).
 template <typename T>
-__global__ __launch_bounds__(64) void gtsv_forward_kernel(int64_t n, const T* __restrict__ S,
-                                                          int64_t lds, T* X, int64_t ldx,
-                                                          int64_t nrhs, T* coef, int32_t* info) {
+__global__ __launch_bounds__(256) void tridiag_extract_kernel(int64_t n, const T* __restrict__ S,
+                                                              int64_t lds, T* sub, T* dia, T* sup) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  dia[i] = S[i + i * lds];
+  sub[i] = i + 1 < n ? S[(i + 1) + i * lds] : T(0);
+  sup[i] = i + 1 < n ? S[i + (i + 1) * lds] : T(0);
+}
+
+constexpr int kChunk = 8;  // rows whose operands are loaded ahead of their elimination
+
+// Forward elimination with partial pivoting of the tridiagonal matrix (sub,
+// dia, sup) applied to the right-hand sides in X (lane r: column col0 + r).
+// The current row i is (d, u, w) at columns i, i+1, i+2; row i+1 is
+// (sub[i], dia[i+1], sup[i+1]); the one of the two with the larger entry in
+// column i becomes the pivot row (final row i of U: d', u', w'), the other
+// is eliminated into the new current row. The rows' operands are loaded
+// kChunk at a time ahead of use. Workgroup 0 writes the final rows to
+// coef[3 i ..]; a zero pivot sets info[5].
+template <typename T>
+__global__ __launch_bounds__(64) void gtsv_forward_kernel(int64_t n, const T* __restrict__ sub,
+                                                          const T* __restrict__ dia,
+                                                          const T* __restrict__ sup, T* X,
+                                                          int64_t ldx, int64_t nrhs, T* coef,
+                                                          int32_t* info) {
   const int64_t col = int64_t(blockIdx.x) * 64 + threadIdx.x;
   const bool has = col < nrhs;
   T* x = X + std::min<int64_t>(col, nrhs - 1) * ldx;
   const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
-  // the current row i: (d, u, w) at columns i, i+1, i+2, and its rhs
-  T d = S[0], u = n > 1 ? S[lds] : T(0), w = T(0);
+  T d = dia[0], u = sup[0], w = T(0);
   T b = x[0];
   bool singular = false;
-  for (int64_t i = 0; i + 1 < n; ++i) {
-    const T l1 = S[(i + 1) + i * lds];
-    const T d1 = S[(i + 1) + (i + 1) * lds];
-    const T u1 = i + 2 < n ? S[(i + 1) + (i + 2) * lds] : T(0);
-    const T b1 = x[i + 1];
-    T pd, pu, pw, pb, nd, nu, nb;
-    if (fabs(d) >= fabs(l1)) {  // keep row i as the pivot row
-      const T m = d != T(0) ? l1 / d : T(0);
-      pd = d, pu = u, pw = w, pb = b;
-      nd = d1 - m * u;
-      nu = u1 - m * w;
-      nb = b1 - m * b;
-    } else {  // row i + 1 becomes the pivot row
-      const T m = d / l1;
-      pd = l1, pu = d1, pw = u1, pb = b1;
-      nd = u - m * d1;
-      nu = w - m * u1;
-      nb = b - m * b1;
+  for (int64_t i0 = 0; i0 + 1 < n; i0 += kChunk) {
+    T l1[kChunk], d1[kChunk], u1[kChunk], b1[kChunk];
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) {  // row i0 + q + 1 (clamped; unused past n - 1)
+      const int64_t r = std::min<int64_t>(i0 + q + 1, n - 1);
+      l1[q] = sub[r - 1];
+      d1[q] = dia[r];
+      u1[q] = sup[r];
+      b1[q] = x[r];
     }
-    if (pd == T(0)) singular = true;
-    if (writer) {
-      coef[3 * i] = pd;
-      coef[3 * i + 1] = pu;
-      coef[3 * i + 2] = pw;
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) {
+      const int64_t i = i0 + q;
+      if (i + 1 >= n) break;
+      T pd, pu, pw, pb, nd, nu, nb;
+      if (fabs(d) >= fabs(l1[q])) {  // keep row i as the pivot row
+        const T m = d != T(0) ? l1[q] / d : T(0);
+        pd = d, pu = u, pw = w, pb = b;
+        nd = d1[q] - m * u;
+        nu = u1[q] - m * w;
+        nb = b1[q] - m * b;
+      } else {  // row i + 1 becomes the pivot row
+        const T m = d / l1[q];
+        pd = l1[q], pu = d1[q], pw = u1[q], pb = b1[q];
+        nd = u - m * d1[q];
+        nu = w - m * u1[q];
+        nb = b - m * b1[q];
+      }
+      if (pd == T(0)) singular = true;
+      if (writer) {
+        coef[3 * i] = pd;
+        coef[3 * i + 1] = pu;
+        coef[3 * i + 2] = pw;
+      }
+      if (has) x[i] = pb;
+      // the new current row i + 1: (nd, nu) at columns i + 1, i + 2, no fill
+      d = nd;
+      u = nu;
+      w = T(0);
+      b = nb;
     }
-    if (has) x[i] = pb;
-    // the new current row i + 1: (nd, nu) at columns i + 1, i + 2 and no
-    // fill at i + 3 yet
-    d = nd;
-    u = nu;
-    w = T(0);
-    b = nb;
   }
   if (d == T(0)) singular = true;
   if (writer) {
@@ -322,7 +509,7 @@ __global__ __launch_bounds__(64) void gtsv_forward_kernel(int64_t n, const T* __
 }
 
 // Back substitution with the rows coef: x_i = (b_i - u'_i x_{i+1} -
-// w'_i x_{i+2}) / d'_i.
+// w'_i x_{i+2}) / d'_i, operands loaded kChunk rows ahead.
 template <typename T>
 __global__ __launch_bounds__(64) void gtsv_backward_kernel(int64_t n, const T* __restrict__ coef,
                                                            T* X, int64_t ldx, int64_t nrhs) {
@@ -330,110 +517,139 @@ __global__ __launch_bounds__(64) void gtsv_backward_kernel(int64_t n, const T* _
   if (col >= nrhs) return;
   T* x = X + col * ldx;
   T x1 = T(0), x2 = T(0);
-  for (int64_t i = n - 1; i >= 0; --i) {
-    const T xi = (x[i] - coef[3 * i + 1] * x1 - coef[3 * i + 2] * x2) / coef[3 * i];
-    x[i] = xi;
-    x2 = x1;
-    x1 = xi;
+  for (int64_t i0 = n - 1; i0 >= 0; i0 -= kChunk) {
+    T cd[kChunk], cu[kChunk], cw[kChunk], bb[kChunk];
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) {
+      const int64_t i = std::max<int64_t>(i0 - q, 0);
+      cd[q] = coef[3 * i];
+      cu[q] = coef[3 * i + 1];
+      cw[q] = coef[3 * i + 2];
+      bb[q] = x[i];
+    }
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) {
+      const int64_t i = i0 - q;
+      if (i < 0) break;
+      const T xi = (bb[q] - cu[q] * x1 - cw[q] * x2) / cd[q];
+      x[i] = xi;
+      x2 = x1;
+      x1 = xi;
+    }
   }
 }
 
 // ------------------------------------------------------------- host side
 
 template <typename T>
-hipError_t gemm_t(int dtype, int mode, int ta, int tb, int64_t m, int64_t n, int64_t kk,
-                  double alpha, const T* A, int64_t lda, const T* B, int64_t ldb, double beta,
-                  T* C, int64_t ldc, hipStream_t s) {
-  if (m <= 0 || n <= 0 || kk <= 0) return hipSuccess;
-  GemmConfig c = gemm_choose(dtype, 0, mode, m, n, kk);
-  c.split = 1;
-  return gemm_launch(dtype, 0, mode, ta, tb, m, n, kk, alpha, A, lda, B, ldb, beta, C, ldc,
-                     nullptr, c, s);
+hipError_t chol_panel(T* A, int64_t lda, int64_t n, int64_t k0, int32_t* info, hipStream_t s) {
+  const int jb = int(std::min<int64_t>(kB, n - k0));
+  hipLaunchKernelGGL((potrf_block_kernel<T>), dim3(1), dim3(kB), 0, s, A, lda, k0, jb, info);
+  hipError_t e = hipGetLastError();
+  const int64_t m = n - k0 - jb;
+  if (e != hipSuccess || m <= 0) return e;
+  // L21 = A21 L11^-T in place
+  hipLaunchKernelGGL((trsm_rows_kernel<T>), dim3(unsigned(cdiv(m, kB))), dim3(kB), 0, s, A, lda,
+                     k0, jb, m);
+  return hipGetLastError();
 }
 
+// Right-looking by 64-column blocks; the trailing matrix takes
+// A22 -= L21 L21^T on its lower tiles (the factorisation reads only the lower
+// triangle). With lookahead the update is split: the next block column's
+// part on s, directly followed by that block's factorisation, and the part
+// right of it on side->s, overlapping the factorisation; the next split
+// update waits for it (both write the columns right of the next block).
 template <typename T>
-hipError_t copy_cols(T* dst, int64_t ldd, const T* src, int64_t lds, int64_t rows, int64_t cols,
-                     hipStream_t s) {
-  if (rows <= 0 || cols <= 0) return hipSuccess;
-  return hipMemcpy2DAsync(dst, size_t(ldd) * sizeof(T), src, size_t(lds) * sizeof(T),
-                          size_t(rows) * sizeof(T), size_t(cols), hipMemcpyDeviceToDevice, s);
-}
-
-template <typename T>
-hipError_t chol_factor_typed(int dtype, int64_t n, T* A, int64_t lda, T* inv, T* W,
-                             int32_t* info, hipStream_t s) {
+hipError_t chol_factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* info, hipStream_t s,
+                             const Lookahead* side) {
   const int64_t np = cdiv(n, kB);
-  for (int64_t p = 0; p < np; ++p) {
-    const int64_t k0 = p * kB;
-    const int jb = int(std::min<int64_t>(kB, n - k0));
-    T* invp = inv + p * kB * kB;
-    hipLaunchKernelGGL((potrf_block_kernel<T>), dim3(1), dim3(kB), 0, s, A, lda, k0, jb, invp,
-                       info);
-    hipError_t e = hipGetLastError();
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(s, &cap);
+  if (e != hipSuccess) return e;
+  const bool lookahead = side && side->s && np >= 3 && cap == hipStreamCaptureStatusNone;
+  bool pending = false;  // side->s holds an update that the next one must follow
+  if ((e = chol_panel<T>(A, lda, n, 0, info, s)) != hipSuccess) return e;
+  for (int64_t p = 0; p + 1 < np; ++p) {
+    const int64_t k0 = p * kB, k1 = k0 + kB;  // this block, the next
+    const int64_t m = n - k1;                  // rows below this block
+    const int64_t near = std::min<int64_t>(kB, m);
+    const T* W = A + k1 + k0 * lda;  // L21, m x 64
+    if (pending) {
+      if ((e = hipStreamWaitEvent(s, side->done, 0)) != hipSuccess) return e;
+      pending = false;
+    }
+    if (!lookahead || near == m) {
+      e = syrk_lower_update_launch(dtype, m, kB, W, lda, A + k1 + k1 * lda, lda, s);
+    } else {
+      // columns k1 .. k1 + 64 (all rows from k1) on s; the rest on side->s
+      e = rank_update_bt_launch(dtype, m, near, kB, W, lda, W, lda, A + k1 + k1 * lda, lda, s);
+      if (e == hipSuccess) e = hipEventRecord(side->ready, s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->ready, 0);
+      if (e == hipSuccess)
+        e = syrk_lower_update_launch(dtype, m - near, kB, W + near, lda,
+                                     A + (k1 + near) + (k1 + near) * lda, lda, side->s);
+      if (e == hipSuccess) e = hipEventRecord(side->done, side->s);
+      pending = e == hipSuccess;
+    }
     if (e != hipSuccess) return e;
-    const int64_t m = n - k0 - jb;
-    if (m <= 0) continue;
-    T* a21 = A + (k0 + jb) + k0 * lda;
-    // W = A21 L11^-T, then A21 = W and A22 -= W W^T (lower tiles, mirrored)
-    e = gemm_t<T>(dtype, 0, 0, 1, m, jb, jb, 1.0, a21, lda, invp, kB, 0.0, W, m, s);
-    if (e == hipSuccess) e = copy_cols<T>(a21, lda, W, m, m, jb, s);
-    if (e == hipSuccess)
-      e = gemm_t<T>(dtype, 1, 0, 1, m, m, jb, -1.0, W, m, W, m, 1.0,
-                    A + (k0 + jb) + (k0 + jb) * lda, lda, s);
-    if (e != hipSuccess) return e;
+    if ((e = chol_panel<T>(A, lda, n, k1, info, s)) != hipSuccess) return e;
   }
-  return hipSuccess;
+  if (pending) e = hipStreamWaitEvent(s, side->done, 0);
+  return e;
 }
 
-// Forward L Y = B block by block (the inverse blocks of the non-unit lower
-// factor), then back substitution U X = Y where U = L^T (chol) or, for a
-// triangular matrix, only one of the two.
-template <typename T>
-hipError_t forward_typed(int dtype, int64_t n, int64_t r, const T* L, int64_t ldl,
-                         const T* inv, T* Xin, int64_t ldx, T* Y, hipStream_t s) {
-  const int64_t np = cdiv(n, kB);
-  for (int64_t p = 0; p < np; ++p) {
-    const int64_t r0 = p * kB;
-    const int jb = int(std::min<int64_t>(kB, n - r0));
-    hipError_t e = gemm_t<T>(dtype, 0, 0, 0, jb, r, jb, 1.0, inv + p * kB * kB, kB, Xin + r0, ldx,
-                             0.0, Y + r0, n, s);
-    if (e == hipSuccess)
-      e = gemm_t<T>(dtype, 0, 0, 0, n - r0 - jb, r, jb, -1.0, L + (r0 + jb) + r0 * ldl, ldl, Y + r0,
-                    n, 1.0, Xin + r0 + jb, ldx, s);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+template <typename T, int MODE>
+hipError_t trsm_step(const T* M, int64_t ldm, int64_t n, int64_t r0, int jb, const T* inv,
+                     T* X, int64_t ldx, T* Y, int64_t ldy, int64_t nrhs, hipStream_t s) {
+  const int64_t rows = MODE == 0 ? n - r0 - jb : r0;  // rows still to solve
+  const int64_t tm = 1 + cdiv(rows, kB), tn = cdiv(nrhs, kB);
+  if (tm * tn > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((trsm_step_kernel<T, MODE>), dim3(unsigned(tm * tn)), dim3(256), 0, s, M, ldm,
+                     n, r0, jb, inv, X, ldx, Y, ldy, nrhs, int(tm));
+  return hipGetLastError();
 }
 
-// U X = Y with U upper (upper = true: U stored in the upper triangle) or
-// U = L^T (upper = false: L stored in the lower triangle, inverse blocks of
-// L, so the blocks of U^-1 are their transposes).
+// X <- M^-1 X in place: which 0: M = L L^T (L the lower triangle), 1: M = L
+// (lower), 2: M = U (upper). The diagonal blocks' inverses first (one
+// launch), then one launch per block and direction. Each pass reads one
+// buffer and writes the other: forward X -> Y, backward Y -> X for L L^T;
+// a single pass's result is copied back to X.
 template <typename T>
-hipError_t backward_typed(int dtype, bool upper, int64_t n, int64_t r, const T* M, int64_t ldm,
-                          const T* inv, T* Y, int64_t ldy, T* X, int64_t ldx, hipStream_t s) {
+hipError_t tri_solve_typed(int which, int64_t n, int64_t r, const T* M, int64_t ldm, T* X,
+                           int64_t ldx, T* work, hipStream_t s) {
   const int64_t np = cdiv(n, kB);
-  for (int64_t p = np - 1; p >= 0; --p) {
-    const int64_t r0 = p * kB;
-    const int jb = int(std::min<int64_t>(kB, n - r0));
-    hipError_t e = gemm_t<T>(dtype, 0, upper ? 0 : 1, 0, jb, r, jb, 1.0, inv + p * kB * kB, kB,
-                             Y + r0, ldy, 0.0, X + r0, ldx, s);
-    if (e != hipSuccess) return e;
-    if (r0 == 0) continue;
-    // rows above: Y[0:r0] -= U[0:r0, r0:r0+jb] X_p
-    if (upper)
-      e = gemm_t<T>(dtype, 0, 0, 0, r0, r, jb, -1.0, M + r0 * ldm, ldm, X + r0, ldx, 1.0, Y, ldy, s);
-    else  // U[0:r0, p] = (L[p, 0:r0])^T
-      e = gemm_t<T>(dtype, 0, 1, 0, r0, r, jb, -1.0, M + r0, ldm, X + r0, ldx, 1.0, Y, ldy, s);
-    if (e != hipSuccess) return e;
+  T* inv = work;
+  T* Y = work + np * kB * kB;
+  const int64_t ldy = n;
+  if (which == 2)
+    hipLaunchKernelGGL((trtri_blocks_kernel<T, true>), dim3(unsigned(np)), dim3(kB), 0, s, M, ldm,
+                       n, inv);
+  else
+    hipLaunchKernelGGL((trtri_blocks_kernel<T, false>), dim3(unsigned(np)), dim3(kB), 0, s, M,
+                       ldm, n, inv);
+  hipError_t e = hipGetLastError();
+  auto jb_of = [&](int64_t p) { return int(std::min<int64_t>(kB, n - p * kB)); };
+  if (which != 2) {  // forward: L Y = X
+    for (int64_t p = 0; p < np && e == hipSuccess; ++p)
+      e = trsm_step<T, 0>(M, ldm, n, p * kB, jb_of(p), inv + p * kB * kB, X, ldx, Y, ldy, r, s);
   }
-  return hipSuccess;
+  if (which == 0) {  // backward: L^T X = Y
+    for (int64_t p = np - 1; p >= 0 && e == hipSuccess; --p)
+      e = trsm_step<T, 1>(M, ldm, n, p * kB, jb_of(p), inv + p * kB * kB, Y, ldy, X, ldx, r, s);
+    return e;
+  }
+  if (which == 2) {  // backward: U Y = X
+    for (int64_t p = np - 1; p >= 0 && e == hipSuccess; --p)
+      e = trsm_step<T, 2>(M, ldm, n, p * kB, jb_of(p), inv + p * kB * kB, X, ldx, Y, ldy, r, s);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpy2DAsync(X, size_t(ldx) * sizeof(T), Y, size_t(ldy) * sizeof(T), size_t(n) * sizeof(T),
+                         size_t(r), hipMemcpyDeviceToDevice, s);
+  return e;
 }
 
 }  // namespace
-
-size_t struct_inv_bytes(int dtype, int64_t n) {
-  return size_t(cdiv(std::max<int64_t>(n, 1), kB)) * kB * kB * (dtype == 0 ? 8 : 4);
-}
 
 hipError_t structure_launch(int dtype, int64_t n, const void* S, int64_t lds, int32_t* info,
                             hipStream_t s) {
@@ -450,84 +666,49 @@ hipError_t structure_launch(int dtype, int64_t n, const void* S, int64_t lds, in
   return hipGetLastError();
 }
 
-hipError_t chol_factor_launch(int dtype, int64_t n, void* A, int64_t lda, void* inv, void* W,
-                              int32_t* info, hipStream_t s) {
+hipError_t chol_factor_launch(int dtype, int64_t n, void* A, int64_t lda, int32_t* info,
+                              hipStream_t s, const Lookahead* side) {
   if (n <= 0) return hipSuccess;
   if (dtype == 0)
-    return chol_factor_typed<double>(0, n, static_cast<double*>(A), lda,
-                                     static_cast<double*>(inv), static_cast<double*>(W), info, s);
-  return chol_factor_typed<float>(1, n, static_cast<float*>(A), lda, static_cast<float*>(inv),
-                                  static_cast<float*>(W), info, s);
+    return chol_factor_typed<double>(0, n, static_cast<double*>(A), lda, info, s, side);
+  return chol_factor_typed<float>(1, n, static_cast<float*>(A), lda, info, s, side);
 }
 
-hipError_t trinv_launch(int dtype, bool lower, int64_t n, const void* S, int64_t lds, void* inv,
-                        int32_t* info, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  const unsigned nb = unsigned(cdiv(n, kB));
-  if (dtype == 0) {
-    if (lower)
-      hipLaunchKernelGGL((trinv_block_kernel<double, true>), dim3(nb), dim3(kB), 0, s,
-                         static_cast<const double*>(S), lds, n, static_cast<double*>(inv), info);
-    else
-      hipLaunchKernelGGL((trinv_block_kernel<double, false>), dim3(nb), dim3(kB), 0, s,
-                         static_cast<const double*>(S), lds, n, static_cast<double*>(inv), info);
-  } else {
-    if (lower)
-      hipLaunchKernelGGL((trinv_block_kernel<float, true>), dim3(nb), dim3(kB), 0, s,
-                         static_cast<const float*>(S), lds, n, static_cast<float*>(inv), info);
-    else
-      hipLaunchKernelGGL((trinv_block_kernel<float, false>), dim3(nb), dim3(kB), 0, s,
-                         static_cast<const float*>(S), lds, n, static_cast<float*>(inv), info);
-  }
-  return hipGetLastError();
+size_t tri_solve_workspace_bytes(int dtype, int64_t n, int64_t nrhs) {
+  const size_t esz = dtype == 0 ? 8 : 4;
+  return esz * size_t(cdiv(n, kB) * kB * kB + n * nrhs);
 }
 
 hipError_t tri_solve_launch(int dtype, int which, int64_t n, int64_t nrhs, const void* M,
-                            int64_t ldm, const void* inv, void* B, int64_t ldb, void* Y,
-                            void* X, int64_t ldx, hipStream_t s) {
+                            int64_t ldm, void* X, int64_t ldx, void* work, hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return hipSuccess;
-  if (dtype == 0) {
-    const double* m = static_cast<const double*>(M);
-    const double* iv = static_cast<const double*>(inv);
-    double *b = static_cast<double*>(B), *y = static_cast<double*>(Y), *x = static_cast<double*>(X);
-    hipError_t e = hipSuccess;
-    if (which == 2) return backward_typed<double>(0, true, n, nrhs, m, ldm, iv, b, ldb, x, ldx, s);
-    e = forward_typed<double>(0, n, nrhs, m, ldm, iv, b, ldb, y, s);
-    if (e != hipSuccess) return e;
-    if (which == 1) return copy_cols<double>(x, ldx, y, n, n, nrhs, s);
-    return backward_typed<double>(0, false, n, nrhs, m, ldm, iv, y, n, x, ldx, s);
-  }
-  const float* m = static_cast<const float*>(M);
-  const float* iv = static_cast<const float*>(inv);
-  float *b = static_cast<float*>(B), *y = static_cast<float*>(Y), *x = static_cast<float*>(X);
-  hipError_t e = hipSuccess;
-  if (which == 2) return backward_typed<float>(1, true, n, nrhs, m, ldm, iv, b, ldb, x, ldx, s);
-  e = forward_typed<float>(1, n, nrhs, m, ldm, iv, b, ldb, y, s);
-  if (e != hipSuccess) return e;
-  if (which == 1) return copy_cols<float>(x, ldx, y, n, n, nrhs, s);
-  return backward_typed<float>(1, false, n, nrhs, m, ldm, iv, y, n, x, ldx, s);
+  if (dtype == 0)
+    return tri_solve_typed<double>(which, n, nrhs, static_cast<const double*>(M), ldm,
+                                   static_cast<double*>(X), ldx, static_cast<double*>(work), s);
+  return tri_solve_typed<float>(which, n, nrhs, static_cast<const float*>(M), ldm,
+                                static_cast<float*>(X), ldx, static_cast<float*>(work), s);
 }
 
 hipError_t gtsv_launch(int dtype, int64_t n, int64_t nrhs, const void* S, int64_t lds, void* X,
-                       int64_t ldx, void* coef, int32_t* info, hipStream_t s) {
+                       int64_t ldx, void* work, int32_t* info, hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return hipSuccess;
-  const unsigned g = unsigned(cdiv(nrhs, 64));
+  const unsigned g = unsigned(cdiv(nrhs, 64)), ge = unsigned(cdiv(n, 256));
   if (dtype == 0) {
-    hipLaunchKernelGGL((gtsv_forward_kernel<double>), dim3(g), dim3(64), 0, s, n,
-                       static_cast<const double*>(S), lds, static_cast<double*>(X), ldx, nrhs,
-                       static_cast<double*>(coef), info);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((gtsv_backward_kernel<double>), dim3(g), dim3(64), 0, s, n,
-                       static_cast<const double*>(coef), static_cast<double*>(X), ldx, nrhs);
+    double* w = static_cast<double*>(work);
+    hipLaunchKernelGGL((tridiag_extract_kernel<double>), dim3(ge), dim3(256), 0, s, n,
+                       static_cast<const double*>(S), lds, w + 3 * n, w + 4 * n, w + 5 * n);
+    hipLaunchKernelGGL((gtsv_forward_kernel<double>), dim3(g), dim3(64), 0, s, n, w + 3 * n,
+                       w + 4 * n, w + 5 * n, static_cast<double*>(X), ldx, nrhs, w, info);
+    hipLaunchKernelGGL((gtsv_backward_kernel<double>), dim3(g), dim3(64), 0, s, n, w,
+                       static_cast<double*>(X), ldx, nrhs);
   } else {
-    hipLaunchKernelGGL((gtsv_forward_kernel<float>), dim3(g), dim3(64), 0, s, n,
-                       static_cast<const float*>(S), lds, static_cast<float*>(X), ldx, nrhs,
-                       static_cast<float*>(coef), info);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((gtsv_backward_kernel<float>), dim3(g), dim3(64), 0, s, n,
-                       static_cast<const float*>(coef), static_cast<float*>(X), ldx, nrhs);
+    float* w = static_cast<float*>(work);
+    hipLaunchKernelGGL((tridiag_extract_kernel<float>), dim3(ge), dim3(256), 0, s, n,
+                       static_cast<const float*>(S), lds, w + 3 * n, w + 4 * n, w + 5 * n);
+    hipLaunchKernelGGL((gtsv_forward_kernel<float>), dim3(g), dim3(64), 0, s, n, w + 3 * n,
+                       w + 4 * n, w + 5 * n, static_cast<float*>(X), ldx, nrhs, w, info);
+    hipLaunchKernelGGL((gtsv_backward_kernel<float>), dim3(g), dim3(64), 0, s, n, w,
+                       static_cast<float*>(X), ldx, nrhs);
   }
   return hipGetLastError();
 }

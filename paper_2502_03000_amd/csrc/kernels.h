@@ -117,37 +117,49 @@ hipError_t ew_sum_launch(int dtype, const EwProgram& p, double alpha, void* out,
                          hipStream_t s);
 
 // ------------------------------------------------------ structured solves
+// Lookahead for the factorisations (Cholesky, LU): a second stream, default priority like the caller's, and two events, owned
+// by the caller: the trailing update beyond the next panel's columns runs
+// there while the next panel is factored (the factorisation makes the
+// caller's stream wait for it before it returns).
+struct Lookahead {
+  hipStream_t s = nullptr;
+  hipEvent_t ready = nullptr, done = nullptr;
+};
+
 // info (16 ints, 8-byte aligned, cleared here): [0] lower bandwidth, [1]
 // upper bandwidth, [2] 1 if S != S^T bitwise, [3] 1 if a diagonal entry is
 // not > 0, [5] 1 if a diagonal entry is zero, 64-bit words at [8] max |S_ij|
 // and [10] max |S_ij - S_ji| (FP64 values). One pass over the n x n S (lds).
 hipError_t structure_launch(int dtype, int64_t n, const void* S, int64_t lds, int32_t* info,
                             hipStream_t s);
-// Bytes of the inverse diagonal blocks (64 x 64 each) of an n x n factor.
-size_t struct_inv_bytes(int dtype, int64_t n);
-// In-place Cholesky A = L L^T (lower triangle of A, lda), blocks of 64; the
-// inverse of each diagonal block of L goes to inv; W: n x 64 scratch.
+// In-place Cholesky A = L L^T (lower triangle of A, lda), blocks of 64.
 // A pivot that is not > 0 sets info[4] (A is then not positive definite and
-// its contents are unspecified).
-hipError_t chol_factor_launch(int dtype, int64_t n, void* A, int64_t lda, void* inv, void* W,
-                              int32_t* info, hipStream_t s);
-// Inverses of the 64 x 64 diagonal blocks of a triangular S (lower or upper,
-// non-unit) into inv; a zero diagonal entry sets info[6].
-hipError_t trinv_launch(int dtype, bool lower, int64_t n, const void* S, int64_t lds, void* inv,
-                        int32_t* info, hipStream_t s);
-// Block substitution with the inverse diagonal blocks in inv:
-//   which 0: L L^T X = B (L: the lower triangle of M), which 1: L X = B,
-//   which 2: U X = B (U: the upper triangle of M).
-// B (ldb) holds the right-hand sides and is overwritten; Y: n x nrhs
-// scratch (ld n); X (ldx) receives the solution and must not alias B or Y.
+// its contents are unspecified). With side, each next diagonal block is
+// factored while the rest of the trailing update runs on side->s.
+hipError_t chol_factor_launch(int dtype, int64_t n, void* A, int64_t lda, int32_t* info,
+                              hipStream_t s, const Lookahead* side = nullptr);
+// The lower-triangle 64 x 64 tiles (diagonal tiles whole) of the n x n C
+// (ldc) take C -= W W^T, W n x K (ldw), K <= 64: the Cholesky factorisation's
+// trailing update, C tile held in the MFMA accumulators.
+hipError_t syrk_lower_update_launch(int dtype, int64_t n, int64_t K, const void* W, int64_t ldw,
+                                   void* C, int64_t ldc, hipStream_t s);
+// C (m x n, ldc) -= A Bt^T, A m x K (lda), Bt n x K (ldbt), K <= 64, with
+// the same kernel (every tile).
+hipError_t rank_update_bt_launch(int dtype, int64_t m, int64_t n, int64_t K, const void* A,
+                                 int64_t lda, const void* Bt, int64_t ldbt, void* C, int64_t ldc,
+                                 hipStream_t s);
+// X <- M^-1 X in place (n x nrhs, ldx), by blocks of 64 with the inverses
+// of the diagonal blocks: which 0: M = L L^T (L the lower triangle of M),
+// 1: M = L (lower), 2: M = U (upper); non-unit diagonals. work:
+// tri_solve_workspace_bytes (the inverses and an n x nrhs buffer).
+size_t tri_solve_workspace_bytes(int dtype, int64_t n, int64_t nrhs);
 hipError_t tri_solve_launch(int dtype, int which, int64_t n, int64_t nrhs, const void* M,
-                            int64_t ldm, const void* inv, void* B, int64_t ldb, void* Y,
-                            void* X, int64_t ldx, hipStream_t s);
+                            int64_t ldm, void* X, int64_t ldx, void* work, hipStream_t s);
 // Tridiagonal part of S with partial pivoting; X (ldx) holds the right-hand
-// sides and receives the solution; coef: 3 n scratch; a zero pivot sets
-// info[5].
+// sides and receives the solution; work: 6 n elements of scratch; a zero
+// pivot sets info[5].
 hipError_t gtsv_launch(int dtype, int64_t n, int64_t nrhs, const void* S, int64_t lds, void* X,
-                       int64_t ldx, void* coef, int32_t* info, hipStream_t s);
+                       int64_t ldx, void* work, int32_t* info, hipStream_t s);
 
 // ---------------------------------------------------------------------- LU
 // In-place LU with partial pivoting of the n x n column-major matrix A (lda),
@@ -163,14 +175,6 @@ hipError_t gtsv_launch(int dtype, int64_t n, int64_t nrhs, const void* S, int64_
 // (FP32, nrhs > 0) the solve's exchange of solved blocks for nrhs right-hand
 // sides.
 constexpr int64_t kLuMaxN = 16384;
-// A second stream, default priority like the caller's, and two events, owned
-// by the caller: the trailing update beyond the next panel's columns runs
-// there while the next panel is factored (the factorisation makes the
-// caller's stream wait for it before it returns).
-struct Lookahead {
-  hipStream_t s = nullptr;
-  hipEvent_t ready = nullptr, done = nullptr;
-};
 size_t lu_workspace_bytes(int dtype, int64_t n, int64_t nrhs = 0);
 hipError_t lu_factor_launch(int dtype, int64_t n, void* A, int64_t lda, int32_t* rowid,
                             void* work, int32_t* status, hipStream_t s, const Lookahead* side,

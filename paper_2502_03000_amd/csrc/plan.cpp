@@ -1599,10 +1599,10 @@ class Planner {
       q.spd_known = spd;
       q.rowid = work(n * 4);
       q.luwork = work(int64_t(k::lu_workspace_bytes(dtype_, n, r)));
-      q.inv = work(int64_t(k::struct_inv_bytes(dtype_, n)));
-      q.ybuf = work(n * r * int64_t(esz_));
-      q.coef = work(3 * n * int64_t(esz_));
-      q.partial = work(n * 64 * int64_t(esz_));
+      // the tridiagonal solver's rows, or the triangular solves' inverted
+      // diagonal blocks and second buffer
+      q.coef = work(std::max<int64_t>(6 * n * int64_t(esz_),
+                                      int64_t(k::tri_solve_workspace_bytes(dtype_, n, r))));
       q.info = work(16 * 4);
       // the general case's work (LU and substitution); the structured
       // solvers do less
