@@ -56,6 +56,11 @@ def parse():
                          "element-wise pass")
     ap.add_argument("--forms", default="", help="comma-separated subset of forms (syrk, solve)")
     ap.add_argument("--no-tune", action="store_true", help="skip product autotuning")
+    ap.add_argument("--tune-save", default="",
+                    help="write the context's tuning table here after the run")
+    ap.add_argument("--tune-load", default="",
+                    help="read a tuning table before planning and skip autotuning (profiling "
+                         "runs: the same configurations as the run that saved it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -877,11 +882,17 @@ def main():
     dev = "cuda:0"
     torch.cuda.set_device(0)
     ctx = hx.Context(0)
+    if args.tune_load:
+        ctx.tune_load(args.tune_load)
+        args.no_tune = True
     single = {"small": bench_small, "syrk": bench_syrk, "solve": bench_solve,
               "batched": bench_batched, "learned": bench_learned, "diag": bench_diag,
               "struct": bench_struct}
     if args.workload in single:
-        print(json.dumps(single[args.workload](args, ctx, hx, torch, inputs)), flush=True)
+        line = single[args.workload](args, ctx, hx, torch, inputs)
+        if args.tune_save:
+            ctx.tune_save(args.tune_save)
+        print(json.dumps(line), flush=True)
         return
 
     # ---- the headline step: the FP32 chain job, then the element-wise job
@@ -1003,6 +1014,8 @@ def main():
     if cpu_inputs is not None:
         res["cpu_baseline"] = cpu_baseline(*cpu_inputs)
         res["cpu_baseline"].update(host_info())
+    if args.tune_save:
+        ctx.tune_save(args.tune_save)
     print(json.dumps(res), flush=True)
 
 
