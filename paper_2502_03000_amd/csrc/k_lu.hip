@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kPT) void panel_kernel(T* __restrict__ A, int64_t l
   __shared__ unsigned s_kh[kWaves], s_kl[kWaves];
   __shared__ int s_kp[kWaves];
   __shared__ C s_row[kNB];  // the candidate row, staged by its owner for its wave
-  __shared__ C s_piv[kNB];  // the pivot row
+  __shared__ C s_piv[2][kNB];  // the pivot row, by column parity
   __shared__ int s_wp, s_ok;
   const int g = blockIdx.x / stride;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -175,13 +175,22 @@ __global__ __launch_bounds__(kPT) void panel_kernel(T* __restrict__ A, int64_t l
   int pos = own ? r : int(kNoPos);
   if (tid == 0) s_ok = 1;
 
+  // Column j's elimination is split: right after column j's pivot row is
+  // known, each row computes only its value in column j + 1, from which the
+  // workgroup's candidate for column j + 1 is found and its header published;
+  // the rest of the row is eliminated while the other participants' headers
+  // travel, and the candidate's row is published after that (readers check
+  // every row word's tag, so the row may follow its header).
+  C cur = v[0];     // the row's value in the current column
+  C l = C(0), last = C(0);
+  int wp = 0;
 #pragma unroll 1
   for (int j = 0; j < jb; ++j) {
     const uint64_t tag = tag0 + unsigned(j);  // < 2^16
     uint64_t* base = slots + size_t(j & 1) * size_t(G) * kSlotW;
     // 1. the workgroup's candidate: largest key, lowest position
     unsigned kh, kl;
-    abs_key(v[0], kh, kl);
+    abs_key(cur, kh, kl);
     const bool cand = own & (pos >= j);
     kh = cand ? kh : 0u;
     kl = cand ? kl : 0u;
@@ -200,23 +209,41 @@ __global__ __launch_bounds__(kPT) void panel_kernel(T* __restrict__ A, int64_t l
     int bp = s_kp[0];
 #pragma unroll
     for (int q = 1; q < kWaves; ++q) {
-      const unsigned h = s_kh[q], l = s_kl[q];
+      const unsigned h = s_kh[q], ll = s_kl[q];
       const int pp = s_kp[q];
-      const bool take = (h > bh) | ((h == bh) & ((l > bl) | ((l == bl) & (pp < bp))));
+      const bool take = (h > bh) | ((h == bh) & ((ll > bl) | ((ll == bl) & (pp < bp))));
       bh = take ? h : bh;
-      bl = take ? l : bl;
+      bl = take ? ll : bl;
       bp = take ? pp : bp;
     }
-    // 2. the wave holding the candidate publishes its row (one value per
-    // lane, the last j positions - its multipliers - zeroed), then the header
-    if (__any(pos == bp)) {
+    // 2. the header: by lane 0 of the wave holding the candidate (wave 0
+    // when the workgroup has none)
+    uint64_t* slot = base + size_t(g) * kSlotW;
+    const bool holder = __any(pos == bp);
+    if (holder && lane == 0) {
+      st_word(slot, (tag << 32) | bh);
+      st_word(slot + 1, (tag << 48) | (uint64_t(unsigned(bp)) << 32) | bl);
+    } else if (bp == 0x7fffffff && wave == 0 && lane == 0) {
+      st_word(slot, tag << 32);
+      st_word(slot + 1, (tag << 48) | (uint64_t(kNoPos) << 32));
+    }
+    // 3. the rest of the previous column's elimination: rotate left by one,
+    // appending the multiplier (rows below the pivot) or the column itself
+    if (j > 0) {
+      const C* prow = s_piv[(j - 1) & 1];
+      v[0] = cur;
+#pragma unroll
+      for (int c = 1; c < kNB - 1; ++c) v[c] = v[c + 1] - l * prow[c + 1];
+      v[kNB - 1] = last;
+    }
+    // 4. the candidate's row (its multiplier part zeroed), one value per lane
+    if (holder) {
       if (pos == bp) {
 #pragma unroll
         for (int c = 0; c < kNB; ++c) s_row[c] = v[c];
       }
       wave_fence();
       const C x = lane < kNB - j ? s_row[lane] : C(0);
-      uint64_t* slot = base + size_t(g) * kSlotW;
       if constexpr (kF64) {
         const uint64_t b = uint64_t(__double_as_longlong(double(x)));
         st_word(slot + kHdrW + 2 * lane, (tag << 32) | (b & 0xffffffffu));
@@ -224,18 +251,8 @@ __global__ __launch_bounds__(kPT) void panel_kernel(T* __restrict__ A, int64_t l
       } else {
         st_word(slot + kHdrW + lane, (tag << 32) | __float_as_uint(float(x)));
       }
-      if (lane == 0) {
-        st_word(slot, (tag << 32) | bh);
-        st_word(slot + 1, (tag << 48) | (uint64_t(unsigned(bp)) << 32) | bl);
-      }
-    } else if (bp == 0x7fffffff && wave == 0) {  // no candidate in this workgroup
-      uint64_t* slot = base + size_t(g) * kSlotW;
-      if (lane == 0) {
-        st_word(slot, tag << 32);
-        st_word(slot + 1, (tag << 48) | (uint64_t(kNoPos) << 32));
-      }
     }
-    // 3. wave 0: every participant's header, the winner, the winner's row
+    // 5. wave 0: every participant's header, the winner, the winner's row
     if (wave == 0) {
       unsigned hh = 0u, hl = 0u;
       int hp = 0x7fffffff;
@@ -258,12 +275,12 @@ __global__ __launch_bounds__(kPT) void panel_kernel(T* __restrict__ A, int64_t l
           break;
         }
       }
-      int wq = 0x7fffffff, wp = 0x7fffffff;
+      int wq = 0x7fffffff, wpp = 0x7fffffff;
       if (ok) {
         const unsigned wh = wave_max_u32(hh);
         const unsigned wl = kF64 ? wave_max_u32(hh == wh ? hl : 0u) : 0u;
-        wp = wave_min_i32(((hh == wh) & (hl == wl)) ? hp : 0x7fffffff);
-        wq = wave_min_i32(((hh == wh) & (hl == wl) & (hp == wp)) ? lane : 0x7fffffff);
+        wpp = wave_min_i32(((hh == wh) & (hl == wl)) ? hp : 0x7fffffff);
+        wq = wave_min_i32(((hh == wh) & (hl == wl) & (hp == wpp)) ? lane : 0x7fffffff);
         // |pivot| > 0 is a key above (1, 0); otherwise the column is singular
         if (g == 0 && lane == 0 && !((wh > 1u) | ((wh == 1u) & (wl > 0u)))) {
           if (atomicCAS(status, 0, kStatusSingular) == 0) status[2] = int(k + j);
@@ -295,27 +312,30 @@ __global__ __launch_bounds__(kPT) void panel_kernel(T* __restrict__ A, int64_t l
             break;
           }
         }
-        s_piv[lane] = pr;
+        s_piv[j & 1][lane] = pr;
       }
       if (lane == 0) {
-        s_wp = wp;
+        s_wp = wpp;
         if (!ok) s_ok = 0;
       }
     }
     __syncthreads();
     if (!s_ok) break;  // the same for every thread of the workgroup
-    C prow[kNB];
-#pragma unroll
-    for (int c = 0; c < kNB; ++c) prow[c] = s_piv[c];
-    const int wp = s_wp;
-    const C pivot = prow[0];
-    // 4. interchange positions j and wp, eliminate below the pivot, rotate
+    wp = s_wp;
+    const C pivot = s_piv[j & 1][0];
+    // 6. interchange positions j and wp; the multiplier and the row's value
+    // in column j + 1 (the rest of the elimination follows the next header)
     pos = pos == wp ? j : (pos == j ? wp : pos);
     const bool active = own & (pos > j) & (pivot != C(0));
-    const C l = active ? v[0] / pivot : C(0);
-    const C last = active ? l : v[0];
+    l = active ? v[0] / pivot : C(0);
+    last = active ? l : v[0];
+    cur = v[1] - l * s_piv[j & 1][1];
+  }
+  if (s_ok) {  // the last column's elimination
+    const C* prow = s_piv[(jb - 1) & 1];
+    v[0] = cur;
 #pragma unroll
-    for (int c = 0; c < kNB - 1; ++c) v[c] = v[c + 1] - l * prow[c + 1];
+    for (int c = 1; c < kNB - 1; ++c) v[c] = v[c + 1] - l * prow[c + 1];
     v[kNB - 1] = last;
   }
 
