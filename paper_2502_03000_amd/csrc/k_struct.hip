@@ -51,8 +51,7 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 template <typename T>
 __global__ __launch_bounds__(256) void structure_kernel(int64_t n, const T* __restrict__ S,
                                                         int64_t lds, int32_t* info) {
-  __shared__ T sa[kB][kB + 1];
-  __shared__ T sm[kB][kB + 1];
+  __shared__ T sm[kB][kB + 1];  // the mirror tile (J, I): sm[r][c] = S(J*64 + r, I*64 + c)
   __shared__ int s_red[4][4];
   __shared__ double s_max[4][2];
   const int64_t t = blockIdx.x;
@@ -61,45 +60,46 @@ __global__ __launch_bounds__(256) void structure_kernel(int64_t n, const T* __re
   while (I * (I + 1) / 2 > t) --I;
   const int64_t J = t - I * (I + 1) / 2;
   const int r = threadIdx.x & 63, cq = threadIdx.x >> 6;
-  // tile (I, J) into sa[r][c]; tile (J, I) into sm[r][c] (both by columns)
+  // tile (I, J) into registers and tile (J, I) into LDS, every load issued
+  // before any is used (clamped addresses; columns cq + 4 q, coalesced rows)
+  T a[16], m[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int c = cq + 4 * q;
-    const int64_t i = I * kB + r, j = J * kB + c;
-    const int64_t i2 = J * kB + r, j2 = I * kB + c;
-    const bool in1 = i < n && j < n, in2 = i2 < n && j2 < n;
-    sa[r][c] = in1 ? S[std::min<int64_t>(i, n - 1) + std::min<int64_t>(j, n - 1) * lds] : T(0);
-    sm[r][c] = in2 ? S[std::min<int64_t>(i2, n - 1) + std::min<int64_t>(j2, n - 1) * lds] : T(0);
+    const int64_t i = std::min<int64_t>(I * kB + r, n - 1), j = std::min<int64_t>(J * kB + c, n - 1);
+    const int64_t i2 = std::min<int64_t>(J * kB + r, n - 1), j2 = std::min<int64_t>(I * kB + c, n - 1);
+    a[q] = S[i + j * lds];
+    m[q] = S[i2 + j2 * lds];
   }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) sm[r][cq + 4 * q] = m[q];
   __syncthreads();
   int kl = 0, ku = 0, asym = 0, nonpos = 0, zero = 0;
   double amax = 0.0, dmax = 0.0;
-#pragma unroll 4
+  const int64_t i = I * kB + r;
+#pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int c = cq + 4 * q;
-    const int64_t i = I * kB + r, j = J * kB + c;  // element of tile (I, J)
-    if (i < n && j < n) {
-      const T a = sa[r][c];
-      const T b = sm[c][r];  // element (j, i)
-      if (a != T(0)) {
-        if (i > j) kl = max(kl, int(std::min<int64_t>(i - j, 0x7fffffff)));
-        if (j > i) ku = max(ku, int(std::min<int64_t>(j - i, 0x7fffffff)));
-      }
-      if (b != T(0)) {  // the mirror element (j, i) counts for the other band
-        if (j > i) kl = max(kl, int(std::min<int64_t>(j - i, 0x7fffffff)));
-        if (i > j) ku = max(ku, int(std::min<int64_t>(i - j, 0x7fffffff)));
-      }
-      if (!(a == b)) asym = 1;  // NaN compares unequal
-      const double da = fmax(fabs(double(a)), fabs(double(b)));
-      const double dd = fabs(double(a) - double(b));
-      amax = da > amax ? da : amax;  // a NaN never replaces the maximum ...
-      dmax = dd > dmax ? dd : dmax;
-      if (a != a || b != b) dmax = __builtin_inf();  // ... but makes S unsymmetric
-      if (i == j) {
-        if (!(a > T(0))) nonpos = 1;
-        if (a == T(0)) zero = 1;
-      }
-    }
+    const int64_t j = J * kB + c;  // element (i, j) of tile (I, J); its mirror (j, i)
+    const bool in = i < n && j < n;
+    const T x = a[q];
+    const T y = sm[c][r];
+    const int d = int(std::min<int64_t>(i > j ? i - j : j - i, 0x7fffffff));
+    // x at (i, j) and y at (j, i): a nonzero below the diagonal widens the
+    // lower band, one above it the upper band
+    const bool low = in && ((i > j && x != T(0)) || (j > i && y != T(0)));
+    const bool up = in && ((j > i && x != T(0)) || (i > j && y != T(0)));
+    kl = max(kl, low ? d : 0);
+    ku = max(ku, up ? d : 0);
+    asym |= (in && !(x == y)) ? 1 : 0;  // NaN compares unequal
+    const double da = in ? fmax(fabs(double(x)), fabs(double(y))) : 0.0;
+    const double dd = in ? fabs(double(x) - double(y)) : 0.0;
+    amax = da > amax ? da : amax;  // a NaN never replaces the maximum ...
+    dmax = dd > dmax ? dd : dmax;
+    if (in && (x != x || y != y)) dmax = __builtin_inf();  // ... but makes S unsymmetric
+    const bool diag = in && i == j;
+    nonpos |= (diag && !(x > T(0))) ? 1 : 0;
+    zero |= (diag && x == T(0)) ? 1 : 0;
   }
   // workgroup maxima, then one atomic per workgroup and field
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -134,14 +134,24 @@ __global__ __launch_bounds__(256) void structure_kernel(int64_t n, const T* __re
       m0 = fmax(m0, s_max[q][0]);
       m1 = fmax(m1, s_max[q][1]);
     }
+    // an atomic only where it changes the word: thousands of workgroups
+    // updating the same few words would otherwise queue at one L2 channel
     unsigned long long* words = reinterpret_cast<unsigned long long*>(info + 8);
-    if (m0 > 0.0) atomicMax(words, static_cast<unsigned long long>(__double_as_longlong(m0)));
-    if (m1 > 0.0) atomicMax(words + 1, static_cast<unsigned long long>(__double_as_longlong(m1)));
-    if (a0) atomicMax(info + 0, a0);
-    if (a1) atomicMax(info + 1, a1);
-    if (a2) atomicOr(info + 2, 1);
-    if (a3 & 1) atomicOr(info + 3, 1);
-    if (a3 & 2) atomicOr(info + 5, 1);
+    auto ld64 = [](unsigned long long* p) {
+      return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    auto ld32 = [](int32_t* p) {
+      return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    const unsigned long long b0 = static_cast<unsigned long long>(__double_as_longlong(m0));
+    const unsigned long long b1 = static_cast<unsigned long long>(__double_as_longlong(m1));
+    if (m0 > 0.0 && b0 > ld64(words)) atomicMax(words, b0);
+    if (m1 > 0.0 && b1 > ld64(words + 1)) atomicMax(words + 1, b1);
+    if (a0 > ld32(info + 0)) atomicMax(info + 0, a0);
+    if (a1 > ld32(info + 1)) atomicMax(info + 1, a1);
+    if (a2 && !ld32(info + 2)) atomicOr(info + 2, 1);
+    if ((a3 & 1) && !ld32(info + 3)) atomicOr(info + 3, 1);
+    if ((a3 & 2) && !ld32(info + 5)) atomicOr(info + 5, 1);
   }
 }
 
