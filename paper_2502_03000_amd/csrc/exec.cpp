@@ -291,7 +291,7 @@ hexla_status run_struct_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipS
     if (e != hipSuccess) return fail(e, "solve: clear");
   }
   if (solver == HEXLA_SOLVER_CHOLESKY) {
-    e = k::chol_factor_launch(s.dtype, n, wm, ldw, info, st, &ctx->side);
+    e = k::chol_factor_launch(s.dtype, n, wm, ldw, info, addr(s.coef, b), st, &ctx->side);
     if (e == hipSuccess) e = read_info(h);
     if (e != hipSuccess) return fail(e, "solve: cholesky");
     if (h[4]) {  // not positive definite: LU on a fresh copy
@@ -301,7 +301,7 @@ hexla_status run_struct_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipS
     } else {
       e = copy_b(xo, X.ld);
       if (e == hipSuccess)
-        e = k::tri_solve_launch(s.dtype, 0, n, r, wm, ldw, xo, X.ld, addr(s.coef, b), st);
+        e = k::tri_solve_launch(s.dtype, 0, n, r, wm, ldw, xo, X.ld, addr(s.coef, b), true, st);
       if (e != hipSuccess) return fail(e, "solve: cholesky substitution");
     }
   }
@@ -331,7 +331,7 @@ hexla_status run_struct_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipS
       e = copy_b(xo, X.ld);
       if (e == hipSuccess)
         e = k::tri_solve_launch(s.dtype, solver == HEXLA_SOLVER_LOWER ? 1 : 2, n, r, wm, ldw, xo,
-                                X.ld, addr(s.coef, b), st);
+                                X.ld, addr(s.coef, b), false, st);
       break;
     case HEXLA_SOLVER_TRIDIAGONAL:
       e = copy_b(xo, X.ld);

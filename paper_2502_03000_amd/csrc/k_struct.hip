@@ -8,12 +8,11 @@
 //               its transpose, whether its diagonal is positive, and zero
 //               diagonal entries;
 //   Cholesky    right-looking, 64-column blocks: each diagonal block is
-//               factored by one wave (a row per lane, in registers); the
-//               block column below is L21 = A21 L11^-T, one row per lane
-//               (forward substitution along the row, in place), and the
-//               trailing matrix's lower tiles take the rank-64 update
-//               L21 L21^T. No pivoting, so no per-column exchange between
-//               workgroups;
+//               factored by one wave (a row per lane, in registers), which
+//               also inverts it; the block column below is L21 = A21 L11^-T
+//               as an MFMA product with that inverse, and the trailing
+//               matrix's lower tiles take the rank-64 update L21 L21^T. No
+//               pivoting, so no per-column exchange between workgroups;
 //   triangular  the inverses of all 64 x 64 diagonal blocks in one launch
 //               (substitution against the identity, one column per lane),
 //               then per block one launch: the block's solution as the
@@ -38,6 +37,15 @@ namespace {
 constexpr int kB = 64;
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Makes x a register value at this point: loads issued in a loop before a
+// loop of these are all in flight together; without it the compiler moves
+// each load next to its first use (or behind the branch of a select), and
+// each then waits for a full memory round trip in turn.
+template <typename T>
+__device__ __forceinline__ void materialize(T& x) {
+  asm volatile("" : "+v"(x));
+}
 
 // ------------------------------------------------------------ structure
 
@@ -173,17 +181,20 @@ __global__ __launch_bounds__(256) void structure_kernel(int64_t n, const T* __re
 // stored.
 template <typename T>
 __global__ __launch_bounds__(64) void potrf_block_kernel(T* __restrict__ A, int64_t lda,
-                                                         int64_t k0, int jb, int32_t* info) {
+                                                         int64_t k0, int jb, int32_t* info,
+                                                         T* __restrict__ inv) {
   __shared__ T piv[kB];      // column j before scaling: the pivot is piv[j]
   __shared__ T colj[2][kB];  // column j of L (two buffers: no reuse before two barriers)
   const int r = threadIdx.x;
   const int rr = std::min(r, jb - 1);
   T a[kB];
 #pragma unroll
-  for (int c = 0; c < kB; ++c) {
-    const T x = A[(k0 + rr) + (k0 + std::min(c, jb - 1)) * lda];
-    a[c] = (r < jb && c < jb) ? (c <= r ? x : T(0)) : (r == c ? T(1) : T(0));
-  }
+  for (int c = 0; c < kB; ++c) a[c] = A[(k0 + rr) + (k0 + std::min(c, jb - 1)) * lda];
+#pragma unroll
+  for (int c = 0; c < kB; ++c) materialize(a[c]);
+#pragma unroll
+  for (int c = 0; c < kB; ++c)
+    a[c] = (r < jb && c < jb) ? (c <= r ? a[c] : T(0)) : (r == c ? T(1) : T(0));
   bool bad = false;
 #pragma unroll
   for (int j = 0; j < kB; ++j) {
@@ -205,42 +216,97 @@ __global__ __launch_bounds__(64) void potrf_block_kernel(T* __restrict__ A, int6
     return;
   }
   if (r < jb) {
+    // descending, so that column min(c, r) finally holds a[min(c, r)]
 #pragma unroll
     for (int c = kB - 1; c >= 0; --c) A[(k0 + r) + (k0 + std::min(c, r)) * lda] = a[c];
   }
-}
-
-// The block column under a factored diagonal block: each lane takes one row
-// a of A21 (m rows) and solves w L11^T = a in place (forward substitution
-// along the row, w_c = (a_c - sum_{k<c} w_k l_ck) / l_cc, four partial sums),
-// with L11 (lower, from the diagonal block) in LDS and the row in registers.
-template <typename T>
-__global__ __launch_bounds__(64) void trsm_rows_kernel(T* __restrict__ A, int64_t lda, int64_t k0,
-                                                       int jb, int64_t m) {
+  // L11^-1 (for the block column below and for the solves): L11 into LDS
+  // (rows and columns past jb are the identity), then lane j solves
+  // L11 x = e_j by forward substitution for column j of the inverse
   __shared__ T L[kB][kB + 1];
-  const int t = threadIdx.x;
-#pragma unroll  // all 64 loads in flight at once
-  for (int c = 0; c < kB; ++c) {  // column c of the block, coalesced down the rows
-    const T x = A[(k0 + std::min(t, jb - 1)) + (k0 + std::min(c, jb - 1)) * lda];
-    L[t][c] = (t < jb && c < jb && c <= t) ? x : (t == c ? T(1) : T(0));
-  }
-  __syncthreads();
-  const int64_t i = int64_t(blockIdx.x) * kB + t;
-  T* row = A + (k0 + jb + std::min<int64_t>(i, m - 1)) + k0 * lda;
-  T w[kB];
 #pragma unroll
-  for (int c = 0; c < kB; ++c) w[c] = row[int64_t(std::min(c, jb - 1)) * lda];
+  for (int c = 0; c < kB; ++c) L[r][c] = c <= r ? a[c] : T(0);
+  __syncthreads();
+  T x[kB];
+#pragma unroll
+  for (int c = 0; c < kB; ++c) x[c] = c == r ? T(1) : T(0);
 #pragma unroll
   for (int c = 0; c < kB; ++c) {
-    T s[4] = {T(0), T(0), T(0), T(0)};
+    T t4[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-    for (int k = 0; k < c; ++k) s[k & 3] += w[k] * L[c][k];
-    w[c] = (w[c] - ((s[0] + s[1]) + (s[2] + s[3]))) / L[c][c];
+    for (int q = 0; q < c; ++q) t4[q & 3] += L[c][q] * x[q];
+    x[c] = (x[c] - ((t4[0] + t4[1]) + (t4[2] + t4[3]))) / L[c][c];
   }
-  if (i < m) {
+  T* out = inv + r * kB;
 #pragma unroll
-    for (int c = kB - 1; c >= 0; --c) row[int64_t(std::min(c, jb - 1)) * lda] = w[c];
+  for (int c = 0; c < kB; ++c) out[c] = x[c];
+}
+
+// The block column under a factored diagonal block, L21 = A21 L11^-T, as a
+// product with the inverse that the diagonal block's kernel left in D
+// (64 x 64, column-major): one workgroup per 64 rows, in place (the tile is
+// read into LDS before it is written). Computed transposed on the MFMAs:
+// result row i (an MFMA row) is column i of the tile, so 16 consecutive lanes
+// hold 16 consecutive rows of one column for the stores.
+template <typename T>
+__global__ __launch_bounds__(256) void trsm_right_kernel(T* __restrict__ A, int64_t lda,
+                                                         int64_t k0, int jb, int64_t m,
+                                                         const T* __restrict__ D) {
+  using Mf = Mfma<T>;
+  using acc_t = typename Mf::acc_t;
+  constexpr int LD = kB + 1, WT = kB / 2, F = WT / 16;
+  __shared__ T sD[kB][LD];  // sD[k][i] = D(i, k)
+  __shared__ T sB[kB][LD];  // sB[k][j] = A21(row j of the tile, k)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1, l16 = lane & 15, g = lane >> 4;
+  const int64_t row0 = k0 + jb + int64_t(blockIdx.x) * kB;  // first row of the tile
+  const int64_t rlast = k0 + jb + m - 1;
+  constexpr int PER = kB * kB / 256;
+  T vd[PER], vb[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = tid + 256 * q, a = e & (kB - 1), c = e / kB;
+    vd[q] = D[a + kB * c];
+    vb[q] = A[std::min<int64_t>(row0 + a, rlast) + (k0 + std::min(c, jb - 1)) * lda];
   }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = tid + 256 * q, a = e & (kB - 1), c = e / kB;
+    sD[c][a] = (a < jb && c < jb) ? vd[q] : T(0);
+    sB[c][a] = (c < jb) ? vb[q] : T(0);
+  }
+  __syncthreads();
+  // acc[fc][fr] register r: column wc*WT + fc*16 + Mf::row(lane, r), row
+  // wr*WT + fr*16 + l16 of the result; operand A[i][k] = D(column i, k),
+  // operand B[k][j] = A21(row j, k)
+  acc_t acc[F][F];
+#pragma unroll
+  for (int fc = 0; fc < F; ++fc)
+#pragma unroll
+    for (int fr = 0; fr < F; ++fr) acc[fc][fr] = acc_t{};
+#pragma unroll 4
+  for (int kk = 0; kk < kB; kk += 4) {
+    T d[F], b[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      d[f] = sD[kk + g][wc * WT + f * 16 + l16];
+      b[f] = sB[kk + g][wr * WT + f * 16 + l16];
+    }
+#pragma unroll
+    for (int fc = 0; fc < F; ++fc)
+#pragma unroll
+      for (int fr = 0; fr < F; ++fr) acc[fc][fr] = Mf::mma(d[fc], b[fr], acc[fc][fr]);
+  }
+#pragma unroll
+  for (int fc = 0; fc < F; ++fc)
+#pragma unroll
+    for (int fr = 0; fr < F; ++fr)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int col = wc * WT + fc * 16 + Mf::row(lane, r);
+        const int64_t row = row0 + wr * WT + fr * 16 + l16;
+        if (row <= rlast && col < jb) A[row + (k0 + col) * lda] = acc[fc][fr][r];
+      }
 }
 
 // Inverses of the diagonal 64 x 64 blocks of the lower (UPPER: upper)
@@ -256,11 +322,17 @@ __global__ __launch_bounds__(64) void trtri_blocks_kernel(const T* __restrict__ 
   const int64_t r0 = int64_t(blockIdx.x) * kB;
   const int jb = int(std::min<int64_t>(kB, n - r0));
   const int t = threadIdx.x;
-#pragma unroll  // all 64 loads in flight at once
-  for (int c = 0; c < kB; ++c) {  // column c of the block, coalesced down the rows
-    const bool tri = UPPER ? c >= t : c <= t;
-    const T x = M[(r0 + std::min(t, jb - 1)) + (r0 + std::min(c, jb - 1)) * ldm];
-    L[t][c] = (t < jb && c < jb && tri) ? x : (t == c ? T(1) : T(0));
+  {
+    T x[kB];  // column c of the block, coalesced down the rows
+#pragma unroll
+    for (int c = 0; c < kB; ++c) x[c] = M[(r0 + std::min(t, jb - 1)) + (r0 + std::min(c, jb - 1)) * ldm];
+#pragma unroll
+    for (int c = 0; c < kB; ++c) materialize(x[c]);
+#pragma unroll
+    for (int c = 0; c < kB; ++c) {
+      const bool tri = UPPER ? c >= t : c <= t;
+      L[t][c] = (t < jb && c < jb && tri) ? x[c] : (t == c ? T(1) : T(0));
+    }
   }
   __syncthreads();
   T x[kB];
@@ -552,15 +624,17 @@ __global__ __launch_bounds__(64) void gtsv_backward_kernel(int64_t n, const T* _
 // ------------------------------------------------------------- host side
 
 template <typename T>
-hipError_t chol_panel(T* A, int64_t lda, int64_t n, int64_t k0, int32_t* info, hipStream_t s) {
+hipError_t chol_panel(T* A, int64_t lda, int64_t n, int64_t k0, int32_t* info, T* inv,
+                      hipStream_t s) {
   const int jb = int(std::min<int64_t>(kB, n - k0));
-  hipLaunchKernelGGL((potrf_block_kernel<T>), dim3(1), dim3(kB), 0, s, A, lda, k0, jb, info);
+  T* d = inv + (k0 / kB) * kB * kB;  // this diagonal block's inverse
+  hipLaunchKernelGGL((potrf_block_kernel<T>), dim3(1), dim3(kB), 0, s, A, lda, k0, jb, info, d);
   hipError_t e = hipGetLastError();
   const int64_t m = n - k0 - jb;
   if (e != hipSuccess || m <= 0) return e;
   // L21 = A21 L11^-T in place
-  hipLaunchKernelGGL((trsm_rows_kernel<T>), dim3(unsigned(cdiv(m, kB))), dim3(kB), 0, s, A, lda,
-                     k0, jb, m);
+  hipLaunchKernelGGL((trsm_right_kernel<T>), dim3(unsigned(cdiv(m, kB))), dim3(256), 0, s, A, lda,
+                     k0, jb, m, d);
   return hipGetLastError();
 }
 
@@ -571,15 +645,15 @@ hipError_t chol_panel(T* A, int64_t lda, int64_t n, int64_t k0, int32_t* info, h
 // right of it on side->s, overlapping the factorisation; the next split
 // update waits for it (both write the columns right of the next block).
 template <typename T>
-hipError_t chol_factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* info, hipStream_t s,
-                             const Lookahead* side) {
+hipError_t chol_factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* info, T* inv,
+                             hipStream_t s, const Lookahead* side) {
   const int64_t np = cdiv(n, kB);
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   hipError_t e = hipStreamIsCapturing(s, &cap);
   if (e != hipSuccess) return e;
   const bool lookahead = side && side->s && np >= 3 && cap == hipStreamCaptureStatusNone;
   bool pending = false;  // side->s holds an update that the next one must follow
-  if ((e = chol_panel<T>(A, lda, n, 0, info, s)) != hipSuccess) return e;
+  if ((e = chol_panel<T>(A, lda, n, 0, info, inv, s)) != hipSuccess) return e;
   for (int64_t p = 0; p + 1 < np; ++p) {
     const int64_t k0 = p * kB, k1 = k0 + kB;  // this block, the next
     const int64_t m = n - k1;                  // rows below this block
@@ -603,7 +677,7 @@ hipError_t chol_factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* i
       pending = e == hipSuccess;
     }
     if (e != hipSuccess) return e;
-    if ((e = chol_panel<T>(A, lda, n, k1, info, s)) != hipSuccess) return e;
+    if ((e = chol_panel<T>(A, lda, n, k1, info, inv, s)) != hipSuccess) return e;
   }
   if (pending) e = hipStreamWaitEvent(s, side->done, 0);
   return e;
@@ -627,17 +701,19 @@ hipError_t trsm_step(const T* M, int64_t ldm, int64_t n, int64_t r0, int jb, con
 // a single pass's result is copied back to X.
 template <typename T>
 hipError_t tri_solve_typed(int which, int64_t n, int64_t r, const T* M, int64_t ldm, T* X,
-                           int64_t ldx, T* work, hipStream_t s) {
+                           int64_t ldx, T* work, bool have_inv, hipStream_t s) {
   const int64_t np = cdiv(n, kB);
   T* inv = work;
   T* Y = work + np * kB * kB;
   const int64_t ldy = n;
-  if (which == 2)
-    hipLaunchKernelGGL((trtri_blocks_kernel<T, true>), dim3(unsigned(np)), dim3(kB), 0, s, M, ldm,
-                       n, inv);
-  else
-    hipLaunchKernelGGL((trtri_blocks_kernel<T, false>), dim3(unsigned(np)), dim3(kB), 0, s, M,
-                       ldm, n, inv);
+  if (!have_inv) {
+    if (which == 2)
+      hipLaunchKernelGGL((trtri_blocks_kernel<T, true>), dim3(unsigned(np)), dim3(kB), 0, s, M,
+                         ldm, n, inv);
+    else
+      hipLaunchKernelGGL((trtri_blocks_kernel<T, false>), dim3(unsigned(np)), dim3(kB), 0, s, M,
+                         ldm, n, inv);
+  }
   hipError_t e = hipGetLastError();
   auto jb_of = [&](int64_t p) { return int(std::min<int64_t>(kB, n - p * kB)); };
   if (which != 2) {  // forward: L Y = X
@@ -677,11 +753,13 @@ hipError_t structure_launch(int dtype, int64_t n, const void* S, int64_t lds, in
 }
 
 hipError_t chol_factor_launch(int dtype, int64_t n, void* A, int64_t lda, int32_t* info,
-                              hipStream_t s, const Lookahead* side) {
+                              void* work, hipStream_t s, const Lookahead* side) {
   if (n <= 0) return hipSuccess;
   if (dtype == 0)
-    return chol_factor_typed<double>(0, n, static_cast<double*>(A), lda, info, s, side);
-  return chol_factor_typed<float>(1, n, static_cast<float*>(A), lda, info, s, side);
+    return chol_factor_typed<double>(0, n, static_cast<double*>(A), lda, info,
+                                     static_cast<double*>(work), s, side);
+  return chol_factor_typed<float>(1, n, static_cast<float*>(A), lda, info,
+                                  static_cast<float*>(work), s, side);
 }
 
 size_t tri_solve_workspace_bytes(int dtype, int64_t n, int64_t nrhs) {
@@ -690,13 +768,16 @@ size_t tri_solve_workspace_bytes(int dtype, int64_t n, int64_t nrhs) {
 }
 
 hipError_t tri_solve_launch(int dtype, int which, int64_t n, int64_t nrhs, const void* M,
-                            int64_t ldm, void* X, int64_t ldx, void* work, hipStream_t s) {
+                            int64_t ldm, void* X, int64_t ldx, void* work, bool have_inv,
+                            hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return hipSuccess;
   if (dtype == 0)
     return tri_solve_typed<double>(which, n, nrhs, static_cast<const double*>(M), ldm,
-                                   static_cast<double*>(X), ldx, static_cast<double*>(work), s);
+                                   static_cast<double*>(X), ldx, static_cast<double*>(work),
+                                   have_inv, s);
   return tri_solve_typed<float>(which, n, nrhs, static_cast<const float*>(M), ldm,
-                                static_cast<float*>(X), ldx, static_cast<float*>(work), s);
+                                static_cast<float*>(X), ldx, static_cast<float*>(work), have_inv,
+                                s);
 }
 
 hipError_t gtsv_launch(int dtype, int64_t n, int64_t nrhs, const void* S, int64_t lds, void* X,

@@ -135,9 +135,11 @@ hipError_t structure_launch(int dtype, int64_t n, const void* S, int64_t lds, in
 // In-place Cholesky A = L L^T (lower triangle of A, lda), blocks of 64.
 // A pivot that is not > 0 sets info[4] (A is then not positive definite and
 // its contents are unspecified). With side, each next diagonal block is
-// factored while the rest of the trailing update runs on side->s.
+// factored while the rest of the trailing update runs on side->s. work: the
+// inverses of the diagonal blocks of L, laid out as tri_solve_launch's work
+// (which then may skip computing them).
 hipError_t chol_factor_launch(int dtype, int64_t n, void* A, int64_t lda, int32_t* info,
-                              hipStream_t s, const Lookahead* side = nullptr);
+                              void* work, hipStream_t s, const Lookahead* side = nullptr);
 // The lower-triangle 64 x 64 tiles (diagonal tiles whole) of the n x n C
 // (ldc) take C -= W W^T, W n x K (ldw), K <= 64: the Cholesky factorisation's
 // trailing update, C tile held in the MFMA accumulators.
@@ -151,10 +153,12 @@ hipError_t rank_update_bt_launch(int dtype, int64_t m, int64_t n, int64_t K, con
 // X <- M^-1 X in place (n x nrhs, ldx), by blocks of 64 with the inverses
 // of the diagonal blocks: which 0: M = L L^T (L the lower triangle of M),
 // 1: M = L (lower), 2: M = U (upper); non-unit diagonals. work:
-// tri_solve_workspace_bytes (the inverses and an n x nrhs buffer).
+// tri_solve_workspace_bytes (the inverses and an n x nrhs buffer); have_inv:
+// work already holds the inverses (left there by chol_factor_launch).
 size_t tri_solve_workspace_bytes(int dtype, int64_t n, int64_t nrhs);
 hipError_t tri_solve_launch(int dtype, int which, int64_t n, int64_t nrhs, const void* M,
-                            int64_t ldm, void* X, int64_t ldx, void* work, hipStream_t s);
+                            int64_t ldm, void* X, int64_t ldx, void* work, bool have_inv,
+                            hipStream_t s);
 // Tridiagonal part of S with partial pivoting; X (ldx) holds the right-hand
 // sides and receives the solution; work: 6 n elements of scratch; a zero
 // pivot sets info[5].
