@@ -807,6 +807,19 @@ def expr_jobs(args, ctx, hx, torch, inputs, dt, tune=True):
            "elementwise": {"ms_median": ms_ew, "ms_cold": cold_ew, "gbytes": d2["bytes"] / 1e9,
                            "gbs": d2["bytes"] / (ms_ew * 1e-3) / 1e9,
                            "rel_err_vs_fp64_sampled_cols": err_ew}}
+    # the same three reads and one write with no arithmetic to speak of: the
+    # HBM rate a generated element-wise kernel of this shape reaches
+    p3 = ctx.plan(A + B + Cm)
+    out3 = p3.output(dev)
+    ws3 = p3.workspace(dev)
+    run3 = lambda: p3.execute(out3, ws3)  # noqa: E731
+    run3()
+    ms_stream = median_ms(torch, run3, reps)
+    d3 = p3.describe()
+    res["stream_probe"] = {"expression": "A + B + C", "ms_median": ms_stream,
+                           "gbs": d3["bytes"] / (ms_stream * 1e-3) / 1e9,
+                           "elementwise_rate_over_probe": (d2["bytes"] / ms_ew) / (d3["bytes"] / ms_stream)}
+    del p3, out3, ws3
     return res
 
 
@@ -948,7 +961,8 @@ def main():
     ew_kernel["kernel"] = "generated element-wise pass, median of per-launch HIP event times"
     chain32 = {k: v for k, v in j32["chain"].items()}
     chain32["frac_fp32_mfma_peak"] = chain32["tflops"] / FP32_MFMA_PEAK_TFLOPS
-    jobs = {"chain_fp32": chain32, "elementwise_fp32": j32["elementwise"]}
+    jobs = {"chain_fp32": chain32, "elementwise_fp32": j32["elementwise"],
+            "stream_probe_fp32": j32["stream_probe"]}
     cpu_inputs = None
     if not args.no_cpu_baseline:
         ncol = max(1, args.n // 2)
