@@ -8,6 +8,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace hexla {
@@ -144,6 +146,38 @@ __device__ __forceinline__ T ew_eval_at(const EwProgram& p, int64_t idx, T extra
   x.v[0] = extra;
   id.v[0] = (i == j) ? T(1) : T(0);
   return ew_eval<T, 1>(p, L, x, id).v[0];
+}
+
+// V elements of column j at rows i0, i0 + S, ..., i0 + (V - 1) S of a
+// rows x cols view through the leaves' strides: the row and column come
+// from the caller's tiling (no division per element), every leaf load is
+// issued before the program runs (rows past the view clamped to the last
+// row; their values are not used).
+template <typename T, int V, int S>
+__device__ __forceinline__ Pack<T, V> ew_eval_col(const EwProgram& p, int64_t i0, int64_t j) {
+  typename LeafRegs<T, V>::type L;
+  Pack<T, V> zero, id;
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    const int64_t i = i0 + int64_t(e) * S;
+    zero.v[e] = T(0);
+    id.v[e] = (i == j) ? T(1) : T(0);
+  }
+#pragma unroll
+  for (int l = 0; l < kEwMaxLeaf; ++l) {
+#pragma unroll
+    for (int e = 0; e < V; ++e) L[l * V + e] = T(0);
+    if (l < p.n_leaf) {
+      const T* ptr = static_cast<const T*>(p.leaf[l].ptr) + j * p.leaf[l].sj;
+      const int64_t si = p.leaf[l].si;
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const int64_t i = std::min<int64_t>(i0 + int64_t(e) * S, p.rows - 1);
+        L[l * V + e] = ptr[i * si];
+      }
+    }
+  }
+  return ew_eval<T, V>(p, L, zero, id);
 }
 
 }  // namespace k

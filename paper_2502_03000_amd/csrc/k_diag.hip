@@ -148,6 +148,33 @@ __global__ __launch_bounds__(256) void ew_sum_kernel(EwProgram p, int64_t per_bl
   }
 }
 
+// The same sum for views of at least kSumColRows rows: tiles of 256 x
+// kSumV rows of one column (row and column found once per tile, kSumV
+// elements per lane, a 16-byte pack's worth, with their loads in flight
+// together); workgroup b takes tiles b, b + G, b + 2G, ... (G workgroups),
+// so the order of the additions is fixed.
+template <typename T>
+constexpr int kSumV = 16 / int(sizeof(T));
+constexpr int64_t kSumColRows = 64;
+template <typename T>
+__global__ __launch_bounds__(256) void ew_sum_columns_kernel(EwProgram p, int64_t tiles_per_col,
+                                                             int64_t tiles, T alpha, T* out,
+                                                             T* partial) {
+  T s = T(0);
+  for (int64_t b = blockIdx.x; b < tiles; b += gridDim.x) {
+    const int64_t j = b / tiles_per_col;
+    const int64_t i0 = (b - j * tiles_per_col) * (256 * kSumV<T>) + threadIdx.x;
+    const Pack<T, kSumV<T>> r = ew_eval_col<T, kSumV<T>, 256>(p, i0, j);
+#pragma unroll
+    for (int e = 0; e < kSumV<T>; ++e) s += (i0 + int64_t(e) * 256 < p.rows) ? r.v[e] : T(0);
+  }
+  s = block_sum<T, 256>(s);
+  if (threadIdx.x == 0) {
+    if (partial) partial[blockIdx.x] = s;
+    else out[0] = alpha * s;
+  }
+}
+
 int diag_split(int64_t nd, int64_t kk) {
   // about 2048 workgroups in flight (8 per CU), each over at least 4 steps
   const int64_t blocks = cdiv(nd, kTI);
@@ -209,8 +236,15 @@ hipError_t ew_sum_typed(const EwProgram& p, double alpha, T* out, T* partial, hi
   const int64_t nb = ew_sum_blocks(count);
   const int64_t per = std::max<int64_t>(1, cdiv(count, nb));
   if (nb > 1 && !partial) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((ew_sum_kernel<T>), dim3(unsigned(nb)), dim3(256), 0, s, p, per, T(alpha), out,
-                     nb > 1 ? partial : static_cast<T*>(nullptr));
+  if (p.rows >= kSumColRows) {
+    const int64_t per_col = cdiv(p.rows, 256 * kSumV<T>);
+    hipLaunchKernelGGL((ew_sum_columns_kernel<T>), dim3(unsigned(nb)), dim3(256), 0, s, p, per_col,
+                       per_col * p.cols, T(alpha), out,
+                       nb > 1 ? partial : static_cast<T*>(nullptr));
+  } else {
+    hipLaunchKernelGGL((ew_sum_kernel<T>), dim3(unsigned(nb)), dim3(256), 0, s, p, per, T(alpha),
+                       out, nb > 1 ? partial : static_cast<T*>(nullptr));
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || nb == 1) return e;
   hipLaunchKernelGGL((sum_all_kernel<T>), dim3(1), dim3(kSumThreads), 0, s, nb,

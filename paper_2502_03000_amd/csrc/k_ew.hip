@@ -4,6 +4,8 @@
 // Sec. III). HBM-bound: per element it moves (leaves + 1) * sizeof(T) bytes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "ew_device.h"
 
 namespace hexla {
@@ -80,6 +82,31 @@ __global__ __launch_bounds__(kThreads) void ew_general_kernel(EwProgram p, T* __
   }
 }
 
+// General path for views of at least kColRows rows: tiles of kThreads x
+// kColV rows of one column, the tile's row and column found once per tile,
+// kColV elements per lane (as many as a 16-byte pack: the interpreter's
+// register vector of leaves stays in registers) with all their loads in
+// flight together.
+template <typename T>
+constexpr int kColV = 16 / int(sizeof(T));
+constexpr int64_t kColRows = 64;
+template <typename T>
+__global__ __launch_bounds__(kThreads) void ew_columns_kernel(EwProgram p, T* __restrict__ out,
+                                                              int64_t osi, int64_t osj,
+                                                              int64_t tiles_per_col,
+                                                              int64_t tiles) {
+  for (int64_t b = blockIdx.x; b < tiles; b += gridDim.x) {
+    const int64_t j = b / tiles_per_col;
+    const int64_t i0 = (b - j * tiles_per_col) * (kThreads * kColV<T>) + threadIdx.x;
+    const Pack<T, kColV<T>> r = ew_eval_col<T, kColV<T>, kThreads>(p, i0, j);
+#pragma unroll
+    for (int e = 0; e < kColV<T>; ++e) {
+      const int64_t i = i0 + int64_t(e) * kThreads;
+      if (i < p.rows) out[i * osi + j * osj] = r.v[e];
+    }
+  }
+}
+
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 template <typename T>
@@ -96,6 +123,12 @@ hipError_t launch_typed(const EwProgram& p, void* out, int64_t osi, int64_t osj,
     const int64_t blocks = (threads + kThreads - 1) / kThreads;
     hipLaunchKernelGGL((ew_contig_kernel<T, V>), dim3(unsigned(blocks)), dim3(kThreads), 0, s, p,
                        static_cast<T*>(out), n_pack, n_total);
+  } else if (p.rows >= kColRows) {
+    const int64_t per_col = (p.rows + kThreads * kColV<T> - 1) / (kThreads * kColV<T>);
+    const int64_t tiles = per_col * p.cols;
+    const int64_t blocks = std::min<int64_t>(tiles, 256 * 32);
+    hipLaunchKernelGGL((ew_columns_kernel<T>), dim3(unsigned(blocks)), dim3(kThreads), 0, s, p,
+                       static_cast<T*>(out), osi, osj, per_col, tiles);
   } else {
     int64_t blocks = (n_total + kThreads - 1) / kThreads;
     if (blocks > 256 * 32) blocks = 256 * 32;

@@ -571,6 +571,31 @@ class Planner {
     return diag_value(e.node, nullptr);
   }
 
+  // A column read with a stride and repeated across many columns (the
+  // diagonal of a matrix in diagmat(A) * B, a row vector scaling columns)
+  // would be gathered again for every column, one cache line per element;
+  // on large passes it is first copied into a contiguous column.
+  void gather_broadcasts(int e) {
+    if (e < 0 || status_ != HEXLA_OK) return;
+    if (E_[e].kind == 0) {
+      gather_broadcasts(E_[e].a);
+      gather_broadcasts(E_[e].b);
+      return;
+    }
+    if (E_[e].kind != 1) return;
+    const View v = E_[e].v;
+    if (!v.strided || v.str_j != 0 || v.str_i == 1 || v.str_i == 0 || v.cols < 8 || v.rows < 64 ||
+        v.rows * v.cols < (int64_t(1) << 20))
+      return;
+    View col = v;
+    col.cols = 1;
+    EwHost p;
+    if (!compile(add_view(col), p, false)) return;
+    View t = temp(v.rows, 1);
+    push_ew(p, t);
+    E_[e].v = bcast_cols(t, v.cols);
+  }
+
   // copy: a lone view is copied into a temporary (or dest) instead of
   // being returned as it is.
   View emit_ew(int root, const View* dest, int64_t rows, int64_t cols, bool copy = false) {
@@ -605,6 +630,7 @@ class Planner {
       }
       return emit_unfused(root, dest);
     }
+    gather_broadcasts(root);
     if (epi >= 0) {
       E_[epi].kind = 4;
       EwHost prog;
@@ -629,6 +655,7 @@ class Planner {
       E_[p].kind = 1;
       E_[p].v = v;
     }
+    gather_broadcasts(root);
     EwHost prog;
     if (status_ != HEXLA_OK || !compile(root, prog, false)) return View{};
     Step st;
