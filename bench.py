@@ -367,6 +367,11 @@ def bench_learned(args, ctx, hx, torch, inputs):
                 "end_to_end_geomean_speedup_vs_dp": float(np.exp(np.mean(np.log((pd_ + ed) / (pp + ee))))),
                 "end_to_end_win_rate_vs_dp": float(np.mean(pp + ee < pd_ + ed)),
                 "end_to_end_speedup_total_vs_dp": float((pd_ + ed).sum() / (pp + ee).sum())})
+            # executions of each plan after which the extra planning time is
+            # repaid by the faster executions (None: never, or no extra cost)
+            extra, gain = float((pp - pd_).sum()), float((ed - ee).sum())
+            summary[name]["break_even_executions_per_plan"] = (
+                extra / gain if gain > 0 and extra > 0 else None)
     summary["learned"]["chains_learned_order"] = n_learned
     t_ln = summary["learned"]["exec_ms_total"]
     t_dp = summary["dp"]["exec_ms_total"]
