@@ -515,56 +515,122 @@ __global__ __launch_bounds__(256) void tridiag_extract_kernel(int64_t n, const T
   sup[i] = i + 1 < n ? S[i + (i + 1) * lds] : T(0);
 }
 
-constexpr int kChunk = 8;  // rows whose operands are loaded ahead of their elimination
+// The right-hand sides pass through LDS in tiles of kGR rows x 64 columns:
+// a tile is loaded with one lane per row (each load instruction reads 64
+// consecutive rows of one column, one coalesced run), stored to LDS, and
+// read back with one lane per column by the elimination; results leave the
+// same way. The next tile's loads are issued before the current tile is
+// processed, so their latency hides under the elimination.
+constexpr int kGR = 64;
+
+template <typename T>
+struct TileRegs {
+  T v[64];  // the tile's row (one per lane) in each of the 64 columns
+  T c[3];   // three matrix coefficients of the lane's row
+};
+
+// Loads rows [t kGR, t kGR + kGR) of the 64 columns col0 .. (clamped past n
+// and nrhs; those values are never used).
+template <typename T>
+__device__ __forceinline__ void tile_load(TileRegs<T>& R, const T* X, int64_t ldx, int64_t n,
+                                          int64_t t, int64_t col0, int64_t nrhs) {
+  const int64_t r = std::min<int64_t>(t * kGR + threadIdx.x, n - 1);
+#pragma unroll
+  for (int c = 0; c < 64; ++c) R.v[c] = X[r + std::min<int64_t>(col0 + c, nrhs - 1) * ldx];
+}
+// INV0: the first coefficient goes to LDS as its reciprocal.
+template <bool INV0 = false, typename T>
+__device__ __forceinline__ void tile_to_lds(TileRegs<T>& R, T (*xs)[65], T (*cs)[kGR]) {
+#pragma unroll
+  for (int c = 0; c < 64; ++c) materialize(R.v[c]);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) materialize(R.c[q]);
+#pragma unroll
+  for (int c = 0; c < 64; ++c) xs[threadIdx.x][c] = R.v[c];
+  cs[0][threadIdx.x] = INV0 ? T(1) / R.c[0] : R.c[0];
+  cs[1][threadIdx.x] = R.c[1];
+  cs[2][threadIdx.x] = R.c[2];
+}
+// Writes rows [t kGR, t kGR + kGR) of the tile in LDS back (rows < n and
+// columns < nrhs only).
+template <typename T>
+__device__ __forceinline__ void tile_store(const T (*xs)[65], T* X, int64_t ldx, int64_t n,
+                                           int64_t t, int64_t col0, int64_t nrhs) {
+  const int64_t r = t * kGR + threadIdx.x;
+  if (r >= n) return;
+  const int cols = int(std::min<int64_t>(64, nrhs - col0));
+  for (int c = 0; c < cols; ++c) X[r + (col0 + c) * ldx] = xs[threadIdx.x][c];
+}
 
 // Forward elimination with partial pivoting of the tridiagonal matrix (sub,
-// dia, sup) applied to the right-hand sides in X (lane r: column col0 + r).
+// dia, sup) applied to the right-hand sides in X (lane c: column col0 + c).
 // The current row i is (d, u, w) at columns i, i+1, i+2; row i+1 is
 // (sub[i], dia[i+1], sup[i+1]); the one of the two with the larger entry in
 // column i becomes the pivot row (final row i of U: d', u', w'), the other
-// is eliminated into the new current row. The rows' operands are loaded
-// kChunk at a time ahead of use. Workgroup 0 writes the final rows to
-// coef[3 i ..]; a zero pivot sets info[5].
+// is eliminated into the new current row. Workgroup 0 writes the final rows
+// to coef[3 i ..]; a zero pivot sets info[5].
 template <typename T>
 __global__ __launch_bounds__(64) void gtsv_forward_kernel(int64_t n, const T* __restrict__ sub,
                                                           const T* __restrict__ dia,
                                                           const T* __restrict__ sup, T* X,
                                                           int64_t ldx, int64_t nrhs, T* coef,
                                                           int32_t* info) {
-  const int64_t col = int64_t(blockIdx.x) * 64 + threadIdx.x;
-  const bool has = col < nrhs;
-  T* x = X + std::min<int64_t>(col, nrhs - 1) * ldx;
-  const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
-  T d = dia[0], u = sup[0], w = T(0);
-  T b = x[0];
+  __shared__ T xs[2][kGR][65];  // [buffer][row in tile][column]
+  __shared__ T cs[2][3][kGR];   // [buffer][sub of the row before, dia, sup][row in tile]
+  const int lane = threadIdx.x;
+  const int64_t col0 = int64_t(blockIdx.x) * 64;
+  const bool writer = blockIdx.x == 0 && lane == 0;
+  const int64_t nt = (n + kGR - 1) / kGR;
+  // row g of the matrix: (sub[g - 1], dia[g], sup[g]), clamped past n
+  auto coeffs = [&](TileRegs<T>& R, int64_t t) {
+    const int64_t g = std::min<int64_t>(t * kGR + lane, n - 1);
+    R.c[0] = sub[std::max<int64_t>(g - 1, 0)];
+    R.c[1] = dia[g];
+    R.c[2] = sup[g];
+  };
+  TileRegs<T> R;
+  tile_load(R, X, ldx, n, 0, col0, nrhs);
+  coeffs(R, 0);
+  tile_to_lds(R, xs[0], cs[0]);
+  if (nt > 1) {
+    tile_load(R, X, ldx, n, 1, col0, nrhs);
+    coeffs(R, 1);
+  }
+  __syncthreads();
+  T d = dia[0], u = n > 1 ? sup[0] : T(0), w = T(0);
+  T b = xs[0][0][lane];
   bool singular = false;
-  for (int64_t i0 = 0; i0 + 1 < n; i0 += kChunk) {
-    T l1[kChunk], d1[kChunk], u1[kChunk], b1[kChunk];
-#pragma unroll
-    for (int q = 0; q < kChunk; ++q) {  // row i0 + q + 1 (clamped; unused past n - 1)
-      const int64_t r = std::min<int64_t>(i0 + q + 1, n - 1);
-      l1[q] = sub[r - 1];
-      d1[q] = dia[r];
-      u1[q] = sup[r];
-      b1[q] = x[r];
+  for (int64_t t = 0; t < nt; ++t) {
+    // the next tile into LDS (its buffer held tile t - 1, already written
+    // back), the one after it into registers
+    if (t + 1 < nt) {
+      tile_to_lds(R, xs[(t + 1) & 1], cs[(t + 1) & 1]);
+      if (t + 2 < nt) {
+        tile_load(R, X, ldx, n, t + 2, col0, nrhs);
+        coeffs(R, t + 2);
+      }
     }
-#pragma unroll
-    for (int q = 0; q < kChunk; ++q) {
-      const int64_t i = i0 + q;
-      if (i + 1 >= n) break;
+    __syncthreads();
+    const int64_t i0 = t * kGR;
+    const int64_t iend = std::min<int64_t>(i0 + kGR, n - 1);  // steps i in [i0, iend)
+    for (int64_t i = i0; i < iend; ++i) {
+      const int64_t r1 = i + 1;
+      const int bq = int(r1 / kGR) & 1, rq = int(r1 % kGR);
+      const T l1 = cs[bq][0][rq], d1 = cs[bq][1][rq], u1 = cs[bq][2][rq];  // same for every lane
+      const T b1 = xs[bq][rq][lane];
       T pd, pu, pw, pb, nd, nu, nb;
-      if (fabs(d) >= fabs(l1[q])) {  // keep row i as the pivot row
-        const T m = d != T(0) ? l1[q] / d : T(0);
+      if (fabs(d) >= fabs(l1)) {  // keep row i as the pivot row
+        const T m = d != T(0) ? l1 / d : T(0);
         pd = d, pu = u, pw = w, pb = b;
-        nd = d1[q] - m * u;
-        nu = u1[q] - m * w;
-        nb = b1[q] - m * b;
+        nd = d1 - m * u;
+        nu = u1 - m * w;
+        nb = b1 - m * b;
       } else {  // row i + 1 becomes the pivot row
-        const T m = d / l1[q];
-        pd = l1[q], pu = d1[q], pw = u1[q], pb = b1[q];
-        nd = u - m * d1[q];
-        nu = w - m * u1[q];
-        nb = b - m * b1[q];
+        const T m = d / l1;
+        pd = l1, pu = d1, pw = u1, pb = b1;
+        nd = u - m * d1;
+        nu = w - m * u1;
+        nb = b - m * b1;
       }
       if (pd == T(0)) singular = true;
       if (writer) {
@@ -572,52 +638,76 @@ __global__ __launch_bounds__(64) void gtsv_forward_kernel(int64_t n, const T* __
         coef[3 * i + 1] = pu;
         coef[3 * i + 2] = pw;
       }
-      if (has) x[i] = pb;
+      xs[t & 1][i - i0][lane] = pb;
       // the new current row i + 1: (nd, nu) at columns i + 1, i + 2, no fill
       d = nd;
-      u = nu;
+      u = r1 + 1 < n ? nu : T(0);
       w = T(0);
       b = nb;
     }
+    if (t == nt - 1) {  // the last row
+      if (d == T(0)) singular = true;
+      if (writer) {
+        coef[3 * (n - 1)] = d;
+        coef[3 * (n - 1) + 1] = T(0);
+        coef[3 * (n - 1) + 2] = T(0);
+      }
+      xs[t & 1][(n - 1) - i0][lane] = b;
+    }
+    __syncthreads();
+    tile_store(xs[t & 1], X, ldx, n, t, col0, nrhs);
   }
-  if (d == T(0)) singular = true;
-  if (writer) {
-    coef[3 * (n - 1)] = d;
-    coef[3 * (n - 1) + 1] = T(0);
-    coef[3 * (n - 1) + 2] = T(0);
-  }
-  if (has) x[n - 1] = b;
-  if (singular && threadIdx.x == 0 && blockIdx.x == 0) info[5] = 1;
+  if (singular && lane == 0 && blockIdx.x == 0) info[5] = 1;
 }
 
 // Back substitution with the rows coef: x_i = (b_i - u'_i x_{i+1} -
-// w'_i x_{i+2}) / d'_i, operands loaded kChunk rows ahead.
+// w'_i x_{i+2}) / d'_i, tiles taken from the last one down.
 template <typename T>
 __global__ __launch_bounds__(64) void gtsv_backward_kernel(int64_t n, const T* __restrict__ coef,
                                                            T* X, int64_t ldx, int64_t nrhs) {
-  const int64_t col = int64_t(blockIdx.x) * 64 + threadIdx.x;
-  if (col >= nrhs) return;
-  T* x = X + col * ldx;
+  __shared__ T xs[2][kGR][65];
+  __shared__ T cs[2][3][kGR];  // [buffer][1 / d', u', w'][row in tile]
+  const int lane = threadIdx.x;
+  const int64_t col0 = int64_t(blockIdx.x) * 64;
+  const int64_t nt = (n + kGR - 1) / kGR;
+  // row g: d'_g (its reciprocal is taken for 64 rows at once when the tile
+  // goes to LDS, off the chain of rows), u'_g, w'_g
+  auto coeffs = [&](TileRegs<T>& R, int64_t t) {
+    const int64_t g = std::min<int64_t>(t * kGR + lane, n - 1);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) R.c[q] = coef[3 * g + q];
+  };
+  TileRegs<T> R;
+  tile_load(R, X, ldx, n, nt - 1, col0, nrhs);
+  coeffs(R, nt - 1);
+  tile_to_lds<true>(R, xs[(nt - 1) & 1], cs[(nt - 1) & 1]);
+  if (nt > 1) {
+    tile_load(R, X, ldx, n, nt - 2, col0, nrhs);
+    coeffs(R, nt - 2);
+  }
+  __syncthreads();
   T x1 = T(0), x2 = T(0);
-  for (int64_t i0 = n - 1; i0 >= 0; i0 -= kChunk) {
-    T cd[kChunk], cu[kChunk], cw[kChunk], bb[kChunk];
-#pragma unroll
-    for (int q = 0; q < kChunk; ++q) {
-      const int64_t i = std::max<int64_t>(i0 - q, 0);
-      cd[q] = coef[3 * i];
-      cu[q] = coef[3 * i + 1];
-      cw[q] = coef[3 * i + 2];
-      bb[q] = x[i];
+  for (int64_t t = nt - 1; t >= 0; --t) {
+    if (t >= 1) {
+      tile_to_lds<true>(R, xs[(t - 1) & 1], cs[(t - 1) & 1]);
+      if (t >= 2) {
+        tile_load(R, X, ldx, n, t - 2, col0, nrhs);
+        coeffs(R, t - 2);
+      }
     }
-#pragma unroll
-    for (int q = 0; q < kChunk; ++q) {
-      const int64_t i = i0 - q;
-      if (i < 0) break;
-      const T xi = (bb[q] - cu[q] * x1 - cw[q] * x2) / cd[q];
-      x[i] = xi;
+    __syncthreads();
+    const int64_t i0 = t * kGR;
+    const int64_t iend = std::min<int64_t>(i0 + kGR, n);
+    for (int64_t i = iend - 1; i >= i0; --i) {
+      const int q = int(i - i0);
+      const T rd = cs[t & 1][0][q], cu = cs[t & 1][1][q], cw = cs[t & 1][2][q];  // uniform
+      const T xi = (xs[t & 1][q][lane] - cu * x1 - cw * x2) * rd;
+      xs[t & 1][q][lane] = xi;
       x2 = x1;
       x1 = xi;
     }
+    __syncthreads();
+    tile_store(xs[t & 1], X, ldx, n, t, col0, nrhs);
   }
 }
 
