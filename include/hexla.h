@@ -268,14 +268,18 @@ hexla_status hexla_static_scratch_bytes(size_t* bytes);
 
 /* Solvers a structure-aware solve chooses (expression (10) of Sec. III: the
  * matrix is analysed and a tailored solver used): S diagonal -> division;
- * lower / upper triangular -> block substitution; tridiagonal -> elimination
- * with partial pivoting between adjacent rows; symmetric (S_ij and S_ji
- * within n u max|S|, u the unit roundoff: the rounding differences of a
- * product X X^T formed by a general GEMM; the factorisation reads the lower
- * triangle) with a positive diagonal, or S = X X^T known from
- * the expression (the solve of Sec. IV's call trace) -> Cholesky, falling
- * back to LU if a pivot is not positive; anything else -> LU with partial
- * pivoting. */
+ * lower / upper triangular -> blocks of 64 rows, each solved as the product
+ * with its diagonal block's inverse (the inverse's error grows with the
+ * condition number of that 64 x 64 block, as in GPU BLAS triangular
+ * solves); tridiagonal -> elimination with partial pivoting between
+ * adjacent rows, back substitution by the pivots' reciprocals; symmetric
+ * (S_ij and S_ji within n u max|S|, u the unit roundoff: the rounding
+ * differences of a product X X^T formed by a general GEMM; the
+ * factorisation reads the lower triangle) with a positive diagonal, or
+ * S = X X^T known from the expression (the solve of Sec. IV's call trace) -> Cholesky by blocks
+ * of 64 (each diagonal block inverted for the block column below it and for
+ * the substitutions), falling back to LU if a pivot is not positive;
+ * anything else -> LU with partial pivoting. */
 typedef enum hexla_solver {
   HEXLA_SOLVER_LU = 0,
   HEXLA_SOLVER_CHOLESKY = 1,

@@ -269,6 +269,24 @@ def test_diagonal_rewrites_plan_no_full_product(ctx):
     assert p.describe()["chain_macs"] == 500 * 300 * 20 + 300 * 500 * 20 + 300 * 20
 
 
+def test_strided_broadcast_copied_before_large_passes(ctx):
+    """diagmat(S) * B reads S's diagonal (stride ld + 1) once per column of
+    B: past 2^20 elements the plan first copies it into a contiguous column
+    (one more element-wise step); small passes, and contiguous vectors, read
+    it in place."""
+    big_s, big_b = leaf(ctx, 2048, 2048), leaf(ctx, 2048, 1024)
+    assert kernels(ctx.plan(hx.diagmat(big_s) @ big_b)) == ["elementwise", "elementwise"]
+    p = ctx.plan(hx.diagmat(big_s) @ big_b)
+    first = p.describe()["steps"][0]  # the copied diagonal, a 2048 x 1 temporary
+    assert (first["out"]["rows"], first["out"]["cols"], first["out"]["buf"]) == (2048, 1, "work")
+    assert kernels(ctx.plan(hx.diagmat(leaf(ctx, 2048, 1)) @ big_b)) == ["elementwise"]
+    small_s, small_b = leaf(ctx, 300, 300), leaf(ctx, 300, 200)
+    assert kernels(ctx.plan(hx.diagmat(small_s) @ small_b)) == ["elementwise"]
+    # a multiply-and-sum over a strided diagonal read once is left alone
+    v = leaf(ctx, 2048, 1)
+    assert kernels(ctx.plan(hx.trans(v) @ hx.diagmat(big_s) @ v)) == ["sum"]
+
+
 def test_submatrix_views(ctx):
     a, b = leaf(ctx, 40, 30), leaf(ctx, 20, 40)
     e = a.col(0) + hx.trans(b.row(1))
