@@ -20,8 +20,9 @@
 //            the accumulators (split-BF16 / FP16 updates use the GEMM).
 // The solves apply the inverses of the diagonal blocks (kept in the
 // workspace): in FP32 each direction is one launch in which workgroups take
-// 64-row blocks in order and exchange solved blocks as tagged words; in FP64
-// each block step is an inverse product and a GEMM update of the rows left.
+// (64-row block, 16-column chunk) tasks in order, multiply with MFMA and
+// exchange solved blocks as tagged words; in FP64 each block step is an
+// inverse product and a GEMM update of the rows left.
 // Every wait for another wave's words spins a bounded number of times; a
 // timeout sets a status bit instead of hanging, and every wave still reaches
 // the end of the kernel.
@@ -49,18 +50,19 @@ constexpr unsigned kNoPos = 0xffff;      // position field of "no candidate"
 constexpr unsigned kSpinLimit = 1u << 20;
 constexpr int kStatusSingular = 5;  // HEXLA_E_SINGULAR
 
-constexpr int kSolveChunks = 16;  // right-hand-side chunks of kNB columns per solve launch
-constexpr int kSolveBlocks = 256;  // 64-row blocks at most (n <= kLuMaxN)
-static_assert(int64_t(kSolveBlocks) * kNB >= kLuMaxN, "solve flags");
+constexpr int kChainW = 16;                 // FP32 solve: columns per task
+constexpr int kChainWords = kNB * kChainW;  // exchange words per solved task
+constexpr int kChainCols = 1024;            // columns per pair of solve launches
+constexpr unsigned kChainGrid = 512;        // solve workgroups at most (resident)
+
 
 struct LuWork {
   void* inv;           // [n_panels][2][kNB][kNB]: L11^-1 and U11^-1 of each diagonal block
   uint64_t* slots;     // [2][G][kSlotW] tagged words, by column parity
   int32_t* swap_cnt;   // [n_panels]
   int32_t* swap_list;  // [n_panels][2 * kNB][2]   (dst, src)
-  unsigned* tickets;   // [2][kSolveChunks] block tickets of the forward and backward solves
-  uint64_t* flags;     // [kSolveChunks][kSolveBlocks] tag of each solved block
-  uint64_t* xw;        // [chunk][block] solved blocks, kNB * kNB values in 64-bit words
+  unsigned* tickets;   // [2] task tickets of the forward and backward FP32 solves
+  uint64_t* xw;        // [chunk][block] solved tasks of the FP32 solve, tagged words
 };
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -84,16 +86,14 @@ LuWork carve(void* work, int64_t n) {
   p = static_cast<char*>(work) + ((size_t(p - static_cast<char*>(work)) + 255) & ~size_t(255));
   w.tickets = reinterpret_cast<unsigned*>(p);
   p += 256;
-  w.flags = reinterpret_cast<uint64_t*>(p);
-  p += size_t(kSolveChunks) * kSolveBlocks * sizeof(uint64_t);
   w.xw = reinterpret_cast<uint64_t*>(p);
   return w;
 }
-// 64-bit exchange words of one launch of the blocked solve (enough for FP64,
-// which takes one word per value; FP32 packs two)
+// 64-bit exchange words of one pair of launches of the FP32 blocked solve
+// (one word per value)
 size_t solve_words(int64_t n, int64_t nrhs) {
-  const int64_t chunks = std::min<int64_t>(cdiv(nrhs, kNB), kSolveChunks);
-  return size_t(chunks) * size_t(cdiv(n, kNB)) * kNB * kNB;
+  const int64_t chunks = std::min<int64_t>(cdiv(nrhs, kChainW), kChainCols / kChainW);
+  return size_t(chunks) * size_t(cdiv(n, kNB)) * kChainWords;
 }
 
 // Words other waves read: single-copy atomic 64-bit stores and loads at
@@ -434,150 +434,151 @@ __global__ __launch_bounds__(kNB) void inv_block_kernel(const T* __restrict__ A,
   for (int i = 0; i < kNB; ++i) out[i + c * kNB] = x[i];
 }
 
-// Blocked triangular solve in one launch: T X = X in place for the unit
-// lower (forward, L) or upper (backward, U) factor, 64-row blocks, with the
-// inverses of the diagonal blocks. Block i of X is T_ii^-1 (X_i - sum_j T_ij
-// X_j) over the blocks j solved before it (j < i forward, j > i backward, in
-// solve order). Workgroups take blocks in solve order from a ticket counter,
-// so every block a workgroup waits for belongs to a workgroup that is already
-// running (no deadlock, whatever the residency). A solved block goes to the
-// exchange as device-coherent 64-bit words (two FP32 values or one FP64 value
-// each); once every thread's stores have completed, the block's flag gets its
-// tag (tag0 + block). A reader polls the flag (one thread), then every thread
-// loads the block's words; each dependency's block T_ij is loaded before
-// that, and both pass through LDS. Thread (row, g) keeps row `row` of 16 of
-// the chunk's 64 columns (g * 16 ...); padding rows and columns are exact
-// zeros. Every wait is bounded: a timeout raises status[1] and the
-// workgroup exits.
-template <typename T, bool UPPER>
-__global__ __launch_bounds__(256) void block_solve_kernel(
-    const T* __restrict__ LU, int64_t lda, int64_t n, const T* __restrict__ inv, T* __restrict__ X,
-    int64_t ldx, int64_t c_begin, int64_t nrhs, uint64_t* xw, uint64_t* flags, unsigned* tickets,
-    unsigned tag0, int32_t* status) {
-  constexpr bool kF64 = sizeof(T) == 8;
-  constexpr int VPW = kF64 ? 1 : 2;        // values per exchange word
-  constexpr int WPB = kNB * kNB / VPW;     // words per block
-  constexpr int WPT = WPB / 256;           // words per thread
-  constexpr int XP = kF64 ? 2 : 4;         // keeps rows of xs 16-byte aligned
-  constexpr int PER = kNB * kNB / 256;     // block elements per thread
-  __shared__ __attribute__((aligned(16))) T xs[kNB][kNB + XP];  // X_j by [row k][column]
-  __shared__ T ts[kNB][kNB + 1];                                 // T_ij by [row][column k]
-  __shared__ int s_t, s_ok;
+// Blocked triangular solve in one launch (FP32): T X = X in place for the
+// unit lower (forward, L) or upper (backward, U) factor, 64-row blocks, with
+// the inverses of the diagonal blocks. Block i of X is T_ii^-1 (X_i - sum_j
+// T_ij X_j) over the blocks j solved before it (j < i forward, j > i
+// backward, in solve order). A task is one 64-row block of one 16-column
+// chunk; workgroups take tasks in solve order (block-major) from a ticket
+// counter, so every task a workgroup waits for belongs to a workgroup that is
+// already running (no deadlock, whatever the residency). Wave w of the
+// workgroup owns rows 16w..16w+15 of the block: its accumulator is one 16x16
+// MFMA tile, X_i(row 16w + 4(l/16) + r, column l%16) in register r of lane
+// l. Per dependency the wave multiplies its 16 rows of T_ij (operand A,
+// loaded straight from the factor) by the solved chunk X_j (operand B, read
+// from the exchange), 16 MFMA steps of k = 4; the loads of the next
+// dependency are issued before the products of this one. The inverse is
+// applied after one pass of the accumulators through LDS. A solved block goes
+// to the exchange as 64-bit words, the FP32 value in the low half and the tag
+// (tag0 + block) in the high half, stored in the order the readers' lanes
+// load them (word 64 s + l: row 4 s + l/16, column l%16), so a reader knows
+// from each word alone whether it holds this solve's value: no flag and no
+// wait for store completion. The exchange and the tickets start at zero
+// (tags start at 1). Padding rows and columns are exact zeros. Every wait is
+// bounded: a timeout raises status[1] and the workgroup exits.
+template <bool UPPER>
+__global__ __launch_bounds__(256) void chain_solve_kernel(
+    const float* __restrict__ LU, int64_t lda, int64_t n, const float* __restrict__ inv,
+    float* __restrict__ X, int64_t ldx, int64_t c_begin, int64_t nrhs, int chunks, uint64_t* xw,
+    unsigned* ticket, unsigned tag0, int32_t* status) {
+  using Mf = Mfma<float>;
+  using acc_t = Mf::acc_t;
+  __shared__ float sacc[kNB][kChainW + 1];
+  __shared__ int s_t, s_bad;
   const int nb = int((n + kNB - 1) / kNB);
-  const int ch = blockIdx.y;
-  const int64_t c0 = c_begin + int64_t(ch) * kNB;
-  const int rc = int(std::min<int64_t>(kNB, nrhs - c0));
-  uint64_t* xch = xw + size_t(ch) * size_t(nb) * WPB;
-  uint64_t* fch = flags + size_t(ch) * kSolveBlocks;
-  const int tid = threadIdx.x, row = tid & 63, g = tid >> 6;
-  if (tid == 0) s_ok = 1;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+  if (tid == 0) s_bad = 0;
   for (;;) {
-    if (tid == 0) s_t = int(atomicAdd(tickets + ch, 1u));
+    if (tid == 0) s_t = int(atomicAdd(ticket, 1u));
     __syncthreads();
     const int t = s_t;
-    if (t >= nb || !s_ok) break;
-    const int bi = UPPER ? nb - 1 - t : t;
+    if (t >= nb * chunks) break;
+    const int bt = t / chunks, ch = t % chunks;
+    const int bi = UPPER ? nb - 1 - bt : bt;
     const int64_t r0 = int64_t(bi) * kNB;
     const int ib = int(std::min<int64_t>(kNB, n - r0));
-    T acc[16];
+    const int64_t c0 = c_begin + int64_t(ch) * kChainW;
+    const int rc = int(std::min<int64_t>(kChainW, nrhs - c0));
+    const uint64_t* xch = xw + size_t(ch) * size_t(nb) * kChainWords;
+    const int arow = 16 * w + l16;  // this lane's operand-A row of the block
+    const int arow_c = std::min(arow, ib - 1);
+    // accumulator: rows 16w + 4g + r, column l16 of X_i
+    acc_t acc;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int c = g * 16 + q;
-      const T v = X[(r0 + min(row, ib - 1)) + (c0 + min(c, rc - 1)) * ldx];
-      acc[q] = (row < ib && c < rc) ? v : T(0);
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * w + 4 * g + r;
+      const float v = X[(r0 + std::min(row, ib - 1)) + (c0 + std::min(l16, rc - 1)) * ldx];
+      acc[r] = (row < ib && l16 < rc) ? v : 0.0f;
     }
-    // T_ii^-1 (column-major, padded with the identity), loaded now, used last
-    const T* iv = inv + size_t(bi) * 2 * kNB * kNB + (UPPER ? kNB * kNB : 0);
-    T ivv[PER];
+    // T_ii^-1 rows 16w.. as operand A (column-major, padded with the identity)
+    const float* iv = inv + size_t(bi) * 2 * kNB * kNB + (UPPER ? kNB * kNB : 0);
+    float ia[16];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) ivv[q] = iv[tid + 256 * q];
-    for (int d = 0; d < t; ++d) {
+    for (int s4 = 0; s4 < 16; ++s4) ia[s4] = iv[arow + kNB * (4 * s4 + g)];
+    // operand A of dependency d: -T(r0 + arow, j0 + 4 s + g), zero outside
+    auto load_t = [&](int d, float* ta) {
       const int bj = UPPER ? nb - 1 - d : d;
       const int64_t j0 = int64_t(bj) * kNB;
       const int jbj = int(std::min<int64_t>(kNB, n - j0));
-      // T_ij: element (i, k) from thread e % 64 (coalesced columns)
-      T lv[PER];
+      const float* base = LU + (r0 + arow_c) + j0 * lda;
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int e = tid + 256 * q, i = e % kNB, k = e / kNB;
-        lv[q] = LU[(r0 + min(i, ib - 1)) + (j0 + min(k, jbj - 1)) * lda];
+      for (int s4 = 0; s4 < 16; ++s4) {
+        const int k = 4 * s4 + g;
+        const float v = base[int64_t(std::min(k, jbj - 1)) * lda];
+        ta[s4] = (arow < ib && k < jbj) ? -v : 0.0f;
       }
-      if (tid == 0) {
-        const uint64_t tag = tag0 + unsigned(bj);
-        unsigned spins = 0;
-        while (ld_word(fch + bj) != tag)
-          if (!keep_waiting(spins, status + 1)) {
-            s_ok = 0;
-            break;
-          }
+    };
+    auto load_x = [&](int d, uint64_t* wd) {
+      const int bj = UPPER ? nb - 1 - d : d;
+      const uint64_t* src = xch + size_t(bj) * kChainWords + lane;
+#pragma unroll
+      for (int s4 = 0; s4 < 16; ++s4) wd[s4] = ld_word(src + 64 * s4);
+    };
+    bool ok = true;
+    float ta[16];
+    uint64_t wd[16];
+    if (bt > 0) {
+      load_t(0, ta);
+      load_x(0, wd);
+    }
+    for (int d = 0; d < bt; ++d) {
+      float tn[16];
+      uint64_t wn[16];
+      if (d + 1 < bt) {
+        load_t(d + 1, tn);
+        load_x(d + 1, wn);
       }
-      __syncthreads();
-      if (!s_ok) break;
-      // X_j: word w holds row w % 64 of column w / 64 (FP64) or of columns
-      // 2 (w / 64) and the next (FP32, low half first)
-      const uint64_t* src = xch + size_t(bj) * WPB;
-      uint64_t wv[WPT];
+      // the words of dependency d: re-read those not yet tagged for it
+      const int bj = UPPER ? nb - 1 - d : d;
+      const unsigned want = tag0 + unsigned(bj);
+      const uint64_t* src = xch + size_t(bj) * kChainWords + lane;
+      unsigned spins = 0;
+      for (;;) {
+        bool mine = true;
 #pragma unroll
-      for (int q = 0; q < WPT; ++q) wv[q] = ld_word(src + tid + 256 * q);
-#pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int e = tid + 256 * q, i = e % kNB, k = e / kNB;
-        ts[i][k] = (i < ib && k < jbj) ? lv[q] : T(0);
-      }
-#pragma unroll
-      for (int q = 0; q < WPT; ++q) {
-        const int w = tid + 256 * q, r = w % kNB, cw = w / kNB;
-        if constexpr (kF64) {
-          xs[r][cw] = T(__longlong_as_double((long long)wv[q]));
-        } else {
-          xs[r][2 * cw] = T(__uint_as_float(unsigned(wv[q])));
-          xs[r][2 * cw + 1] = T(__uint_as_float(unsigned(wv[q] >> 32)));
+        for (int s4 = 0; s4 < 16; ++s4) mine &= unsigned(wd[s4] >> 32) == want;
+        if (__all(mine)) break;
+        if (__any(!keep_waiting(spins, status + 1))) {
+          ok = false;
+          break;
         }
+#pragma unroll
+        for (int s4 = 0; s4 < 16; ++s4)
+          if (unsigned(wd[s4] >> 32) != want) wd[s4] = ld_word(src + 64 * s4);
       }
-      __syncthreads();
-#pragma unroll 4
-      for (int k = 0; k < kNB; ++k) {
-        const T a = ts[row][k];
+      if (!ok) break;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] -= a * xs[k][g * 16 + q];
+      for (int s4 = 0; s4 < 16; ++s4)
+        acc = Mf::mma(ta[s4], __uint_as_float(unsigned(wd[s4])), acc);
+#pragma unroll
+      for (int s4 = 0; s4 < 16; ++s4) {
+        ta[s4] = tn[s4];
+        wd[s4] = wn[s4];
       }
-      __syncthreads();
     }
-    if (!s_ok) break;
-    // X_i = T_ii^-1 acc
+    if (!ok) s_bad = 1;  // read only after the barrier below
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = tid + 256 * q;
-      ts[e % kNB][e / kNB] = ivv[q];  // (i, k) at i + 64 k
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) xs[row][g * 16 + q] = acc[q];
+    for (int r = 0; r < 4; ++r) sacc[16 * w + 4 * g + r][l16] = acc[r];
     __syncthreads();
-    T x[16];
+    if (s_bad) break;
+    // X_i = T_ii^-1 acc: operand B[k][j] = acc(4 s + g, l16)
+    acc_t x = acc_t{};
 #pragma unroll
-    for (int q = 0; q < 16; ++q) x[q] = T(0);
-#pragma unroll 4
-    for (int k = 0; k < kNB; ++k) {
-      const T a = ts[row][k];
+    for (int s4 = 0; s4 < 16; ++s4) x = Mf::mma(ia[s4], sacc[4 * s4 + g][l16], x);
+    uint64_t* dst = xw + size_t(ch) * size_t(nb) * kChainWords + size_t(bi) * kChainWords;
+    const uint64_t tag = uint64_t(tag0 + unsigned(bi)) << 32;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) x[q] += a * xs[k][g * 16 + q];
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * w + 4 * g + r;  // word 64 s + l holds row 4 s + l/16
+      st_word(dst + row * kChainW + l16, tag | __float_as_uint(x[r]));
     }
-    uint64_t* dst = xch + size_t(bi) * WPB;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int c = g * 16 + q;
-      if (row < ib && c < rc) X[(r0 + row) + (c0 + c) * ldx] = x[q];
-      if constexpr (kF64) {
-        st_word(dst + row + c * kNB, uint64_t(__double_as_longlong(double(x[q]))));
-      } else if (q % 2 == 0) {
-        st_word(dst + row + (c / 2) * kNB,
-                (uint64_t(__float_as_uint(float(x[q + 1]))) << 32) | __float_as_uint(float(x[q])));
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * w + 4 * g + r;
+      if (row < ib && l16 < rc) X[(r0 + row) + (c0 + l16) * ldx] = x[r];
     }
-    __builtin_amdgcn_s_waitcnt(0);  // this thread's block words have completed
-    __syncthreads();
-    if (tid == 0) st_word(fch + bi, tag0 + unsigned(bi));
-    __syncthreads();  // ts, xs and s_t are reused
+    __syncthreads();  // sacc, s_t and s_bad are reused
   }
 }
 
@@ -876,11 +877,9 @@ hipError_t apply_inverse(int dtype, int jb, int64_t nrhs, const T* inv, T* X, in
 }
 
 // Solve in FP32: forward and backward substitution each in one launch of
-// block_solve_kernel. Solve in FP64: one launch per block step (the inverse
-// of the diagonal block applied, then the rows still to solve updated with a
-// product), which measured faster than the one-launch form in FP64 (5.9 vs
-// 8.3 ms for n = 8192, 64 right-hand sides), while FP32 measured the other
-// way (3.3 vs 5.3 ms).
+// chain_solve_kernel per 1024 columns. Solve in FP64: one launch per block
+// step (the inverse of the diagonal block applied, then the rows still to
+// solve updated with a product).
 template <typename T>
 hipError_t solve_typed(int64_t n, int64_t nrhs, const T* LU, int64_t lda, const int32_t* rowid,
                        void* work, const T* B, int64_t ldb, T* X, int64_t ldx, int32_t* status,
@@ -915,24 +914,21 @@ hipError_t solve_typed(int64_t n, int64_t nrhs, const T* LU, int64_t lda, const 
     }
     return hipSuccess;
   } else {
-    if (reinterpret_cast<uintptr_t>(w.xw) % 8 != 0) return hipErrorInvalidValue;
     const T* inv = static_cast<const T*>(w.inv);
     const int64_t nb = cdiv(n, kNB);
-    const unsigned grid = unsigned(std::min<int64_t>(nb, 256));
-    for (int64_t cb = 0; cb < nrhs; cb += int64_t(kSolveChunks) * kNB) {
-      const int64_t cols = std::min<int64_t>(nrhs - cb, int64_t(kSolveChunks) * kNB);
-      const unsigned chunks = unsigned(cdiv(cols, kNB));
-      // fresh tickets and flags (forward tags 1..nb, backward nb+1..2nb)
-      e = fill_i32_launch(reinterpret_cast<int32_t*>(w.tickets), 2 * kSolveChunks, 0, s);
-      if (e == hipSuccess)
-        e = fill_i32_launch(reinterpret_cast<int32_t*>(w.flags), 2 * kSolveChunks * kSolveBlocks, 0, s);
+    for (int64_t cb = 0; cb < nrhs; cb += kChainCols) {
+      const int64_t cols = std::min<int64_t>(nrhs - cb, kChainCols);
+      const int chunks = int(cdiv(cols, kChainW));
+      const unsigned grid = unsigned(std::min<int64_t>(nb * chunks, kChainGrid));
+      // fresh tickets and words (forward tags 1..nb, backward nb+1..2nb)
+      e = fill_i32_launch(reinterpret_cast<int32_t*>(w.tickets),
+                          256 / 4 + 2 * int64_t(chunks) * nb * kChainWords, 0, s);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((block_solve_kernel<T, false>), dim3(grid, chunks), dim3(256), 0, s, LU,
-                         lda, n, inv, X, ldx, cb, nrhs, w.xw, w.flags, w.tickets, 1u, status);
+      hipLaunchKernelGGL((chain_solve_kernel<false>), dim3(grid), dim3(256), 0, s, LU, lda, n, inv,
+                         X, ldx, cb, nrhs, chunks, w.xw, w.tickets, 1u, status);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL((block_solve_kernel<T, true>), dim3(grid, chunks), dim3(256), 0, s, LU,
-                         lda, n, inv, X, ldx, cb, nrhs, w.xw, w.flags, w.tickets + kSolveChunks,
-                         unsigned(nb + 1), status);
+      hipLaunchKernelGGL((chain_solve_kernel<true>), dim3(grid), dim3(256), 0, s, LU, lda, n, inv,
+                         X, ldx, cb, nrhs, chunks, w.xw, w.tickets + 1, unsigned(nb + 1), status);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
@@ -950,7 +946,6 @@ size_t lu_workspace_bytes(int dtype, int64_t n, int64_t nrhs) {
   b += size_t(np) * 4 * kNB * sizeof(int32_t);
   b = (b + 255) & ~size_t(255);
   b += 256;  // tickets
-  b += size_t(kSolveChunks) * kSolveBlocks * sizeof(uint64_t);  // block flags
   // the FP32 solve's exchange (the FP64 solve launches per block step)
   if (dtype == 1 && nrhs > 0) b += solve_words(std::max<int64_t>(n, 1), nrhs) * sizeof(uint64_t);
   return (b + 255) & ~size_t(255);
