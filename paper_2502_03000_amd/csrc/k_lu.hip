@@ -356,16 +356,18 @@ __global__ __launch_bounds__(kPT) void panel_kernel(T* __restrict__ A, int64_t l
   }
 }
 
-// Gather of the moved rows on the columns outside the panel; column index n
-// stands for the row-origin vector. One wave per column.
+// Gather of the moved rows on the columns outside the panel and the `skip`
+// columns after it; column index n stands for the row-origin vector. One
+// wave per column.
 template <typename T>
 __global__ __launch_bounds__(256) void laswp_kernel(T* __restrict__ A, int64_t lda, int64_t n,
-                                                    int64_t k, int jb, const int32_t* swap_cnt,
+                                                    int64_t k, int jb, int64_t skip,
+                                                    const int32_t* swap_cnt,
                                                     const int32_t* swap_list, int32_t* rowid) {
   const int lane = threadIdx.x & 63;
   int64_t c = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  if (c >= n - jb + 1) return;
-  if (c >= k) c += jb;  // skip the panel's own columns; c == n is rowid
+  if (c >= n - jb - skip + 1) return;
+  if (c >= k) c += jb + skip;  // c == n is rowid
   const int cnt = min(*swap_cnt, 2 * kNB);
   if (c == n) {
     int32_t a0 = 0, a1 = 0;
@@ -383,6 +385,97 @@ __global__ __launch_bounds__(256) void laswp_kernel(T* __restrict__ A, int64_t l
   __builtin_amdgcn_wave_barrier();
   if (lane < cnt) col[swap_list[2 * lane]] = a0;
   if (lane + 64 < cnt) col[swap_list[2 * (lane + 64)]] = a1;
+}
+
+// The critical-path work between two panels in one workgroup: the panel's
+// row interchanges on the next nn (<= kNB) columns, L11^-1 (into inv) and
+// U12 = L11^-1 A12 on those columns, in place. Every load (the interchanged
+// rows, L11 and A12 through the interchange map) returns before any store.
+// Wave 0 builds L11^-1 column by column (lane c: L11 x = e_c), wave 1 the nn
+// columns of U12 (lane c: L11 x = A12(:, c)), both by right-looking
+// substitution with the column in registers (64 steps; each step's updates
+// are independent) and L11 in LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void panel_step_kernel(T* __restrict__ A, int64_t lda, int64_t n,
+                                                         int64_t k, int jb, int nn,
+                                                         const int32_t* swap_cnt,
+                                                         const int32_t* swap_list,
+                                                         T* __restrict__ inv) {
+  __shared__ T Lt[kNB][kNB];  // Lt[l][i] = L11(i, l), unit diagonal, identity padding
+  __shared__ int64_t src_of[kNB];  // row that lands at position k + i
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int cnt = min(*swap_cnt, 2 * kNB);
+  const int64_t c0 = k + jb;  // first of the nn columns
+  if (tid < kNB) src_of[tid] = k + tid;
+  // L11: element (i, l) from thread e % 64 (coalesced columns)
+  constexpr int PER = kNB * kNB / 256;
+  T lv[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = tid + 256 * q, i = e % kNB, l = e / kNB;
+    lv[q] = A[(k + min(i, jb - 1)) + (k + min(l, jb - 1)) * lda];
+  }
+  // interchanged rows of the nn columns: wave w takes columns w, w + 4, ...;
+  // lane takes entries lane and lane + 64
+  int32_t dst[2];
+  T gv[2][kNB / 4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = min(lane + 64 * h, max(cnt - 1, 0));
+    dst[h] = lane + 64 * h < cnt ? swap_list[2 * e] : -1;
+    const int64_t src = cnt > 0 ? swap_list[2 * e + 1] : k;
+#pragma unroll
+    for (int j = 0; j < kNB / 4; ++j) {  // (nn == 0: a column of the panel, not used)
+      const int64_t c = nn > 0 ? c0 + min(w + 4 * j, nn - 1) : k;
+      gv[h][j] = A[src + c * lda];
+    }
+  }
+  __syncthreads();  // src_of initialised
+  if (tid < cnt) {
+    const int64_t d = swap_list[2 * tid];
+    if (d < k + jb) src_of[d - k] = swap_list[2 * tid + 1];
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = tid + 256 * q, i = e % kNB, l = e / kNB;
+    Lt[l][i] = (i < jb && l < jb && i > l) ? lv[q] : T(i == l ? 1 : 0);
+  }
+  __syncthreads();
+  T x[kNB];
+  if (w == 0) {
+#pragma unroll
+    for (int i = 0; i < kNB; ++i) x[i] = i == lane ? T(1) : T(0);
+  } else if (w == 1 && nn > 0) {  // nn > 0 only below a full panel (jb == kNB)
+    const int64_t col = (c0 + min(lane, nn - 1)) * lda;
+#pragma unroll
+    for (int i = 0; i < kNB; ++i) x[i] = A[src_of[i] + col];
+  }
+  __builtin_amdgcn_s_waitcnt(0);  // every load of this thread has returned
+  __syncthreads();                // ... and of every other thread
+  // the interchanges below the U12 rows (those rows get U12 itself)
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    if (dst[h] >= k + jb) {
+#pragma unroll
+      for (int j = 0; j < kNB / 4; ++j) {
+        const int c = w + 4 * j;
+        if (c < nn) A[dst[h] + (c0 + c) * lda] = gv[h][j];
+      }
+    }
+  if (w > 1 || (w == 1 && nn == 0)) return;
+#pragma unroll
+  for (int l = 0; l < kNB; ++l) {
+    const T xl = x[l];
+#pragma unroll
+    for (int i = l + 1; i < kNB; ++i) x[i] -= Lt[l][i] * xl;
+  }
+  if (w == 0) {
+#pragma unroll
+    for (int i = 0; i < kNB; ++i) inv[i + lane * kNB] = x[i];
+  } else if (lane < nn) {
+#pragma unroll
+    for (int i = 0; i < kNB; ++i) A[(k + i) + (c0 + lane) * lda] = x[i];
+  }
 }
 
 // Inverses of the diagonal blocks (jb x jb, padded to kNB x kNB with the
@@ -816,50 +909,56 @@ hipError_t factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* rowid,
       if ((e = hipStreamWaitEvent(s, side->done, 0)) != hipSuccess) return e;
       pending = false;
     }
-    const int64_t cols = n - jb + 1;
-    hipLaunchKernelGGL((laswp_kernel<T>), dim3(unsigned(cdiv(cols, 4))), dim3(256), 0, s, A, lda,
-                       n, k, jb, w.swap_cnt + p, list, rowid);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // on s: the interchanges and U12 on the next panel's columns and L11^-1
     const int64_t right = n - k - jb;
-    if (right > 0) {
-      T* a12 = A + k + (k + jb) * lda;
+    const int nn = int(std::min<int64_t>(kNB, right));
+    const int64_t far = right - nn;
+    T* linv = static_cast<T*>(w.inv) + size_t(p) * 2 * kNB * kNB;
+    hipLaunchKernelGGL((panel_step_kernel<T>), dim3(1), dim3(256), 0, s, A, lda, n, k, jb, nn,
+                       w.swap_cnt + p, list, linv);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // the rest (interchanges on the other columns and the row origins, U12 and
+    // the update beyond the next panel's columns) on the side stream when it
+    // can run beside the next panel
+    const bool use_side = lookahead && far > 0;
+    hipStream_t rs = s;
+    if (use_side) {
+      if ((e = hipEventRecord(side->ready, s)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(side->s, side->ready, 0)) != hipSuccess) return e;
+      rs = side->s;
+    }
+    hipLaunchKernelGGL((laswp_kernel<T>), dim3(unsigned(cdiv(n - jb - nn + 1, 4))), dim3(256), 0,
+                       rs, A, lda, n, k, jb, int64_t(nn), w.swap_cnt + p, list, rowid);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const T* l21 = A + (k + jb) + k * lda;
+    if (far > 0) {
       // U12 = L11^-1 A12 as a product with the explicit inverse, in place:
       // a tile's workgroup (BM >= kNB rows, no split) reads all of its
       // columns of A12 before it writes them, and no other workgroup reads them
-      T* linv = static_cast<T*>(w.inv) + size_t(p) * 2 * kNB * kNB;
-      hipLaunchKernelGGL((inv_block_kernel<T, false>), dim3(1), dim3(kNB), 0, s, A, lda, n, p,
-                         static_cast<T*>(w.inv));
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-      GemmConfig tc = gemm_choose(dtype, 0, 0, jb, right, jb);
+      T* a12 = A + k + (k + jb + nn) * lda;
+      GemmConfig tc = gemm_choose(dtype, 0, 0, jb, far, jb);
       tc.split = 1;
-      e = gemm_launch(dtype, 0, 0, 0, 0, jb, right, jb, 1.0, linv, kNB, a12, lda, 0.0, a12, lda,
-                      nullptr, tc, s);
+      e = gemm_launch(dtype, 0, 0, 0, 0, jb, far, jb, 1.0, linv, kNB, a12, lda, 0.0, a12, lda,
+                      nullptr, tc, rs);
       if (e != hipSuccess) return e;
-      // A22 -= L21 U12: the next panel's columns on s, so that the next
-      // panel starts at once; with lookahead the rest on the side stream
-      const int64_t near = lookahead ? std::min<int64_t>(kNB, right) : right;
-      if (near < right) {
-        if ((e = hipEventRecord(side->ready, s)) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(side->s, side->ready, 0)) != hipSuccess) return e;
-      }
-      e = update<T>(dtype, n - k - jb, near, jb, A + (k + jb) + k * lda, lda, a12, lda,
-                    A + (k + jb) + (k + jb) * lda, lda, s, prec, true);
+      e = update<T>(dtype, right, far, jb, l21, lda, a12, lda, A + (k + jb) + (k + jb + nn) * lda,
+                    lda, rs, prec, true);
       if (e != hipSuccess) return e;
-      if (near < right) {
-        e = update<T>(dtype, n - k - jb, right - near, jb, A + (k + jb) + k * lda, lda,
-                      a12 + near * lda, lda, A + (k + jb) + (k + jb + near) * lda, lda, side->s,
-                      prec, true);
-        if (e != hipSuccess) return e;
-        if ((e = hipEventRecord(side->done, side->s)) != hipSuccess) return e;
-        pending = true;
-      }
+    }
+    if (use_side) {
+      if ((e = hipEventRecord(side->done, side->s)) != hipSuccess) return e;
+      pending = true;
+    }
+    // A22 -= L21 U12 on the next panel's columns, on s and in the storage
+    // precision (the next panel waits for it)
+    if (nn > 0) {
+      e = update<T>(dtype, right, nn, jb, l21, lda, A + k + (k + jb) * lda, lda,
+                    A + (k + jb) + (k + jb) * lda, lda, s, GEMM_PLAIN, true);
+      if (e != hipSuccess) return e;
     }
   }
   if (pending && (e = hipStreamWaitEvent(s, side->done, 0)) != hipSuccess) return e;
-  // the last block's L11^-1 (no update followed it) and every U11^-1, for the solves
-  hipLaunchKernelGGL((inv_block_kernel<T, false>), dim3(1), dim3(kNB), 0, s, A, lda, n, np - 1,
-                     static_cast<T*>(w.inv));
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // every U11^-1, for the solves (each L11^-1 came with its panel step)
   hipLaunchKernelGGL((inv_block_kernel<T, true>), dim3(unsigned(np)), dim3(kNB), 0, s, A, lda, n,
                      int64_t(0), static_cast<T*>(w.inv));
   return hipGetLastError();
