@@ -203,7 +203,7 @@ def bench_solve(args, ctx, hx, torch, inputs):
     flops = 2.0 / 3.0 * n ** 3 + 2.0 * n * n * nrhs
     es, eb = ctx.leaf(s_dev), ctx.leaf(b_dev)
     forms = []
-    wanted = [f for f in args.forms.split(",") if f] or ["plain", "ir_fp32", "ir_bf16x3", "ir_fp16"]
+    wanted = [f for f in args.forms.split(",") if f] or ["plain", "ir_fp32", "ir_bf16x3", "ir_bf16x6", "ir_fp16"]
     for form in wanted:
         p = ctx.plan(hx.solve(es, eb), solve_precision=form)
         out, ws = p.output(), p.workspace()

@@ -167,8 +167,10 @@ typedef enum hexla_product_precision {
  * low-precision factorisation; the paper names reduced-precision types as
  * future work, Sec. IV). The LU is stored in FP32 and its panels are factored
  * in FP32 (IR_FP32) or in FP64, pivots chosen on FP64 values and the panel
- * rounded to FP32 when stored (IR_FP16, IR_BF16X3); the trailing updates run
- * in the form's product precision with FP32 accumulation. The residual
+ * rounded to FP32 when stored (IR_FP16, IR_BF16X3, IR_BF16X6). The trailing
+ * updates run in the form's product precision with FP32 accumulation, except
+ * the next panel's 64 columns, which the next panel waits for: those are
+ * updated in FP32 (about 96 / n of the update's products). The residual
  * R = B - S X and the update X += D are FP64, D solved on the low-precision
  * factors. The loop stops when ||R||inf <= ir_tol_scale * 2^-53 * ||S||inf *
  * ||X||inf (ir_tol_scale 0: 1; converged), when ir_max_iter is reached, when
@@ -185,7 +187,9 @@ typedef enum hexla_solve_precision {
   HEXLA_SOLVE_IR_FP32 = 1,   /* FP32 LU (FP32 panels), FP32 trailing updates      */
   HEXLA_SOLVE_IR_FP16 = 2,   /* FP32 LU, FP64 panels, FP16-MFMA trailing updates
                                 (FP32 accumulation)                              */
-  HEXLA_SOLVE_IR_BF16X3 = 3  /* FP32 LU, FP64 panels, split-BF16 (x3) MFMA
+  HEXLA_SOLVE_IR_BF16X3 = 3, /* FP32 LU, FP64 panels, split-BF16 (x3) MFMA
+                                trailing updates                                 */
+  HEXLA_SOLVE_IR_BF16X6 = 4  /* FP32 LU, FP64 panels, split-BF16 (x6) MFMA
                                 trailing updates                                 */
 } hexla_solve_precision;
 

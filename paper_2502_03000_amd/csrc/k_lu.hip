@@ -356,20 +356,25 @@ __global__ __launch_bounds__(kPT) void panel_kernel(T* __restrict__ A, int64_t l
   }
 }
 
-// Gather of the moved rows on the columns outside the panel and the `skip`
-// columns after it; column index n stands for the row-origin vector. One
-// wave per column.
+// Makes x a register value at this point (every load feeding it completed).
 template <typename T>
-__global__ __launch_bounds__(256) void laswp_kernel(T* __restrict__ A, int64_t lda, int64_t n,
-                                                    int64_t k, int jb, int64_t skip,
-                                                    const int32_t* swap_cnt,
+__device__ __forceinline__ void lk_materialize(T& x) {
+  asm volatile("" : "+v"(x));
+}
+
+// Gather of the moved rows on the columns [lo1, hi1) and [lo2, hi2), and on
+// the row-origin vector when `with_rowid`. One wave per column.
+template <typename T>
+__global__ __launch_bounds__(256) void laswp_kernel(T* __restrict__ A, int64_t lda, int64_t lo1,
+                                                    int64_t hi1, int64_t lo2, int64_t hi2,
+                                                    int with_rowid, const int32_t* swap_cnt,
                                                     const int32_t* swap_list, int32_t* rowid) {
   const int lane = threadIdx.x & 63;
-  int64_t c = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  if (c >= n - jb - skip + 1) return;
-  if (c >= k) c += jb + skip;  // c == n is rowid
+  const int64_t v = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int64_t n1 = hi1 - lo1, n2 = hi2 - lo2;
+  if (v >= n1 + n2 + with_rowid) return;
   const int cnt = min(*swap_cnt, 2 * kNB);
-  if (c == n) {
+  if (v == n1 + n2) {
     int32_t a0 = 0, a1 = 0;
     if (lane < cnt) a0 = rowid[swap_list[2 * lane + 1]];
     if (lane + 64 < cnt) a1 = rowid[swap_list[2 * (lane + 64) + 1]];
@@ -378,7 +383,7 @@ __global__ __launch_bounds__(256) void laswp_kernel(T* __restrict__ A, int64_t l
     if (lane + 64 < cnt) rowid[swap_list[2 * (lane + 64)]] = a1;
     return;
   }
-  T* col = A + c * lda;
+  T* col = A + (v < n1 ? lo1 + v : lo2 + (v - n1)) * lda;
   T a0 = 0, a1 = 0;
   if (lane < cnt) a0 = col[swap_list[2 * lane + 1]];
   if (lane + 64 < cnt) a1 = col[swap_list[2 * (lane + 64) + 1]];
@@ -387,94 +392,109 @@ __global__ __launch_bounds__(256) void laswp_kernel(T* __restrict__ A, int64_t l
   if (lane + 64 < cnt) col[swap_list[2 * (lane + 64)]] = a1;
 }
 
-// The critical-path work between two panels in one workgroup: the panel's
-// row interchanges on the next nn (<= kNB) columns, L11^-1 (into inv) and
-// U12 = L11^-1 A12 on those columns, in place. Every load (the interchanged
-// rows, L11 and A12 through the interchange map) returns before any store.
-// Wave 0 builds L11^-1 column by column (lane c: L11 x = e_c), wave 1 the nn
-// columns of U12 (lane c: L11 x = A12(:, c)), both by right-looking
-// substitution with the column in registers (64 steps; each step's updates
-// are independent) and L11 in LDS.
+// The critical-path work between two panels in one workgroup, after the
+// interchanges on the next nn (<= kNB) columns: R = L11^-1 [I | A12] with
+// A12 the nn columns, i.e. L11^-1 (into inv) and U12 (in place). Blocked
+// forward substitution over four 16-row blocks with MFMA: D_b = L_bb^-1 by
+// substitution (wave 0, lane (b, c) takes column c of D_b), M_bj = D_b L_bj
+// for j < b (MFMA), then R_b = D_b B_b - sum_j M_bj R_j. Wave w owns columns
+// 32w.. of R (waves 0-1 the identity's, 2-3 those of A12) and keeps them in
+// LDS by columns; blocks of one wave depend only on that wave's earlier
+// blocks. Loads and stores are coalesced by tile columns.
 template <typename T>
 __global__ __launch_bounds__(256) void panel_step_kernel(T* __restrict__ A, int64_t lda, int64_t n,
                                                          int64_t k, int jb, int nn,
-                                                         const int32_t* swap_cnt,
-                                                         const int32_t* swap_list,
                                                          T* __restrict__ inv) {
-  __shared__ T Lt[kNB][kNB];  // Lt[l][i] = L11(i, l), unit diagonal, identity padding
-  __shared__ int64_t src_of[kNB];  // row that lands at position k + i
+  using Mf = Mfma<T>;
+  using acc_t = typename Mf::acc_t;
+  constexpr int LL = kNB + 16;  // Lc column stride (operand reads without bank conflicts)
+  constexpr int LR = kNB + 4;
+  __shared__ T Lc[kNB][LL];        // Lc[l][i] = L11(i, l): unit diagonal, identity padding
+  __shared__ T Ds[4][16][16 + 4];  // Ds[b][t][i] = D_b(i, t)
+  __shared__ T Ms[6][16][16 + 4];  // Ms[p][t][i] = M_bj(i, t), p = b(b-1)/2 + j
+  __shared__ T Rs[4][32][LR];      // Rs[w][c][i] = column 32w + c of [I | A12], then of R
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int cnt = min(*swap_cnt, 2 * kNB);
-  const int64_t c0 = k + jb;  // first of the nn columns
-  if (tid < kNB) src_of[tid] = k + tid;
-  // L11: element (i, l) from thread e % 64 (coalesced columns)
+  const int l16 = lane & 15, g = lane >> 4;
+  const int64_t c0 = k + jb;  // first of the nn columns (nn > 0 only when jb == kNB)
   constexpr int PER = kNB * kNB / 256;
-  T lv[PER];
+  T lv[PER], bv[PER];
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
+  for (int q = 0; q < PER; ++q) {  // element (i, l) from thread e % 64
     const int e = tid + 256 * q, i = e % kNB, l = e / kNB;
     lv[q] = A[(k + min(i, jb - 1)) + (k + min(l, jb - 1)) * lda];
-  }
-  // interchanged rows of the nn columns: wave w takes columns w, w + 4, ...;
-  // lane takes entries lane and lane + 64
-  int32_t dst[2];
-  T gv[2][kNB / 4];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int e = min(lane + 64 * h, max(cnt - 1, 0));
-    dst[h] = lane + 64 * h < cnt ? swap_list[2 * e] : -1;
-    const int64_t src = cnt > 0 ? swap_list[2 * e + 1] : k;
-#pragma unroll
-    for (int j = 0; j < kNB / 4; ++j) {  // (nn == 0: a column of the panel, not used)
-      const int64_t c = nn > 0 ? c0 + min(w + 4 * j, nn - 1) : k;
-      gv[h][j] = A[src + c * lda];
-    }
-  }
-  __syncthreads();  // src_of initialised
-  if (tid < cnt) {
-    const int64_t d = swap_list[2 * tid];
-    if (d < k + jb) src_of[d - k] = swap_list[2 * tid + 1];
+    bv[q] = nn > 0 ? A[(k + i) + (c0 + min(l, nn - 1)) * lda] : T(0);
   }
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = tid + 256 * q, i = e % kNB, l = e / kNB;
-    Lt[l][i] = (i < jb && l < jb && i > l) ? lv[q] : T(i == l ? 1 : 0);
+    Lc[l][i] = (i < jb && l < jb && i > l) ? lv[q] : T(i == l ? 1 : 0);
+    Rs[2 + l / 32][l % 32][i] = bv[q];
   }
   __syncthreads();
-  T x[kNB];
-  if (w == 0) {
+  if (w == 0) {  // D_b = L_bb^-1, lane (b, c) = (g, l16) builds column c
+    T x[16];
 #pragma unroll
-    for (int i = 0; i < kNB; ++i) x[i] = i == lane ? T(1) : T(0);
-  } else if (w == 1 && nn > 0) {  // nn > 0 only below a full panel (jb == kNB)
-    const int64_t col = (c0 + min(lane, nn - 1)) * lda;
+    for (int i = 0; i < 16; ++i) x[i] = T(i == l16 ? 1 : 0);
 #pragma unroll
-    for (int i = 0; i < kNB; ++i) x[i] = A[src_of[i] + col];
+    for (int l = 0; l < 16; ++l) {
+      const T xl = x[l];
+#pragma unroll
+      for (int i = l + 1; i < 16; ++i) x[i] -= Lc[16 * g + l][16 * g + i] * xl;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Ds[g][l16][i] = x[i];
   }
-  __builtin_amdgcn_s_waitcnt(0);  // every load of this thread has returned
-  __syncthreads();                // ... and of every other thread
-  // the interchanges below the U12 rows (those rows get U12 itself)
+  __syncthreads();
+  // M_bj = D_b L_bj: operand A[i][t] = D_b(i, t), B[t][c] = L(16b + t, 16j + c)
+  for (int p = w; p < 6; p += 4) {
+    const int b = p < 1 ? 1 : p < 3 ? 2 : 3;
+    const int j = p - b * (b - 1) / 2;
+    acc_t m = acc_t{};
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
-    if (dst[h] >= k + jb) {
+    for (int s4 = 0; s4 < 4; ++s4)
+      m = Mf::mma(Ds[b][4 * s4 + g][l16], Lc[16 * j + l16][16 * b + 4 * s4 + g], m);
 #pragma unroll
-      for (int j = 0; j < kNB / 4; ++j) {
-        const int c = w + 4 * j;
-        if (c < nn) A[dst[h] + (c0 + c) * lda] = gv[h][j];
+    for (int r = 0; r < 4; ++r) Ms[p][l16][Mf::row(lane, r)] = m[r];
+  }
+  __syncthreads();
+  // R_b = D_b B_b - sum_{j<b} M_bj R_j on this wave's columns (two fragments)
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    acc_t acc[2] = {acc_t{}, acc_t{}};
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const T a = Ds[b][4 * s4 + g][l16];
+      const int row = 16 * b + 4 * s4 + g;
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        const T bb = w < 2 ? T(row == 32 * w + 16 * f + l16 ? 1 : 0) : Rs[w][16 * f + l16][row];
+        acc[f] = Mf::mma(a, bb, acc[f]);
       }
     }
-  if (w > 1 || (w == 1 && nn == 0)) return;
 #pragma unroll
-  for (int l = 0; l < kNB; ++l) {
-    const T xl = x[l];
+    for (int j = 0; j < b; ++j) {
+      const int p = b * (b - 1) / 2 + j;
 #pragma unroll
-    for (int i = l + 1; i < kNB; ++i) x[i] -= Lt[l][i] * xl;
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const T a = -Ms[p][4 * s4 + g][l16];
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+          acc[f] = Mf::mma(a, Rs[w][16 * f + l16][16 * j + 4 * s4 + g], acc[f]);
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Rs[w][16 * f + l16][16 * b + Mf::row(lane, r)] = acc[f][r];
+    __builtin_amdgcn_s_waitcnt(0);  // the block is in LDS before the next reads it
+    __builtin_amdgcn_wave_barrier();
   }
-  if (w == 0) {
+  __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kNB; ++i) inv[i + lane * kNB] = x[i];
-  } else if (lane < nn) {
-#pragma unroll
-    for (int i = 0; i < kNB; ++i) A[(k + i) + (c0 + lane) * lda] = x[i];
+  for (int q = 0; q < PER; ++q) {
+    const int e = tid + 256 * q, i = e % kNB, c = e / kNB;
+    inv[e] = Rs[c / 32][c % 32][i];  // (i, c) at i + kNB c
+    if (c < nn) A[(k + i) + (c0 + c) * lda] = Rs[2 + c / 32][c % 32][i];
   }
 }
 
@@ -909,13 +929,19 @@ hipError_t factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* rowid,
       if ((e = hipStreamWaitEvent(s, side->done, 0)) != hipSuccess) return e;
       pending = false;
     }
-    // on s: the interchanges and U12 on the next panel's columns and L11^-1
+    // on s: the interchanges on the next panel's columns, L11^-1 and U12 there
     const int64_t right = n - k - jb;
     const int nn = int(std::min<int64_t>(kNB, right));
     const int64_t far = right - nn;
     T* linv = static_cast<T*>(w.inv) + size_t(p) * 2 * kNB * kNB;
+    if (nn > 0) {
+      hipLaunchKernelGGL((laswp_kernel<T>), dim3(unsigned(cdiv(nn, 4))), dim3(256), 0, s, A, lda,
+                         k + jb, k + jb + nn, int64_t(0), int64_t(0), 0, w.swap_cnt + p, list,
+                         rowid);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     hipLaunchKernelGGL((panel_step_kernel<T>), dim3(1), dim3(256), 0, s, A, lda, n, k, jb, nn,
-                       w.swap_cnt + p, list, linv);
+                       linv);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // the rest (interchanges on the other columns and the row origins, U12 and
     // the update beyond the next panel's columns) on the side stream when it
@@ -927,8 +953,8 @@ hipError_t factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* rowid,
       if ((e = hipStreamWaitEvent(side->s, side->ready, 0)) != hipSuccess) return e;
       rs = side->s;
     }
-    hipLaunchKernelGGL((laswp_kernel<T>), dim3(unsigned(cdiv(n - jb - nn + 1, 4))), dim3(256), 0,
-                       rs, A, lda, n, k, jb, int64_t(nn), w.swap_cnt + p, list, rowid);
+    hipLaunchKernelGGL((laswp_kernel<T>), dim3(unsigned(cdiv(k + far + 1, 4))), dim3(256), 0, rs,
+                       A, lda, int64_t(0), k, k + jb + nn, n, 1, w.swap_cnt + p, list, rowid);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const T* l21 = A + (k + jb) + k * lda;
     if (far > 0) {

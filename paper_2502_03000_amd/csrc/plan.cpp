@@ -1567,15 +1567,16 @@ class Planner {
     w.res_cfg = k::gemm_choose(HEXLA_F64, 0, 0, n, r, n);
     const size_t pb = k::gemm_partial_bytes(HEXLA_F64, w.res_cfg, n, r);
     if (pb) w.partial = work(int64_t(pb));
-    w.update_precision = o_.solve_precision == HEXLA_SOLVE_IR_FP16   ? k::GEMM_F16
+    w.update_precision = o_.solve_precision == HEXLA_SOLVE_IR_FP16     ? k::GEMM_F16
                          : o_.solve_precision == HEXLA_SOLVE_IR_BF16X3 ? k::GEMM_BF16X3
+                         : o_.solve_precision == HEXLA_SOLVE_IR_BF16X6 ? k::GEMM_BF16X6
                                                                        : k::GEMM_PLAIN;
-    w.panel_fp64 = o_.solve_precision == HEXLA_SOLVE_IR_FP16 ||
-                   o_.solve_precision == HEXLA_SOLVE_IR_BF16X3;
+    w.panel_fp64 = o_.solve_precision != HEXLA_SOLVE_IR_FP32;
     w.max_iter = o_.ir_max_iter;
     w.tol_scale = o_.ir_tol_scale;
     q.name = o_.solve_precision == HEXLA_SOLVE_IR_FP16     ? "lu_solve_ir_fp16"
              : o_.solve_precision == HEXLA_SOLVE_IR_BF16X3 ? "lu_solve_ir_bf16x3"
+             : o_.solve_precision == HEXLA_SOLVE_IR_BF16X6 ? "lu_solve_ir_bf16x6"
                                                            : "lu_solve_ir_fp32";
     // LU + first solve; each refinement step adds a residual and a solve
     q.flops = 2.0 / 3.0 * double(n) * n * n + 2.0 * double(n) * n * r;
@@ -1803,7 +1804,7 @@ hexla_status hexla_plan_create(hexla_ctx* ctx, hexla_node root, const hexla_plan
   if (opts) o = *opts;
   if (o.planner < 0 || o.planner > HEXLA_PLANNER_ROOFLINE || o.product_precision < 0 ||
       o.product_precision > HEXLA_PRODUCT_BF16X6 || o.solve_precision < 0 ||
-      o.solve_precision > HEXLA_SOLVE_IR_BF16X3)
+      o.solve_precision > HEXLA_SOLVE_IR_BF16X6)
     return set_err(ctx, HEXLA_E_INVALID_ARG, "plan: bad options");
   if (o.ir_max_iter < 0) o.ir_max_iter = 30;  // 0: no refinement step
   hexla_plan* p = new hexla_plan();

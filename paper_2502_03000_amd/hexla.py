@@ -29,7 +29,7 @@ OP_TRANS, OP_NEG, OP_EXP, OP_INV, OP_DIAG, OP_DIAGMAT, OP_TRACE = 1, 2, 3, 4, 5,
 OP_TIMES, OP_PLUS, OP_MINUS, OP_SCHUR, OP_DIV, OP_SOLVE = 16, 17, 18, 19, 20, 21
 PLANNERS = {"dp": 0, "greedy": 1, "naive": 2, "learned": 3, "roofline": 4}
 PRODUCT_PRECISION = {"plain": 0, "bf16x3": 1, "bf16x6": 2}
-SOLVE_PRECISION = {"plain": 0, "ir_fp32": 1, "ir_fp16": 2, "ir_bf16x3": 3}
+SOLVE_PRECISION = {"plain": 0, "ir_fp32": 1, "ir_fp16": 2, "ir_bf16x3": 3, "ir_bf16x6": 4}
 SOLVE_STRUCTURE = {"auto": 0, "general": 1}
 SOLVERS = {0: "lu", 1: "cholesky", 2: "lower", 3: "upper", 4: "tridiagonal", 5: "diagonal"}
 

@@ -154,7 +154,7 @@ def solve_inputs():
     return s_dev, dev(bh), bh, closed
 
 
-@pytest.mark.parametrize("form", ["plain", "ir_fp32", "ir_bf16x3", "ir_fp16"])
+@pytest.mark.parametrize("form", ["plain", "ir_fp32", "ir_bf16x3", "ir_bf16x6", "ir_fp16"])
 def test_solve_full_size(solve_inputs, form):
     s_dev, b_dev, bh, closed = solve_inputs
     ctx = hx.Context(0)

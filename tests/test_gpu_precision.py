@@ -131,7 +131,8 @@ def test_split_family_every_split(tmp_path, prec, tol, syrk, cols):
 
 # ------------------------------------------------ mixed-precision solves
 
-@pytest.mark.parametrize("form,cond", [("ir_fp32", 1e3), ("ir_bf16x3", 1e3), ("ir_fp16", 1e2)])
+@pytest.mark.parametrize("form,cond", [("ir_fp32", 1e3), ("ir_bf16x3", 1e3), ("ir_bf16x6", 1e3),
+                                       ("ir_fp16", 1e2)])
 @pytest.mark.parametrize("n", [200, 513])
 def test_refined_solve_reaches_fp64_accuracy(ctx, form, cond, n):
     s, u, sv, v = inputs.svd_matrix(60 + n, n, n, cond)
@@ -159,7 +160,7 @@ def test_refined_solve_reaches_fp64_accuracy(ctx, form, cond, n):
     assert rel(got, ref) <= 1e-12
 
 
-@pytest.mark.parametrize("form", ["ir_fp32", "ir_bf16x3", "ir_fp16"])
+@pytest.mark.parametrize("form", ["ir_fp32", "ir_bf16x3", "ir_bf16x6", "ir_fp16"])
 @pytest.mark.parametrize("n", [200, 513])
 def test_refined_solve_reports_divergence(ctx, form, n):
     """cond 1e9 is beyond what FP32 factors can refine (cond * 2^-24 > 1): the
