@@ -308,6 +308,151 @@ __global__ __launch_bounds__(256) void gemm_split_kernel(GemmArgs g, int vec) {
       }
 }
 
+
+// C -= A B for K <= 64 (the LU's rank-K trailing update) in split terms: A
+// m x K, B K x n, C m x n, FP32, column-major. One 256-thread workgroup per
+// 64 x 64 tile of C, loaded straight into the accumulators; both operand
+// tiles (the whole K range) are split on the way to LDS as [row][k] BF16 (or
+// FP16) terms, B negated; the products are computed transposed (operand A
+// from B's columns, operand B from A's rows), so a 16-lane group holds 16
+// consecutive rows of one column of C and C moves in 64-byte runs. The
+// traffic is the C tile twice plus the operand tiles once, as in the plain
+// rank-K update: the split terms cost MFMA time only, which stays under the
+// C traffic at this K.
+constexpr int RU_T = 64;  // tile side
+constexpr int RU_K = 64;  // K at most
+
+// LDS position of element k of row `row` in a [row][k] term tile of RU_K
+// columns: 16-byte chunk k / 8 XORed with the row's low three bits.
+__device__ __forceinline__ int ru_off(int row, int k) {
+  return row * RU_K + (((k >> 3) ^ (row & 7)) << 3) + (k & 7);
+}
+
+template <int TERMS, typename E>
+__global__ __launch_bounds__(256) void rank_update_split_kernel(
+    int64_t m, int64_t n, int K, const float* __restrict__ A, int64_t lda,
+    const float* __restrict__ B, int64_t ldb, float* __restrict__ C, int64_t ldc, int tiles_m,
+    int vec) {
+  using M = Mfma16<E>;
+  typedef typename M::v8 v8;
+  typedef typename M::v4 v4;
+  constexpr int TE = RU_T * RU_K;  // elements of one term tile
+  __shared__ __attribute__((aligned(16))) E sa[TERMS * TE];  // A(row, k)
+  __shared__ __attribute__((aligned(16))) E sb[TERMS * TE];  // -B(k, col) as [col][k]
+  const int tm = int(blockIdx.x) % tiles_m, tn = int(blockIdx.x) / tiles_m;
+  const int64_t m0 = int64_t(tm) * RU_T, n0 = int64_t(tn) * RU_T;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, wc = wave >> 1;
+  const int l16 = lane & 15, g = lane >> 4;
+  // 1. the C tile into the accumulators: block (fc, fr) register r holds
+  // column n0 + 32 wc + 16 fc + 4 g + r, row m0 + 32 wr + 16 fr + l16
+  accv acc[2][2];
+#pragma unroll
+  for (int fc = 0; fc < 2; ++fc)
+#pragma unroll
+    for (int fr = 0; fr < 2; ++fr)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t col = n0 + 32 * wc + 16 * fc + 4 * g + r;
+        const int64_t row = m0 + 32 * wr + 16 * fr + l16;
+        const float v = C[std::min<int64_t>(row, m - 1) + std::min<int64_t>(col, n - 1) * ldc];
+        acc[fc][fr][r] = (row < m && col < n) ? v : 0.f;
+      }
+  // 2. the operand tiles: A(row, 4q..4q+3) and B(4q..4q+3, col) per thread
+  // and pass, every load in flight at once (clamped addresses, zeros after)
+  f4 va[4], vb[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int e = tid + 256 * p;
+    const int row = e % RU_T, qa = e / RU_T;  // A: coalesced along rows
+    const int64_t gr = std::min<int64_t>(m0 + row, m - 1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) va[p][q] = A[gr + int64_t(min(4 * qa + q, K - 1)) * lda];
+    const int qb = e % (RU_K / 4), col = e / (RU_K / 4);  // B: k contiguous
+    const float* pb = B + std::min<int64_t>(n0 + col, n - 1) * ldb;
+    if (vec) {
+      vb[p] = *reinterpret_cast<const f4*>(pb + 4 * qb);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) vb[p][q] = pb[min(4 * qb + q, K - 1)];
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int e = tid + 256 * p;
+    {
+      const int row = e % RU_T, qa = e / RU_T;
+      E t[4][TERMS];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        split_terms<TERMS, E>((m0 + row < m && 4 * qa + q < K) ? va[p][q] : 0.f, t[q]);
+#pragma unroll
+      for (int s4 = 0; s4 < TERMS; ++s4) {
+        v4 v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = t[q][s4];
+        *reinterpret_cast<v4*>(sa + s4 * TE + ru_off(row, 4 * qa)) = v;
+      }
+    }
+    {
+      const int qb = e % (RU_K / 4), col = e / (RU_K / 4);
+      E t[4][TERMS];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        split_terms<TERMS, E>((n0 + col < n && 4 * qb + q < K) ? -vb[p][q] : 0.f, t[q]);
+#pragma unroll
+      for (int s4 = 0; s4 < TERMS; ++s4) {
+        v4 v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = t[q][s4];
+        *reinterpret_cast<v4*>(sb + s4 * TE + ru_off(col, 4 * qb)) = v;
+      }
+    }
+  }
+  __syncthreads();
+  // 3. acc += (-B^T) A^T in term products, small terms first: operand A
+  // from lane (i, g) = -B(8 g.., column i), operand B from A(row j, 8 g..)
+#pragma unroll
+  for (int ks = 0; ks < RU_K / 32; ++ks) {
+    v8 a[TERMS][2], b[TERMS][2];
+#pragma unroll
+    for (int s4 = 0; s4 < TERMS; ++s4)
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        a[s4][f] = *reinterpret_cast<const v8*>(sb + s4 * TE +
+                                                ru_off(32 * wc + 16 * f + l16, 32 * ks + 8 * g));
+        b[s4][f] = *reinterpret_cast<const v8*>(sa + s4 * TE +
+                                                ru_off(32 * wr + 16 * f + l16, 32 * ks + 8 * g));
+      }
+#pragma unroll
+    for (int fc = 0; fc < 2; ++fc)
+#pragma unroll
+      for (int fr = 0; fr < 2; ++fr) {
+        if (TERMS == 3) {
+          acc[fc][fr] = M::mma(a[2 % TERMS][fc], b[0][fr], acc[fc][fr]);
+          acc[fc][fr] = M::mma(a[0][fc], b[2 % TERMS][fr], acc[fc][fr]);
+          acc[fc][fr] = M::mma(a[1 % TERMS][fc], b[1 % TERMS][fr], acc[fc][fr]);
+        }
+        if (TERMS >= 2) {
+          acc[fc][fr] = M::mma(a[1 % TERMS][fc], b[0][fr], acc[fc][fr]);
+          acc[fc][fr] = M::mma(a[0][fc], b[1 % TERMS][fr], acc[fc][fr]);
+        }
+        acc[fc][fr] = M::mma(a[0][fc], b[0][fr], acc[fc][fr]);
+      }
+  }
+  // 4. back to C
+#pragma unroll
+  for (int fc = 0; fc < 2; ++fc)
+#pragma unroll
+    for (int fr = 0; fr < 2; ++fr)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t col = n0 + 32 * wc + 16 * fc + 4 * g + r;
+        const int64_t row = m0 + 32 * wr + 16 * fr + l16;
+        if (row < m && col < n) C[row + col * ldc] = acc[fc][fr][r];
+      }
+}
+
 typedef void (*SplitFn)(GemmArgs, int);
 
 template <int TERMS, typename E>
@@ -392,6 +537,29 @@ hipError_t gemm_split_launch(int dtype, int precision, int mode, int ta, int tb,
   int64_t rb = cdiv(m * n, 256);
   if (rb > 4096) rb = 4096;
   hipLaunchKernelGGL(splitk_reduce_kernel<float>, dim3(unsigned(rb)), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t rank_update_split_launch(int precision, int64_t m, int64_t n, int64_t K,
+                                    const float* A, int64_t lda, const float* B, int64_t ldb,
+                                    float* C, int64_t ldc, hipStream_t s) {
+  if (m <= 0 || n <= 0 || K <= 0) return hipSuccess;
+  const int64_t tm = cdiv(m, RU_T), tn = cdiv(n, RU_T);
+  if (K > RU_K || tm * tn > INT32_MAX) return hipErrorInvalidValue;
+  // whole 16-byte B loads when every column's K run is aligned and complete
+  const int vec = K == RU_K && ldb % 4 == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
+  const dim3 grid(unsigned(tm * tn)), block(256);
+  if (precision == GEMM_BF16X3)
+    hipLaunchKernelGGL((rank_update_split_kernel<2, __bf16>), grid, block, 0, s, m, n, int(K), A,
+                       lda, B, ldb, C, ldc, int(tm), vec);
+  else if (precision == GEMM_BF16X6)
+    hipLaunchKernelGGL((rank_update_split_kernel<3, __bf16>), grid, block, 0, s, m, n, int(K), A,
+                       lda, B, ldb, C, ldc, int(tm), vec);
+  else if (precision == GEMM_F16)
+    hipLaunchKernelGGL((rank_update_split_kernel<1, _Float16>), grid, block, 0, s, m, n, int(K),
+                       A, lda, B, ldb, C, ldc, int(tm), vec);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

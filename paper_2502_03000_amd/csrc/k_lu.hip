@@ -856,9 +856,9 @@ hipError_t rank_update(int64_t m, int64_t n, int64_t K, const T* A, int64_t lda,
 }
 
 // C (m x ncol) -= A (m x kk) * B (kk x ncol): GEMV for one column; the
-// factorization's trailing updates (`trailing`) in plain precision take the
-// rank-K kernel; the rest (the solves' narrow updates, split-BF16 and FP16
-// updates) the GEMM in the requested precision.
+// factorization's trailing updates (`trailing`) take the rank-K kernel of
+// their precision (plain, or split-BF16 / FP16 terms); the rest (the solves'
+// narrow updates) the GEMM.
 template <typename T>
 hipError_t update(int dtype, int64_t m, int64_t ncol, int64_t kk, const T* A, int64_t lda,
                   const T* B, int64_t ldb, T* C, int64_t ldc, hipStream_t s, int prec = 0,
@@ -881,6 +881,10 @@ hipError_t update(int dtype, int64_t m, int64_t ncol, int64_t kk, const T* A, in
   }
   if (trailing && prec == GEMM_PLAIN && kk <= kNB)
     return rank_update<T>(m, ncol, kk, A, lda, B, ldb, C, ldc, s);
+  if constexpr (sizeof(T) == 4) {
+    if (trailing && kk <= kNB)
+      return rank_update_split_launch(prec, m, ncol, kk, A, lda, B, ldb, C, ldc, s);
+  }
   GemmConfig cfg = gemm_choose(dtype, prec, 0, m, ncol, kk);
   cfg.split = 1;
   return gemm_launch(dtype, prec, 0, 0, 0, m, ncol, kk, -1.0, A, lda, B, ldb, 1.0, C, ldc,

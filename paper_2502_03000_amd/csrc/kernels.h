@@ -98,6 +98,12 @@ hipError_t gemm_launch(int dtype, int precision, int mode, int ta, int tb, int64
 
 // The bfloat16 terms of FP32 values (raw bit patterns): t0 = rne(x),
 // t1 = rne(x - t0), t2 = rne(x - t0 - t1) (written when terms == 3).
+// C -= A B with K <= 64 in split terms (precision GEMM_BF16X3, GEMM_BF16X6 or
+// GEMM_F16), FP32 operands, column-major: the LU's low-precision trailing
+// update.
+hipError_t rank_update_split_launch(int precision, int64_t m, int64_t n, int64_t K,
+                                    const float* A, int64_t lda, const float* B, int64_t ldb,
+                                    float* C, int64_t ldc, hipStream_t s);
 hipError_t split_bf16_launch(const float* x, int64_t n, uint16_t* t0, uint16_t* t1, uint16_t* t2,
                              int terms, hipStream_t s);
 
