@@ -19,10 +19,9 @@
 //            the whole K range of its A and B tiles in LDS and its C tile in
 //            the accumulators (split-BF16 / FP16 updates use the GEMM).
 // The solves apply the inverses of the diagonal blocks (kept in the
-// workspace): in FP32 each direction is one launch in which workgroups take
-// (64-row block, 16-column chunk) tasks in order, multiply with MFMA and
-// exchange solved blocks as tagged words; in FP64 each block step is an
-// inverse product and a GEMM update of the rows left.
+// workspace): each direction is one launch in which workgroups take (64-row
+// block, 16-column chunk) tasks in order, multiply with MFMA and exchange
+// solved blocks as tagged words.
 // Every wait for another wave's words spins a bounded number of times; a
 // timeout sets a status bit instead of hanging, and every wave still reaches
 // the end of the kernel.
@@ -61,8 +60,8 @@ struct LuWork {
   uint64_t* slots;     // [2][G][kSlotW] tagged words, by column parity
   int32_t* swap_cnt;   // [n_panels]
   int32_t* swap_list;  // [n_panels][2 * kNB][2]   (dst, src)
-  unsigned* tickets;   // [2] task tickets of the forward and backward FP32 solves
-  uint64_t* xw;        // [chunk][block] solved tasks of the FP32 solve, tagged words
+  unsigned* tickets;   // [2] task tickets of the forward and backward solves
+  uint64_t* xw;        // [chunk][block] solved tasks of the solve, tagged words
 };
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -89,8 +88,8 @@ LuWork carve(void* work, int64_t n) {
   w.xw = reinterpret_cast<uint64_t*>(p);
   return w;
 }
-// 64-bit exchange words of one pair of launches of the FP32 blocked solve
-// (one word per value)
+// values in the exchange of one pair of launches of the blocked solve (one
+// 64-bit word per FP32 value, two per FP64 value)
 size_t solve_words(int64_t n, int64_t nrhs) {
   const int64_t chunks = std::min<int64_t>(cdiv(nrhs, kChainW), kChainCols / kChainW);
   return size_t(chunks) * size_t(cdiv(n, kNB)) * kChainWords;
@@ -547,36 +546,39 @@ __global__ __launch_bounds__(kNB) void inv_block_kernel(const T* __restrict__ A,
   for (int i = 0; i < kNB; ++i) out[i + c * kNB] = x[i];
 }
 
-// Blocked triangular solve in one launch (FP32): T X = X in place for the
-// unit lower (forward, L) or upper (backward, U) factor, 64-row blocks, with
-// the inverses of the diagonal blocks. Block i of X is T_ii^-1 (X_i - sum_j
-// T_ij X_j) over the blocks j solved before it (j < i forward, j > i
-// backward, in solve order). A task is one 64-row block of one 16-column
-// chunk; workgroups take tasks in solve order (block-major) from a ticket
-// counter, so every task a workgroup waits for belongs to a workgroup that is
-// already running (no deadlock, whatever the residency). Wave w of the
-// workgroup owns rows 16w..16w+15 of the block: its accumulator is one 16x16
-// MFMA tile, X_i(row 16w + 4(l/16) + r, column l%16) in register r of lane
-// l. Per dependency the wave multiplies its 16 rows of T_ij (operand A,
-// loaded straight from the factor) by the solved chunk X_j (operand B, read
-// from the exchange), 16 MFMA steps of k = 4; the loads of the next
-// dependency are issued before the products of this one. The inverse is
-// applied after one pass of the accumulators through LDS. A solved block goes
-// to the exchange as 64-bit words, the FP32 value in the low half and the tag
-// (tag0 + block) in the high half, stored in the order the readers' lanes
-// load them (word 64 s + l: row 4 s + l/16, column l%16), so a reader knows
-// from each word alone whether it holds this solve's value: no flag and no
-// wait for store completion. The exchange and the tickets start at zero
-// (tags start at 1). Padding rows and columns are exact zeros. Every wait is
-// bounded: a timeout raises status[1] and the workgroup exits.
-template <bool UPPER>
+// Blocked triangular solve in one launch: T X = X in place for the unit
+// lower (forward, L) or upper (backward, U) factor, 64-row blocks, with the
+// inverses of the diagonal blocks. Block i of X is T_ii^-1 (X_i - sum_j T_ij
+// X_j) over the blocks j solved before it (j < i forward, j > i backward, in
+// solve order). A task is one 64-row block of one 16-column chunk;
+// workgroups take tasks in solve order (block-major) from a ticket counter,
+// so every task a workgroup waits for belongs to a workgroup that is already
+// running (no deadlock, whatever the residency). Wave w of the workgroup owns
+// rows 16w..16w+15 of the block: its accumulator is one 16x16 MFMA tile,
+// X_i(row 16w + Mf::row(l, r), column l%16) in register r of lane l. Per
+// dependency the wave multiplies its 16 rows of T_ij (operand A, loaded
+// straight from the factor) by the solved chunk X_j (operand B, read from the
+// exchange), 16 MFMA steps of k = 4; the loads of the next dependency are
+// issued before the products of this one. The inverse is applied after one
+// pass of the accumulators through LDS. A solved block goes to the exchange
+// as 64-bit words whose high half is the tag (tag0 + block) and whose low
+// half is the FP32 value, or one 32-bit half of the FP64 value (two words
+// per value), stored in the order the readers' lanes load them (value 64 s +
+// l: row 4 s + l/16, column l%16), so a reader knows from each word alone
+// whether it holds this solve's value: no flag and no wait for store
+// completion. The exchange and the tickets start at zero (tags start at 1).
+// Padding rows and columns are exact zeros. Every wait is bounded: a timeout
+// raises status[1] and the workgroup exits.
+template <typename T, bool UPPER>
 __global__ __launch_bounds__(256) void chain_solve_kernel(
-    const float* __restrict__ LU, int64_t lda, int64_t n, const float* __restrict__ inv,
-    float* __restrict__ X, int64_t ldx, int64_t c_begin, int64_t nrhs, int chunks, uint64_t* xw,
+    const T* __restrict__ LU, int64_t lda, int64_t n, const T* __restrict__ inv,
+    T* __restrict__ X, int64_t ldx, int64_t c_begin, int64_t nrhs, int chunks, uint64_t* xw,
     unsigned* ticket, unsigned tag0, int32_t* status) {
-  using Mf = Mfma<float>;
-  using acc_t = Mf::acc_t;
-  __shared__ float sacc[kNB][kChainW + 1];
+  using Mf = Mfma<T>;
+  using acc_t = typename Mf::acc_t;
+  constexpr int WPV = sizeof(T) / 4;  // exchange words per value
+  constexpr size_t kTaskW = size_t(kChainWords) * WPV;
+  __shared__ T sacc[kNB][kChainW + 1];
   __shared__ int s_t, s_bad;
   const int nb = int((n + kNB - 1) / kNB);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -593,51 +595,53 @@ __global__ __launch_bounds__(256) void chain_solve_kernel(
     const int ib = int(std::min<int64_t>(kNB, n - r0));
     const int64_t c0 = c_begin + int64_t(ch) * kChainW;
     const int rc = int(std::min<int64_t>(kChainW, nrhs - c0));
-    const uint64_t* xch = xw + size_t(ch) * size_t(nb) * kChainWords;
+    const uint64_t* xch = xw + size_t(ch) * size_t(nb) * kTaskW;
     const int arow = 16 * w + l16;  // this lane's operand-A row of the block
     const int arow_c = std::min(arow, ib - 1);
-    // accumulator: rows 16w + 4g + r, column l16 of X_i
+    // accumulator: rows 16w + Mf::row(lane, r), column l16 of X_i
     acc_t acc;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = 16 * w + 4 * g + r;
-      const float v = X[(r0 + std::min(row, ib - 1)) + (c0 + std::min(l16, rc - 1)) * ldx];
-      acc[r] = (row < ib && l16 < rc) ? v : 0.0f;
+      const int row = 16 * w + Mf::row(lane, r);
+      const T v = X[(r0 + std::min(row, ib - 1)) + (c0 + std::min(l16, rc - 1)) * ldx];
+      acc[r] = (row < ib && l16 < rc) ? v : T(0);
     }
     // T_ii^-1 rows 16w.. as operand A (column-major, padded with the identity)
-    const float* iv = inv + size_t(bi) * 2 * kNB * kNB + (UPPER ? kNB * kNB : 0);
-    float ia[16];
+    const T* iv = inv + size_t(bi) * 2 * kNB * kNB + (UPPER ? kNB * kNB : 0);
+    T ia[16];
 #pragma unroll
     for (int s4 = 0; s4 < 16; ++s4) ia[s4] = iv[arow + kNB * (4 * s4 + g)];
     // operand A of dependency d: -T(r0 + arow, j0 + 4 s + g), zero outside
-    auto load_t = [&](int d, float* ta) {
+    auto load_t = [&](int d, T* ta) {
       const int bj = UPPER ? nb - 1 - d : d;
       const int64_t j0 = int64_t(bj) * kNB;
       const int jbj = int(std::min<int64_t>(kNB, n - j0));
-      const float* base = LU + (r0 + arow_c) + j0 * lda;
+      const T* base = LU + (r0 + arow_c) + j0 * lda;
 #pragma unroll
       for (int s4 = 0; s4 < 16; ++s4) {
         const int k = 4 * s4 + g;
-        const float v = base[int64_t(std::min(k, jbj - 1)) * lda];
-        ta[s4] = (arow < ib && k < jbj) ? -v : 0.0f;
+        const T v = base[int64_t(std::min(k, jbj - 1)) * lda];
+        ta[s4] = (arow < ib && k < jbj) ? -v : T(0);
       }
     };
-    auto load_x = [&](int d, uint64_t* wd) {
+    auto load_x = [&](int d, uint64_t (*wd)[WPV]) {
       const int bj = UPPER ? nb - 1 - d : d;
-      const uint64_t* src = xch + size_t(bj) * kChainWords + lane;
+      const uint64_t* src = xch + size_t(bj) * kTaskW + WPV * lane;
 #pragma unroll
-      for (int s4 = 0; s4 < 16; ++s4) wd[s4] = ld_word(src + 64 * s4);
+      for (int s4 = 0; s4 < 16; ++s4)
+#pragma unroll
+        for (int h = 0; h < WPV; ++h) wd[s4][h] = ld_word(src + WPV * 64 * s4 + h);
     };
     bool ok = true;
-    float ta[16];
-    uint64_t wd[16];
+    T ta[16];
+    uint64_t wd[16][WPV];
     if (bt > 0) {
       load_t(0, ta);
       load_x(0, wd);
     }
     for (int d = 0; d < bt; ++d) {
-      float tn[16];
-      uint64_t wn[16];
+      T tn[16];
+      uint64_t wn[16][WPV];
       if (d + 1 < bt) {
         load_t(d + 1, tn);
         load_x(d + 1, wn);
@@ -645,12 +649,14 @@ __global__ __launch_bounds__(256) void chain_solve_kernel(
       // the words of dependency d: re-read those not yet tagged for it
       const int bj = UPPER ? nb - 1 - d : d;
       const unsigned want = tag0 + unsigned(bj);
-      const uint64_t* src = xch + size_t(bj) * kChainWords + lane;
+      const uint64_t* src = xch + size_t(bj) * kTaskW + WPV * lane;
       unsigned spins = 0;
       for (;;) {
         bool mine = true;
 #pragma unroll
-        for (int s4 = 0; s4 < 16; ++s4) mine &= unsigned(wd[s4] >> 32) == want;
+        for (int s4 = 0; s4 < 16; ++s4)
+#pragma unroll
+          for (int h = 0; h < WPV; ++h) mine &= unsigned(wd[s4][h] >> 32) == want;
         if (__all(mine)) break;
         if (__any(!keep_waiting(spins, status + 1))) {
           ok = false;
@@ -658,37 +664,54 @@ __global__ __launch_bounds__(256) void chain_solve_kernel(
         }
 #pragma unroll
         for (int s4 = 0; s4 < 16; ++s4)
-          if (unsigned(wd[s4] >> 32) != want) wd[s4] = ld_word(src + 64 * s4);
+#pragma unroll
+          for (int h = 0; h < WPV; ++h)
+            if (unsigned(wd[s4][h] >> 32) != want) wd[s4][h] = ld_word(src + WPV * 64 * s4 + h);
       }
       if (!ok) break;
 #pragma unroll
-      for (int s4 = 0; s4 < 16; ++s4)
-        acc = Mf::mma(ta[s4], __uint_as_float(unsigned(wd[s4])), acc);
+      for (int s4 = 0; s4 < 16; ++s4) {
+        T xv;
+        if constexpr (WPV == 2)
+          xv = __longlong_as_double(
+              (long long)(((wd[s4][1] & 0xffffffffu) << 32) | (wd[s4][0] & 0xffffffffu)));
+        else
+          xv = __uint_as_float(unsigned(wd[s4][0]));
+        acc = Mf::mma(ta[s4], xv, acc);
+      }
 #pragma unroll
       for (int s4 = 0; s4 < 16; ++s4) {
         ta[s4] = tn[s4];
-        wd[s4] = wn[s4];
+#pragma unroll
+        for (int h = 0; h < WPV; ++h) wd[s4][h] = wn[s4][h];
       }
     }
     if (!ok) s_bad = 1;  // read only after the barrier below
 #pragma unroll
-    for (int r = 0; r < 4; ++r) sacc[16 * w + 4 * g + r][l16] = acc[r];
+    for (int r = 0; r < 4; ++r) sacc[16 * w + Mf::row(lane, r)][l16] = acc[r];
     __syncthreads();
     if (s_bad) break;
     // X_i = T_ii^-1 acc: operand B[k][j] = acc(4 s + g, l16)
     acc_t x = acc_t{};
 #pragma unroll
     for (int s4 = 0; s4 < 16; ++s4) x = Mf::mma(ia[s4], sacc[4 * s4 + g][l16], x);
-    uint64_t* dst = xw + size_t(ch) * size_t(nb) * kChainWords + size_t(bi) * kChainWords;
+    uint64_t* dst = xw + size_t(ch) * size_t(nb) * kTaskW + size_t(bi) * kTaskW;
     const uint64_t tag = uint64_t(tag0 + unsigned(bi)) << 32;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = 16 * w + 4 * g + r;  // word 64 s + l holds row 4 s + l/16
-      st_word(dst + row * kChainW + l16, tag | __float_as_uint(x[r]));
+      const int row = 16 * w + Mf::row(lane, r);  // value 64 s + l holds row 4 s + l/16
+      uint64_t* p = dst + size_t(row * kChainW + l16) * WPV;
+      if constexpr (WPV == 2) {
+        const uint64_t b = uint64_t(__double_as_longlong(double(x[r])));
+        st_word(p, tag | (b & 0xffffffffu));
+        st_word(p + 1, tag | (b >> 32));
+      } else {
+        st_word(p, tag | __float_as_uint(float(x[r])));
+      }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = 16 * w + 4 * g + r;
+      const int row = 16 * w + Mf::row(lane, r);
       if (row < ib && l16 < rc) X[(r0 + row) + (c0 + l16) * ldx] = x[r];
     }
     __syncthreads();  // sacc, s_t and s_bad are reused
@@ -994,21 +1017,8 @@ hipError_t factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* rowid,
   return hipGetLastError();
 }
 
-// x <- (diagonal block inverse) x, in place (same argument as the panel's
-// triangular solve: BM >= kNB covers every row, no split-K).
-template <typename T>
-hipError_t apply_inverse(int dtype, int jb, int64_t nrhs, const T* inv, T* X, int64_t ldx,
-                         hipStream_t s) {
-  GemmConfig c = gemm_choose(dtype, 0, 0, jb, nrhs, jb);
-  c.split = 1;
-  return gemm_launch(dtype, 0, 0, 0, 0, jb, nrhs, jb, 1.0, inv, kNB, X, ldx, 0.0, X, ldx, nullptr,
-                     c, s);
-}
-
-// Solve in FP32: forward and backward substitution each in one launch of
-// chain_solve_kernel per 1024 columns. Solve in FP64: one launch per block
-// step (the inverse of the diagonal block applied, then the rows still to
-// solve updated with a product).
+// Forward and backward substitution, each one launch of chain_solve_kernel
+// per 1024 columns.
 template <typename T>
 hipError_t solve_typed(int64_t n, int64_t nrhs, const T* LU, int64_t lda, const int32_t* rowid,
                        void* work, const T* B, int64_t ldb, T* X, int64_t ldx, int32_t* status,
@@ -1019,49 +1029,28 @@ hipError_t solve_typed(int64_t n, int64_t nrhs, const T* LU, int64_t lda, const 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   LuWork w = carve(work, n);
-  if constexpr (sizeof(T) == 8) {
-    const int dtype = 0;
-    const int64_t np = cdiv(n, kNB);
-    const T* inv = static_cast<const T*>(w.inv);
-    for (int64_t p = 0; p < np; ++p) {  // forward: L y = P b
-      const int64_t r0 = p * kNB;
-      const int jb = int(std::min<int64_t>(kNB, n - r0));
-      e = apply_inverse<T>(dtype, jb, nrhs, inv + size_t(p) * 2 * kNB * kNB, X + r0, ldx, s);
-      if (e != hipSuccess) return e;
-      e = update<T>(dtype, n - r0 - jb, nrhs, jb, LU + (r0 + jb) + r0 * lda, lda, X + r0, ldx,
-                    X + r0 + jb, ldx, s);
-      if (e != hipSuccess) return e;
-    }
-    for (int64_t p = np - 1; p >= 0; --p) {  // backward: U x = y
-      const int64_t r0 = p * kNB;
-      const int jb = int(std::min<int64_t>(kNB, n - r0));
-      e = apply_inverse<T>(dtype, jb, nrhs, inv + size_t(p) * 2 * kNB * kNB + kNB * kNB, X + r0,
-                           ldx, s);
-      if (e != hipSuccess) return e;
-      e = update<T>(dtype, r0, nrhs, jb, LU + r0 * lda, lda, X + r0, ldx, X, ldx, s);
-      if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-  } else {
-    const T* inv = static_cast<const T*>(w.inv);
-    const int64_t nb = cdiv(n, kNB);
-    for (int64_t cb = 0; cb < nrhs; cb += kChainCols) {
-      const int64_t cols = std::min<int64_t>(nrhs - cb, kChainCols);
-      const int chunks = int(cdiv(cols, kChainW));
-      const unsigned grid = unsigned(std::min<int64_t>(nb * chunks, kChainGrid));
-      // fresh tickets and words (forward tags 1..nb, backward nb+1..2nb)
-      e = fill_i32_launch(reinterpret_cast<int32_t*>(w.tickets),
-                          256 / 4 + 2 * int64_t(chunks) * nb * kChainWords, 0, s);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((chain_solve_kernel<false>), dim3(grid), dim3(256), 0, s, LU, lda, n, inv,
-                         X, ldx, cb, nrhs, chunks, w.xw, w.tickets, 1u, status);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL((chain_solve_kernel<true>), dim3(grid), dim3(256), 0, s, LU, lda, n, inv,
-                         X, ldx, cb, nrhs, chunks, w.xw, w.tickets + 1, unsigned(nb + 1), status);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    return hipSuccess;
+  const T* inv = static_cast<const T*>(w.inv);
+  const int64_t nb = cdiv(n, kNB);
+  constexpr int64_t wpv = sizeof(T) / 4;
+  for (int64_t cb = 0; cb < nrhs; cb += kChainCols) {
+    const int64_t cols = std::min<int64_t>(nrhs - cb, kChainCols);
+    const int chunks = int(cdiv(cols, kChainW));
+    // resident workgroups: two waves per SIMD in FP32, one in FP64
+    const unsigned grid =
+        unsigned(std::min<int64_t>(nb * chunks, sizeof(T) == 8 ? kChainGrid / 2 : kChainGrid));
+    // fresh tickets and words (forward tags 1..nb, backward nb+1..2nb)
+    e = fill_i32_launch(reinterpret_cast<int32_t*>(w.tickets),
+                        256 / 4 + 2 * wpv * int64_t(chunks) * nb * kChainWords, 0, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((chain_solve_kernel<T, false>), dim3(grid), dim3(256), 0, s, LU, lda, n,
+                       inv, X, ldx, cb, nrhs, chunks, w.xw, w.tickets, 1u, status);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((chain_solve_kernel<T, true>), dim3(grid), dim3(256), 0, s, LU, lda, n,
+                       inv, X, ldx, cb, nrhs, chunks, w.xw, w.tickets + 1, unsigned(nb + 1),
+                       status);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
+  return hipSuccess;
 }
 
 }  // namespace
@@ -1075,8 +1064,9 @@ size_t lu_workspace_bytes(int dtype, int64_t n, int64_t nrhs) {
   b += size_t(np) * 4 * kNB * sizeof(int32_t);
   b = (b + 255) & ~size_t(255);
   b += 256;  // tickets
-  // the FP32 solve's exchange (the FP64 solve launches per block step)
-  if (dtype == 1 && nrhs > 0) b += solve_words(std::max<int64_t>(n, 1), nrhs) * sizeof(uint64_t);
+  // the solve's exchange (one 64-bit word per FP32 value, two per FP64 value)
+  if (nrhs > 0)
+    b += solve_words(std::max<int64_t>(n, 1), nrhs) * sizeof(uint64_t) * (dtype == 0 ? 2 : 1);
   return (b + 255) & ~size_t(255);
 }
 

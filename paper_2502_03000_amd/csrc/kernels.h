@@ -182,18 +182,16 @@ hipError_t gtsv_launch(int dtype, int64_t n, int64_t nrhs, const void* S, int64_
 // to FP32 when it is stored.
 // n <= kLuMaxN (larger n: hipErrorInvalidValue). The workspace also keeps the
 // inverses of the 64 x 64 diagonal blocks, which lu_solve_launch applies, and
-// (FP32, nrhs > 0) the solve's exchange of solved blocks for nrhs right-hand
-// sides.
+// (nrhs > 0) the solve's exchange of solved blocks for nrhs right-hand sides.
 constexpr int64_t kLuMaxN = 16384;
 size_t lu_workspace_bytes(int dtype, int64_t n, int64_t nrhs = 0);
 hipError_t lu_factor_launch(int dtype, int64_t n, void* A, int64_t lda, int32_t* rowid,
                             void* work, int32_t* status, hipStream_t s, const Lookahead* side,
                             int update_precision = 0, bool panel_fp64 = false);
 // X (n x nrhs, ldx) <- U^{-1} L^{-1} B[rowid], B with ldb; work: the
-// factorisation's workspace, sized for at least nrhs right-hand sides. FP32:
-// two launches per 1024 right-hand sides (forward, backward), a wait that
-// timed out raises status[1]; FP64: a launch pair per 64-row block and
-// direction. X may not alias B.
+// factorisation's workspace, sized for at least nrhs right-hand sides. Two
+// launches per 1024 right-hand sides (forward, backward); a wait that timed
+// out raises status[1]. X may not alias B.
 hipError_t lu_solve_launch(int dtype, int64_t n, int64_t nrhs, const void* LU, int64_t lda,
                            const int32_t* rowid, void* work, const void* B, int64_t ldb, void* X,
                            int64_t ldx, int32_t* status, hipStream_t s);
