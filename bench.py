@@ -54,7 +54,9 @@ def parse():
     ap.add_argument("--overlap", action="store_true",
                     help="expr workload: the chain's launches on a second stream beside the "
                          "element-wise pass")
-    ap.add_argument("--forms", default="", help="comma-separated subset of forms (syrk, solve)")
+    ap.add_argument("--forms", default="",
+                    help="comma-separated subset of forms (syrk, solve; batched: batched_fp64, "
+                         "plain_fp64_per_instance beside the FP32 launch, which always runs)")
     ap.add_argument("--no-tune", action="store_true", help="skip product autotuning")
     ap.add_argument("--tune-save", default="",
                     help="write the context's tuning table here after the run")
@@ -476,8 +478,11 @@ def bench_batched(args, ctx, hx, torch, inputs):
 
     forms = []
     batches = {}
+    wanted = [f for f in args.forms.split(",") if f] or ["batched_fp64", "plain_fp64_per_instance"]
     for name, tdt, hdt, ptrs in [("batched_fp32", torch.float32, hx.F32, ptrs32),
                                  ("batched_fp64", torch.float64, hx.F64, ptrs64)]:
+        if name != "batched_fp32" and name not in wanted:
+            continue
         root, leaves = template(hdt)
         out, optrs, offs = hx.output_arena(sizes, tdt)
         bt = ctx.batch(root, leaves, sizes, ptrs, optrs)
@@ -499,40 +504,41 @@ def bench_batched(args, ctx, hx, torch, inputs):
         batches[name] = (bt, ws, out, info)
 
     # plain FP64 path: one ordinary plan per instance over views of the FP64 arena
-    base = arena64.data_ptr()
-    out64, optrs64, offs64 = hx.output_arena(sizes, torch.float64)
-    plans, max_ws = [], 1
-    t1 = time.perf_counter()
-    for i, n in enumerate(sizes):
-        n = int(n)
-        off = [(int(ptrs64[i, j]) - base) // 8 for j in range(7)]
-        mat = lambda j: arena64[off[j]:off[j] + n * n].view(n, n).t()
-        vec = lambda j: arena64[off[j]:off[j] + n]
-        A, B, v, S, b, p, q = (ctx.leaf(mat(j) if j in (0, 1, 3) else vec(j)) for j in range(7))
-        pl = ctx.plan(hx.trans(A) * B * v + hx.solve(S, b) + 2 * (p % q))
-        plans.append((pl, out64[offs64[i]:offs64[i] + n]))
-        max_ws = max(max_ws, pl.workspace_bytes)
-        ctx.clear()
-    plan_s = time.perf_counter() - t1
-    ws64 = torch.empty(max_ws, dtype=torch.uint8, device="cuda")
+    if "plain_fp64_per_instance" in wanted:
+        base = arena64.data_ptr()
+        out64, optrs64, offs64 = hx.output_arena(sizes, torch.float64)
+        plans, max_ws = [], 1
+        t1 = time.perf_counter()
+        for i, n in enumerate(sizes):
+            n = int(n)
+            off = [(int(ptrs64[i, j]) - base) // 8 for j in range(7)]
+            mat = lambda j: arena64[off[j]:off[j] + n * n].view(n, n).t()
+            vec = lambda j: arena64[off[j]:off[j] + n]
+            A, B, v, S, b, p, q = (ctx.leaf(mat(j) if j in (0, 1, 3) else vec(j)) for j in range(7))
+            pl = ctx.plan(hx.trans(A) * B * v + hx.solve(S, b) + 2 * (p % q))
+            plans.append((pl, out64[offs64[i]:offs64[i] + n]))
+            max_ws = max(max_ws, pl.workspace_bytes)
+            ctx.clear()
+        plan_s = time.perf_counter() - t1
+        ws64 = torch.empty(max_ws, dtype=torch.uint8, device="cuda")
 
-    def plain_all():
-        for pl, o in plans:
-            pl.execute(o, ws64)
+        def plain_all():
+            for pl, o in plans:
+                pl.execute(o, ws64)
 
-    plain_all()  # warm-up
-    ctx.sync()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    plain_all()
-    torch.cuda.synchronize()
-    ms_plain = (time.perf_counter() - t1) * 1e3
-    rep = ctx.sync()
-    flops = batches["batched_fp32"][3]["flops"]
-    forms.append({"form": "plain_fp64_per_instance", "ms": ms_plain, "status": int(rep.status),
-                  "gflops": flops / (ms_plain * 1e-3) / 1e9,
-                  "max_rel_err_sampled": err_of(out64.cpu().numpy(), offs64),
-                  "plan_s": plan_s, "launch": "eager, one plan per instance"})
+        plain_all()  # warm-up
+        ctx.sync()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plain_all()
+        torch.cuda.synchronize()
+        ms_plain = (time.perf_counter() - t1) * 1e3
+        rep = ctx.sync()
+        flops = batches["batched_fp32"][3]["flops"]
+        forms.append({"form": "plain_fp64_per_instance", "ms": ms_plain, "status": int(rep.status),
+                      "gflops": flops / (ms_plain * 1e-3) / 1e9,
+                      "max_rel_err_sampled": err_of(out64.cpu().numpy(), offs64),
+                      "plan_s": plan_s, "launch": "eager, one plan per instance"})
     by = {f["form"]: f for f in forms}
     chosen = by["batched_fp32"]
     info = batches["batched_fp32"][3]
@@ -558,7 +564,8 @@ def bench_batched(args, ctx, hx, torch, inputs):
                    "form": "one persistent launch, autotuned, hip graph replay",
                    "total_gflop": info["flops"] / 1e9, "total_gbytes": info["bytes"] / 1e9},
         "roofline": roof,
-        "speedup_vs_plain_fp64": by["plain_fp64_per_instance"]["ms"] / ms,
+        "speedup_vs_plain_fp64": (by["plain_fp64_per_instance"]["ms"] / ms
+                                  if "plain_fp64_per_instance" in by else None),
         "forms": forms, "generate_s": gen_s,
     }
     if not args.no_cpu_baseline:
