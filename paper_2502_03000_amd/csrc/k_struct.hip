@@ -171,75 +171,152 @@ __global__ __launch_bounds__(256) void structure_kernel(int64_t n, const T* __re
 // conditions around loads or stores: those make the compiler keep all 64
 // values live across each branch and spill them.
 
+// Orders a wave's LDS stores before its later LDS loads (one wave works).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Cholesky of the diagonal block at (k0, k0) (jb <= 64 rows; rows and
-// columns past jb are the identity) by one wave, lane r holding row r of the
-// block: per column j the pivot (lane j's entry, read by all through LDS),
-// its square root, the column of multipliers published through LDS, then
-// each lane's rank-1 update of its row. Only entries on or below the
-// diagonal feed later columns. L11 is written over the block's lower
-// triangle; a pivot that is not > 0 sets info[4] and the block is then not
-// stored.
+// columns past jb are the identity) and its inverse. The factorisation is
+// wave 0's, lane r holding row r of the block: per column j the pivot (lane
+// j's entry, read by all through LDS), its square root, the column of
+// multipliers published through LDS and read back 16 entries at a time
+// (every read of a group in flight together), then each lane's rank-1 update
+// of its row. Only entries on or below the diagonal feed later columns. L11
+// is written over the block's lower triangle; a pivot that is not > 0 sets
+// info[4] and nothing is stored. The inverse R = L11^-1 then takes all four
+// waves, by blocked substitution over 16-row blocks: D_b = L_bb^-1 by
+// substitution (wave 0, lane (b, c) building column c of D_b), M_bj = D_b
+// L_bj for j < b (MFMA), R_b = D_b E_b - sum_j M_bj R_j with E the identity
+// (MFMA, wave w taking columns 16w..16w+15); it is stored column-major.
 template <typename T>
-__global__ __launch_bounds__(64) void potrf_block_kernel(T* __restrict__ A, int64_t lda,
-                                                         int64_t k0, int jb, int32_t* info,
-                                                         T* __restrict__ inv) {
-  __shared__ T piv[kB];      // column j before scaling: the pivot is piv[j]
-  __shared__ T colj[2][kB];  // column j of L (two buffers: no reuse before two barriers)
-  const int r = threadIdx.x;
-  const int rr = std::min(r, jb - 1);
-  T a[kB];
+__global__ __launch_bounds__(256) void potrf_block_kernel(T* __restrict__ A, int64_t lda,
+                                                          int64_t k0, int jb, int32_t* info,
+                                                          T* __restrict__ inv) {
+  using Mf = Mfma<T>;
+  using acc_t = typename Mf::acc_t;
+  __shared__ T piv[kB];             // column j before scaling: the pivot is piv[j]
+  __shared__ T colj[kB];            // column j of L
+  __shared__ T Lc[kB][kB + 16];     // Lc[l][i] = L11(i, l), identity padding
+  __shared__ T Ds[4][16][16 + 4];   // Ds[b][t][i] = D_b(i, t)
+  __shared__ T Ms[6][16][16 + 4];   // Ms[p][t][i] = M_bj(i, t), p = b(b-1)/2 + j
+  __shared__ T Rs[4][16][kB + 4];   // Rs[w][c][i] = R(i, 16w + c)
+  __shared__ int s_bad;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+  if (w == 0) {
+    const int r = lane;
+    const int rr = std::min(r, jb - 1);
+    if (r == 0) s_bad = 0;
+    T a[kB];
 #pragma unroll
-  for (int c = 0; c < kB; ++c) a[c] = A[(k0 + rr) + (k0 + std::min(c, jb - 1)) * lda];
+    for (int c = 0; c < kB; ++c) a[c] = A[(k0 + rr) + (k0 + std::min(c, jb - 1)) * lda];
 #pragma unroll
-  for (int c = 0; c < kB; ++c) materialize(a[c]);
+    for (int c = 0; c < kB; ++c) materialize(a[c]);
 #pragma unroll
-  for (int c = 0; c < kB; ++c)
-    a[c] = (r < jb && c < jb) ? (c <= r ? a[c] : T(0)) : (r == c ? T(1) : T(0));
-  bool bad = false;
+    for (int c = 0; c < kB; ++c)
+      a[c] = (r < jb && c < jb) ? (c <= r ? a[c] : T(0)) : (r == c ? T(1) : T(0));
+    bool bad = false;
+#pragma clang loop unroll(full)
+    for (int j = 0; j < kB; ++j) {
+      piv[r] = a[j];
+      wave_sync();
+      const T d = piv[j];
+      const bool ok = d > T(0);
+      bad = bad || !ok;
+      const T ljj = ok ? sqrt(d) : T(1);
+      const T l = r == j ? ljj : a[j] / ljj;
+      a[j] = l;
+      colj[r] = l;
+      wave_sync();
 #pragma unroll
-  for (int j = 0; j < kB; ++j) {
-    piv[r] = a[j];
-    __syncthreads();
-    const T d = piv[j];
-    const bool ok = d > T(0);
-    bad = bad || !ok;
-    const T ljj = ok ? sqrt(d) : T(1);
-    const T l = r == j ? ljj : a[j] / ljj;
-    a[j] = l;
-    colj[j & 1][r] = l;
-    __syncthreads();
+      for (int c0 = (j + 1) & ~15; c0 < kB; c0 += 16) {
+        T cj[16];
 #pragma unroll
-    for (int c = j + 1; c < kB; ++c) a[c] -= l * colj[j & 1][c];
+        for (int q = 0; q < 16; ++q)
+          if (c0 + q > j) cj[q] = colj[c0 + q];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (c0 + q > j) materialize(cj[q]);
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (c0 + q > j) a[c0 + q] -= l * cj[q];
+      }
+      wave_sync();  // piv and colj are rewritten by the next column
+    }
+    if (bad) {
+      if (r == 0) s_bad = 1;
+    } else {
+      if (r < jb) {
+        // descending, so that column min(c, r) finally holds a[min(c, r)]
+#pragma unroll
+        for (int c = kB - 1; c >= 0; --c) A[(k0 + r) + (k0 + std::min(c, r)) * lda] = a[c];
+      }
+#pragma unroll
+      for (int c = 0; c < kB; ++c) Lc[c][r] = c <= r ? a[c] : T(0);
+    }
   }
-  if (bad) {
-    if (r == 0) info[4] = 1;
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) info[4] = 1;
     return;
   }
-  if (r < jb) {
-    // descending, so that column min(c, r) finally holds a[min(c, r)]
+  if (w == 0) {  // D_b = L_bb^-1, lane (b, c) = (g, l16) builds column c
+    T x[16];
 #pragma unroll
-    for (int c = kB - 1; c >= 0; --c) A[(k0 + r) + (k0 + std::min(c, r)) * lda] = a[c];
+    for (int i = 0; i < 16; ++i) x[i] = T(i == l16 ? 1 : 0);
+#pragma unroll
+    for (int l = 0; l < 16; ++l) {
+      const T xl = x[l] / Lc[16 * g + l][16 * g + l];
+      x[l] = xl;
+#pragma unroll
+      for (int i = l + 1; i < 16; ++i) x[i] -= Lc[16 * g + l][16 * g + i] * xl;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Ds[g][l16][i] = x[i];
   }
-  // L11^-1 (for the block column below and for the solves): L11 into LDS
-  // (rows and columns past jb are the identity), then lane j solves
-  // L11 x = e_j by forward substitution for column j of the inverse
-  __shared__ T L[kB][kB + 1];
-#pragma unroll
-  for (int c = 0; c < kB; ++c) L[r][c] = c <= r ? a[c] : T(0);
   __syncthreads();
-  T x[kB];
+  // M_bj = D_b L_bj: operand A[i][t] = D_b(i, t), B[t][c] = L(16b + t, 16j + c)
+  for (int p = w; p < 6; p += 4) {
+    const int b = p < 1 ? 1 : p < 3 ? 2 : 3;
+    const int j = p - b * (b - 1) / 2;
+    acc_t mm = acc_t{};
 #pragma unroll
-  for (int c = 0; c < kB; ++c) x[c] = c == r ? T(1) : T(0);
+    for (int s4 = 0; s4 < 4; ++s4)
+      mm = Mf::mma(Ds[b][4 * s4 + g][l16], Lc[16 * j + l16][16 * b + 4 * s4 + g], mm);
 #pragma unroll
-  for (int c = 0; c < kB; ++c) {
-    T t4[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll
-    for (int q = 0; q < c; ++q) t4[q & 3] += L[c][q] * x[q];
-    x[c] = (x[c] - ((t4[0] + t4[1]) + (t4[2] + t4[3]))) / L[c][c];
+    for (int r = 0; r < 4; ++r) Ms[p][l16][Mf::row(lane, r)] = mm[r];
   }
-  T* out = inv + r * kB;
+  __syncthreads();
+  // R_b = D_b E_b - sum_{j<b} M_bj R_j on this wave's 16 columns
 #pragma unroll
-  for (int c = 0; c < kB; ++c) out[c] = x[c];
+  for (int b = 0; b < 4; ++b) {
+    acc_t acc = acc_t{};
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int row = 16 * b + 4 * s4 + g;
+      acc = Mf::mma(Ds[b][4 * s4 + g][l16], T(row == 16 * w + l16 ? 1 : 0), acc);
+    }
+#pragma unroll
+    for (int j = 0; j < b; ++j) {
+      const int p = b * (b - 1) / 2 + j;
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+        acc = Mf::mma(-Ms[p][4 * s4 + g][l16], Rs[w][l16][16 * j + 4 * s4 + g], acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Rs[w][l16][16 * b + Mf::row(lane, r)] = acc[r];
+    __builtin_amdgcn_s_waitcnt(0);  // the block is in LDS before the next reads it
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  constexpr int PER = kB * kB / 256;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = tid + 256 * q, i = e % kB, c = e / kB;
+    inv[e] = Rs[c / 16][c % 16][i];  // (i, c) at i + kB c
+  }
 }
 
 // The block column under a factored diagonal block, L21 = A21 L11^-T, as a
@@ -718,7 +795,7 @@ hipError_t chol_panel(T* A, int64_t lda, int64_t n, int64_t k0, int32_t* info, T
                       hipStream_t s) {
   const int jb = int(std::min<int64_t>(kB, n - k0));
   T* d = inv + (k0 / kB) * kB * kB;  // this diagonal block's inverse
-  hipLaunchKernelGGL((potrf_block_kernel<T>), dim3(1), dim3(kB), 0, s, A, lda, k0, jb, info, d);
+  hipLaunchKernelGGL((potrf_block_kernel<T>), dim3(1), dim3(256), 0, s, A, lda, k0, jb, info, d);
   hipError_t e = hipGetLastError();
   const int64_t m = n - k0 - jb;
   if (e != hipSuccess || m <= 0) return e;
