@@ -301,7 +301,8 @@ hexla_status run_struct_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipS
     } else {
       e = copy_b(xo, X.ld);
       if (e == hipSuccess)
-        e = k::tri_solve_launch(s.dtype, 0, n, r, wm, ldw, xo, X.ld, addr(s.coef, b), true, st);
+        e = k::tri_solve_launch(s.dtype, 0, n, r, wm, ldw, xo, X.ld, addr(s.coef, b), true,
+                                ctx->d_status, st);
       if (e != hipSuccess) return fail(e, "solve: cholesky substitution");
     }
   }
@@ -331,7 +332,7 @@ hexla_status run_struct_solve(hexla_ctx* ctx, const Step& s, const Bind& b, hipS
       e = copy_b(xo, X.ld);
       if (e == hipSuccess)
         e = k::tri_solve_launch(s.dtype, solver == HEXLA_SOLVER_LOWER ? 1 : 2, n, r, wm, ldw, xo,
-                                X.ld, addr(s.coef, b), false, st);
+                                X.ld, addr(s.coef, b), false, ctx->d_status, st);
       break;
     case HEXLA_SOLVER_TRIDIAGONAL:
       e = copy_b(xo, X.ld);

@@ -569,11 +569,15 @@ __global__ __launch_bounds__(kNB) void inv_block_kernel(const T* __restrict__ A,
 // completion. The exchange and the tickets start at zero (tags start at 1).
 // Padding rows and columns are exact zeros. Every wait is bounded: a timeout
 // raises status[1] and the workgroup exits.
-template <typename T, bool UPPER>
+// TRANS: the factor is the transpose of the stored lower triangle (L^T of a
+// Cholesky factor, backward): T_ij = L_ji^T, read along rows of L, and the
+// diagonal blocks' inverses are read transposed. The inverse of block i is
+// at inv + i inv_stride (column-major 64 x 64).
+template <typename T, bool UPPER, bool TRANS = false>
 __global__ __launch_bounds__(256) void chain_solve_kernel(
     const T* __restrict__ LU, int64_t lda, int64_t n, const T* __restrict__ inv,
-    T* __restrict__ X, int64_t ldx, int64_t c_begin, int64_t nrhs, int chunks, uint64_t* xw,
-    unsigned* ticket, unsigned tag0, int32_t* status) {
+    int64_t inv_stride, T* __restrict__ X, int64_t ldx, int64_t c_begin, int64_t nrhs, int chunks,
+    uint64_t* xw, unsigned* ticket, unsigned tag0, int32_t* status) {
   using Mf = Mfma<T>;
   using acc_t = typename Mf::acc_t;
   constexpr int WPV = sizeof(T) / 4;  // exchange words per value
@@ -607,20 +611,21 @@ __global__ __launch_bounds__(256) void chain_solve_kernel(
       acc[r] = (row < ib && l16 < rc) ? v : T(0);
     }
     // T_ii^-1 rows 16w.. as operand A (column-major, padded with the identity)
-    const T* iv = inv + size_t(bi) * 2 * kNB * kNB + (UPPER ? kNB * kNB : 0);
+    const T* iv = inv + size_t(bi) * inv_stride;
     T ia[16];
 #pragma unroll
-    for (int s4 = 0; s4 < 16; ++s4) ia[s4] = iv[arow + kNB * (4 * s4 + g)];
+    for (int s4 = 0; s4 < 16; ++s4)
+      ia[s4] = TRANS ? iv[(4 * s4 + g) + kNB * arow] : iv[arow + kNB * (4 * s4 + g)];
     // operand A of dependency d: -T(r0 + arow, j0 + 4 s + g), zero outside
     auto load_t = [&](int d, T* ta) {
       const int bj = UPPER ? nb - 1 - d : d;
       const int64_t j0 = int64_t(bj) * kNB;
       const int jbj = int(std::min<int64_t>(kNB, n - j0));
-      const T* base = LU + (r0 + arow_c) + j0 * lda;
 #pragma unroll
       for (int s4 = 0; s4 < 16; ++s4) {
         const int k = 4 * s4 + g;
-        const T v = base[int64_t(std::min(k, jbj - 1)) * lda];
+        const int64_t kc = j0 + std::min(k, jbj - 1);
+        const T v = TRANS ? LU[kc + (r0 + arow_c) * lda] : LU[(r0 + arow_c) + kc * lda];
         ta[s4] = (arow < ib && k < jbj) ? -v : T(0);
       }
     };
@@ -1017,6 +1022,47 @@ hipError_t factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* rowid,
   return hipGetLastError();
 }
 
+// One direction of the blocked triangular solve over all columns of X, one
+// launch per 1024 columns: mode 0 lower (forward), 1 upper (backward), 2
+// the transpose of the stored lower triangle (backward). tickets (two
+// counters) and xw (the exchange) come from the caller's workspace; tag0
+// distinguishes a second direction sharing the same exchange (tags of the
+// first: 1..nb, the second: nb+1..2nb); the words are cleared with the
+// first direction.
+template <typename T>
+hipError_t chain_run(int mode, int64_t n, int64_t nrhs, const T* M, int64_t ldm, const T* inv,
+                     int64_t inv_stride, T* X, int64_t ldx, unsigned* tickets, uint64_t* xw,
+                     bool second, int32_t* status, hipStream_t s) {
+  const int64_t nb = cdiv(n, kNB);
+  constexpr int64_t wpv = sizeof(T) / 4;
+  hipError_t e = hipSuccess;
+  for (int64_t cb = 0; cb < nrhs; cb += kChainCols) {
+    const int64_t cols = std::min<int64_t>(nrhs - cb, kChainCols);
+    const int chunks = int(cdiv(cols, kChainW));
+    // resident workgroups: two waves per SIMD in FP32, one in FP64
+    const unsigned grid =
+        unsigned(std::min<int64_t>(nb * chunks, sizeof(T) == 8 ? kChainGrid / 2 : kChainGrid));
+    if (!second || cb > 0) {  // fresh tickets and words
+      e = fill_i32_launch(reinterpret_cast<int32_t*>(tickets),
+                          256 / 4 + 2 * wpv * int64_t(chunks) * nb * kChainWords, 0, s);
+      if (e != hipSuccess) return e;
+    }
+    unsigned* tk = tickets + (second ? 1 : 0);
+    const unsigned tag0 = second ? unsigned(nb + 1) : 1u;
+    if (mode == 0)
+      hipLaunchKernelGGL((chain_solve_kernel<T, false>), dim3(grid), dim3(256), 0, s, M, ldm, n,
+                         inv, inv_stride, X, ldx, cb, nrhs, chunks, xw, tk, tag0, status);
+    else if (mode == 1)
+      hipLaunchKernelGGL((chain_solve_kernel<T, true>), dim3(grid), dim3(256), 0, s, M, ldm, n,
+                         inv, inv_stride, X, ldx, cb, nrhs, chunks, xw, tk, tag0, status);
+    else
+      hipLaunchKernelGGL((chain_solve_kernel<T, true, true>), dim3(grid), dim3(256), 0, s, M,
+                         ldm, n, inv, inv_stride, X, ldx, cb, nrhs, chunks, xw, tk, tag0, status);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // Forward and backward substitution, each one launch of chain_solve_kernel
 // per 1024 columns.
 template <typename T>
@@ -1030,25 +1076,15 @@ hipError_t solve_typed(int64_t n, int64_t nrhs, const T* LU, int64_t lda, const 
   if (e != hipSuccess) return e;
   LuWork w = carve(work, n);
   const T* inv = static_cast<const T*>(w.inv);
-  const int64_t nb = cdiv(n, kNB);
-  constexpr int64_t wpv = sizeof(T) / 4;
   for (int64_t cb = 0; cb < nrhs; cb += kChainCols) {
     const int64_t cols = std::min<int64_t>(nrhs - cb, kChainCols);
-    const int chunks = int(cdiv(cols, kChainW));
-    // resident workgroups: two waves per SIMD in FP32, one in FP64
-    const unsigned grid =
-        unsigned(std::min<int64_t>(nb * chunks, sizeof(T) == 8 ? kChainGrid / 2 : kChainGrid));
-    // fresh tickets and words (forward tags 1..nb, backward nb+1..2nb)
-    e = fill_i32_launch(reinterpret_cast<int32_t*>(w.tickets),
-                        256 / 4 + 2 * wpv * int64_t(chunks) * nb * kChainWords, 0, s);
+    T* xc = X + cb * ldx;
+    e = chain_run<T>(0, n, cols, LU, lda, inv, 2 * kNB * kNB, xc, ldx, w.tickets, w.xw, false,
+                     status, s);
+    if (e == hipSuccess)
+      e = chain_run<T>(1, n, cols, LU, lda, inv + kNB * kNB, 2 * kNB * kNB, xc, ldx, w.tickets,
+                       w.xw, true, status, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((chain_solve_kernel<T, false>), dim3(grid), dim3(256), 0, s, LU, lda, n,
-                       inv, X, ldx, cb, nrhs, chunks, w.xw, w.tickets, 1u, status);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL((chain_solve_kernel<T, true>), dim3(grid), dim3(256), 0, s, LU, lda, n,
-                       inv, X, ldx, cb, nrhs, chunks, w.xw, w.tickets + 1, unsigned(nb + 1),
-                       status);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -1068,6 +1104,45 @@ size_t lu_workspace_bytes(int dtype, int64_t n, int64_t nrhs) {
   if (nrhs > 0)
     b += solve_words(std::max<int64_t>(n, 1), nrhs) * sizeof(uint64_t) * (dtype == 0 ? 2 : 1);
   return (b + 255) & ~size_t(255);
+}
+
+size_t tri_chain_work_bytes(int dtype, int64_t n, int64_t nrhs) {
+  if (n <= 0 || nrhs <= 0) return 0;
+  return 256 + solve_words(n, nrhs) * sizeof(uint64_t) * (dtype == 0 ? 2 : 1);
+}
+
+hipError_t tri_chain_launch(int dtype, int64_t n, int64_t nrhs, const void* M, int64_t ldm,
+                            int mode1, const void* inv1, int64_t stride1, int mode2,
+                            const void* inv2, int64_t stride2, void* X, int64_t ldx, void* work,
+                            int32_t* status, hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return hipSuccess;
+  if (n > kLuMaxN || mode1 < 0 || mode1 > 2 || mode2 < -1 || mode2 > 2 ||
+      (reinterpret_cast<uintptr_t>(work) & 255))
+    return hipErrorInvalidValue;
+  unsigned* tickets = static_cast<unsigned*>(work);
+  uint64_t* xw = reinterpret_cast<uint64_t*>(static_cast<char*>(work) + 256);
+  hipError_t e = hipSuccess;
+  // per 1024 columns: the first direction, then the second on the same words
+  for (int64_t cb = 0; cb < nrhs && e == hipSuccess; cb += kChainCols) {
+    const int64_t cols = std::min<int64_t>(nrhs - cb, kChainCols);
+    for (int d = 0; d < 2 && e == hipSuccess; ++d) {
+      const int mode = d == 0 ? mode1 : mode2;
+      if (mode < 0) break;
+      const void* inv = d == 0 ? inv1 : inv2;
+      const int64_t stride = d == 0 ? stride1 : stride2;
+      if (dtype == 0)
+        e = chain_run<double>(mode, n, cols, static_cast<const double*>(M), ldm,
+                              static_cast<const double*>(inv), stride,
+                              static_cast<double*>(X) + cb * ldx, ldx, tickets, xw, d == 1,
+                              status, s);
+      else
+        e = chain_run<float>(mode, n, cols, static_cast<const float*>(M), ldm,
+                             static_cast<const float*>(inv), stride,
+                             static_cast<float*>(X) + cb * ldx, ldx, tickets, xw, d == 1, status,
+                             s);
+    }
+  }
+  return e;
 }
 
 hipError_t rank_update_bt_launch(int dtype, int64_t m, int64_t n, int64_t K, const void* A,

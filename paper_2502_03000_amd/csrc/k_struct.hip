@@ -437,147 +437,6 @@ __global__ __launch_bounds__(64) void trtri_blocks_kernel(const T* __restrict__ 
   for (int c = 0; c < kB; ++c) out[c] = x[c];
 }
 
-// One step of a block triangular solve with the inverted diagonal block
-// (blocks of 64 rows, diagonal block p at rows r0 .. r0 + jb): with X_p the
-// block's rows of the right-hand sides X,
-//   Y_p = D X_p,  D = T_pp^-1 (MODE 0: T = L, MODE 2: T = U) or L_pp^-T
-//                 (MODE 1, the transposed solve with the lower L),
-// written to Y by the workgroups of tile row 0; every other workgroup
-// recomputes Y_p for its 64 columns and updates one 64 x 64 tile of the rows
-// still to solve in place: X_i -= A_i Y_p, with A_i = L(i, p) below the block
-// (MODE 0), L(p, i)^T (MODE 1) or U(i, p) (MODE 2) above it. No workgroup
-// writes rows another one reads. Both products are computed transposed on
-// the MFMAs (rows of the MFMA result are columns of Y and of the tile), so
-// 16 consecutive lanes hold 16 consecutive rows of one column for the global
-// stores.
-template <typename T, int MODE>
-__global__ __launch_bounds__(256) void trsm_step_kernel(const T* __restrict__ M, int64_t ldm,
-                                                        int64_t n, int64_t r0, int jb,
-                                                        const T* __restrict__ inv, T* X,
-                                                        int64_t ldx, T* __restrict__ Y,
-                                                        int64_t ldy, int64_t nrhs, int tiles_m) {
-  using Mf = Mfma<T>;
-  using acc_t = typename Mf::acc_t;
-  constexpr int LD = kB + 1, WT = kB / 2, F = WT / 16;
-  __shared__ T sI[kB][LD];  // sI[k][j] = D(j, k)
-  __shared__ T sX[kB][LD];  // sX[k][j] = X_p(k, j), then Y_p(k, j)
-  __shared__ T sA[kB][LD];  // sA[k][i] = A_tile(i, k)
-  const int tm = int(blockIdx.x) % tiles_m, tn = int(blockIdx.x) / tiles_m;
-  const int64_t n0 = int64_t(tn) * kB;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave & 1, wc = wave >> 1, l16 = lane & 15, g = lane >> 4;
-  const int64_t u0 = MODE == 0 ? r0 + jb : 0;        // first row still to solve
-  const int64_t ue = MODE == 0 ? n : r0;             // one past the last
-  const int64_t m0 = u0 + int64_t(tm - 1) * kB;      // this tile's first row (tm >= 1)
-  const int64_t mlast = std::max<int64_t>(ue - 1, 0);
-  // 1. D, X_p and the A tile into LDS: every load issued first (clamped
-  // addresses), the zeros past jb, nrhs and the rows chosen when storing
-  constexpr int PER = kB * kB / 256;
-  T vi[PER], vx[PER], va[PER];
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int e = tid + 256 * q, a = e & (kB - 1), c = e / kB;
-    vi[q] = inv[a + kB * c];  // inverse block element (a, c)
-    vx[q] = X[(r0 + std::min(a, jb - 1)) + std::min<int64_t>(n0 + c, nrhs - 1) * ldx];
-    if (tm > 0)
-      va[q] = MODE == 1 ? M[(r0 + std::min(a, jb - 1)) + std::min<int64_t>(m0 + c, mlast) * ldm]
-                        : M[std::min<int64_t>(m0 + a, mlast) + (r0 + std::min(c, jb - 1)) * ldm];
-  }
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int e = tid + 256 * q, a = e & (kB - 1), c = e / kB;
-    const bool in = a < jb && c < jb;
-    if (MODE == 1) sI[a][c] = in ? vi[q] : T(0);  // D(c, a) = inverse(a, c)
-    else sI[c][a] = in ? vi[q] : T(0);            // D(a, c) = inverse(a, c)
-    sX[a][c] = (a < jb && n0 + c < nrhs) ? vx[q] : T(0);
-    if (tm > 0) {
-      if (MODE == 1) sA[a][c] = (a < jb && m0 + c < ue) ? va[q] : T(0);  // A(c, a) = L(r0+a, m0+c)
-      else sA[c][a] = (c < jb && m0 + a < ue) ? va[q] : T(0);            // A(a, c)
-    }
-  }
-  __syncthreads();
-  // 2. Y_p^T = X_p^T D^T: operand A[i][k] = X_p(k, column i), operand
-  // B[k][j] = D(row j, k); acc[fc][fr] register r holds Y_p(row wr*WT +
-  // fr*16 + l16, column wc*WT + fc*16 + Mf::row(lane, r))
-  acc_t acc[F][F];
-#pragma unroll
-  for (int fc = 0; fc < F; ++fc)
-#pragma unroll
-    for (int fr = 0; fr < F; ++fr) acc[fc][fr] = acc_t{};
-#pragma unroll 4
-  for (int k0 = 0; k0 < kB; k0 += 4) {
-    T x[F], d[F];
-#pragma unroll
-    for (int f = 0; f < F; ++f) {
-      x[f] = sX[k0 + g][wc * WT + f * 16 + l16];
-      d[f] = sI[k0 + g][wr * WT + f * 16 + l16];
-    }
-#pragma unroll
-    for (int fc = 0; fc < F; ++fc)
-#pragma unroll
-      for (int fr = 0; fr < F; ++fr) acc[fc][fr] = Mf::mma(x[fc], d[fr], acc[fc][fr]);
-  }
-  if (tm == 0) {  // the solved block
-#pragma unroll
-    for (int fc = 0; fc < F; ++fc)
-#pragma unroll
-      for (int fr = 0; fr < F; ++fr)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = wr * WT + fr * 16 + l16;
-          const int64_t col = n0 + wc * WT + fc * 16 + Mf::row(lane, r);
-          if (row < jb && col < nrhs) Y[(r0 + row) + col * ldy] = acc[fc][fr][r];
-        }
-    return;
-  }
-  __syncthreads();  // every read of X_p done
-#pragma unroll
-  for (int fc = 0; fc < F; ++fc)
-#pragma unroll
-    for (int fr = 0; fr < F; ++fr)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        sX[wr * WT + fr * 16 + l16][wc * WT + fc * 16 + Mf::row(lane, r)] = acc[fc][fr][r];
-  // 3. the tile, transposed like Y_p: register r of acc[fc][fr] holds
-  // X(m0 + wr*WT + fr*16 + l16, n0 + wc*WT + fc*16 + Mf::row(lane, r))
-#pragma unroll
-  for (int fc = 0; fc < F; ++fc)
-#pragma unroll
-    for (int fr = 0; fr < F; ++fr)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + wr * WT + fr * 16 + l16;
-        const int64_t col = n0 + wc * WT + fc * 16 + Mf::row(lane, r);
-        acc[fc][fr][r] = X[std::min<int64_t>(row, mlast) + std::min<int64_t>(col, nrhs - 1) * ldx];
-      }
-  __syncthreads();
-  // X_tile^T -= Y_p^T A^T: operand A[i][k] = -Y_p(k, column i), operand
-  // B[k][j] = A(row j, k)
-#pragma unroll 4
-  for (int k0 = 0; k0 < kB; k0 += 4) {
-    T y[F], a[F];
-#pragma unroll
-    for (int f = 0; f < F; ++f) {
-      y[f] = -sX[k0 + g][wc * WT + f * 16 + l16];
-      a[f] = sA[k0 + g][wr * WT + f * 16 + l16];
-    }
-#pragma unroll
-    for (int fc = 0; fc < F; ++fc)
-#pragma unroll
-      for (int fr = 0; fr < F; ++fr) acc[fc][fr] = Mf::mma(y[fc], a[fr], acc[fc][fr]);
-  }
-#pragma unroll
-  for (int fc = 0; fc < F; ++fc)
-#pragma unroll
-    for (int fr = 0; fr < F; ++fr)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + wr * WT + fr * 16 + l16;
-        const int64_t col = n0 + wc * WT + fc * 16 + Mf::row(lane, r);
-        if (row < ue && col < nrhs) X[row + col * ldx] = acc[fc][fr][r];
-      }
-}
-
 // ------------------------------------------------------------ tridiagonal
 
 // The three diagonals of S into contiguous arrays: sub[i] = S[i+1][i],
@@ -850,29 +709,17 @@ hipError_t chol_factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* i
   return e;
 }
 
-template <typename T, int MODE>
-hipError_t trsm_step(const T* M, int64_t ldm, int64_t n, int64_t r0, int jb, const T* inv,
-                     T* X, int64_t ldx, T* Y, int64_t ldy, int64_t nrhs, hipStream_t s) {
-  const int64_t rows = MODE == 0 ? n - r0 - jb : r0;  // rows still to solve
-  const int64_t tm = 1 + cdiv(rows, kB), tn = cdiv(nrhs, kB);
-  if (tm * tn > INT32_MAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((trsm_step_kernel<T, MODE>), dim3(unsigned(tm * tn)), dim3(256), 0, s, M, ldm,
-                     n, r0, jb, inv, X, ldx, Y, ldy, nrhs, int(tm));
-  return hipGetLastError();
-}
-
 // X <- M^-1 X in place: which 0: M = L L^T (L the lower triangle), 1: M = L
 // (lower), 2: M = U (upper). The diagonal blocks' inverses first (one
-// launch), then one launch per block and direction. Each pass reads one
-// buffer and writes the other: forward X -> Y, backward Y -> X for L L^T;
-// a single pass's result is copied back to X.
+// launch, unless the Cholesky left them), then the one-launch blocked solve
+// per direction (L forward, L^T or U backward).
 template <typename T>
-hipError_t tri_solve_typed(int which, int64_t n, int64_t r, const T* M, int64_t ldm, T* X,
-                           int64_t ldx, T* work, bool have_inv, hipStream_t s) {
+hipError_t tri_solve_typed(int dtype, int which, int64_t n, int64_t r, const T* M, int64_t ldm,
+                           T* X, int64_t ldx, T* work, bool have_inv, int32_t* status,
+                           hipStream_t s) {
   const int64_t np = cdiv(n, kB);
   T* inv = work;
-  T* Y = work + np * kB * kB;
-  const int64_t ldy = n;
+  void* cw = work + np * kB * kB;  // 256-byte aligned: np * 64^2 elements
   if (!have_inv) {
     if (which == 2)
       hipLaunchKernelGGL((trtri_blocks_kernel<T, true>), dim3(unsigned(np)), dim3(kB), 0, s, M,
@@ -882,24 +729,12 @@ hipError_t tri_solve_typed(int which, int64_t n, int64_t r, const T* M, int64_t 
                          ldm, n, inv);
   }
   hipError_t e = hipGetLastError();
-  auto jb_of = [&](int64_t p) { return int(std::min<int64_t>(kB, n - p * kB)); };
-  if (which != 2) {  // forward: L Y = X
-    for (int64_t p = 0; p < np && e == hipSuccess; ++p)
-      e = trsm_step<T, 0>(M, ldm, n, p * kB, jb_of(p), inv + p * kB * kB, X, ldx, Y, ldy, r, s);
-  }
-  if (which == 0) {  // backward: L^T X = Y
-    for (int64_t p = np - 1; p >= 0 && e == hipSuccess; --p)
-      e = trsm_step<T, 1>(M, ldm, n, p * kB, jb_of(p), inv + p * kB * kB, Y, ldy, X, ldx, r, s);
-    return e;
-  }
-  if (which == 2) {  // backward: U Y = X
-    for (int64_t p = np - 1; p >= 0 && e == hipSuccess; --p)
-      e = trsm_step<T, 2>(M, ldm, n, p * kB, jb_of(p), inv + p * kB * kB, X, ldx, Y, ldy, r, s);
-  }
-  if (e == hipSuccess)
-    e = hipMemcpy2DAsync(X, size_t(ldx) * sizeof(T), Y, size_t(ldy) * sizeof(T), size_t(n) * sizeof(T),
-                         size_t(r), hipMemcpyDeviceToDevice, s);
-  return e;
+  if (e != hipSuccess) return e;
+  const int64_t bs = int64_t(kB) * kB;
+  if (which == 0)
+    return tri_chain_launch(dtype, n, r, M, ldm, 0, inv, bs, 2, inv, bs, X, ldx, cw, status, s);
+  return tri_chain_launch(dtype, n, r, M, ldm, which == 1 ? 0 : 1, inv, bs, -1, nullptr, 0, X,
+                          ldx, cw, status, s);
 }
 
 }  // namespace
@@ -931,20 +766,20 @@ hipError_t chol_factor_launch(int dtype, int64_t n, void* A, int64_t lda, int32_
 
 size_t tri_solve_workspace_bytes(int dtype, int64_t n, int64_t nrhs) {
   const size_t esz = dtype == 0 ? 8 : 4;
-  return esz * size_t(cdiv(n, kB) * kB * kB + n * nrhs);
+  return esz * size_t(cdiv(n, kB) * kB * kB) + tri_chain_work_bytes(dtype, n, nrhs);
 }
 
 hipError_t tri_solve_launch(int dtype, int which, int64_t n, int64_t nrhs, const void* M,
                             int64_t ldm, void* X, int64_t ldx, void* work, bool have_inv,
-                            hipStream_t s) {
+                            int32_t* status, hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return hipSuccess;
   if (dtype == 0)
-    return tri_solve_typed<double>(which, n, nrhs, static_cast<const double*>(M), ldm,
+    return tri_solve_typed<double>(0, which, n, nrhs, static_cast<const double*>(M), ldm,
                                    static_cast<double*>(X), ldx, static_cast<double*>(work),
-                                   have_inv, s);
-  return tri_solve_typed<float>(which, n, nrhs, static_cast<const float*>(M), ldm,
+                                   have_inv, status, s);
+  return tri_solve_typed<float>(1, which, n, nrhs, static_cast<const float*>(M), ldm,
                                 static_cast<float*>(X), ldx, static_cast<float*>(work), have_inv,
-                                s);
+                                status, s);
 }
 
 hipError_t gtsv_launch(int dtype, int64_t n, int64_t nrhs, const void* S, int64_t lds, void* X,

@@ -132,6 +132,19 @@ struct Lookahead {
   hipEvent_t ready = nullptr, done = nullptr;
 };
 
+// Blocked triangular solves in one launch per direction and 1024 columns (the
+// one-launch MFMA solve of lu_solve_launch): X <- op(M)^-1 X in place, for
+// mode 0 the lower triangle of M (forward), 1 its upper triangle (backward),
+// 2 the transpose of its lower triangle (backward); the diagonal blocks'
+// inverses (64 x 64, column-major, identity-padded) at inv + block * stride.
+// mode2 (or -1) is a second direction applied after the first, per 1024
+// columns. work: tri_chain_work_bytes, 256-byte aligned. A wait that timed
+// out raises status[1].
+size_t tri_chain_work_bytes(int dtype, int64_t n, int64_t nrhs);
+hipError_t tri_chain_launch(int dtype, int64_t n, int64_t nrhs, const void* M, int64_t ldm,
+                            int mode1, const void* inv1, int64_t stride1, int mode2,
+                            const void* inv2, int64_t stride2, void* X, int64_t ldx, void* work,
+                            int32_t* status, hipStream_t s);
 // info (16 ints, 8-byte aligned, cleared here): [0] lower bandwidth, [1]
 // upper bandwidth, [2] 1 if S != S^T bitwise, [3] 1 if a diagonal entry is
 // not > 0, [5] 1 if a diagonal entry is zero, 64-bit words at [8] max |S_ij|
@@ -158,13 +171,15 @@ hipError_t rank_update_bt_launch(int dtype, int64_t m, int64_t n, int64_t K, con
                                  hipStream_t s);
 // X <- M^-1 X in place (n x nrhs, ldx), by blocks of 64 with the inverses
 // of the diagonal blocks: which 0: M = L L^T (L the lower triangle of M),
-// 1: M = L (lower), 2: M = U (upper); non-unit diagonals. work:
-// tri_solve_workspace_bytes (the inverses and an n x nrhs buffer); have_inv:
-// work already holds the inverses (left there by chol_factor_launch).
+// 1: M = L (lower), 2: M = U (upper); non-unit diagonals; n <= kLuMaxN.
+// work: tri_solve_workspace_bytes (the inverses, then the blocked solve's
+// tickets and exchange), 256-byte aligned; have_inv: work already holds the
+// inverses (left there by chol_factor_launch). A wait that timed out raises
+// status[1].
 size_t tri_solve_workspace_bytes(int dtype, int64_t n, int64_t nrhs);
 hipError_t tri_solve_launch(int dtype, int which, int64_t n, int64_t nrhs, const void* M,
                             int64_t ldm, void* X, int64_t ldx, void* work, bool have_inv,
-                            hipStream_t s);
+                            int32_t* status, hipStream_t s);
 // Tridiagonal part of S with partial pivoting; X (ldx) holds the right-hand
 // sides and receives the solution; work: 6 n elements of scratch; a zero
 // pivot sets info[5].
