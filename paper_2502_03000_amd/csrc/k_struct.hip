@@ -177,90 +177,127 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Lane `src`'s value of x for the whole wave (src a compile-time constant).
+__device__ __forceinline__ float lane_value(float x, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), src));
+}
+__device__ __forceinline__ double lane_value(double x, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), src);
+  return __hiloint2double(hi, lo);
+}
+
 // Cholesky of the diagonal block at (k0, k0) (jb <= 64 rows; rows and
-// columns past jb are the identity) and its inverse. The factorisation is
-// wave 0's, lane r holding row r of the block: per column j the pivot (lane
-// j's entry, read by all through LDS), its square root, the column of
-// multipliers published through LDS and read back 16 entries at a time
-// (every read of a group in flight together), then each lane's rank-1 update
-// of its row. Only entries on or below the diagonal feed later columns. L11
-// is written over the block's lower triangle; a pivot that is not > 0 sets
-// info[4] and nothing is stored. The inverse R = L11^-1 then takes all four
-// waves, by blocked substitution over 16-row blocks: D_b = L_bb^-1 by
-// substitution (wave 0, lane (b, c) building column c of D_b), M_bj = D_b
-// L_bj for j < b (MFMA), R_b = D_b E_b - sum_j M_bj R_j with E the identity
-// (MFMA, wave w taking columns 16w..16w+15); it is stored column-major.
+// columns past jb are the identity) and its inverse, the block in LDS.
+// Blocked over four 16-column panels: wave 0 factors the panel's rows (lane
+// r holding row r's 16 panel entries in registers; per column the pivot read
+// from its lane with v_readlane, the multipliers published through LDS and
+// read back together), then the four waves apply the panel's rank-16 update
+// to the lower 16 x 16 tiles right of it with MFMA. A pivot that is not > 0
+// sets info[4] and nothing is stored; otherwise L11 is written over the
+// block's lower triangle. The inverse R = L11^-1 follows by blocked
+// substitution over 16-row blocks: D_b = L_bb^-1 by substitution (wave 0,
+// lane (b, c) building column c of D_b), M_bj = D_b L_bj for j < b (MFMA),
+// R_b = D_b E_b - sum_j M_bj R_j with E the identity (MFMA, wave w taking
+// columns 16w..16w+15); it is stored column-major.
 template <typename T>
 __global__ __launch_bounds__(256) void potrf_block_kernel(T* __restrict__ A, int64_t lda,
                                                           int64_t k0, int jb, int32_t* info,
                                                           T* __restrict__ inv) {
   using Mf = Mfma<T>;
   using acc_t = typename Mf::acc_t;
-  __shared__ T piv[kB];             // column j before scaling: the pivot is piv[j]
-  __shared__ T colj[kB];            // column j of L
-  __shared__ T Lc[kB][kB + 16];     // Lc[l][i] = L11(i, l), identity padding
+  constexpr int LA = kB + 4;
+  __shared__ T As[kB][LA];          // As[r][c]: the block (lower part), then L11
+  __shared__ T colj[16];            // the current column's multipliers in the panel
   __shared__ T Ds[4][16][16 + 4];   // Ds[b][t][i] = D_b(i, t)
   __shared__ T Ms[6][16][16 + 4];   // Ms[p][t][i] = M_bj(i, t), p = b(b-1)/2 + j
   __shared__ T Rs[4][16][kB + 4];   // Rs[w][c][i] = R(i, 16w + c)
   __shared__ int s_bad;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int l16 = lane & 15, g = lane >> 4;
-  if (w == 0) {
-    const int r = lane;
-    const int rr = std::min(r, jb - 1);
-    if (r == 0) s_bad = 0;
-    T a[kB];
+  constexpr int PER = kB * kB / 256;
+  {
+    T v[PER];
 #pragma unroll
-    for (int c = 0; c < kB; ++c) a[c] = A[(k0 + rr) + (k0 + std::min(c, jb - 1)) * lda];
-#pragma unroll
-    for (int c = 0; c < kB; ++c) materialize(a[c]);
-#pragma unroll
-    for (int c = 0; c < kB; ++c)
-      a[c] = (r < jb && c < jb) ? (c <= r ? a[c] : T(0)) : (r == c ? T(1) : T(0));
-    bool bad = false;
-#pragma clang loop unroll(full)
-    for (int j = 0; j < kB; ++j) {
-      piv[r] = a[j];
-      wave_sync();
-      const T d = piv[j];
-      const bool ok = d > T(0);
-      bad = bad || !ok;
-      const T ljj = ok ? sqrt(d) : T(1);
-      const T l = r == j ? ljj : a[j] / ljj;
-      a[j] = l;
-      colj[r] = l;
-      wave_sync();
-#pragma unroll
-      for (int c0 = (j + 1) & ~15; c0 < kB; c0 += 16) {
-        T cj[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q)
-          if (c0 + q > j) cj[q] = colj[c0 + q];
-#pragma unroll
-        for (int q = 0; q < 16; ++q)
-          if (c0 + q > j) materialize(cj[q]);
-#pragma unroll
-        for (int q = 0; q < 16; ++q)
-          if (c0 + q > j) a[c0 + q] -= l * cj[q];
-      }
-      wave_sync();  // piv and colj are rewritten by the next column
+    for (int q = 0; q < PER; ++q) {  // element (i, c) from thread e % 64 (coalesced columns)
+      const int e = tid + 256 * q, i = e % kB, c = e / kB;
+      v[q] = A[(k0 + std::min(i, jb - 1)) + (k0 + std::min(c, jb - 1)) * lda];
     }
-    if (bad) {
-      if (r == 0) s_bad = 1;
-    } else {
-      if (r < jb) {
-        // descending, so that column min(c, r) finally holds a[min(c, r)]
 #pragma unroll
-        for (int c = kB - 1; c >= 0; --c) A[(k0 + r) + (k0 + std::min(c, r)) * lda] = a[c];
-      }
-#pragma unroll
-      for (int c = 0; c < kB; ++c) Lc[c][r] = c <= r ? a[c] : T(0);
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q, i = e % kB, c = e / kB;
+      As[i][c] = (i < jb && c < jb) ? (c <= i ? v[q] : T(0)) : T(i == c ? 1 : 0);
     }
   }
+  if (tid == 0) s_bad = 0;
   __syncthreads();
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    if (w == 0 && lane >= 16 * b) {  // the panel's rows
+      const int r = lane;
+      T a[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) a[c] = As[r][16 * b + c];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) materialize(a[c]);
+      bool bad = false;
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        const int j = 16 * b + jj;
+        const T d = lane_value(a[jj], j);  // the pivot, lane j's diagonal entry
+        const bool ok = d > T(0);
+        bad = bad || !ok;
+        const T ljj = ok ? sqrt(d) : T(1);
+        const T l = r == j ? ljj : a[jj] / ljj;
+        a[jj] = l;
+        if (jj < 15) {
+          if (r >= j && r < 16 * b + 16) colj[r - 16 * b] = l;
+          wave_sync();
+          T cj[16];
+#pragma unroll
+          for (int c = jj + 1; c < 16; ++c) cj[c] = colj[c];
+#pragma unroll
+          for (int c = jj + 1; c < 16; ++c) materialize(cj[c]);
+#pragma unroll
+          for (int c = jj + 1; c < 16; ++c) a[c] -= l * cj[c];
+          wave_sync();  // colj is rewritten by the next column
+        }
+      }
+      if (bad && r == 16 * b) s_bad = 1;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) As[r][16 * b + c] = 16 * b + c <= r ? a[c] : T(0);
+    }
+    __syncthreads();
+    // the lower tiles (I, J), b < J <= I, minus L_I,b L_J,b^T (operand A[i][k]
+    // = L(16I + i, 16b + k), operand B[k][j] = L(16J + j, 16b + k))
+    const int nt = (3 - b) * (4 - b) / 2;
+    for (int t = w; t < nt; t += 4) {
+      int I = b + 1, J = b + 1, u = t;
+      while (u > I - (b + 1)) {
+        u -= I - b;
+        ++I;
+      }
+      J = b + 1 + u;
+      acc_t acc;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) acc[rr] = As[16 * I + Mf::row(lane, rr)][16 * J + l16];
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+        acc = Mf::mma(-As[16 * I + l16][16 * b + 4 * s4 + g], As[16 * J + l16][16 * b + 4 * s4 + g],
+                      acc);
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) As[16 * I + Mf::row(lane, rr)][16 * J + l16] = acc[rr];
+    }
+    __syncthreads();
+  }
   if (s_bad) {
     if (tid == 0) info[4] = 1;
     return;
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = tid + 256 * q, i = e % kB, c = e / kB;
+    if (i < jb && c <= i) A[(k0 + i) + (k0 + c) * lda] = As[i][c];
   }
   if (w == 0) {  // D_b = L_bb^-1, lane (b, c) = (g, l16) builds column c
     T x[16];
@@ -268,10 +305,10 @@ __global__ __launch_bounds__(256) void potrf_block_kernel(T* __restrict__ A, int
     for (int i = 0; i < 16; ++i) x[i] = T(i == l16 ? 1 : 0);
 #pragma unroll
     for (int l = 0; l < 16; ++l) {
-      const T xl = x[l] / Lc[16 * g + l][16 * g + l];
+      const T xl = x[l] / As[16 * g + l][16 * g + l];
       x[l] = xl;
 #pragma unroll
-      for (int i = l + 1; i < 16; ++i) x[i] -= Lc[16 * g + l][16 * g + i] * xl;
+      for (int i = l + 1; i < 16; ++i) x[i] -= As[16 * g + i][16 * g + l] * xl;
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) Ds[g][l16][i] = x[i];
@@ -284,7 +321,7 @@ __global__ __launch_bounds__(256) void potrf_block_kernel(T* __restrict__ A, int
     acc_t mm = acc_t{};
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4)
-      mm = Mf::mma(Ds[b][4 * s4 + g][l16], Lc[16 * j + l16][16 * b + 4 * s4 + g], mm);
+      mm = Mf::mma(Ds[b][4 * s4 + g][l16], As[16 * b + 4 * s4 + g][16 * j + l16], mm);
 #pragma unroll
     for (int r = 0; r < 4; ++r) Ms[p][l16][Mf::row(lane, r)] = mm[r];
   }
@@ -311,7 +348,6 @@ __global__ __launch_bounds__(256) void potrf_block_kernel(T* __restrict__ A, int
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  constexpr int PER = kB * kB / 256;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int e = tid + 256 * q, i = e % kB, c = e / kB;
