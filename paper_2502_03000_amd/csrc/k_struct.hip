@@ -728,15 +728,17 @@ hipError_t chol_factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* i
     if (!lookahead || near == m) {
       e = syrk_lower_update_launch(dtype, m, kB, W, lda, A + k1 + k1 * lda, lda, s);
     } else {
-      // columns k1 .. k1 + 64 (all rows from k1) on s; the rest on side->s
-      e = rank_update_bt_launch(dtype, m, near, kB, W, lda, W, lda, A + k1 + k1 * lda, lda, s);
-      if (e == hipSuccess) e = hipEventRecord(side->ready, s);
+      // columns k1 .. k1 + 64 (all rows from k1) on s; the rest on side->s,
+      // which needs only L21, so it is released before the near part starts
+      e = hipEventRecord(side->ready, s);
       if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->ready, 0);
       if (e == hipSuccess)
         e = syrk_lower_update_launch(dtype, m - near, kB, W + near, lda,
                                      A + (k1 + near) + (k1 + near) * lda, lda, side->s);
       if (e == hipSuccess) e = hipEventRecord(side->done, side->s);
       pending = e == hipSuccess;
+      if (e == hipSuccess)
+        e = rank_update_bt_launch(dtype, m, near, kB, W, lda, W, lda, A + k1 + k1 * lda, lda, s);
     }
     if (e != hipSuccess) return e;
     if ((e = chol_panel<T>(A, lda, n, k1, info, inv, s)) != hipSuccess) return e;
