@@ -497,13 +497,13 @@ __global__ __launch_bounds__(256) void panel_step_kernel(T* __restrict__ A, int6
   }
 }
 
-// Inverses of the diagonal blocks (jb x jb, padded to kNB x kNB with the
-// identity), one thread per column, the block in LDS and the column in
-// registers: L11^-1 (unit lower, forward substitution) for the panel's
-// triangular solve and the forward solve, U11^-1 (backward substitution)
-// for the backward solve. block p of the grid takes rows/columns p * kNB.
-template <typename T, bool UPPER>
-__global__ __launch_bounds__(kNB) void inv_block_kernel(const T* __restrict__ A, int64_t lda,
+// Inverses of the upper diagonal blocks U11 (jb x jb, padded to kNB x kNB
+// with the identity) for the backward solve, one thread per column, the
+// block in LDS and the column in registers (backward substitution); block p
+// of the grid takes rows/columns p * kNB. (The unit lower blocks' inverses
+// come from the panel steps.)
+template <typename T>
+__global__ __launch_bounds__(kNB) void inv_upper_kernel(const T* __restrict__ A, int64_t lda,
                                                         int64_t n, int64_t first_block,
                                                         T* __restrict__ inv) {
   __shared__ T Ls[kNB][kNB + 1];
@@ -524,24 +524,14 @@ __global__ __launch_bounds__(kNB) void inv_block_kernel(const T* __restrict__ A,
   }
   __syncthreads();
   T x[kNB];
-  if (!UPPER) {
 #pragma unroll
-    for (int i = 0; i < kNB; ++i) {
-      T s = i == c ? T(1) : T(0);
+  for (int i = kNB - 1; i >= 0; --i) {
+    T s = i == c ? T(1) : T(0);
 #pragma unroll
-      for (int l = 0; l < i; ++l) s -= Ls[i][l] * x[l];
-      x[i] = s;
-    }
-  } else {
-#pragma unroll
-    for (int i = kNB - 1; i >= 0; --i) {
-      T s = i == c ? T(1) : T(0);
-#pragma unroll
-      for (int l = i + 1; l < kNB; ++l) s -= Ls[i][l] * x[l];
-      x[i] = s / Ls[i][i];
-    }
+    for (int l = i + 1; l < kNB; ++l) s -= Ls[i][l] * x[l];
+    x[i] = s / Ls[i][i];
   }
-  T* out = inv + size_t(p) * 2 * kNB * kNB + (UPPER ? kNB * kNB : 0);
+  T* out = inv + size_t(p) * 2 * kNB * kNB + kNB * kNB;
 #pragma unroll
   for (int i = 0; i < kNB; ++i) out[i + c * kNB] = x[i];
 }
@@ -1017,7 +1007,7 @@ hipError_t factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* rowid,
   }
   if (pending && (e = hipStreamWaitEvent(s, side->done, 0)) != hipSuccess) return e;
   // every U11^-1, for the solves (each L11^-1 came with its panel step)
-  hipLaunchKernelGGL((inv_block_kernel<T, true>), dim3(unsigned(np)), dim3(kNB), 0, s, A, lda, n,
+  hipLaunchKernelGGL((inv_upper_kernel<T>), dim3(unsigned(np)), dim3(kNB), 0, s, A, lda, n,
                      int64_t(0), static_cast<T*>(w.inv));
   return hipGetLastError();
 }
