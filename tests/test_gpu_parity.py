@@ -235,12 +235,13 @@ def test_solve_and_inverse_rewrite(ctx, n, nrhs):
     assert rel(run(ctx, hx.inv(es) @ eb, planner="naive"), ref) <= 1e-10
 
 
-@pytest.mark.parametrize("n,nrhs", [(513, 1), (513, 3), (1200, 2), (577, 70)])
+@pytest.mark.parametrize("n,nrhs", [(513, 1), (513, 3), (1200, 2), (577, 70), (130, 1030)])
 def test_blocked_solve_repeats(ctx, n, nrhs):
     """The one-launch blocked triangular solves exchange solved blocks as
-    tagged 64-bit words: odd panel counts (513: 9 panels, 1200: 19) and a
-    second right-hand-side chunk (70 columns), each solved four times with
-    the deferred status read after every run."""
+    tagged 64-bit words: odd panel counts (513: 9 panels, 1200: 19), several
+    16-column chunks (70 columns) and two groups of launches (1030 columns:
+    1024 + 6 on the same exchange), each solved four times with the deferred
+    status read after every run."""
     g = inputs.rng(n + 7 * nrhs)
     s = inputs.diag_dominant(g, n)
     b = inputs.normal(g, n, nrhs)

@@ -160,6 +160,22 @@ def test_refined_solve_reaches_fp64_accuracy(ctx, form, cond, n):
     assert rel(got, ref) <= 1e-12
 
 
+def test_refined_solve_many_columns(ctx):
+    """1030 right-hand sides: the low-precision triangular solves of every
+    refinement step run as two groups of launches (1024 + 6 columns)."""
+    n, nrhs = 130, 1030
+    s, u, sv, v = inputs.svd_matrix(67, n, n, 1e3)
+    b = inputs.normal(inputs.rng(68), n, nrhs)
+    ref = oracle.evaluate("solve(S,B)", {"S": s, "B": b})
+    p = ctx.plan(hx.solve(ctx.leaf(dev(s)), ctx.leaf(dev(b))), solve_precision="ir_fp32")
+    out = p.output()
+    p.execute(out, p.workspace())
+    rep = ctx.sync()
+    assert rep.status == hx.OK
+    assert 1 <= rep.ir_iterations <= 30
+    assert rel(host(out), ref) <= 1e-12
+
+
 @pytest.mark.parametrize("form", ["ir_fp32", "ir_bf16x3", "ir_bf16x6", "ir_fp16"])
 @pytest.mark.parametrize("n", [200, 513])
 def test_refined_solve_reports_divergence(ctx, form, n):

@@ -102,6 +102,25 @@ def test_solver_chosen_by_structure(ctx, dt, kind, n):
 
 
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("kind", ["lower", "upper", "spd"])
+def test_structured_solve_many_columns(ctx, dt, kind):
+    """1030 right-hand sides: the triangular solves run as two groups of
+    launches (1024 + 6 columns) on one exchange; L and L^T for the SPD
+    matrix, one direction for the triangular ones."""
+    n, nrhs = 130, 1030
+    g = inputs.rng(3100 + len(kind))
+    s = matrix(kind, g, n, dt)
+    b = inputs.normal(g, n, nrhs, dt)
+    p = ctx.plan(hx.solve(ctx.leaf(dev(s)), ctx.leaf(dev(b))))
+    out = p.output()
+    p.execute(out, p.workspace())
+    rep = ctx.sync()
+    assert rep.status == hx.OK
+    assert hx.SOLVERS[rep.solver] == EXPECT[kind]
+    check_solution(host(out), s, b, dt)
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
 @pytest.mark.parametrize("n,nrhs", [(300, 1), (257, 70), (1000, 5)])
 def test_solve_of_gram_product(ctx, dt, n, nrhs):
     """solve(A*A.t(), b): SYRK, then a Cholesky the planner chose (no
