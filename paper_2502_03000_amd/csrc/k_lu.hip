@@ -549,14 +549,17 @@ __global__ __launch_bounds__(kNB) void inv_upper_kernel(const T* __restrict__ A,
 // dependency the wave multiplies its 16 rows of T_ij (operand A, loaded
 // straight from the factor) by the solved chunk X_j (operand B, read from the
 // exchange), 16 MFMA steps of k = 4; the loads of the next dependency are
-// issued before the products of this one. The inverse is applied after one
-// pass of the accumulators through LDS. A solved block goes to the exchange
-// as 64-bit words whose high half is the tag (tag0 + block) and whose low
-// half is the FP32 value, or one 32-bit half of the FP64 value (two words
-// per value), stored in the order the readers' lanes load them (value 64 s +
-// l: row 4 s + l/16, column l%16), so a reader knows from each word alone
-// whether it holds this solve's value: no flag and no wait for store
-// completion. The exchange and the tickets start at zero (tags start at 1).
+// issued before the products of this one. The last dependency in solve
+// order is kept apart: before any wait each wave forms its rows of M_i =
+// T_ii^-1 T_i,last, after the others the inverse is applied (one pass of the
+// accumulators through LDS) giving Z_i, and once the last block arrives X_i
+// = Z_i - M_i X_last is one product on the critical path. A solved block
+// goes to the exchange as 64-bit words whose high half is the tag (tag0 +
+// block) and whose low half is the FP32 value, or one 32-bit half of the
+// FP64 value (two words per value), stored in the order the readers' lanes
+// load them (value 64 s + l: row 4 s + l/16, column l%16), so a reader knows
+// from each word alone whether it holds this solve's value: no flag and no
+// wait for store completion. The exchange and the tickets start at zero (tags start at 1).
 // Padding rows and columns are exact zeros. Every wait is bounded: a timeout
 // raises status[1] and the workgroup exits.
 // TRANS: the factor is the transpose of the stored lower triangle (L^T of a
@@ -573,6 +576,7 @@ __global__ __launch_bounds__(256) void chain_solve_kernel(
   constexpr int WPV = sizeof(T) / 4;  // exchange words per value
   constexpr size_t kTaskW = size_t(kChainWords) * WPV;
   __shared__ T sacc[kNB][kChainW + 1];
+  __shared__ T sM[4][16][kNB + 1];  // a wave's 16 rows of M_i = T_ii^-1 T_i,last
   __shared__ int s_t, s_bad;
   const int nb = int((n + kNB - 1) / kNB);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -627,17 +631,44 @@ __global__ __launch_bounds__(256) void chain_solve_kernel(
 #pragma unroll
         for (int h = 0; h < WPV; ++h) wd[s4][h] = ld_word(src + WPV * 64 * s4 + h);
     };
+    // -M_i rows 16w.. as operand A, M_i = T_ii^-1 T_i,last for the last
+    // dependency (solve order), formed before any wait: the last step is
+    // then X_i = Z_i - M_i X_last, one product on the critical path
+    T ma[16];
+    if (bt > 0) {
+      const int bj = UPPER ? nb - 1 - (bt - 1) : bt - 1;
+      const int64_t j0 = int64_t(bj) * kNB;
+      const int jbj = int(std::min<int64_t>(kNB, n - j0));
+#pragma unroll
+      for (int fc = 0; fc < 4; ++fc) {
+        acc_t mm = acc_t{};
+#pragma unroll
+        for (int s4 = 0; s4 < 16; ++s4) {
+          const int k = 4 * s4 + g, c = 16 * fc + l16;  // T_i,last(k, c)
+          const int64_t kr = r0 + std::min(k, ib - 1), cc = j0 + std::min(c, jbj - 1);
+          const T v = TRANS ? LU[cc + kr * lda] : LU[kr + cc * lda];
+          mm = Mf::mma(ia[s4], (k < ib && c < jbj) ? v : T(0), mm);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sM[w][Mf::row(lane, r)][16 * fc + l16] = mm[r];
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int s4 = 0; s4 < 16; ++s4) ma[s4] = -sM[w][l16][4 * s4 + g];
+    }
     bool ok = true;
     T ta[16];
     uint64_t wd[16][WPV];
-    if (bt > 0) {
+    const int nd = bt > 0 ? bt - 1 : 0;  // dependencies before the last
+    if (nd > 0) {
       load_t(0, ta);
       load_x(0, wd);
     }
-    for (int d = 0; d < bt; ++d) {
+    for (int d = 0; d < nd; ++d) {
       T tn[16];
       uint64_t wn[16][WPV];
-      if (d + 1 < bt) {
+      if (d + 1 < nd) {
         load_t(d + 1, tn);
         load_x(d + 1, wn);
       }
@@ -686,14 +717,52 @@ __global__ __launch_bounds__(256) void chain_solve_kernel(
     for (int r = 0; r < 4; ++r) sacc[16 * w + Mf::row(lane, r)][l16] = acc[r];
     __syncthreads();
     if (s_bad) break;
-    // X_i = T_ii^-1 acc: operand B[k][j] = acc(4 s + g, l16)
+    // Z_i = T_ii^-1 acc: operand B[k][j] = acc(4 s + g, l16)
     acc_t x = acc_t{};
 #pragma unroll
     for (int s4 = 0; s4 < 16; ++s4) x = Mf::mma(ia[s4], sacc[4 * s4 + g][l16], x);
+    if (bt > 0) {  // X_i = Z_i - M_i X_last
+      load_x(bt - 1, wd);
+      const int bj = UPPER ? nb - 1 - (bt - 1) : bt - 1;
+      const unsigned want = tag0 + unsigned(bj);
+      const uint64_t* src = xch + size_t(bj) * kTaskW + WPV * lane;
+      unsigned spins = 0;
+      for (;;) {
+        bool mine = true;
+#pragma unroll
+        for (int s4 = 0; s4 < 16; ++s4)
+#pragma unroll
+          for (int h = 0; h < WPV; ++h) mine &= unsigned(wd[s4][h] >> 32) == want;
+        if (__all(mine)) break;
+        if (__any(!keep_waiting(spins, status + 1))) {
+          ok = false;
+          break;
+        }
+#pragma unroll
+        for (int s4 = 0; s4 < 16; ++s4)
+#pragma unroll
+          for (int h = 0; h < WPV; ++h)
+            if (unsigned(wd[s4][h] >> 32) != want) wd[s4][h] = ld_word(src + WPV * 64 * s4 + h);
+      }
+      if (ok) {
+#pragma unroll
+        for (int s4 = 0; s4 < 16; ++s4) {
+          T xv;
+          if constexpr (WPV == 2)
+            xv = __longlong_as_double(
+                (long long)(((wd[s4][1] & 0xffffffffu) << 32) | (wd[s4][0] & 0xffffffffu)));
+          else
+            xv = __uint_as_float(unsigned(wd[s4][0]));
+          x = Mf::mma(ma[s4], xv, x);
+        }
+      } else {
+        s_bad = 1;  // read after the barrier at the end of the task
+      }
+    }
     uint64_t* dst = xw + size_t(ch) * size_t(nb) * kTaskW + size_t(bi) * kTaskW;
     const uint64_t tag = uint64_t(tag0 + unsigned(bi)) << 32;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < 4 && ok; ++r) {
       const int row = 16 * w + Mf::row(lane, r);  // value 64 s + l holds row 4 s + l/16
       uint64_t* p = dst + size_t(row * kChainW + l16) * WPV;
       if constexpr (WPV == 2) {
@@ -707,9 +776,10 @@ __global__ __launch_bounds__(256) void chain_solve_kernel(
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * w + Mf::row(lane, r);
-      if (row < ib && l16 < rc) X[(r0 + row) + (c0 + l16) * ldx] = x[r];
+      if (ok && row < ib && l16 < rc) X[(r0 + row) + (c0 + l16) * ldx] = x[r];
     }
     __syncthreads();  // sacc, s_t and s_bad are reused
+    if (s_bad) break;
   }
 }
 
