@@ -1565,6 +1565,9 @@ class Planner {
     w.scratch = work(int64_t(k::norm_scratch_elems(n)) * 8);
     w.norms = work(4 * 8);
     w.res_cfg = k::gemm_choose(HEXLA_F64, 0, 0, n, r, n);
+    // the residual's product has an n x nrhs result: about four workgroups
+    // per CU of K splits instead of one (8192^2 x 64: 287 -> 200 us)
+    w.res_cfg.split = k::gemm_split_for(HEXLA_F64, w.res_cfg.tile, 0, n, r, n, 1024, 8);
     const size_t pb = k::gemm_partial_bytes(HEXLA_F64, w.res_cfg, n, r);
     if (pb) w.partial = work(int64_t(pb));
     w.update_precision = o_.solve_precision == HEXLA_SOLVE_IR_FP16     ? k::GEMM_F16
