@@ -494,6 +494,8 @@ __global__ __launch_bounds__(256) void tridiag_extract_kernel(int64_t n, const T
 // same way. The next tile's loads are issued before the current tile is
 // processed, so their latency hides under the elimination.
 constexpr int kGR = 64;
+// Rows per group of the eliminations: their LDS operands are read together.
+constexpr int kGU = 8;
 
 template <typename T>
 struct TileRegs {
@@ -510,19 +512,29 @@ __device__ __forceinline__ void tile_load(TileRegs<T>& R, const T* X, int64_t ld
 #pragma unroll
   for (int c = 0; c < 64; ++c) R.v[c] = X[r + std::min<int64_t>(col0 + c, nrhs - 1) * ldx];
 }
-// INV0: the first coefficient goes to LDS as its reciprocal.
-template <bool INV0 = false, typename T>
-__device__ __forceinline__ void tile_to_lds(TileRegs<T>& R, T (*xs)[65], T (*cs)[kGR]) {
-#pragma unroll
-  for (int c = 0; c < 64; ++c) materialize(R.v[c]);
+__device__ __forceinline__ int frexp_exp(double x) { return __builtin_amdgcn_frexp_exp(x); }
+__device__ __forceinline__ int frexp_exp(float x) { return __builtin_amdgcn_frexp_expf(x); }
+__device__ __forceinline__ double ldexp2(double x, int e) { return __builtin_amdgcn_ldexp(x, e); }
+__device__ __forceinline__ float ldexp2(float x, int e) { return __builtin_amdgcn_ldexpf(x, e); }
+
+// The forward elimination's staging of rows [t kGR, t kGR + kGR): each row
+// (its entries l = c[0] left of the diagonal, c[1], c[2], and its right-hand
+// sides) is scaled by 2^-k, k the exponent of its largest entry, so that
+// products of two rows' entries stay in range; l itself is kept for the
+// pivot comparison. cs: [l, l 2^-k, c[1] 2^-k, c[2] 2^-k, k][row in tile].
+template <typename T>
+__device__ __forceinline__ void tile_to_lds_rows(TileRegs<T>& R, T (*xs)[65], T (*cs)[kGR]) {
 #pragma unroll
   for (int q = 0; q < 3; ++q) materialize(R.c[q]);
+  const int k = frexp_exp(fmax(fabs(R.c[0]), fmax(fabs(R.c[1]), fabs(R.c[2]))));
 #pragma unroll
-  for (int c = 0; c < 64; ++c) xs[threadIdx.x][c] = R.v[c];
-  cs[0][threadIdx.x] = INV0 ? T(1) / R.c[0] : R.c[0];
-  cs[1][threadIdx.x] = R.c[1];
-  cs[2][threadIdx.x] = R.c[2];
+  for (int c = 0; c < 64; ++c) xs[threadIdx.x][c] = ldexp2(R.v[c], -k);
+  cs[0][threadIdx.x] = R.c[0];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) cs[1 + q][threadIdx.x] = ldexp2(R.c[q], -k);
+  cs[4][threadIdx.x] = T(k);
 }
+
 // Writes rows [t kGR, t kGR + kGR) of the tile in LDS back (rows < n and
 // columns < nrhs only).
 template <typename T>
@@ -535,12 +547,14 @@ __device__ __forceinline__ void tile_store(const T (*xs)[65], T* X, int64_t ldx,
 }
 
 // Forward elimination with partial pivoting of the tridiagonal matrix (sub,
-// dia, sup) applied to the right-hand sides in X (lane c: column col0 + c).
-// The current row i is (d, u, w) at columns i, i+1, i+2; row i+1 is
-// (sub[i], dia[i+1], sup[i+1]); the one of the two with the larger entry in
-// column i becomes the pivot row (final row i of U: d', u', w'), the other
-// is eliminated into the new current row. Workgroup 0 writes the final rows
-// to coef[3 i ..]; a zero pivot sets info[5].
+// dia, sup; sup[n - 1] = 0) applied to the right-hand sides in X (lane c:
+// column col0 + c). The current row i is (d, u, 0) at columns i, i+1, i+2;
+// row i+1 is (sub[i], dia[i+1], sup[i+1]); the one of the two with the
+// larger entry in column i becomes the pivot row (final row i of U: d', u',
+// w', up to a common scale with its right-hand sides), the other is
+// eliminated into the new current row. Lane j keeps final row i0 + j of
+// the tile starting at row i0, and workgroup 0 writes the tile's rows to
+// coef[3 i ..] once it is done; a zero pivot sets info[5].
 template <typename T>
 __global__ __launch_bounds__(64) void gtsv_forward_kernel(int64_t n, const T* __restrict__ sub,
                                                           const T* __restrict__ dia,
@@ -548,35 +562,36 @@ __global__ __launch_bounds__(64) void gtsv_forward_kernel(int64_t n, const T* __
                                                           int64_t ldx, int64_t nrhs, T* coef,
                                                           int32_t* info) {
   __shared__ T xs[2][kGR][65];  // [buffer][row in tile][column]
-  __shared__ T cs[2][3][kGR];   // [buffer][sub of the row before, dia, sup][row in tile]
+  __shared__ T cs[2][5][kGR];   // [buffer][as staged][row in tile]
   const int lane = threadIdx.x;
   const int64_t col0 = int64_t(blockIdx.x) * 64;
-  const bool writer = blockIdx.x == 0 && lane == 0;
   const int64_t nt = (n + kGR - 1) / kGR;
   // row g of the matrix: (sub[g - 1], dia[g], sup[g]), clamped past n
   auto coeffs = [&](TileRegs<T>& R, int64_t t) {
     const int64_t g = std::min<int64_t>(t * kGR + lane, n - 1);
-    R.c[0] = sub[std::max<int64_t>(g - 1, 0)];
+    R.c[0] = g > 0 ? sub[g - 1] : T(0);
     R.c[1] = dia[g];
     R.c[2] = sup[g];
   };
   TileRegs<T> R;
   tile_load(R, X, ldx, n, 0, col0, nrhs);
   coeffs(R, 0);
-  tile_to_lds(R, xs[0], cs[0]);
+  tile_to_lds_rows(R, xs[0], cs[0]);
   if (nt > 1) {
     tile_load(R, X, ldx, n, 1, col0, nrhs);
     coeffs(R, 1);
   }
   __syncthreads();
-  T d = dia[0], u = n > 1 ? sup[0] : T(0), w = T(0);
-  T b = xs[0][0][lane];
+  // row 0 as it is (sc = 1; its staged copy could need sc = 2^-k0 out of range)
+  T d = dia[0], u = sup[0], sc = T(1);
+  T b = X[std::min<int64_t>(col0 + lane, nrhs - 1) * ldx];
+  T rd = T(0), ru = T(0), rw = T(0);  // final row i0 + lane of the current tile
   bool singular = false;
   for (int64_t t = 0; t < nt; ++t) {
     // the next tile into LDS (its buffer held tile t - 1, already written
     // back), the one after it into registers
     if (t + 1 < nt) {
-      tile_to_lds(R, xs[(t + 1) & 1], cs[(t + 1) & 1]);
+      tile_to_lds_rows(R, xs[(t + 1) & 1], cs[(t + 1) & 1]);
       if (t + 2 < nt) {
         tile_load(R, X, ldx, n, t + 2, col0, nrhs);
         coeffs(R, t + 2);
@@ -584,66 +599,108 @@ __global__ __launch_bounds__(64) void gtsv_forward_kernel(int64_t n, const T* __
     }
     __syncthreads();
     const int64_t i0 = t * kGR;
-    const int64_t iend = std::min<int64_t>(i0 + kGR, n - 1);  // steps i in [i0, iend)
-    for (int64_t i = i0; i < iend; ++i) {
-      const int64_t r1 = i + 1;
-      const int bq = int(r1 / kGR) & 1, rq = int(r1 % kGR);
-      const T l1 = cs[bq][0][rq], d1 = cs[bq][1][rq], u1 = cs[bq][2][rq];  // same for every lane
-      const T b1 = xs[bq][rq][lane];
-      T pd, pu, pw, pb, nd, nu, nb;
-      if (fabs(d) >= fabs(l1)) {  // keep row i as the pivot row
-        const T m = d != T(0) ? l1 / d : T(0);
-        pd = d, pu = u, pw = w, pb = b;
-        nd = d1 - m * u;
-        nu = u1 - m * w;
-        nb = b1 - m * b;
-      } else {  // row i + 1 becomes the pivot row
-        const T m = d / l1;
-        pd = l1, pu = d1, pw = u1, pb = b1;
-        nd = u - m * d1;
-        nu = w - m * u1;
-        nb = b - m * b1;
-      }
-      if (pd == T(0)) singular = true;
-      if (writer) {
-        coef[3 * i] = pd;
-        coef[3 * i + 1] = pu;
-        coef[3 * i + 2] = pw;
-      }
-      xs[t & 1][i - i0][lane] = pb;
-      // the new current row i + 1: (nd, nu) at columns i + 1, i + 2, no fill
-      d = nd;
-      u = r1 + 1 < n ? nu : T(0);
-      w = T(0);
-      b = nb;
+    const int cur = int(t & 1);
+    const int steps = int(std::min<int64_t>(i0 + kGR, n - 1) - i0);  // rows i0 .. i0 + steps - 1
+    // One step on rows i = i0 + q and i + 1. The current row i (d, u, 0, b)
+    // is held as sc times its value in the elimination; row i + 1 is (l1,
+    // d1, u1, b1) as staged, 2^-k times its value, and lo its entry l1 as it
+    // is. The row with the larger entry in column i is the pivot row, final
+    // row i (either scaling of it serves the back substitution). Up to its
+    // scale, the new current row is d (row i + 1) - l1 (row i) whichever row
+    // pivots; its scale is 2^-k times the pivot's magnitude piv = max(|d|,
+    // sc |lo|), and the power of two of piv is taken out (sc back in [1/2,
+    // 1)). The choice depends on the matrix alone, the same on every lane,
+    // and only selects the final row: no division, and one multiply-add, a
+    // maximum and a power-of-two rescaling on the chain of rows.
+    auto step = [&](int q, T lo, T l1, T d1, T u1, int k, T b1) {
+      const T sl = sc * fabs(lo);
+      const bool keep = fabs(d) >= sl;
+      const T pd = keep ? d : l1, pu = keep ? u : d1, pw = keep ? T(0) : u1;
+      singular = singular || pd == T(0);
+      const bool mine = lane == q;
+      rd = mine ? pd : rd;
+      ru = mine ? pu : ru;
+      rw = mine ? pw : rw;
+      xs[cur][q][lane] = keep ? b : b1;
+      const T piv = fmax(fabs(d), sl);
+      const int ep = frexp_exp(piv), e = ep - k;
+      const T nd = d * d1 - l1 * u, nu = d * u1, nb = d * b1 - l1 * b;
+      sc = ldexp2(piv, -ep);
+      d = ldexp2(nd, -e);
+      u = ldexp2(nu, -e);
+      b = ldexp2(nb, -e);
+    };
+    // row r of this tile or (r = kGR) the first row of the next one
+    auto next_row = [&](int r, T& lo, T& l1, T& d1, T& u1, int& k, T& b1) {
+      const int bq = r < kGR ? cur : cur ^ 1, rr = r & (kGR - 1);
+      lo = cs[bq][0][rr];
+      l1 = cs[bq][1][rr];
+      d1 = cs[bq][2][rr];
+      u1 = cs[bq][3][rr];
+      k = int(cs[bq][4][rr]);
+      b1 = xs[bq][rr][lane];
+    };
+    // kGU steps at a time: their operands are read from LDS before the
+    // first of them, off the chain of rows
+    int q = 0;
+    for (; q + kGU <= steps; q += kGU) {
+      T lo[kGU], l1[kGU], d1[kGU], u1[kGU], b1[kGU];
+      int k[kGU];
+#pragma unroll
+      for (int j = 0; j < kGU; ++j) next_row(q + 1 + j, lo[j], l1[j], d1[j], u1[j], k[j], b1[j]);
+#pragma unroll
+      for (int j = 0; j < kGU; ++j) step(q + j, lo[j], l1[j], d1[j], u1[j], k[j], b1[j]);
+    }
+    for (; q < steps; ++q) {
+      T lo, l1, d1, u1, b1;
+      int k;
+      next_row(q + 1, lo, l1, d1, u1, k, b1);
+      step(q, lo, l1, d1, u1, k, b1);
     }
     if (t == nt - 1) {  // the last row
-      if (d == T(0)) singular = true;
-      if (writer) {
-        coef[3 * (n - 1)] = d;
-        coef[3 * (n - 1) + 1] = T(0);
-        coef[3 * (n - 1) + 2] = T(0);
-      }
-      xs[t & 1][(n - 1) - i0][lane] = b;
+      singular = singular || d == T(0);
+      const bool mine = lane == steps;
+      rd = mine ? d : rd;
+      ru = mine ? T(0) : ru;
+      rw = mine ? T(0) : rw;
+      xs[cur][steps][lane] = b;
+    }
+    if (blockIdx.x == 0 && i0 + lane < n) {
+      coef[3 * (i0 + lane)] = rd;
+      coef[3 * (i0 + lane) + 1] = ru;
+      coef[3 * (i0 + lane) + 2] = rw;
     }
     __syncthreads();
-    tile_store(xs[t & 1], X, ldx, n, t, col0, nrhs);
+    tile_store(xs[cur], X, ldx, n, t, col0, nrhs);
   }
   if (singular && lane == 0 && blockIdx.x == 0) info[5] = 1;
 }
 
-// Back substitution with the rows coef: x_i = (b_i - u'_i x_{i+1} -
-// w'_i x_{i+2}) / d'_i, tiles taken from the last one down.
+// Back substitution with the rows coef: x_i = b_i / d'_i - (u'_i / d'_i)
+// x_{i+1} - (w'_i / d'_i) x_{i+2}, tiles taken from the last one down. The
+// three scalings are made for a whole tile as it goes to LDS, off the chain of
+// rows, which is then one multiply-add per row: x_i = t_i - (u'_i / d'_i)
+// x_{i+1}, with t_i = b_i / d'_i - (w'_i / d'_i) x_{i+2} formed a row earlier.
+template <typename T>
+__device__ __forceinline__ void tile_to_lds_scaled(TileRegs<T>& R, T (*xs)[65], T (*cs)[kGR]) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q) materialize(R.c[q]);
+  const T rd = T(1) / R.c[0];
+#pragma unroll
+  for (int c = 0; c < 64; ++c) xs[threadIdx.x][c] = R.v[c] * rd;
+  cs[0][threadIdx.x] = R.c[1] * rd;
+  cs[1][threadIdx.x] = R.c[2] * rd;
+}
+
 template <typename T>
 __global__ __launch_bounds__(64) void gtsv_backward_kernel(int64_t n, const T* __restrict__ coef,
                                                            T* X, int64_t ldx, int64_t nrhs) {
   __shared__ T xs[2][kGR][65];
-  __shared__ T cs[2][3][kGR];  // [buffer][1 / d', u', w'][row in tile]
+  __shared__ T cs[2][2][kGR];  // [buffer][u' / d', w' / d'][row in tile]
   const int lane = threadIdx.x;
   const int64_t col0 = int64_t(blockIdx.x) * 64;
   const int64_t nt = (n + kGR - 1) / kGR;
-  // row g: d'_g (its reciprocal is taken for 64 rows at once when the tile
-  // goes to LDS, off the chain of rows), u'_g, w'_g
+  // row g: d'_g, u'_g, w'_g
   auto coeffs = [&](TileRegs<T>& R, int64_t t) {
     const int64_t g = std::min<int64_t>(t * kGR + lane, n - 1);
 #pragma unroll
@@ -652,7 +709,7 @@ __global__ __launch_bounds__(64) void gtsv_backward_kernel(int64_t n, const T* _
   TileRegs<T> R;
   tile_load(R, X, ldx, n, nt - 1, col0, nrhs);
   coeffs(R, nt - 1);
-  tile_to_lds<true>(R, xs[(nt - 1) & 1], cs[(nt - 1) & 1]);
+  tile_to_lds_scaled(R, xs[(nt - 1) & 1], cs[(nt - 1) & 1]);
   if (nt > 1) {
     tile_load(R, X, ldx, n, nt - 2, col0, nrhs);
     coeffs(R, nt - 2);
@@ -661,7 +718,7 @@ __global__ __launch_bounds__(64) void gtsv_backward_kernel(int64_t n, const T* _
   T x1 = T(0), x2 = T(0);
   for (int64_t t = nt - 1; t >= 0; --t) {
     if (t >= 1) {
-      tile_to_lds<true>(R, xs[(t - 1) & 1], cs[(t - 1) & 1]);
+      tile_to_lds_scaled(R, xs[(t - 1) & 1], cs[(t - 1) & 1]);
       if (t >= 2) {
         tile_load(R, X, ldx, n, t - 2, col0, nrhs);
         coeffs(R, t - 2);
@@ -669,17 +726,28 @@ __global__ __launch_bounds__(64) void gtsv_backward_kernel(int64_t n, const T* _
     }
     __syncthreads();
     const int64_t i0 = t * kGR;
-    const int64_t iend = std::min<int64_t>(i0 + kGR, n);
-    for (int64_t i = iend - 1; i >= i0; --i) {
-      const int q = int(i - i0);
-      const T rd = cs[t & 1][0][q], cu = cs[t & 1][1][q], cw = cs[t & 1][2][q];  // uniform
-      const T xi = (xs[t & 1][q][lane] - cu * x1 - cw * x2) * rd;
-      xs[t & 1][q][lane] = xi;
+    const int cur = int(t & 1);
+    auto row = [&](int q, T b, T cu, T cw) {
+      const T xi = (b - cw * x2) - cu * x1;
+      xs[cur][q][lane] = xi;
       x2 = x1;
       x1 = xi;
+    };
+    int q = int(std::min<int64_t>(i0 + kGR, n) - i0) - 1;  // rows i0 + q down to i0
+    for (; q >= kGU - 1; q -= kGU) {
+      T b[kGU], cu[kGU], cw[kGU];
+#pragma unroll
+      for (int k = 0; k < kGU; ++k) {
+        b[k] = xs[cur][q - k][lane];
+        cu[k] = cs[cur][0][q - k];
+        cw[k] = cs[cur][1][q - k];
+      }
+#pragma unroll
+      for (int k = 0; k < kGU; ++k) row(q - k, b[k], cu[k], cw[k]);
     }
+    for (; q >= 0; --q) row(q, xs[cur][q][lane], cs[cur][0][q], cs[cur][1][q]);
     __syncthreads();
-    tile_store(xs[t & 1], X, ldx, n, t, col0, nrhs);
+    tile_store(xs[cur], X, ldx, n, t, col0, nrhs);
   }
 }
 

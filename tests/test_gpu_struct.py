@@ -164,6 +164,32 @@ def test_singular_structured_systems(ctx):
     assert hx.SOLVERS[rep.solver] == "tridiagonal" and rep.status == hx.E_SINGULAR
 
 
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("nrhs", [3, 70])
+def test_tridiagonal_rows_of_every_scale(ctx, dt, nrhs):
+    """Rows scaled by powers of two across most of the storage type's range
+    (2^+-100 for FP32, 2^+-500 for FP64): products of two rows' entries
+    would leave that range, so the elimination must keep them apart. Row
+    scaling leaves the solution alone, so the bound takes the condition
+    number of the unscaled matrix."""
+    n = 300
+    g = inputs.rng(3300 + nrhs)
+    s0 = matrix("tridiagonal", g, n, np.float64)
+    b0 = inputs.normal(g, n, nrhs)
+    span = 100 if dt == np.float32 else 500
+    rs = 2.0 ** np.round(g.uniform(-span, span, n))
+    s = np.asfortranarray((rs[:, None] * s0).astype(dt))
+    b = (rs[:, None] * b0).astype(dt)
+    assert np.all(np.isfinite(s)) and np.count_nonzero(s) == np.count_nonzero(s0)
+    p = ctx.plan(hx.solve(ctx.leaf(dev(s)), ctx.leaf(dev(b))))
+    out = p.output()
+    p.execute(out, p.workspace())
+    rep = ctx.sync()
+    assert rep.status == hx.OK and hx.SOLVERS[rep.solver] == "tridiagonal"
+    ref = oracle.evaluate("solve(S,B)", {"S": s0, "B": b0})
+    assert rel(host(out), ref) <= max(TOL[dt], 10.0 * np.linalg.cond(s0) * np.sqrt(n) * U[dt])
+
+
 def test_structured_solve_capture_rules(ctx):
     g = inputs.rng(3200)
     s, b = inputs.diag_dominant(g, 100), inputs.normal(g, 100, 2)
