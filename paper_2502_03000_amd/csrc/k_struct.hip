@@ -487,14 +487,19 @@ __global__ __launch_bounds__(256) void tridiag_extract_kernel(int64_t n, const T
   sup[i] = i + 1 < n ? S[i + (i + 1) * lds] : T(0);
 }
 
-// The right-hand sides pass through LDS in tiles of kGR rows x 64 columns:
-// a tile is loaded with one lane per row (each load instruction reads 64
-// consecutive rows of one column, one coalesced run), stored to LDS, and
-// read back with one lane per column by the elimination; results leave the
-// same way. The next tile's loads are issued before the current tile is
-// processed, so their latency hides under the elimination.
+// The right-hand sides pass through LDS in tiles of kGR rows x 64 columns.
+// A workgroup has two waves: wave 0 runs the sequential sweep over the rows
+// of one tile while wave 1 writes the tile before it back to X and stages the
+// one after it, so that the global traffic and the staging are off the
+// chain of rows. Wave 1 loads a tile with one lane per row (each load
+// instruction reads 64 consecutive rows of one column, one coalesced run)
+// into registers a step before it stores it to LDS, so that the loads are in
+// flight across a step; the sweep reads it with one lane per column. Four
+// buffers: the tile being swept, the next one (whose first row the forward
+// sweep reads), the one being staged and the one being written back.
 constexpr int kGR = 64;
-// Rows per group of the eliminations: their LDS operands are read together.
+constexpr int kGBuf = 4;
+// Rows per group of the sweeps: their LDS operands are read together.
 constexpr int kGU = 8;
 
 template <typename T>
@@ -504,11 +509,11 @@ struct TileRegs {
 };
 
 // Loads rows [t kGR, t kGR + kGR) of the 64 columns col0 .. (clamped past n
-// and nrhs; those values are never used).
+// and nrhs; those values are never used); lane = row in the tile.
 template <typename T>
 __device__ __forceinline__ void tile_load(TileRegs<T>& R, const T* X, int64_t ldx, int64_t n,
-                                          int64_t t, int64_t col0, int64_t nrhs) {
-  const int64_t r = std::min<int64_t>(t * kGR + threadIdx.x, n - 1);
+                                          int64_t t, int64_t col0, int64_t nrhs, int lane) {
+  const int64_t r = std::min<int64_t>(t * kGR + lane, n - 1);
 #pragma unroll
   for (int c = 0; c < 64; ++c) R.v[c] = X[r + std::min<int64_t>(col0 + c, nrhs - 1) * ldx];
 }
@@ -517,238 +522,242 @@ __device__ __forceinline__ int frexp_exp(float x) { return __builtin_amdgcn_frex
 __device__ __forceinline__ double ldexp2(double x, int e) { return __builtin_amdgcn_ldexp(x, e); }
 __device__ __forceinline__ float ldexp2(float x, int e) { return __builtin_amdgcn_ldexpf(x, e); }
 
-// The forward elimination's staging of rows [t kGR, t kGR + kGR): each row
-// (its entries l = c[0] left of the diagonal, c[1], c[2], and its right-hand
-// sides) is scaled by 2^-k, k the exponent of its largest entry, so that
-// products of two rows' entries stay in range; l itself is kept for the
-// pivot comparison. cs: [l, l 2^-k, c[1] 2^-k, c[2] 2^-k, k][row in tile].
-template <typename T>
-__device__ __forceinline__ void tile_to_lds_rows(TileRegs<T>& R, T (*xs)[65], T (*cs)[kGR]) {
-#pragma unroll
-  for (int q = 0; q < 3; ++q) materialize(R.c[q]);
-  const int k = frexp_exp(fmax(fabs(R.c[0]), fmax(fabs(R.c[1]), fabs(R.c[2]))));
-#pragma unroll
-  for (int c = 0; c < 64; ++c) xs[threadIdx.x][c] = ldexp2(R.v[c], -k);
-  cs[0][threadIdx.x] = R.c[0];
-#pragma unroll
-  for (int q = 0; q < 3; ++q) cs[1 + q][threadIdx.x] = ldexp2(R.c[q], -k);
-  cs[4][threadIdx.x] = T(k);
-}
-
 // Writes rows [t kGR, t kGR + kGR) of the tile in LDS back (rows < n and
-// columns < nrhs only).
+// columns < nrhs only); lane = row in the tile.
 template <typename T>
 __device__ __forceinline__ void tile_store(const T (*xs)[65], T* X, int64_t ldx, int64_t n,
-                                           int64_t t, int64_t col0, int64_t nrhs) {
-  const int64_t r = t * kGR + threadIdx.x;
+                                           int64_t t, int64_t col0, int64_t nrhs, int lane) {
+  const int64_t r = t * kGR + lane;
   if (r >= n) return;
   const int cols = int(std::min<int64_t>(64, nrhs - col0));
-  for (int c = 0; c < cols; ++c) X[r + (col0 + c) * ldx] = xs[threadIdx.x][c];
+  // 16 columns at a time: their LDS reads are issued together
+  for (int c0 = 0; c0 < cols; c0 += 16) {
+    T v[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) v[c] = xs[lane][c0 + c];
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (c0 + c < cols) X[r + (col0 + c0 + c) * ldx] = v[c];
+  }
 }
 
 // Forward elimination with partial pivoting of the tridiagonal matrix (sub,
-// dia, sup; sup[n - 1] = 0) applied to the right-hand sides in X (lane c:
-// column col0 + c). The current row i is (d, u, 0) at columns i, i+1, i+2;
-// row i+1 is (sub[i], dia[i+1], sup[i+1]); the one of the two with the
-// larger entry in column i becomes the pivot row (final row i of U: d', u',
-// w', up to a common scale with its right-hand sides), the other is
-// eliminated into the new current row. Lane j keeps final row i0 + j of
-// the tile starting at row i0, and workgroup 0 writes the tile's rows to
-// coef[3 i ..] once it is done; a zero pivot sets info[5].
+// dia, sup; sup[n - 1] = 0) applied to the right-hand sides in X (lane c of
+// wave 0: column col0 + c). The current row i is (d, u, 0) at columns i,
+// i+1, i+2; row i+1 is (sub[i], dia[i+1], sup[i+1]); the one of the two with
+// the larger entry in column i becomes the pivot row (final row i of U: d',
+// u', w', up to a common scale with its right-hand sides), the other is
+// eliminated into the new current row. At the end of a tile workgroup 0
+// writes its final rows to coef[3 i ..], lane j row i0 + j of the tile that
+// starts at row i0; a zero pivot sets info[5].
+//
+// Staging of a tile (wave 1): each row (its entries l = sub[g - 1] left of
+// the diagonal, dia[g], sup[g], and its right-hand sides) is scaled by 2^-k,
+// k the exponent of its largest entry, so that products of two rows'
+// entries stay in range; l itself is kept for the pivot comparison.
+// cs: [l, l 2^-k, dia 2^-k, sup 2^-k][row in tile], ks: k.
 template <typename T>
-__global__ __launch_bounds__(64) void gtsv_forward_kernel(int64_t n, const T* __restrict__ sub,
-                                                          const T* __restrict__ dia,
-                                                          const T* __restrict__ sup, T* X,
-                                                          int64_t ldx, int64_t nrhs, T* coef,
-                                                          int32_t* info) {
-  __shared__ T xs[2][kGR][65];  // [buffer][row in tile][column]
-  __shared__ T cs[2][5][kGR];   // [buffer][as staged][row in tile]
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(128) void gtsv_forward_kernel(int64_t n, const T* __restrict__ sub,
+                                                           const T* __restrict__ dia,
+                                                           const T* __restrict__ sup, T* X,
+                                                           int64_t ldx, int64_t nrhs, T* coef,
+                                                           int32_t* info) {
+  __shared__ T xs[kGBuf][kGR][65];  // [buffer][row in tile][column]
+  __shared__ T cs[kGBuf][4][kGR];   // [buffer][as staged][row in tile]
+  __shared__ int ks[kGBuf][kGR];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int64_t col0 = int64_t(blockIdx.x) * 64;
   const int64_t nt = (n + kGR - 1) / kGR;
-  // row g of the matrix: (sub[g - 1], dia[g], sup[g]), clamped past n
-  auto coeffs = [&](TileRegs<T>& R, int64_t t) {
+  // wave 1: fetch(t) loads tile t into R, put(t) stages R into LDS
+  TileRegs<T> R;
+  auto fetch = [&](int64_t t) {
+    tile_load(R, X, ldx, n, t, col0, nrhs, lane);
     const int64_t g = std::min<int64_t>(t * kGR + lane, n - 1);
     R.c[0] = g > 0 ? sub[g - 1] : T(0);
     R.c[1] = dia[g];
     R.c[2] = sup[g];
   };
-  TileRegs<T> R;
-  tile_load(R, X, ldx, n, 0, col0, nrhs);
-  coeffs(R, 0);
-  tile_to_lds_rows(R, xs[0], cs[0]);
-  if (nt > 1) {
-    tile_load(R, X, ldx, n, 1, col0, nrhs);
-    coeffs(R, 1);
+  auto put = [&](int64_t t) {
+    const int k = frexp_exp(fmax(fabs(R.c[0]), fmax(fabs(R.c[1]), fabs(R.c[2]))));
+    T(*x)[65] = xs[t % kGBuf];
+    T(*c)[kGR] = cs[t % kGBuf];
+#pragma unroll
+    for (int j = 0; j < 64; ++j) x[lane][j] = ldexp2(R.v[j], -k);
+    c[0][lane] = R.c[0];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) c[1 + q][lane] = ldexp2(R.c[q], -k);
+    ks[t % kGBuf][lane] = k;
+  };
+  if (wave == 1) {
+    for (int64_t t = 0; t < std::min<int64_t>(nt, 2); ++t) {
+      fetch(t);
+      put(t);
+    }
+    if (nt > 2) fetch(2);
   }
-  __syncthreads();
   // row 0 as it is (sc = 1; its staged copy could need sc = 2^-k0 out of range)
   T d = dia[0], u = sup[0], sc = T(1);
   T b = X[std::min<int64_t>(col0 + lane, nrhs - 1) * ldx];
-  T rd = T(0), ru = T(0), rw = T(0);  // final row i0 + lane of the current tile
+  T sd = T(0), su = T(0);  // current row i0 + lane (d, u) as it stood
   bool singular = false;
+  __syncthreads();
   for (int64_t t = 0; t < nt; ++t) {
-    // the next tile into LDS (its buffer held tile t - 1, already written
-    // back), the one after it into registers
-    if (t + 1 < nt) {
-      tile_to_lds_rows(R, xs[(t + 1) & 1], cs[(t + 1) & 1]);
-      if (t + 2 < nt) {
-        tile_load(R, X, ldx, n, t + 2, col0, nrhs);
-        coeffs(R, t + 2);
+    if (wave == 1) {  // tile t + 2 was fetched in the previous step
+      if (t >= 1) tile_store(xs[(t - 1) % kGBuf], X, ldx, n, t - 1, col0, nrhs, lane);
+      if (t + 2 < nt) put(t + 2);
+      if (t + 3 < nt) fetch(t + 3);
+    } else {
+      const int64_t i0 = t * kGR;
+      const int cur = int(t % kGBuf), nxt = int((t + 1) % kGBuf);
+      const int steps = int(std::min<int64_t>(i0 + kGR, n - 1) - i0);  // rows i0 .. i0 + steps - 1
+      // One step on rows i = i0 + q and i + 1. The current row i (d, u, 0, b)
+      // is held as sc times its value in the elimination; row i + 1 is (l1,
+      // d1, u1, b1) as staged, 2^-k times its value, and lo its entry l1 as it
+      // is. The row with the larger entry in column i is the pivot row, final
+      // row i (either scaling of it serves the back substitution). Up to its
+      // scale, the new current row is d (row i + 1) - l1 (row i) whichever row
+      // pivots; its scale is 2^-k times the pivot's magnitude piv = max(|d|,
+      // sc |lo|), and the power of two of piv is taken out (sc back in [1/2,
+      // 1)). The choice depends on the matrix alone, the same on every lane,
+      // and only selects the final row: no division, and one multiply-add, a
+      // maximum and a power-of-two rescaling on the chain of rows.
+      // Final row i is row i (d, u, 0) if bit q of keeps is set, else row i
+      // + 1 as staged; the rows are put together at the end of the tile.
+      uint64_t keeps = 0;
+      auto step = [&](int q, T lo, T l1, T d1, T u1, int k, T b1) {
+        const T sl = sc * fabs(lo);
+        const bool keep = fabs(d) >= sl;
+        keeps |= __builtin_amdgcn_ballot_w64(keep) & (uint64_t(1) << q);
+        singular = singular || (keep && d == T(0));  // |l1| > 0 when row i + 1 pivots
+        const bool mine = lane == q;
+        sd = mine ? d : sd;
+        su = mine ? u : su;
+        xs[cur][q][lane] = keep ? b : b1;
+        const T piv = fmax(fabs(d), sl);
+        const int ep = frexp_exp(piv), e = ep - k;
+        const T nd = d * d1 - l1 * u, nu = d * u1, nb = d * b1 - l1 * b;
+        sc = ldexp2(piv, -ep);
+        d = ldexp2(nd, -e);
+        u = ldexp2(nu, -e);
+        b = ldexp2(nb, -e);
+      };
+      // row r of this tile or (r = kGR) the first row of the next one
+      auto next_row = [&](int r, T& lo, T& l1, T& d1, T& u1, int& k, T& b1) {
+        const int bq = r < kGR ? cur : nxt, rr = r & (kGR - 1);
+        lo = cs[bq][0][rr];
+        l1 = cs[bq][1][rr];
+        d1 = cs[bq][2][rr];
+        u1 = cs[bq][3][rr];
+        k = ks[bq][rr];
+        b1 = xs[bq][rr][lane];
+      };
+      // kGU steps at a time: their operands are read from LDS before the
+      // first of them, off the chain of rows
+      int q = 0;
+      for (; q + kGU <= steps; q += kGU) {
+        T lo[kGU], l1[kGU], d1[kGU], u1[kGU], b1[kGU];
+        int k[kGU];
+#pragma unroll
+        for (int j = 0; j < kGU; ++j) next_row(q + 1 + j, lo[j], l1[j], d1[j], u1[j], k[j], b1[j]);
+#pragma unroll
+        for (int j = 0; j < kGU; ++j) step(q + j, lo[j], l1[j], d1[j], u1[j], k[j], b1[j]);
+      }
+      for (; q < steps; ++q) {
+        T lo, l1, d1, u1, b1;
+        int k;
+        next_row(q + 1, lo, l1, d1, u1, k, b1);
+        step(q, lo, l1, d1, u1, k, b1);
+      }
+      if (t == nt - 1) {  // the last row
+        singular = singular || d == T(0);
+        keeps |= uint64_t(1) << steps;
+        const bool mine = lane == steps;
+        sd = mine ? d : sd;
+        su = mine ? T(0) : su;
+        xs[cur][steps][lane] = b;
+      }
+      if (blockIdx.x == 0 && i0 + lane < n) {
+        const bool kp = (keeps >> lane) & 1;
+        const int bq = lane + 1 < kGR ? cur : nxt, rr = (lane + 1) & (kGR - 1);
+        coef[3 * (i0 + lane)] = kp ? sd : cs[bq][1][rr];
+        coef[3 * (i0 + lane) + 1] = kp ? su : cs[bq][2][rr];
+        coef[3 * (i0 + lane) + 2] = kp ? T(0) : cs[bq][3][rr];
       }
     }
     __syncthreads();
-    const int64_t i0 = t * kGR;
-    const int cur = int(t & 1);
-    const int steps = int(std::min<int64_t>(i0 + kGR, n - 1) - i0);  // rows i0 .. i0 + steps - 1
-    // One step on rows i = i0 + q and i + 1. The current row i (d, u, 0, b)
-    // is held as sc times its value in the elimination; row i + 1 is (l1,
-    // d1, u1, b1) as staged, 2^-k times its value, and lo its entry l1 as it
-    // is. The row with the larger entry in column i is the pivot row, final
-    // row i (either scaling of it serves the back substitution). Up to its
-    // scale, the new current row is d (row i + 1) - l1 (row i) whichever row
-    // pivots; its scale is 2^-k times the pivot's magnitude piv = max(|d|,
-    // sc |lo|), and the power of two of piv is taken out (sc back in [1/2,
-    // 1)). The choice depends on the matrix alone, the same on every lane,
-    // and only selects the final row: no division, and one multiply-add, a
-    // maximum and a power-of-two rescaling on the chain of rows.
-    auto step = [&](int q, T lo, T l1, T d1, T u1, int k, T b1) {
-      const T sl = sc * fabs(lo);
-      const bool keep = fabs(d) >= sl;
-      const T pd = keep ? d : l1, pu = keep ? u : d1, pw = keep ? T(0) : u1;
-      singular = singular || pd == T(0);
-      const bool mine = lane == q;
-      rd = mine ? pd : rd;
-      ru = mine ? pu : ru;
-      rw = mine ? pw : rw;
-      xs[cur][q][lane] = keep ? b : b1;
-      const T piv = fmax(fabs(d), sl);
-      const int ep = frexp_exp(piv), e = ep - k;
-      const T nd = d * d1 - l1 * u, nu = d * u1, nb = d * b1 - l1 * b;
-      sc = ldexp2(piv, -ep);
-      d = ldexp2(nd, -e);
-      u = ldexp2(nu, -e);
-      b = ldexp2(nb, -e);
-    };
-    // row r of this tile or (r = kGR) the first row of the next one
-    auto next_row = [&](int r, T& lo, T& l1, T& d1, T& u1, int& k, T& b1) {
-      const int bq = r < kGR ? cur : cur ^ 1, rr = r & (kGR - 1);
-      lo = cs[bq][0][rr];
-      l1 = cs[bq][1][rr];
-      d1 = cs[bq][2][rr];
-      u1 = cs[bq][3][rr];
-      k = int(cs[bq][4][rr]);
-      b1 = xs[bq][rr][lane];
-    };
-    // kGU steps at a time: their operands are read from LDS before the
-    // first of them, off the chain of rows
-    int q = 0;
-    for (; q + kGU <= steps; q += kGU) {
-      T lo[kGU], l1[kGU], d1[kGU], u1[kGU], b1[kGU];
-      int k[kGU];
-#pragma unroll
-      for (int j = 0; j < kGU; ++j) next_row(q + 1 + j, lo[j], l1[j], d1[j], u1[j], k[j], b1[j]);
-#pragma unroll
-      for (int j = 0; j < kGU; ++j) step(q + j, lo[j], l1[j], d1[j], u1[j], k[j], b1[j]);
-    }
-    for (; q < steps; ++q) {
-      T lo, l1, d1, u1, b1;
-      int k;
-      next_row(q + 1, lo, l1, d1, u1, k, b1);
-      step(q, lo, l1, d1, u1, k, b1);
-    }
-    if (t == nt - 1) {  // the last row
-      singular = singular || d == T(0);
-      const bool mine = lane == steps;
-      rd = mine ? d : rd;
-      ru = mine ? T(0) : ru;
-      rw = mine ? T(0) : rw;
-      xs[cur][steps][lane] = b;
-    }
-    if (blockIdx.x == 0 && i0 + lane < n) {
-      coef[3 * (i0 + lane)] = rd;
-      coef[3 * (i0 + lane) + 1] = ru;
-      coef[3 * (i0 + lane) + 2] = rw;
-    }
-    __syncthreads();
-    tile_store(xs[cur], X, ldx, n, t, col0, nrhs);
   }
-  if (singular && lane == 0 && blockIdx.x == 0) info[5] = 1;
+  if (wave == 1) tile_store(xs[(nt - 1) % kGBuf], X, ldx, n, nt - 1, col0, nrhs, lane);
+  if (wave == 0 && singular && lane == 0 && blockIdx.x == 0) info[5] = 1;
 }
 
 // Back substitution with the rows coef: x_i = b_i / d'_i - (u'_i / d'_i)
-// x_{i+1} - (w'_i / d'_i) x_{i+2}, tiles taken from the last one down. The
-// three scalings are made for a whole tile as it goes to LDS, off the chain of
+// x_{i+1} - (w'_i / d'_i) x_{i+2}, tiles taken from the last one down, the
+// sweep on wave 0 and the staging and write-back on wave 1 as above. The
+// three scalings are made for a whole tile as it is staged, off the chain of
 // rows, which is then one multiply-add per row: x_i = t_i - (u'_i / d'_i)
 // x_{i+1}, with t_i = b_i / d'_i - (w'_i / d'_i) x_{i+2} formed a row earlier.
 template <typename T>
-__device__ __forceinline__ void tile_to_lds_scaled(TileRegs<T>& R, T (*xs)[65], T (*cs)[kGR]) {
-#pragma unroll
-  for (int q = 0; q < 3; ++q) materialize(R.c[q]);
-  const T rd = T(1) / R.c[0];
-#pragma unroll
-  for (int c = 0; c < 64; ++c) xs[threadIdx.x][c] = R.v[c] * rd;
-  cs[0][threadIdx.x] = R.c[1] * rd;
-  cs[1][threadIdx.x] = R.c[2] * rd;
-}
-
-template <typename T>
-__global__ __launch_bounds__(64) void gtsv_backward_kernel(int64_t n, const T* __restrict__ coef,
-                                                           T* X, int64_t ldx, int64_t nrhs) {
-  __shared__ T xs[2][kGR][65];
-  __shared__ T cs[2][2][kGR];  // [buffer][u' / d', w' / d'][row in tile]
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(128) void gtsv_backward_kernel(int64_t n, const T* __restrict__ coef,
+                                                            T* X, int64_t ldx, int64_t nrhs) {
+  __shared__ T xs[kGBuf][kGR][65];
+  __shared__ T cs[kGBuf][2][kGR];  // [buffer][u' / d', w' / d'][row in tile]
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int64_t col0 = int64_t(blockIdx.x) * 64;
   const int64_t nt = (n + kGR - 1) / kGR;
-  // row g: d'_g, u'_g, w'_g
-  auto coeffs = [&](TileRegs<T>& R, int64_t t) {
+  // wave 1: fetch(t) loads tile t into R, put(t) stages R into LDS
+  TileRegs<T> R;
+  auto fetch = [&](int64_t t) {
+    tile_load(R, X, ldx, n, t, col0, nrhs, lane);
     const int64_t g = std::min<int64_t>(t * kGR + lane, n - 1);
 #pragma unroll
     for (int q = 0; q < 3; ++q) R.c[q] = coef[3 * g + q];
   };
-  TileRegs<T> R;
-  tile_load(R, X, ldx, n, nt - 1, col0, nrhs);
-  coeffs(R, nt - 1);
-  tile_to_lds_scaled(R, xs[(nt - 1) & 1], cs[(nt - 1) & 1]);
-  if (nt > 1) {
-    tile_load(R, X, ldx, n, nt - 2, col0, nrhs);
-    coeffs(R, nt - 2);
+  auto put = [&](int64_t t) {
+    const T rd = T(1) / R.c[0];
+    T(*x)[65] = xs[t % kGBuf];
+#pragma unroll
+    for (int j = 0; j < 64; ++j) x[lane][j] = R.v[j] * rd;
+    cs[t % kGBuf][0][lane] = R.c[1] * rd;
+    cs[t % kGBuf][1][lane] = R.c[2] * rd;
+  };
+  if (wave == 1) {
+    fetch(nt - 1);
+    put(nt - 1);
+    if (nt > 1) fetch(nt - 2);
   }
   __syncthreads();
   T x1 = T(0), x2 = T(0);
   for (int64_t t = nt - 1; t >= 0; --t) {
-    if (t >= 1) {
-      tile_to_lds_scaled(R, xs[(t - 1) & 1], cs[(t - 1) & 1]);
-      if (t >= 2) {
-        tile_load(R, X, ldx, n, t - 2, col0, nrhs);
-        coeffs(R, t - 2);
+    if (wave == 1) {  // tile t - 1 was fetched in the previous step
+      if (t + 1 < nt) tile_store(xs[(t + 1) % kGBuf], X, ldx, n, t + 1, col0, nrhs, lane);
+      if (t >= 1) put(t - 1);
+      if (t >= 2) fetch(t - 2);
+    } else {
+      const int64_t i0 = t * kGR;
+      const int cur = int(t % kGBuf);
+      auto row = [&](int q, T b, T cu, T cw) {
+        const T xi = (b - cw * x2) - cu * x1;
+        xs[cur][q][lane] = xi;
+        x2 = x1;
+        x1 = xi;
+      };
+      int q = int(std::min<int64_t>(i0 + kGR, n) - i0) - 1;  // rows i0 + q down to i0
+      for (; q >= kGU - 1; q -= kGU) {
+        T b[kGU], cu[kGU], cw[kGU];
+#pragma unroll
+        for (int k = 0; k < kGU; ++k) {
+          b[k] = xs[cur][q - k][lane];
+          cu[k] = cs[cur][0][q - k];
+          cw[k] = cs[cur][1][q - k];
+        }
+#pragma unroll
+        for (int k = 0; k < kGU; ++k) row(q - k, b[k], cu[k], cw[k]);
       }
+      for (; q >= 0; --q) row(q, xs[cur][q][lane], cs[cur][0][q], cs[cur][1][q]);
     }
     __syncthreads();
-    const int64_t i0 = t * kGR;
-    const int cur = int(t & 1);
-    auto row = [&](int q, T b, T cu, T cw) {
-      const T xi = (b - cw * x2) - cu * x1;
-      xs[cur][q][lane] = xi;
-      x2 = x1;
-      x1 = xi;
-    };
-    int q = int(std::min<int64_t>(i0 + kGR, n) - i0) - 1;  // rows i0 + q down to i0
-    for (; q >= kGU - 1; q -= kGU) {
-      T b[kGU], cu[kGU], cw[kGU];
-#pragma unroll
-      for (int k = 0; k < kGU; ++k) {
-        b[k] = xs[cur][q - k][lane];
-        cu[k] = cs[cur][0][q - k];
-        cw[k] = cs[cur][1][q - k];
-      }
-#pragma unroll
-      for (int k = 0; k < kGU; ++k) row(q - k, b[k], cu[k], cw[k]);
-    }
-    for (; q >= 0; --q) row(q, xs[cur][q][lane], cs[cur][0][q], cs[cur][1][q]);
-    __syncthreads();
-    tile_store(xs[cur], X, ldx, n, t, col0, nrhs);
   }
+  if (wave == 1) tile_store(xs[0], X, ldx, n, 0, col0, nrhs, lane);
 }
 
 // ------------------------------------------------------------- host side
@@ -896,17 +905,17 @@ hipError_t gtsv_launch(int dtype, int64_t n, int64_t nrhs, const void* S, int64_
     double* w = static_cast<double*>(work);
     hipLaunchKernelGGL((tridiag_extract_kernel<double>), dim3(ge), dim3(256), 0, s, n,
                        static_cast<const double*>(S), lds, w + 3 * n, w + 4 * n, w + 5 * n);
-    hipLaunchKernelGGL((gtsv_forward_kernel<double>), dim3(g), dim3(64), 0, s, n, w + 3 * n,
+    hipLaunchKernelGGL((gtsv_forward_kernel<double>), dim3(g), dim3(128), 0, s, n, w + 3 * n,
                        w + 4 * n, w + 5 * n, static_cast<double*>(X), ldx, nrhs, w, info);
-    hipLaunchKernelGGL((gtsv_backward_kernel<double>), dim3(g), dim3(64), 0, s, n, w,
+    hipLaunchKernelGGL((gtsv_backward_kernel<double>), dim3(g), dim3(128), 0, s, n, w,
                        static_cast<double*>(X), ldx, nrhs);
   } else {
     float* w = static_cast<float*>(work);
     hipLaunchKernelGGL((tridiag_extract_kernel<float>), dim3(ge), dim3(256), 0, s, n,
                        static_cast<const float*>(S), lds, w + 3 * n, w + 4 * n, w + 5 * n);
-    hipLaunchKernelGGL((gtsv_forward_kernel<float>), dim3(g), dim3(64), 0, s, n, w + 3 * n,
+    hipLaunchKernelGGL((gtsv_forward_kernel<float>), dim3(g), dim3(128), 0, s, n, w + 3 * n,
                        w + 4 * n, w + 5 * n, static_cast<float*>(X), ldx, nrhs, w, info);
-    hipLaunchKernelGGL((gtsv_backward_kernel<float>), dim3(g), dim3(64), 0, s, n, w,
+    hipLaunchKernelGGL((gtsv_backward_kernel<float>), dim3(g), dim3(128), 0, s, n, w,
                        static_cast<float*>(X), ldx, nrhs);
   }
   return hipGetLastError();
