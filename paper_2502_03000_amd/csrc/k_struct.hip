@@ -209,6 +209,7 @@ __global__ __launch_bounds__(256) void potrf_block_kernel(T* __restrict__ A, int
   constexpr int LA = kB + 4;
   __shared__ T As[kB][LA];          // As[r][c]: the block (lower part), then L11
   __shared__ T colj[16];            // the current column's multipliers in the panel
+  __shared__ T rdg[kB];             // 1 / L(j, j)
   __shared__ T Ds[4][16][16 + 4];   // Ds[b][t][i] = D_b(i, t)
   __shared__ T Ms[6][16][16 + 4];   // Ms[p][t][i] = M_bj(i, t), p = b(b-1)/2 + j
   __shared__ T Rs[4][16][kB + 4];   // Rs[w][c][i] = R(i, 16w + c)
@@ -247,8 +248,11 @@ __global__ __launch_bounds__(256) void potrf_block_kernel(T* __restrict__ A, int
         const T d = lane_value(a[jj], j);  // the pivot, lane j's diagonal entry
         const bool ok = d > T(0);
         bad = bad || !ok;
-        const T ljj = ok ? sqrt(d) : T(1);
-        const T l = r == j ? ljj : a[jj] / ljj;
+        // one reciprocal square root on the chain of columns: L(j, j) =
+        // d / sqrt(d), the column below it scaled by 1 / sqrt(d)
+        const T rs = ok ? rsqrt(d) : T(1);
+        const T l = (r == j ? d : a[jj]) * rs;
+        if (r == j) rdg[j] = rs;
         a[jj] = l;
         if (jj < 15) {
           if (r >= j && r < 16 * b + 16) colj[r - 16 * b] = l;
@@ -305,7 +309,7 @@ __global__ __launch_bounds__(256) void potrf_block_kernel(T* __restrict__ A, int
     for (int i = 0; i < 16; ++i) x[i] = T(i == l16 ? 1 : 0);
 #pragma unroll
     for (int l = 0; l < 16; ++l) {
-      const T xl = x[l] / As[16 * g + l][16 * g + l];
+      const T xl = x[l] * rdg[16 * g + l];
       x[l] = xl;
 #pragma unroll
       for (int i = l + 1; i < 16; ++i) x[i] -= As[16 * g + i][16 * g + l] * xl;
