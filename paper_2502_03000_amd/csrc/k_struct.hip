@@ -492,11 +492,13 @@ __global__ __launch_bounds__(256) void tridiag_extract_kernel(int64_t n, const T
 }
 
 // The right-hand sides pass through LDS in tiles of kGR rows x 64 columns.
-// A workgroup has two waves: wave 0 runs the sequential sweep over the rows
-// of one tile while wave 1 writes the tile before it back to X and stages the
-// one after it, so that the global traffic and the staging are off the
-// chain of rows. Wave 1 loads a tile with one lane per row (each load
-// instruction reads 64 consecutive rows of one column, one coalesced run)
+// A workgroup has three waves: wave 0 runs the sequential sweep over the
+// rows of one tile while wave 1 stages the tiles after it and wave 2 writes
+// the one before it back to X, so that the global traffic and the staging
+// are off the chain of rows (a wave counts at most 63 memory instructions
+// in flight, and a tile takes 64 loads and 64 stores). Wave 1 loads a tile
+// with one lane per row (each load instruction reads 64 consecutive rows of
+// one column, one coalesced run)
 // into registers a step before it stores it to LDS, so that the loads are in
 // flight across a step; the sweep reads it with one lane per column. Four
 // buffers: the tile being swept, the next one (whose first row the forward
@@ -561,7 +563,7 @@ __device__ __forceinline__ void tile_store(const T (*xs)[65], T* X, int64_t ldx,
 // entries stay in range; l itself is kept for the pivot comparison.
 // cs: [l, l 2^-k, dia 2^-k, sup 2^-k][row in tile], ks: k.
 template <typename T>
-__global__ __launch_bounds__(128) void gtsv_forward_kernel(int64_t n, const T* __restrict__ sub,
+__global__ __launch_bounds__(192) void gtsv_forward_kernel(int64_t n, const T* __restrict__ sub,
                                                            const T* __restrict__ dia,
                                                            const T* __restrict__ sup, T* X,
                                                            int64_t ldx, int64_t nrhs, T* coef,
@@ -606,8 +608,9 @@ __global__ __launch_bounds__(128) void gtsv_forward_kernel(int64_t n, const T* _
   bool singular = false;
   __syncthreads();
   for (int64_t t = 0; t < nt; ++t) {
-    if (wave == 1) {  // tile t + 2 was fetched in the previous step
+    if (wave == 2) {
       if (t >= 1) tile_store(xs[(t - 1) % kGBuf], X, ldx, n, t - 1, col0, nrhs, lane);
+    } else if (wave == 1) {  // tile t + 2 was fetched in the previous step
       if (t + 2 < nt) put(t + 2);
       if (t + 3 < nt) fetch(t + 3);
     } else {
@@ -690,18 +693,18 @@ __global__ __launch_bounds__(128) void gtsv_forward_kernel(int64_t n, const T* _
     }
     __syncthreads();
   }
-  if (wave == 1) tile_store(xs[(nt - 1) % kGBuf], X, ldx, n, nt - 1, col0, nrhs, lane);
+  if (wave == 2) tile_store(xs[(nt - 1) % kGBuf], X, ldx, n, nt - 1, col0, nrhs, lane);
   if (wave == 0 && singular && lane == 0 && blockIdx.x == 0) info[5] = 1;
 }
 
 // Back substitution with the rows coef: x_i = b_i / d'_i - (u'_i / d'_i)
 // x_{i+1} - (w'_i / d'_i) x_{i+2}, tiles taken from the last one down, the
-// sweep on wave 0 and the staging and write-back on wave 1 as above. The
+// sweep on wave 0, the staging on wave 1 and the write-back on wave 2 as above. The
 // three scalings are made for a whole tile as it is staged, off the chain of
 // rows, which is then one multiply-add per row: x_i = t_i - (u'_i / d'_i)
 // x_{i+1}, with t_i = b_i / d'_i - (w'_i / d'_i) x_{i+2} formed a row earlier.
 template <typename T>
-__global__ __launch_bounds__(128) void gtsv_backward_kernel(int64_t n, const T* __restrict__ coef,
+__global__ __launch_bounds__(192) void gtsv_backward_kernel(int64_t n, const T* __restrict__ coef,
                                                             T* X, int64_t ldx, int64_t nrhs) {
   __shared__ T xs[kGBuf][kGR][65];
   __shared__ T cs[kGBuf][2][kGR];  // [buffer][u' / d', w' / d'][row in tile]
@@ -732,8 +735,9 @@ __global__ __launch_bounds__(128) void gtsv_backward_kernel(int64_t n, const T* 
   __syncthreads();
   T x1 = T(0), x2 = T(0);
   for (int64_t t = nt - 1; t >= 0; --t) {
-    if (wave == 1) {  // tile t - 1 was fetched in the previous step
+    if (wave == 2) {
       if (t + 1 < nt) tile_store(xs[(t + 1) % kGBuf], X, ldx, n, t + 1, col0, nrhs, lane);
+    } else if (wave == 1) {  // tile t - 1 was fetched in the previous step
       if (t >= 1) put(t - 1);
       if (t >= 2) fetch(t - 2);
     } else {
@@ -761,7 +765,7 @@ __global__ __launch_bounds__(128) void gtsv_backward_kernel(int64_t n, const T* 
     }
     __syncthreads();
   }
-  if (wave == 1) tile_store(xs[0], X, ldx, n, 0, col0, nrhs, lane);
+  if (wave == 2) tile_store(xs[0], X, ldx, n, 0, col0, nrhs, lane);
 }
 
 // ------------------------------------------------------------- host side
@@ -909,17 +913,17 @@ hipError_t gtsv_launch(int dtype, int64_t n, int64_t nrhs, const void* S, int64_
     double* w = static_cast<double*>(work);
     hipLaunchKernelGGL((tridiag_extract_kernel<double>), dim3(ge), dim3(256), 0, s, n,
                        static_cast<const double*>(S), lds, w + 3 * n, w + 4 * n, w + 5 * n);
-    hipLaunchKernelGGL((gtsv_forward_kernel<double>), dim3(g), dim3(128), 0, s, n, w + 3 * n,
+    hipLaunchKernelGGL((gtsv_forward_kernel<double>), dim3(g), dim3(192), 0, s, n, w + 3 * n,
                        w + 4 * n, w + 5 * n, static_cast<double*>(X), ldx, nrhs, w, info);
-    hipLaunchKernelGGL((gtsv_backward_kernel<double>), dim3(g), dim3(128), 0, s, n, w,
+    hipLaunchKernelGGL((gtsv_backward_kernel<double>), dim3(g), dim3(192), 0, s, n, w,
                        static_cast<double*>(X), ldx, nrhs);
   } else {
     float* w = static_cast<float*>(work);
     hipLaunchKernelGGL((tridiag_extract_kernel<float>), dim3(ge), dim3(256), 0, s, n,
                        static_cast<const float*>(S), lds, w + 3 * n, w + 4 * n, w + 5 * n);
-    hipLaunchKernelGGL((gtsv_forward_kernel<float>), dim3(g), dim3(128), 0, s, n, w + 3 * n,
+    hipLaunchKernelGGL((gtsv_forward_kernel<float>), dim3(g), dim3(192), 0, s, n, w + 3 * n,
                        w + 4 * n, w + 5 * n, static_cast<float*>(X), ldx, nrhs, w, info);
-    hipLaunchKernelGGL((gtsv_backward_kernel<float>), dim3(g), dim3(128), 0, s, n, w,
+    hipLaunchKernelGGL((gtsv_backward_kernel<float>), dim3(g), dim3(192), 0, s, n, w,
                        static_cast<float*>(X), ldx, nrhs);
   }
   return hipGetLastError();
