@@ -190,6 +190,42 @@ def test_tridiagonal_rows_of_every_scale(ctx, dt, nrhs):
     assert rel(host(out), ref) <= max(TOL[dt], 10.0 * np.linalg.cond(s0) * np.sqrt(n) * U[dt])
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_tridiagonal_full_size(ctx, dt):
+    """The structured-solve workload's tridiagonal system at its own size (n =
+    8192, B 8192 x 64; |diagonal| < |off-diagonals|, so that most steps swap
+    rows): 128 tiles through the three waves' four LDS buffers. Checked
+    against LAPACK's banded solver in FP64 (scipy; a textbook routine, not
+    the oracle, whose dense GEPP takes minutes here) within 10 cond_1(S) u,
+    and by the FP64 backward error <= n u."""
+    import scipy.linalg
+    n, r = 8192, 64
+    g = inputs.rng(3400)
+    dia = g.uniform(-0.3, 0.3, n)
+    sub = 0.2 * g.standard_normal(n - 1) + 1.0
+    sup = 0.2 * g.standard_normal(n - 1) - 1.0
+    s = np.diag(dia) + np.diag(sub, -1) + np.diag(sup, 1)
+    s = np.asfortranarray(s.astype(dt))
+    b = inputs.normal(g, n, r, dt)
+    ab = np.zeros((3, n))
+    ab[0, 1:], ab[1], ab[2, :-1] = np.diag(s, 1), np.diag(s), np.diag(s, -1)
+    ref = scipy.linalg.solve_banded((1, 1), ab, b.astype(np.float64))
+    inv = scipy.linalg.solve_banded((1, 1), ab, np.eye(n))
+    cond1 = np.abs(s.astype(np.float64)).sum(axis=0).max() * np.abs(inv).sum(axis=0).max()
+    del inv
+    p = ctx.plan(hx.solve(ctx.leaf(dev(s)), ctx.leaf(dev(b))))
+    out = p.output()
+    p.execute(out, p.workspace())
+    rep = ctx.sync()
+    assert rep.status == hx.OK and hx.SOLVERS[rep.solver] == "tridiagonal"
+    got = host(out)
+    assert rel(got, ref) <= max(TOL[dt], 10.0 * cond1 * U[dt]), (rel(got, ref), cond1)
+    s64, b64 = s.astype(np.float64), b.astype(np.float64)
+    berr = np.linalg.norm(b64 - s64 @ got) / (np.linalg.norm(s64) * np.linalg.norm(got))
+    assert berr <= n * U[dt]
+
+
 def test_structured_solve_capture_rules(ctx):
     g = inputs.rng(3200)
     s, b = inputs.diag_dominant(g, 100), inputs.normal(g, 100, 2)
