@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 namespace hexla {
 namespace k {
 
@@ -342,9 +344,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
       }
 }
 
-// C = alpha * sum_z P[z] + beta * C, summed in z order (deterministic).
-// Full mode: each lane reduces four consecutive elements of a column with
-// 16-byte loads when the shape allows, so the pass streams at HBM rate.
+// C = alpha * sum_z P[z] + beta * C, summed in a fixed order (deterministic).
+// Full mode with m % 4 == 0: one workgroup per 64 quads of consecutive
+// elements of a column (16- or 32-byte loads); lane = quad, and wave w sums
+// the partials z = w, w + 4, ... in ascending z, up to four loads in flight,
+// so that a launch has four times the quads' parallelism and a few memory
+// round trips; the four wave sums are added in w order. Other modes: one
+// element per thread, z ascending, over a grid-stride loop.
 template <typename T>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g) {
   const int64_t total = g.m * g.n;
@@ -354,38 +360,33 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g) {
   const T alpha = T(g.alpha), beta = T(g.beta);
   const int S = g.split;
   if (g.mode == 0 && (g.m % 4) == 0) {
-    const int64_t quads = total / 4;
-    for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < quads; q += stride) {
-      const int64_t e = q * 4;
+    typedef T v4 __attribute__((ext_vector_type(4)));
+    __shared__ v4 red[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t quads = total / 4, q = int64_t(blockIdx.x) * 64 + lane;
+    const int64_t e = (q < quads ? q : quads - 1) * 4;
+    v4 acc = {T(0), T(0), T(0), T(0)};
+    int z = w;
+    for (; z + 12 < S; z += 16) {
+      const v4 a0 = *reinterpret_cast<const v4*>(P + int64_t(z) * total + e);
+      const v4 a1 = *reinterpret_cast<const v4*>(P + int64_t(z + 4) * total + e);
+      const v4 a2 = *reinterpret_cast<const v4*>(P + int64_t(z + 8) * total + e);
+      const v4 a3 = *reinterpret_cast<const v4*>(P + int64_t(z + 12) * total + e);
+      acc += a0;
+      acc += a1;
+      acc += a2;
+      acc += a3;
+    }
+    for (; z < S; z += 4) acc += *reinterpret_cast<const v4*>(P + int64_t(z) * total + e);
+    red[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && q < quads) {
+      const v4 sum = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
       const int64_t i = e % g.m, j = e / g.m;
-      T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-      int z = 0;
-      for (; z + 4 <= S; z += 4) {
-        T v[4][4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) v[u][r] = P[int64_t(z + u) * total + e + r];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          s0 += v[u][0];
-          s1 += v[u][1];
-          s2 += v[u][2];
-          s3 += v[u][3];
-        }
-      }
-      for (; z < S; ++z) {
-        const T* p = P + int64_t(z) * total + e;
-        s0 += p[0];
-        s1 += p[1];
-        s2 += p[2];
-        s3 += p[3];
-      }
       T* c = C + i + j * g.ldc;
-      const T sv[4] = {s0, s1, s2, s3};
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        T out = alpha * sv[r];
+        T out = alpha * sum[r];
         if (beta != T(0)) out += beta * c[r];
         c[r] = out;
       }
@@ -402,6 +403,20 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs g) {
     C[i + j * g.ldc] = out;
     if (g.mode == 1 && i > j) C[j + i * g.ldc] = out;
   }
+}
+
+// Launches the reduction of a split-K product described by g.
+template <typename T>
+inline hipError_t splitk_reduce_launch(const GemmArgs& g, hipStream_t s) {
+  const int64_t total = g.m * g.n;
+  if (total <= 0) return hipSuccess;
+  int64_t blocks;
+  if (g.mode == 0 && (g.m % 4) == 0)
+    blocks = (total / 4 + 63) / 64;
+  else
+    blocks = std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(splitk_reduce_kernel<T>, dim3(unsigned(blocks)), dim3(256), 0, s, g);
+  return hipGetLastError();
 }
 
 }  // namespace k

@@ -169,13 +169,7 @@ hipError_t gemm_launch(int dtype, int precision, int mode, int ta, int tb, int64
   hipLaunchKernelGGL(fn, dim3(unsigned(blocks), unsigned(cfg.split)), dim3(256), 0, s, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || cfg.split <= 1) return e;
-  int64_t rb = cdiv(m * n, 256);
-  if (rb > 4096) rb = 4096;
-  if (dtype == 0)
-    hipLaunchKernelGGL(splitk_reduce_kernel<double>, dim3(unsigned(rb)), dim3(256), 0, s, g);
-  else
-    hipLaunchKernelGGL(splitk_reduce_kernel<float>, dim3(unsigned(rb)), dim3(256), 0, s, g);
-  return hipGetLastError();
+  return dtype == 0 ? splitk_reduce_launch<double>(g, s) : splitk_reduce_launch<float>(g, s);
 }
 
 }  // namespace k

@@ -534,10 +534,7 @@ hipError_t gemm_split_launch(int dtype, int precision, int mode, int ta, int tb,
   hipLaunchKernelGGL(fn, dim3(unsigned(blocks), unsigned(g.split)), dim3(256), 0, s, g, vec);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || g.split <= 1) return e;
-  int64_t rb = cdiv(m * n, 256);
-  if (rb > 4096) rb = 4096;
-  hipLaunchKernelGGL(splitk_reduce_kernel<float>, dim3(unsigned(rb)), dim3(256), 0, s, g);
-  return hipGetLastError();
+  return splitk_reduce_launch<float>(g, s);
 }
 
 hipError_t rank_update_split_launch(int precision, int64_t m, int64_t n, int64_t K,
