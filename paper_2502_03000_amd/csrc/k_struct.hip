@@ -498,11 +498,11 @@ __global__ __launch_bounds__(256) void tridiag_extract_kernel(int64_t n, const T
 // are off the chain of rows (a wave counts at most 63 memory instructions
 // in flight, and a tile takes 64 loads and 64 stores). Wave 1 loads a tile
 // with one lane per row (each load instruction reads 64 consecutive rows of
-// one column, one coalesced run)
-// into registers a step before it stores it to LDS, so that the loads are in
-// flight across a step; the sweep reads it with one lane per column. Four
-// buffers: the tile being swept, the next one (whose first row the forward
-// sweep reads), the one being staged and the one being written back.
+// one column, one coalesced run) into registers a step before it stores it
+// to LDS, so that the loads are in flight across a step; the sweep reads it
+// with one lane per column. Four buffers: the tile being swept, the next one
+// (whose first row the forward sweep reads), the one being staged and the
+// one being written back.
 constexpr int kGR = 64;
 constexpr int kGBuf = 4;
 // Rows per group of the sweeps: their LDS operands are read together.
