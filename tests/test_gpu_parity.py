@@ -488,3 +488,27 @@ def test_graph_replay_matches_eager(ctx):
         p.replay()
         assert ctx.sync().status == hx.OK
         assert np.array_equal(host(out), eager)
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+@pytest.mark.parametrize("split", [5, 17, 32])
+def test_split_k_reduction_waves(tmp_path, dt, split):
+    """The reduction's quad path (m % 4 == 0): wave w of a workgroup sums the
+    partials z = w, w + 4, ..., four at a time and then the rest, and the four
+    wave sums are added in w order; split counts that leave the waves unequal
+    shares (5), a remainder past the groups of four (17) and eight per wave
+    (32), with a ragged last quad of workgroups (300 x 130 = 39000 elements,
+    9750 quads: 152 full workgroups of 64 quads and a last one of 22)."""
+    ctx = hx.Context(0)
+    g = inputs.rng(78 + split)
+    m, n, k = 300, 130, 2000
+    a, b = inputs.normal(g, m, k, dt), inputs.normal(g, k, n, dt)
+    ref = oracle.evaluate("A*B", {"A": a, "B": b})
+    mag = oracle.magnitude("A*B", {"A": a, "B": b})
+    e = ctx.leaf(dev(a)) @ ctx.leaf(dev(b))
+    q = _force(ctx, tmp_path, e, 0, split)
+    out, ws = q.output(), q.workspace()
+    ws.fill_(255)
+    q.execute(out, ws)
+    assert ctx.sync().status == hx.OK
+    assert_close(host(out), ref, mag, dt, k + 2, what=f"split {split}")
