@@ -791,6 +791,8 @@ hipError_t chol_panel(T* A, int64_t lda, int64_t n, int64_t k0, int32_t* info, T
 // part on s, directly followed by that block's factorisation, and the part
 // right of it on side->s, overlapping the factorisation; the next split
 // update waits for it (both write the columns right of the next block).
+constexpr int64_t kCholInline = 3072;
+
 template <typename T>
 hipError_t chol_factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* info, T* inv,
                              hipStream_t s, const Lookahead* side) {
@@ -810,7 +812,10 @@ hipError_t chol_factor_typed(int dtype, int64_t n, T* A, int64_t lda, int32_t* i
       if ((e = hipStreamWaitEvent(s, side->done, 0)) != hipSuccess) return e;
       pending = false;
     }
-    if (!lookahead || near == m) {
+    // Below kCholInline rows the whole update on s costs less than the two
+    // event operations (about 7 us each) and the near part that the
+    // lookahead puts on the critical path.
+    if (!lookahead || near == m || m <= kCholInline) {
       e = syrk_lower_update_launch(dtype, m, kB, W, lda, A + k1 + k1 * lda, lda, s);
     } else {
       // columns k1 .. k1 + 64 (all rows from k1) on s; the rest on side->s,
